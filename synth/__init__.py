@@ -1,0 +1,275 @@
+"""Seeded synthetic inputs: random rooted trees and sparse sample x tip count tables.
+
+This module is shared by the oracle and by the GPU library's tests and bench.
+It only draws random inputs; it computes nothing of the UniFrac method itself.
+
+Workload laws (the paper measures on the Earth Microbiome Project tables, which
+are not available here; these synthetic laws stand in for them):
+
+* tree topology: random merge (coalescent) -- repeatedly join two uniformly
+  chosen lineages under a new parent.  Tips get ids 0..n-1, internal nodes get
+  ids n..2n-2 in creation order, the root is 2n-2.  Depth grows like log n.
+* branch lengths: i.i.d. Exponential(mean) for every non-root node; the root's
+  entry is 0 and is ignored by the method.
+* "uniform" tables: exactly ``nnz`` distinct tips per sample, uniform without
+  replacement.
+* "zipf" tables: tip popularity ~ rank^-s over all tips with a seeded random
+  rank->tip permutation; i.i.d. draws until ``nnz`` distinct tips are seen.
+* counts: round(LogNormal(mu=2, sigma=1.5)) + 1 per (sample, tip).
+* rarefaction: subsampling without replacement (multivariate hypergeometric)
+  to an exact depth; samples with fewer reads are dropped.
+
+A table is returned as CSR: ``indptr`` (n_samples+1), ``tips`` (tree node id of
+each nonzero), ``counts`` (int64 > 0); all int64.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = [
+    "Tree", "Table", "gen_tree", "gen_table_uniform", "gen_table_zipf",
+    "rarefy", "subset_rows", "config", "CONFIGS",
+]
+
+
+@dataclasses.dataclass
+class Tree:
+    parent: np.ndarray   # int64 [n_nodes], -1 for the root
+    length: np.ndarray   # float64 [n_nodes], >= 0
+    n_tips: int
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.parent.shape[0])
+
+
+@dataclasses.dataclass
+class Table:
+    indptr: np.ndarray   # int64 [n_samples+1]
+    tips: np.ndarray     # int64 [nnz] tree node ids
+    counts: np.ndarray   # int64 [nnz] > 0
+
+    @property
+    def n_samples(self) -> int:
+        return int(self.indptr.shape[0] - 1)
+
+    def dense(self, n_nodes: int) -> np.ndarray:
+        """Dense [n_samples, n_nodes] int64 count matrix (small inputs only)."""
+        out = np.zeros((self.n_samples, n_nodes), dtype=np.int64)
+        rows = np.repeat(np.arange(self.n_samples), np.diff(self.indptr))
+        np.add.at(out, (rows, self.tips), self.counts)
+        return out
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng([int(seed), int(stream)])
+
+
+def gen_tree(n_tips: int, mean_len: float, seed: int) -> Tree:
+    """Random-merge rooted binary tree with Exponential(mean_len) branch lengths."""
+    if n_tips < 1:
+        raise ValueError("n_tips must be >= 1")
+    rng = _rng(seed, 1)
+    n_nodes = 2 * n_tips - 1
+    parent = np.full(n_nodes, -1, dtype=np.int64)
+    m = np.arange(n_tips, 1, -1, dtype=np.float64)          # lineages before each merge
+    ua = np.floor(rng.random(n_tips - 1) * m).astype(np.int64)
+    ub = np.floor(rng.random(n_tips - 1) * (m - 1)).astype(np.int64)
+    lineages: List[int] = list(range(n_tips))
+    nxt = n_tips
+    for k in range(n_tips - 1):
+        a = int(ua[k])
+        b = int(ub[k])
+        if b >= a:
+            b += 1
+        la, lb = lineages[a], lineages[b]
+        parent[la] = nxt
+        parent[lb] = nxt
+        # remove the two picked lineages (swap-with-last), then add the new one
+        hi, lo = (a, b) if a > b else (b, a)
+        lineages[hi] = lineages[-1]
+        lineages.pop()
+        lineages[lo] = lineages[-1]
+        lineages.pop()
+        lineages.append(nxt)
+        nxt += 1
+    length = rng.exponential(mean_len, size=n_nodes)
+    length[n_nodes - 1] = 0.0
+    return Tree(parent=parent, length=length, n_tips=n_tips)
+
+
+def _counts(rng: np.random.Generator, size: int) -> np.ndarray:
+    return (np.rint(rng.lognormal(2.0, 1.5, size=size)) + 1).astype(np.int64)
+
+
+def gen_table_uniform(n_samples: int, tip_ids: np.ndarray, nnz: int, seed: int) -> Table:
+    """Exactly ``nnz`` distinct tips per sample, uniform without replacement."""
+    rng = _rng(seed, 2)
+    tip_ids = np.asarray(tip_ids, dtype=np.int64)
+    n = tip_ids.shape[0]
+    if nnz > n:
+        raise ValueError("nnz exceeds the number of tips")
+    keys = rng.random((n_samples, n))
+    pick = np.argpartition(keys, nnz - 1, axis=1)[:, :nnz]
+    pick.sort(axis=1)
+    tips = tip_ids[pick].reshape(-1)
+    counts = _counts(rng, n_samples * nnz)
+    indptr = np.arange(n_samples + 1, dtype=np.int64) * nnz
+    return Table(indptr=indptr, tips=tips, counts=counts)
+
+
+def _alias(p: np.ndarray):
+    """Walker alias table for O(1) draws from a discrete law."""
+    n = p.shape[0]
+    q = p * n
+    alias = np.zeros(n, dtype=np.int64)
+    small = list(np.nonzero(q < 1.0)[0])
+    large = list(np.nonzero(q >= 1.0)[0])
+    while small and large:
+        s = small.pop()
+        g = large.pop()
+        alias[s] = g
+        q[g] -= 1.0 - q[s]
+        (small if q[g] < 1.0 else large).append(g)
+    for rest in (small, large):
+        for s in rest:
+            q[s] = 1.0
+    return alias, q
+
+
+def gen_table_zipf(n_samples: int, tip_ids: np.ndarray, nnz: int, seed: int,
+                   s: float = 1.1, batch: int = 1024) -> Table:
+    """Zipf(s) tip popularity; i.i.d. draws per sample until ``nnz`` distinct tips."""
+    rng = _rng(seed, 3)
+    tip_ids = np.asarray(tip_ids, dtype=np.int64)
+    n = tip_ids.shape[0]
+    if nnz > n:
+        raise ValueError("nnz exceeds the number of tips")
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-s)
+    alias, q = _alias(w / w.sum())
+    rank_to_tip = tip_ids[rng.permutation(n)]
+    rows = []
+    draws = max(4 * nnz, 64)
+    done = 0
+    while done < n_samples:
+        b = min(batch, n_samples - done)
+        need = np.arange(b)
+        out = np.empty((b, nnz), dtype=np.int64)
+        d = draws
+        while need.size:
+            i = rng.integers(0, n, size=(need.size, d))
+            u = rng.random((need.size, d))
+            r = np.where(u < q[i], i, alias[i])
+            order = np.argsort(r, axis=1, kind="stable")
+            rs = np.take_along_axis(r, order, 1)
+            first_sorted = np.ones_like(rs, dtype=bool)
+            first_sorted[:, 1:] = rs[:, 1:] != rs[:, :-1]
+            first = np.zeros_like(first_sorted)
+            np.put_along_axis(first, order, first_sorted, 1)
+            c = np.cumsum(first, axis=1, dtype=np.int64)
+            ok = c[:, -1] >= nnz
+            sel = first & (c <= nnz)
+            okr = np.nonzero(ok)[0]
+            if okr.size:
+                out[need[okr]] = r[okr][sel[okr]].reshape(okr.size, nnz)
+            need = need[~ok]
+            d *= 2
+        tips = np.sort(rank_to_tip[out], axis=1)
+        rows.append(tips)
+        done += b
+    tips = np.concatenate(rows, axis=0).reshape(-1)
+    counts = _counts(rng, n_samples * nnz)
+    indptr = np.arange(n_samples + 1, dtype=np.int64) * nnz
+    return Table(indptr=indptr, tips=tips, counts=counts)
+
+
+def rarefy(table: Table, depth: int, seed: int) -> Table:
+    """Subsample each sample without replacement to exactly ``depth`` reads.
+
+    Samples with fewer than ``depth`` reads are dropped; zero entries removed.
+    """
+    rng = _rng(seed, 4)
+    indptr, tips, counts = table.indptr, table.tips, table.counts
+    out_ptr = [0]
+    out_tips = []
+    out_counts = []
+    for r in range(table.n_samples):
+        a, b = int(indptr[r]), int(indptr[r + 1])
+        c = counts[a:b]
+        if int(c.sum()) < depth:
+            continue
+        sub = rng.multivariate_hypergeometric(c, depth)
+        keep = sub > 0
+        out_tips.append(tips[a:b][keep])
+        out_counts.append(sub[keep].astype(np.int64))
+        out_ptr.append(out_ptr[-1] + int(keep.sum()))
+    if out_tips:
+        t = np.concatenate(out_tips)
+        c = np.concatenate(out_counts)
+    else:
+        t = np.zeros(0, np.int64)
+        c = np.zeros(0, np.int64)
+    return Table(indptr=np.asarray(out_ptr, dtype=np.int64), tips=t, counts=c)
+
+
+def subset_rows(table: Table, rows) -> Table:
+    """Table restricted to the given sample rows (in the given order)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    lens = table.indptr[rows + 1] - table.indptr[rows]
+    indptr = np.zeros(rows.shape[0] + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    idx = np.concatenate([np.arange(table.indptr[r], table.indptr[r + 1]) for r in rows]) \
+        if rows.size else np.zeros(0, np.int64)
+    return Table(indptr=indptr, tips=table.tips[idx], counts=table.counts[idx])
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Sizes and laws follow the configurations the project is
+# measured on; C1 is small enough for the oracle to finish in seconds.
+# ---------------------------------------------------------------------------
+CONFIGS = {
+    "C1": dict(n_tips=1000, mean_len=0.1, n_samples=256, nnz=50, law="uniform", seed=101),
+    "C2": dict(n_tips=200000, mean_len=0.05, n_samples=25000, nnz=1000, law="zipf", seed=102),
+    "C3": dict(n_tips=200000, mean_len=0.05, n_samples=50000, nnz=1000, law="zipf", seed=103),
+    "C4": dict(n_tips=100000, mean_len=0.05, n_tables=64, n_min=2000, n_max=20000,
+               nnz=1000, law="zipf", depth=5000, seed=104),
+    "C5": dict(n_tips=200000, mean_len=0.05, n_ref=25000, n_query=10000, nnz=1000,
+               law="zipf", seed=102, query_seed=105),
+}
+
+
+def config(name: str, n_samples: Optional[int] = None, n_tips: Optional[int] = None):
+    """Generate (tree, table) for C1/C2/C3, optionally scaled down.
+
+    The tree seed and the table seed are the configuration's seed on separate
+    streams, so a scaled-down table on the full tree reuses the same tree.
+    """
+    c = CONFIGS[name]
+    nt = int(n_tips if n_tips is not None else c["n_tips"])
+    ns = int(n_samples if n_samples is not None else c["n_samples"])
+    tree = gen_tree(nt, c["mean_len"], c["seed"])
+    tip_ids = np.arange(nt, dtype=np.int64)
+    nnz = min(c["nnz"], nt)
+    if c["law"] == "uniform":
+        table = gen_table_uniform(ns, tip_ids, nnz, c["seed"])
+    else:
+        table = gen_table_zipf(ns, tip_ids, nnz, c["seed"])
+    return tree, table
+
+
+def batch_tables(n_tips: int = 100000, n_tables: int = 64, n_min: int = 2000,
+                 n_max: int = 20000, nnz: int = 1000, depth: int = 5000,
+                 seed: int = 104):
+    """Tree + ``n_tables`` rarefied tables of uneven size (the batching workload)."""
+    tree = gen_tree(n_tips, CONFIGS["C4"]["mean_len"], seed)
+    rng = _rng(seed, 5)
+    sizes = rng.integers(n_min, n_max + 1, size=n_tables)
+    tip_ids = np.arange(n_tips, dtype=np.int64)
+    tables = []
+    for r, n in enumerate(sizes):
+        t = gen_table_zipf(int(n), tip_ids, min(nnz, n_tips), seed * 1000 + r)
+        tables.append(rarefy(t, depth, seed * 1000 + r))
+    return tree, tables
