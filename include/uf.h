@@ -1,0 +1,195 @@
+/*
+ * uf.h -- C ABI of the MI355X (gfx950) striped UniFrac library.
+ *
+ * What is computed.  The paper (section II) computes the all-pairs UniFrac
+ * distance matrix, unweighted and weighted normalized, for the samples of a
+ * sparse sample x feature count table whose features are the tips of a rooted
+ * phylogeny, with the "Striped UniFrac" method: a postorder pass over the tree
+ * gives every sample's embedded proportion on every branch, then the sample
+ * pairs are accumulated stripe by stripe.  The definitions (standard UniFrac):
+ *
+ *   c[s,v] = sum of sample s's counts on the tips under node v;  T_s = total
+ *   u[s,v] = c[s,v] / T_s ;  a[s,v] = (c[s,v] > 0)
+ *   unweighted           d = sum_v l_v |a_iv - a_jv| / sum_v l_v max(a_iv, a_jv)
+ *   weighted normalized  d = sum_v l_v |u_iv - u_jv| / sum_v l_v (u_iv + u_jv)
+ *
+ * with v over the non-root nodes and l_v the length of v's branch to its
+ * parent.  A zero denominator gives d = 0.
+ *
+ * Stripes (the paper splits the problem into "a set of stripes" so a device
+ * with little memory can compute it piece by piece, section II): with
+ * S = floor(N/2) stripes, stripe s holds the N pairs (i, (i+s+1) mod N).  For
+ * odd N every pair appears once; for even N the last stripe holds each of its
+ * N/2 pairs twice.  Stripe-major output is [s_end - s_begin][N].  Condensed
+ * output is the row-major upper triangle: pair i<j at N*i - i(i+1)/2 + j-i-1.
+ *
+ * PCoA inputs (the paper computes principal coordinates as part of the same
+ * job, section II): with A_ij = -d_ij^2 / 2 (A_ii = 0), row means
+ * r_i = (1/N) sum_j A_ij and grand mean g = (1/N) sum_i r_i, in FP64, summed
+ * in a fixed order (bitwise reproducible).
+ *
+ * Conventions.  Every function returns uf_status (UF_OK = 0) and never throws
+ * or aborts.  Host input arrays are copied during *_load; the caller may free
+ * them afterwards.  Handles are owned by the library, immutable after creation
+ * and may be shared between threads and streams.  Outputs, workspaces and
+ * streams belong to the caller: device pointers (hipMalloc'd or torch CUDA
+ * tensors on the current device) and a hipStream_t passed as void* (NULL =
+ * the default stream).  Compute calls are asynchronous on that stream; errors
+ * of a kernel surface at the next synchronising call.  On UF_ERR_ARG, _TREE,
+ * _TABLE, _EMPTY_SAMPLE, _RANGE or _WORKSPACE nothing is written.  On
+ * UF_ERR_DEVICE output contents are undefined.  uf_last_error_message()
+ * describes the last failure of the calling thread.
+ */
+#ifndef UF_H
+#define UF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UF_OK = 0,
+    UF_ERR_ARG = 1,          /* null pointer, bad enum, size mismatch          */
+    UF_ERR_TREE = 2,         /* not one root, cycle, bad parent, bad length     */
+    UF_ERR_TABLE = 3,        /* bad CSR, feature not a tip, duplicate, count<0  */
+    UF_ERR_EMPTY_SAMPLE = 4, /* a sample with zero total count                  */
+    UF_ERR_RANGE = 5,        /* stripe range outside [0, floor(N/2)]            */
+    UF_ERR_NOMEM = 6,        /* host or device allocation failed               */
+    UF_ERR_DEVICE = 7,       /* HIP runtime error, or no usable gfx950 device   */
+    UF_ERR_UNSUPPORTED = 8,  /* precision not offered for this variant          */
+    UF_ERR_WORKSPACE = 9     /* workspace missing or smaller than required      */
+} uf_status;
+
+typedef enum {
+    UF_FP64 = 0,        /* FP64 embedding and FP64 accumulation (vector ALU)           */
+    UF_FP32 = 1,        /* FP32 embedding and FP32 accumulation, FP64 final division   */
+    UF_MFMA_BF16X2 = 2  /* unweighted only: Gram product on MFMA, 0/1 x (l_hi + l_lo)  */
+                        /* in BF16 with FP32 accumulation, FP64 final division         */
+} uf_precision;
+
+typedef enum { UF_CONDENSED = 0, UF_STRIPES = 1 } uf_layout;
+typedef enum { UF_OUT_F64 = 0, UF_OUT_F32 = 1 } uf_out_dtype;
+
+typedef struct uf_tree uf_tree;            /* host: validated tree in postorder    */
+typedef struct uf_table uf_table;          /* host: validated table, tips by rank  */
+typedef struct uf_embedding uf_embedding;  /* device: table + tree ready to stream */
+
+/* ---- inputs ------------------------------------------------------------ */
+
+/* Load a rooted tree given as a parent array.  parent[v] = -1 for the one
+ * root, otherwise a node id in [0, n_nodes); ids may come in any order.
+ * length[v] >= 0 and finite for every non-root v; the root's entry is
+ * ignored.  Multifurcations, unary nodes and zero lengths are allowed.
+ * Errors: UF_ERR_ARG (null, n_nodes < 1), UF_ERR_TREE. */
+uf_status uf_tree_load(int64_t n_nodes, const int64_t* parent, const double* length,
+                       uf_tree** out);
+int64_t uf_tree_n_nodes(const uf_tree* tree);
+int64_t uf_tree_n_tips(const uf_tree* tree);
+
+/* Load a sample x tip count table in CSR form: indptr[n_samples+1] (indptr[0]
+ * = 0, non-decreasing), tip_node[nnz] = node id of a tip of `tree`,
+ * counts[nnz] >= 0.  A tip may appear at most once per sample.
+ * Errors: UF_ERR_ARG, UF_ERR_TABLE, UF_ERR_EMPTY_SAMPLE (zero total). */
+uf_status uf_table_load(const uf_tree* tree, int64_t n_samples, const int64_t* indptr,
+                        const int64_t* tip_node, const int64_t* counts, uf_table** out);
+int64_t uf_table_n_samples(const uf_table* table);
+
+/* Upload tree + table to the current HIP device (library-owned memory) and
+ * compute the per-sample FP64 scalars on `hip_stream`: the weighted
+ * denominator part sum_v l_v u_sv (= sum_t D_t p_st, D_t = root distance)
+ * and the unweighted sum_v l_v a_sv (for FP64, FP32-rounded and BF16
+ * hi+lo lengths).  The dense per-branch embedding itself is produced chunk by
+ * chunk inside the uf_dm_* calls.  The call synchronises `hip_stream` before
+ * returning.  Errors: UF_ERR_ARG, UF_ERR_NOMEM, UF_ERR_DEVICE. */
+uf_status uf_embed(const uf_tree* tree, const uf_table* table, void* hip_stream,
+                   uf_embedding** out);
+int64_t uf_embedding_n_samples(const uf_embedding* emb);
+
+/* Copy the per-sample scalars to host arrays of n_samples doubles (nullable):
+ * sw = sum_v l_v u_sv, wu = sum_v l_v a_sv (FP64 lengths). */
+uf_status uf_embedding_scalars(const uf_embedding* emb, double* sw, double* wu);
+
+/* ---- workspace --------------------------------------------------------- */
+
+/* Bytes of device workspace needed by a uf_dm_* call with the same
+ * arguments.  weighted: 1 for the weighted-normalized variant, 0 for
+ * unweighted.  want_row_stats: non-zero if the call will request row sums /
+ * means.  The node-chunk length follows uf_set_chunk_nodes(). */
+uf_status uf_workspace_size(const uf_embedding* emb, int weighted, uf_precision precision,
+                            int64_t stripe_begin, int64_t stripe_end, int want_row_stats,
+                            size_t* bytes);
+
+/* Number of branches streamed per chunk (0 = automatic: as many as fit in
+ * 8 GiB of chunk buffer).  Process-wide; affects later workspace sizes. */
+void uf_set_chunk_nodes(int64_t nodes);
+
+/* ---- distance matrices --------------------------------------------------- */
+
+/* Full N x N matrix, condensed layout (length N(N-1)/2, dtype out_dtype).
+ * row_means (device, N doubles) and grand_mean (device, 1 double) are the
+ * PCoA centring terms defined above; either may be NULL.
+ * ws/ws_bytes: device workspace of at least uf_workspace_size(..., 0,
+ * floor(N/2), row_means || grand_mean) bytes.
+ * Precisions: weighted {UF_FP64, UF_FP32}; unweighted {UF_FP64, UF_FP32,
+ * UF_MFMA_BF16X2}.  Errors: UF_ERR_ARG, UF_ERR_UNSUPPORTED,
+ * UF_ERR_WORKSPACE, UF_ERR_DEVICE. */
+uf_status uf_dm_unweighted(const uf_embedding* emb, uf_precision precision,
+                           uf_out_dtype out_dtype, void* out_condensed,
+                           double* row_means, double* grand_mean,
+                           void* ws, size_t ws_bytes, void* hip_stream);
+uf_status uf_dm_weighted_normalized(const uf_embedding* emb, uf_precision precision,
+                                    uf_out_dtype out_dtype, void* out_condensed,
+                                    double* row_means, double* grand_mean,
+                                    void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Stripe range [stripe_begin, stripe_end) of the matrix, 0 <= begin <= end
+ * <= floor(N/2).  layout UF_STRIPES: out is [end-begin][N] stripe-major.
+ * layout UF_CONDENSED: out is a full condensed buffer of N(N-1)/2 entries of
+ * which only the pairs in the range are written (so disjoint ranges fill it
+ * piece by piece).  row_sums (device, N doubles, nullable) receives, for each
+ * sample, the sum of -d^2/2 over the distinct pairs of the range that contain
+ * it (overwritten, not accumulated).  The per-pair values are bitwise equal
+ * to those of the full call with the same precision.
+ * Errors: as above plus UF_ERR_RANGE. */
+uf_status uf_dm_unweighted_stripes(const uf_embedding* emb, uf_precision precision,
+                                   int64_t stripe_begin, int64_t stripe_end,
+                                   uf_layout layout, uf_out_dtype out_dtype, void* out,
+                                   double* row_sums, void* ws, size_t ws_bytes,
+                                   void* hip_stream);
+uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* emb, uf_precision precision,
+                                            int64_t stripe_begin, int64_t stripe_end,
+                                            uf_layout layout, uf_out_dtype out_dtype,
+                                            void* out, double* row_sums, void* ws,
+                                            size_t ws_bytes, void* hip_stream);
+
+/* ---- kernel timing --------------------------------------------------------- */
+
+/* Per-kernel timing with HIP events recorded on the call's stream around each
+ * launch (process-wide; off by default).  Names: "embed_nm", "embed_pres",
+ * "band_wn_f64", "band_wn_f32", "band_uw_f64", "band_uw_f32", "gram_mfma",
+ * "finalize", "row_sums".  uf_profile_read synchronises the recorded events
+ * and returns the total milliseconds and launch count of one kernel name
+ * since the last reset.  Errors: UF_ERR_ARG (NULL), UF_ERR_DEVICE. */
+void uf_profile_enable(int on);
+void uf_profile_reset(void);
+uf_status uf_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+
+/* ---- helpers --------------------------------------------------------------- */
+int64_t uf_n_stripes(int64_t n);                          /* floor(n/2)                 */
+int64_t uf_condensed_index(int64_t n, int64_t i, int64_t j); /* i != j, -1 if invalid  */
+
+void uf_free_tree(uf_tree* tree);
+void uf_free_table(uf_table* table);
+void uf_free_embedding(uf_embedding* emb);
+
+const char* uf_status_string(uf_status status);
+const char* uf_last_error_message(void);   /* thread-local; never NULL */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UF_H */

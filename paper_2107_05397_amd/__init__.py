@@ -1,0 +1,344 @@
+"""Striped UniFrac on MI355X (gfx950): Python binding of ``libuf.so``.
+
+Argument marshalling only: every step of the distance computation runs in the
+HIP kernels behind the C ABI of ``include/uf.h``.  PyTorch supplies device
+memory (outputs and workspace are CUDA tensors) and streams.  There is no CPU
+fallback: if the library is missing or no gfx950 device is present the calls
+raise.
+
+Typical use::
+
+    import paper_2107_05397_amd as uf
+    tree = uf.Tree(parent, length)
+    table = uf.Table(tree, indptr, tips, counts)
+    emb = uf.Embedding(tree, table)
+    d, row_means, grand_mean = uf.dm_weighted_normalized(emb, "fp32", row_means=True)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "UFError", "lib", "Tree", "Table", "Embedding", "workspace_size", "dm", "dm_unweighted",
+    "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
+    "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
+    "profile_read",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libuf.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "uf.h")
+
+PRECISION = {"fp64": 0, "fp32": 1, "mfma": 2, "mfma_bf16x2": 2}
+LAYOUT = {"condensed": 0, "stripes": 1}
+STATUS = {0: "UF_OK", 1: "UF_ERR_ARG", 2: "UF_ERR_TREE", 3: "UF_ERR_TABLE",
+          4: "UF_ERR_EMPTY_SAMPLE", 5: "UF_ERR_RANGE", 6: "UF_ERR_NOMEM", 7: "UF_ERR_DEVICE",
+          8: "UF_ERR_UNSUPPORTED", 9: "UF_ERR_WORKSPACE"}
+
+
+class UFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "uf_tree_load": (ctypes.c_int, [_i64, _i64p, _f64p, ctypes.POINTER(_vp)]),
+    "uf_tree_n_nodes": (_i64, [_vp]),
+    "uf_tree_n_tips": (_i64, [_vp]),
+    "uf_table_load": (ctypes.c_int, [_vp, _i64, _i64p, _i64p, _i64p, ctypes.POINTER(_vp)]),
+    "uf_table_n_samples": (_i64, [_vp]),
+    "uf_embed": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "uf_embedding_n_samples": (_i64, [_vp]),
+    "uf_embedding_scalars": (ctypes.c_int, [_vp, _f64p, _f64p]),
+    "uf_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_set_chunk_nodes": (None, [_i64]),
+    "uf_dm_unweighted": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                        ctypes.c_size_t, _vp]),
+    "uf_dm_weighted_normalized": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                                 _vp, ctypes.c_size_t, _vp]),
+    "uf_dm_unweighted_stripes": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, ctypes.c_int,
+                                                ctypes.c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "uf_dm_weighted_normalized_stripes": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64,
+                                                         ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
+                                                         ctypes.c_size_t, _vp]),
+    "uf_n_stripes": (_i64, [_i64]),
+    "uf_condensed_index": (_i64, [_i64, _i64, _i64]),
+    "uf_free_tree": (None, [_vp]),
+    "uf_free_table": (None, [_vp]),
+    "uf_free_embedding": (None, [_vp]),
+    "uf_profile_enable": (None, [ctypes.c_int]),
+    "uf_profile_reset": (None, []),
+    "uf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _f64p, _i64p]),
+    "uf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "uf_last_error_message": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libuf.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2107_05397_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """Function names declared in include/uf.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(uf_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().uf_last_error_message().decode(errors="replace")
+        raise UFError(status, msg)
+
+
+def _as(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def n_stripes(n: int) -> int:
+    return int(lib().uf_n_stripes(int(n)))
+
+
+def condensed_index(n: int, i: int, j: int) -> int:
+    return int(lib().uf_condensed_index(int(n), int(i), int(j)))
+
+
+def set_chunk_nodes(nodes: int) -> None:
+    """Branches per streamed chunk (0 = automatic, 8 GiB of chunk buffer)."""
+    lib().uf_set_chunk_nodes(int(nodes))
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP events around every kernel launch (on the call's stream)."""
+    lib().uf_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    lib().uf_profile_reset()
+
+
+def profile_read(kernel: str) -> Tuple[float, int]:
+    """(total milliseconds, launches) of one kernel since the last reset."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().uf_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return float(ms.value), int(cnt.value)
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self):
+        self._h = _vp()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            getattr(lib(), self._free)(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree(_Handle):
+    """Validated rooted tree (host).  parent: -1 for the root; any id order."""
+    _free = "uf_free_tree"
+
+    def __init__(self, parent, length):
+        super().__init__()
+        p = _as(parent, np.int64)
+        l = _as(length, np.float64)
+        if p.shape != l.shape:
+            raise UFError(1, "parent and length differ in size")
+        _check(lib().uf_tree_load(p.shape[0], _ptr(p, ctypes.c_int64), _ptr(l, ctypes.c_double),
+                                  ctypes.byref(self._h)))
+
+    @property
+    def n_nodes(self) -> int:
+        return int(lib().uf_tree_n_nodes(self._h))
+
+    @property
+    def n_tips(self) -> int:
+        return int(lib().uf_tree_n_tips(self._h))
+
+
+class Table(_Handle):
+    """Validated CSR sample x tip count table (host)."""
+    _free = "uf_free_table"
+
+    def __init__(self, tree: Tree, indptr, tips, counts):
+        super().__init__()
+        self.tree = tree
+        ip = _as(indptr, np.int64)
+        tp = _as(tips, np.int64)
+        ct = _as(counts, np.int64)
+        if ip.ndim != 1 or ip.shape[0] < 1 or tp.shape != ct.shape or tp.shape[0] < ip[-1]:
+            raise UFError(1, "malformed CSR arrays")
+        _check(lib().uf_table_load(tree.handle, ip.shape[0] - 1, _ptr(ip, ctypes.c_int64),
+                                   _ptr(tp, ctypes.c_int64), _ptr(ct, ctypes.c_int64),
+                                   ctypes.byref(self._h)))
+
+    @property
+    def n_samples(self) -> int:
+        return int(lib().uf_table_n_samples(self._h))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(int(stream.cuda_stream))
+
+
+class Embedding(_Handle):
+    """Tree + table uploaded to the current HIP device, per-sample scalars computed."""
+    _free = "uf_free_embedding"
+
+    def __init__(self, tree: Tree, table: Table, stream=None):
+        super().__init__()
+        self.tree, self.table = tree, table
+        _check(lib().uf_embed(tree.handle, table.handle, _stream_ptr(stream), ctypes.byref(self._h)))
+
+    @property
+    def n_samples(self) -> int:
+        return int(lib().uf_embedding_n_samples(self._h))
+
+    def scalars(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(sw, wu): sum_v l_v u_sv and sum_v l_v a_sv per sample (FP64)."""
+        n = self.n_samples
+        sw = np.zeros(max(n, 1))
+        wu = np.zeros(max(n, 1))
+        _check(lib().uf_embedding_scalars(self._h, _ptr(sw, ctypes.c_double),
+                                          _ptr(wu, ctypes.c_double)))
+        return sw[:n], wu[:n]
+
+
+def _variant(v: str) -> int:
+    if v in ("weighted_normalized", "weighted", "wn"):
+        return 1
+    if v in ("unweighted", "uw"):
+        return 0
+    raise UFError(1, f"unknown variant {v!r}")
+
+
+def workspace_size(emb: Embedding, variant: str, precision: str, stripe_begin: int = 0,
+                   stripe_end: Optional[int] = None, row_stats: bool = False) -> int:
+    if stripe_end is None:
+        stripe_end = emb.n_samples // 2
+    out = ctypes.c_size_t(0)
+    _check(lib().uf_workspace_size(emb.handle, _variant(variant), PRECISION[precision],
+                                   int(stripe_begin), int(stripe_end), int(bool(row_stats)),
+                                   ctypes.byref(out)))
+    return int(out.value)
+
+
+def _workspace(nbytes: int, workspace):
+    import torch
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise UFError(9, "workspace tensor smaller than workspace_size()")
+        return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+
+
+def _tptr(t):
+    return _vp(int(t.data_ptr())) if t is not None else _vp()
+
+
+def dm(emb: Embedding, variant: str, precision: str = "fp64", out_dtype=None, out=None,
+       row_means: bool = False, stream=None, workspace=None):
+    """Full condensed distance matrix on the device.
+
+    Returns (d, row_means, grand_mean); the last two are None unless requested.
+    """
+    import torch
+    out_dtype = out_dtype or torch.float64
+    n = emb.n_samples
+    npairs = n * (n - 1) // 2
+    if out is None:
+        out = torch.empty(max(npairs, 1), dtype=out_dtype, device="cuda")
+    if out.dtype not in (torch.float64, torch.float32) or out.numel() < npairs or not out.is_contiguous():
+        raise UFError(1, "out must be a contiguous float32/float64 CUDA tensor of N(N-1)/2 entries")
+    rm = gm = None
+    if row_means:
+        rm = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        gm = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = _workspace(workspace_size(emb, variant, precision, 0, n // 2, row_means), workspace)
+    fn = lib().uf_dm_weighted_normalized if _variant(variant) else lib().uf_dm_unweighted
+    _check(fn(emb.handle, PRECISION[precision], 1 if out.dtype == torch.float32 else 0,
+              _tptr(out), _tptr(rm), _tptr(gm), _tptr(ws), ws.numel() * ws.element_size(),
+              _stream_ptr(stream)))
+    return out[:npairs], (rm[:n] if rm is not None else None), gm
+
+
+def dm_unweighted(emb, precision="mfma", **kw):
+    return dm(emb, "unweighted", precision, **kw)
+
+
+def dm_weighted_normalized(emb, precision="fp64", **kw):
+    return dm(emb, "weighted_normalized", precision, **kw)
+
+
+def dm_stripes(emb: Embedding, variant: str, precision: str, stripe_begin: int, stripe_end: int,
+               layout: str = "stripes", out_dtype=None, out=None, row_sums: bool = False,
+               stream=None, workspace=None):
+    """Stripes [begin, end) of the matrix; returns (out, row_sums or None)."""
+    import torch
+    out_dtype = out_dtype or torch.float64
+    n = emb.n_samples
+    if layout == "stripes":
+        need = max(stripe_end - stripe_begin, 0) * n
+        shape = (max(stripe_end - stripe_begin, 0), n)
+    else:
+        need = n * (n - 1) // 2
+        shape = (need,)
+    if out is None:
+        out = torch.zeros(max(need, 1), dtype=out_dtype, device="cuda")
+    if out.numel() < need or not out.is_contiguous():
+        raise UFError(1, "out too small or not contiguous")
+    rs = torch.empty(max(n, 1), dtype=torch.float64, device="cuda") if row_sums else None
+    ws = _workspace(workspace_size(emb, variant, precision, stripe_begin, stripe_end, row_sums),
+                    workspace)
+    fn = (lib().uf_dm_weighted_normalized_stripes if _variant(variant)
+          else lib().uf_dm_unweighted_stripes)
+    _check(fn(emb.handle, PRECISION[precision], int(stripe_begin), int(stripe_end),
+              LAYOUT[layout], 1 if out.dtype == torch.float32 else 0, _tptr(out), _tptr(rs),
+              _tptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
+    return out[:need].view(shape), (rs[:n] if rs is not None else None)

@@ -1,0 +1,725 @@
+// Host side of the striped UniFrac library: input validation, tree and table
+// preparation, device upload, workspace planning and the C ABI of uf.h.
+//
+// No exception or abort crosses the ABI: every entry point catches, records a
+// thread-local message and returns a uf_status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "uf_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+std::atomic<int64_t> g_chunk_nodes{0};
+
+uf_status fail(uf_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+uf_status hip_fail(hipError_t e, const char* what) {
+    return fail(UF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define UF_HIP(call)                                            \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);       \
+    } while (0)
+
+template <class F>
+uf_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(UF_ERR_NOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        return fail(UF_ERR_ARG, std::string("unexpected error: ") + ex.what());
+    } catch (...) {
+        return fail(UF_ERR_ARG, "unexpected error");
+    }
+}
+
+// Round an FP64 value to the nearest bfloat16 (ties to even) and return its
+// bits.  Works on the FP64 bit pattern: keep sign, exponent and the top 7
+// fraction bits, rounding on the 45 dropped bits.  Values below the bfloat16
+// normal range are placed on its subnormal grid (spacing 2^-133).
+uint16_t bf16_bits(double x) {
+    if (x == 0.0 || !std::isfinite(x)) {
+        float f = static_cast<float>(x);
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        return static_cast<uint16_t>(b >> 16);
+    }
+    const double ax = std::fabs(x);
+    double r;
+    if (ax < 0x1p-126) {
+        r = std::nearbyint(ax * 0x1p133) * 0x1p-133;   // exact scaling, RNE on the grid
+    } else {
+        uint64_t b;
+        std::memcpy(&b, &ax, 8);
+        const uint64_t drop = 45;
+        const uint64_t half = (uint64_t(1) << (drop - 1)) - 1;
+        const uint64_t odd = (b >> drop) & 1;
+        b = (b + half + odd) & ~((uint64_t(1) << drop) - 1);
+        std::memcpy(&r, &b, 8);
+    }
+    float f = static_cast<float>(x < 0 ? -r : r);      // exact: r has <= 8 significant bits
+    uint32_t fb;
+    std::memcpy(&fb, &f, 4);
+    return static_cast<uint16_t>(fb >> 16);
+}
+
+double bf16_value(uint16_t h) {
+    uint32_t b = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
+uf_status check_device(int* dev_out) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(UF_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    UF_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    UF_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(UF_ERR_DEVICE, std::string("library is built for gfx950; device is ") +
+                                       prop.gcnArchName);
+    *dev_out = dev;
+    return UF_OK;
+}
+
+// ------------------------------------------------------------------ timing
+// Events around kernel launches, recorded only while profiling is enabled.
+struct ProfRec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+std::mutex g_prof_mu;
+std::atomic<int> g_prof_on{0};
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, std::pair<double, int64_t>> g_prof_done;
+
+class ProfScope {
+  public:
+    ProfScope(const char* name, hipStream_t s) : s_(s) {
+        if (!g_prof_on.load()) return;
+        rec_.name = name;
+        if (hipEventCreate(&rec_.a) != hipSuccess || hipEventCreate(&rec_.b) != hipSuccess ||
+            hipEventRecord(rec_.a, s) != hipSuccess) {
+            release();
+            return;
+        }
+        live_ = true;
+    }
+    ~ProfScope() {
+        if (!live_) return;
+        if (hipEventRecord(rec_.b, s_) != hipSuccess) {
+            release();
+            return;
+        }
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_pending.push_back(rec_);
+    }
+
+  private:
+    void release() {
+        if (rec_.a) (void)hipEventDestroy(rec_.a);
+        if (rec_.b) (void)hipEventDestroy(rec_.b);
+        rec_.a = rec_.b = nullptr;
+    }
+    hipStream_t s_;
+    ProfRec rec_;
+    bool live_ = false;
+};
+
+// Carve sub-buffers out of one allocation, 256-byte aligned.
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t at = (off + 255) & ~size_t(255);
+        off = at + bytes;
+        return at;
+    }
+};
+
+// ------------------------------------------------------------------ planning
+struct Plan {
+    int64_t n = 0, S = 0, sb = 0, se = 0, sr = 0;
+    int weighted = 0;
+    uf_precision prec = UF_FP64;
+    bool rowstats = false;
+    int64_t kc = 0, nchunks = 0, kpad = 0;
+    int64_t n_parts = 0;
+    size_t off_acc = 0, off_q = 0, off_chunk = 0, off_part = 0, off_rm = 0, total = 0;
+};
+
+uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
+                    int64_t se, bool rowstats, Plan* p) {
+    if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+    if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2)
+        return fail(UF_ERR_ARG, "unknown precision");
+    if (weighted && prec == UF_MFMA_BF16X2)
+        return fail(UF_ERR_UNSUPPORTED,
+                    "the MFMA Gram path exists for the unweighted variant only");
+    const int64_t n = e->n;
+    const int64_t S = n / 2;
+    if (sb < 0 || se < sb || se > S)
+        return fail(UF_ERR_RANGE, "stripe range must satisfy 0 <= begin <= end <= floor(N/2)");
+    p->n = n;
+    p->S = S;
+    p->sb = sb;
+    p->se = se;
+    p->sr = se - sb;
+    p->weighted = weighted;
+    p->prec = prec;
+    p->rowstats = rowstats;
+    const int64_t nb = e->nb;
+    const size_t elem = prec == UF_FP64 ? 8 : (prec == UF_FP32 ? 4 : 2);
+    int64_t kc = g_chunk_nodes.load();
+    if (kc <= 0) {
+        const double budget = 8.0 * 1024 * 1024 * 1024;
+        kc = static_cast<int64_t>(budget / (double(std::max<int64_t>(n, 1)) * double(elem)));
+    }
+    kc = std::max<int64_t>(kc, 32);
+    if (prec == UF_MFMA_BF16X2) kc = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    kc = std::min<int64_t>(kc, std::max<int64_t>(nb, 1));
+    p->kc = kc;
+    p->nchunks = nb > 0 ? (nb + kc - 1) / kc : 0;
+    p->kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    p->n_parts = std::max<int64_t>(1, (p->sr + 255) / 256);
+    Carver c;
+    const size_t acc_elem = (prec == UF_FP64) ? 8 : 4;
+    p->off_acc = c.take(size_t(p->sr) * size_t(n) * acc_elem);
+    p->off_q = rowstats ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
+    if (prec == UF_MFMA_BF16X2)
+        p->off_chunk = c.take(size_t(n) * size_t(p->kpad) * 2);
+    else
+        p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
+    p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
+    p->off_rm = rowstats ? c.take(size_t(n) * 8) : 0;
+    p->total = c.off + 256;
+    return UF_OK;
+}
+
+uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb, int64_t se,
+                 int layout, uf_out_dtype odt, void* out, double* row_out, double* grand_mean,
+                 bool full_means, void* ws, size_t ws_bytes, void* stream) {
+    if (!out) return fail(UF_ERR_ARG, "output pointer is NULL");
+    if (layout != UF_CONDENSED && layout != UF_STRIPES) return fail(UF_ERR_ARG, "bad layout");
+    if (odt != UF_OUT_F64 && odt != UF_OUT_F32) return fail(UF_ERR_ARG, "bad output dtype");
+    const bool rowstats = row_out != nullptr || grand_mean != nullptr;
+    Plan p;
+    uf_status st = make_plan(e, weighted, prec, sb, se, rowstats, &p);
+    if (st != UF_OK) return st;
+    if (!ws || ws_bytes < p.total)
+        return fail(UF_ERR_WORKSPACE, "workspace missing or smaller than uf_workspace_size()");
+    int dev = 0;
+    st = check_device(&dev);
+    if (st != UF_OK) return st;
+    if (dev != e->device) return fail(UF_ERR_DEVICE, "embedding lives on another device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p.sr == 0 || p.n < 2) {
+        if (row_out && p.n > 0) UF_HIP(hipMemsetAsync(row_out, 0, size_t(p.n) * 8, s));
+        if (grand_mean) UF_HIP(hipMemsetAsync(grand_mean, 0, 8, s));
+        return UF_OK;
+    }
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    void* acc = base + p.off_acc;
+    double* q = rowstats ? reinterpret_cast<double*>(base + p.off_q) : nullptr;
+    void* chunk = base + p.off_chunk;
+    const int64_t nb = e->nb;
+
+    for (int64_t c = 0; c < p.nchunks; ++c) {
+        const int64_t k0 = c * p.kc;
+        const int64_t kc = std::min<int64_t>(p.kc, nb - k0);
+        const int first = c == 0;
+        if (prec == UF_FP64) {
+            double* E = static_cast<double*>(chunk);
+            {
+                ProfScope ps("embed_nm", s);
+                UF_HIP(ufk::embed_node_major_f64(*e, k0, kc, weighted, E, s));
+            }
+            ProfScope ps(weighted ? "band_wn_f64" : "band_uw_f64", s);
+            UF_HIP(ufk::band_f64(E, e->len + k0, kc, p.n, p.sb, p.se, weighted, first,
+                                 static_cast<double*>(acc), s));
+        } else if (prec == UF_FP32) {
+            float* E = static_cast<float*>(chunk);
+            {
+                ProfScope ps("embed_nm", s);
+                UF_HIP(ufk::embed_node_major_f32(*e, k0, kc, weighted, E, s));
+            }
+            ProfScope ps(weighted ? "band_wn_f32" : "band_uw_f32", s);
+            UF_HIP(ufk::band_f32(E, e->len32 + k0, kc, p.n, p.sb, p.se, weighted, first,
+                                 static_cast<float*>(acc), s));
+        } else {
+            uint16_t* P = static_cast<uint16_t*>(chunk);
+            const int64_t kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+            {
+                ProfScope ps("embed_pres", s);
+                UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s));
+            }
+            ProfScope ps("gram_mfma", s);
+            UF_HIP(ufk::gram_mfma(P, e->len_hi + k0, e->len_lo + k0, kpad, p.n, p.sb, p.se,
+                                  first, static_cast<float*>(acc), s));
+        }
+    }
+    if (p.nchunks == 0) {  // a tree with only a root: every distance is 0
+        const size_t acc_elem = prec == UF_FP64 ? 8 : 4;
+        UF_HIP(hipMemsetAsync(acc, 0, size_t(p.sr) * size_t(p.n) * acc_elem, s));
+    }
+    const double* scal = weighted ? e->sw
+                                  : (prec == UF_FP64 ? e->wu : (prec == UF_FP32 ? e->wu32 : e->wub));
+    {
+        ProfScope ps("finalize", s);
+        UF_HIP(ufk::finalize(weighted ? 0 : 1, acc, prec == UF_FP64 ? 1 : 0, scal, p.n, p.sb,
+                             p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s));
+    }
+    if (rowstats) {
+        ProfScope ps("row_sums", s);
+        double* part = reinterpret_cast<double*>(base + p.off_part);
+        double* rm = row_out ? row_out : reinterpret_cast<double*>(base + p.off_rm);
+        const double scale = full_means ? 1.0 / double(p.n) : 1.0;
+        UF_HIP(ufk::row_sums(q, p.n, p.sb, p.se, part, p.n_parts, scale, rm, s));
+        if (grand_mean) UF_HIP(ufk::grand_mean(rm, p.n, grand_mean, s));
+    }
+    return UF_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+const char* uf_status_string(uf_status s) {
+    switch (s) {
+        case UF_OK: return "ok";
+        case UF_ERR_ARG: return "invalid argument";
+        case UF_ERR_TREE: return "invalid tree";
+        case UF_ERR_TABLE: return "invalid table";
+        case UF_ERR_EMPTY_SAMPLE: return "sample with zero total count";
+        case UF_ERR_RANGE: return "stripe range out of bounds";
+        case UF_ERR_NOMEM: return "out of memory";
+        case UF_ERR_DEVICE: return "device error";
+        case UF_ERR_UNSUPPORTED: return "unsupported precision for this variant";
+        case UF_ERR_WORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char* uf_last_error_message(void) { return g_last_error.c_str(); }
+
+int64_t uf_n_stripes(int64_t n) { return n < 0 ? 0 : n / 2; }
+
+int64_t uf_condensed_index(int64_t n, int64_t i, int64_t j) {
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) return -1;
+    if (i > j) std::swap(i, j);
+    return n * i - i * (i + 1) / 2 + (j - i - 1);
+}
+
+void uf_set_chunk_nodes(int64_t nodes) { g_chunk_nodes.store(nodes < 0 ? 0 : nodes); }
+
+void uf_profile_enable(int on) { g_prof_on.store(on ? 1 : 0); }
+
+void uf_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof_pending) {
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    g_prof_done.clear();
+}
+
+uf_status uf_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
+    return guarded([&]() -> uf_status {
+        if (!kernel || !total_ms || !launches) return fail(UF_ERR_ARG, "NULL argument");
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        uf_status st = UF_OK;
+        for (auto& r : g_prof_pending) {
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(r.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+            if (e != hipSuccess) st = hip_fail(e, "profile event");
+            auto& d = g_prof_done[r.name];
+            d.first += ms;
+            d.second += 1;
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        g_prof_pending.clear();
+        auto it = g_prof_done.find(kernel);
+        *total_ms = it == g_prof_done.end() ? 0.0 : it->second.first;
+        *launches = it == g_prof_done.end() ? 0 : it->second.second;
+        return st;
+    });
+}
+
+// ------------------------------------------------------------------ tree
+uf_status uf_tree_load(int64_t m, const int64_t* parent, const double* length, uf_tree** out) {
+    return guarded([&]() -> uf_status {
+        if (!out) return fail(UF_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (m < 1 || !parent || !length) return fail(UF_ERR_ARG, "need n_nodes >= 1 and arrays");
+        if (m > (int64_t(1) << 30)) return fail(UF_ERR_ARG, "more than 2^30 nodes");
+        int64_t root = -1;
+        for (int64_t v = 0; v < m; ++v) {
+            const int64_t p = parent[v];
+            if (p == -1) {
+                if (root >= 0) return fail(UF_ERR_TREE, "more than one root");
+                root = v;
+            } else if (p < 0 || p >= m || p == v) {
+                return fail(UF_ERR_TREE, "parent id out of range at node " + std::to_string(v));
+            } else if (!std::isfinite(length[v]) || length[v] < 0.0) {
+                return fail(UF_ERR_TREE, "branch length must be finite and >= 0 at node " +
+                                             std::to_string(v));
+            }
+        }
+        if (root < 0) return fail(UF_ERR_TREE, "no root (parent -1)");
+        // children in CSR, ascending child id
+        std::vector<int64_t> first(m + 1, 0), kids(m > 1 ? m - 1 : 1);
+        for (int64_t v = 0; v < m; ++v)
+            if (parent[v] >= 0) first[parent[v] + 1]++;
+        for (int64_t v = 0; v < m; ++v) first[v + 1] += first[v];
+        {
+            std::vector<int64_t> fill(first.begin(), first.end() - 1);
+            for (int64_t v = 0; v < m; ++v)
+                if (parent[v] >= 0) kids[fill[parent[v]]++] = v;
+        }
+        auto t = new uf_tree();
+        std::unique_ptr<uf_tree> guard(t);
+        t->n_nodes = m;
+        t->node_at.reserve(m);
+        // iterative postorder from the root
+        std::vector<std::pair<int64_t, int64_t>> stack;
+        stack.reserve(64);
+        stack.emplace_back(root, first[root]);
+        while (!stack.empty()) {
+            auto& top = stack.back();
+            if (top.second < first[top.first + 1]) {
+                const int64_t c = kids[top.second++];
+                if (int64_t(stack.size()) > m) return fail(UF_ERR_TREE, "cycle");
+                stack.emplace_back(c, first[c]);
+            } else {
+                t->node_at.push_back(top.first);
+                stack.pop_back();
+            }
+        }
+        if (int64_t(t->node_at.size()) != m)
+            return fail(UF_ERR_TREE, "not every node is reachable from the root (cycle?)");
+        t->pos_of.assign(m, -1);
+        for (int64_t k = 0; k < m; ++k) t->pos_of[t->node_at[k]] = k;
+        t->parent_pos.resize(m);
+        t->len.resize(m);
+        t->tip_rank.assign(m, -1);
+        std::vector<int64_t> size(m, 1);
+        std::vector<int64_t> tips_before(m + 1, 0);
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t v = t->node_at[k];
+            t->parent_pos[k] = parent[v] >= 0 ? int32_t(t->pos_of[parent[v]]) : -1;
+            t->len[k] = parent[v] >= 0 ? length[v] : 0.0;
+            const bool is_tip = first[v + 1] == first[v];
+            tips_before[k + 1] = tips_before[k] + (is_tip ? 1 : 0);
+            if (is_tip) {
+                t->tip_rank[v] = int32_t(tips_before[k]);
+                t->tip_pos.push_back(int32_t(k));
+            }
+        }
+        for (int64_t k = 0; k < m - 1; ++k) size[t->parent_pos[k]] += size[k];
+        t->lo.resize(m);
+        t->hi.resize(m);
+        for (int64_t k = 0; k < m; ++k) {
+            t->lo[k] = int32_t(tips_before[k - size[k] + 1]);
+            t->hi[k] = int32_t(tips_before[k + 1]);
+        }
+        t->n_tips = tips_before[m];
+        *out = guard.release();
+        return UF_OK;
+    });
+}
+
+int64_t uf_tree_n_nodes(const uf_tree* t) { return t ? t->n_nodes : -1; }
+int64_t uf_tree_n_tips(const uf_tree* t) { return t ? t->n_tips : -1; }
+void uf_free_tree(uf_tree* t) { delete t; }
+
+// ------------------------------------------------------------------ table
+uf_status uf_table_load(const uf_tree* t, int64_t n, const int64_t* indptr, const int64_t* tip,
+                        const int64_t* counts, uf_table** out) {
+    return guarded([&]() -> uf_status {
+        if (!out) return fail(UF_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (!t || n < 0 || !indptr) return fail(UF_ERR_ARG, "need a tree and indptr");
+        if (indptr[0] != 0) return fail(UF_ERR_TABLE, "indptr[0] must be 0");
+        for (int64_t s = 0; s < n; ++s)
+            if (indptr[s + 1] < indptr[s]) return fail(UF_ERR_TABLE, "indptr must not decrease");
+        const int64_t nnz = indptr[n];
+        if (nnz > 0 && (!tip || !counts)) return fail(UF_ERR_ARG, "tip/count arrays are NULL");
+        if (n > (int64_t(1) << 31) - 1) return fail(UF_ERR_ARG, "too many samples");
+        auto tb = new uf_table();
+        std::unique_ptr<uf_table> guard(tb);
+        tb->n_samples = n;
+        tb->n_tips = t->n_tips;
+        tb->row_ptr.assign(n + 1, 0);
+        tb->total.assign(n, 0);
+        tb->rank.reserve(nnz);
+        tb->count.reserve(nnz);
+        std::vector<std::pair<int32_t, int64_t>> row;
+        for (int64_t s = 0; s < n; ++s) {
+            row.clear();
+            for (int64_t e = indptr[s]; e < indptr[s + 1]; ++e) {
+                const int64_t v = tip[e];
+                if (v < 0 || v >= t->n_nodes)
+                    return fail(UF_ERR_TABLE, "feature id out of range in sample " + std::to_string(s));
+                if (t->tip_rank[v] < 0)
+                    return fail(UF_ERR_TABLE, "feature maps to an internal node in sample " +
+                                                  std::to_string(s));
+                if (counts[e] < 0) return fail(UF_ERR_TABLE, "negative count in sample " + std::to_string(s));
+                row.emplace_back(t->tip_rank[v], counts[e]);
+            }
+            std::sort(row.begin(), row.end());
+            int64_t total = 0;
+            for (size_t k = 0; k < row.size(); ++k) {
+                if (k > 0 && row[k].first == row[k - 1].first)
+                    return fail(UF_ERR_TABLE, "duplicate feature in sample " + std::to_string(s));
+                if (row[k].second == 0) continue;
+                if (total > (int64_t(1) << 52) - row[k].second)
+                    return fail(UF_ERR_TABLE, "sample total exceeds 2^52");
+                total += row[k].second;
+                tb->rank.push_back(row[k].first);
+                tb->count.push_back(row[k].second);
+            }
+            if (total <= 0)
+                return fail(UF_ERR_EMPTY_SAMPLE, "sample " + std::to_string(s) + " has zero total count");
+            tb->total[s] = total;
+            tb->row_ptr[s + 1] = int64_t(tb->rank.size());
+        }
+        *out = guard.release();
+        return UF_OK;
+    });
+}
+
+int64_t uf_table_n_samples(const uf_table* t) { return t ? t->n_samples : -1; }
+void uf_free_table(uf_table* t) { delete t; }
+
+// ------------------------------------------------------------------ embedding
+uf_status uf_embed(const uf_tree* t, const uf_table* tb, void* stream, uf_embedding** out) {
+    return guarded([&]() -> uf_status {
+        if (!out) return fail(UF_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (!t || !tb) return fail(UF_ERR_ARG, "tree or table is NULL");
+        if (tb->n_tips != t->n_tips) return fail(UF_ERR_ARG, "table was loaded against another tree");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t n = tb->n_samples;
+        const int64_t m = t->n_nodes;
+        const int64_t nb = m - 1;
+        const int64_t nnz = int64_t(tb->rank.size());
+        const int64_t nb_pad = (nb + 2 * ufk::kGramK + 63) / 64 * 64;  // room for the last K step
+        // host-side arrays
+        std::vector<int64_t> cum(size_t(nnz + n), 0);
+        for (int64_t r = 0; r < n; ++r) {
+            int64_t acc = 0;
+            const int64_t a = tb->row_ptr[r], b = tb->row_ptr[r + 1];
+            for (int64_t e = a; e < b; ++e) {
+                cum[a + r + (e - a)] = acc;
+                acc += tb->count[e];
+            }
+            cum[b + r] = acc;
+        }
+        std::vector<double> total(n);
+        for (int64_t r = 0; r < n; ++r) total[r] = double(tb->total[r]);
+        std::vector<float> len32(nb_pad, 0.0f);
+        std::vector<uint16_t> lhi(nb_pad, 0), llo(nb_pad, 0);
+        for (int64_t k = 0; k < nb; ++k) {
+            len32[k] = static_cast<float>(t->len[k]);
+            lhi[k] = bf16_bits(t->len[k]);
+            llo[k] = bf16_bits(t->len[k] - bf16_value(lhi[k]));
+        }
+        // root distances by position for the three length roundings (FP64 sums)
+        std::vector<double> d64(m, 0.0), d32(m, 0.0), dbf(m, 0.0);
+        for (int64_t k = m - 2; k >= 0; --k) {
+            const int32_t p = t->parent_pos[k];
+            d64[k] = d64[p] + t->len[k];
+            d32[k] = d32[p] + double(len32[k]);
+            dbf[k] = dbf[p] + (bf16_value(lhi[k]) + bf16_value(llo[k]));
+        }
+        // one device allocation for everything
+        Carver c;
+        const size_t o_rowptr = c.take(size_t(n + 1) * 8);
+        const size_t o_rank = c.take(size_t(std::max<int64_t>(nnz, 1)) * 4);
+        const size_t o_cum = c.take(size_t(nnz + n) * 8 + 8);
+        const size_t o_total = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+        const size_t o_lo = c.take(size_t(m) * 4);   // includes the root's interval
+        const size_t o_hi = c.take(size_t(m) * 4);
+        const size_t o_len = c.take(size_t(std::max<int64_t>(nb, 1)) * 8);
+        const size_t o_len32 = c.take(size_t(nb_pad) * 4);
+        const size_t o_lhi = c.take(size_t(nb_pad) * 2);
+        const size_t o_llo = c.take(size_t(nb_pad) * 2);
+        const size_t o_sw = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+        const size_t o_wu = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+        const size_t o_wu32 = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+        const size_t o_wub = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+        const size_t o_ppos = c.take(size_t(m) * 4);
+        const size_t o_tpos = c.take(size_t(std::max<int64_t>(t->n_tips, 1)) * 4);
+        const size_t o_d64 = c.take(size_t(m) * 8);
+        const size_t o_d32 = c.take(size_t(m) * 8);
+        const size_t o_dbf = c.take(size_t(m) * 8);
+        void* arena = nullptr;
+        hipError_t he = hipMalloc(&arena, c.off + 256);
+        if (he != hipSuccess) return fail(UF_ERR_NOMEM, "device allocation of the embedding failed");
+        auto e = new uf_embedding();
+        std::unique_ptr<uf_embedding> guard(e);
+        e->arena = arena;
+        e->device = dev;
+        e->n = n;
+        e->nb = nb;
+        e->nnz = nnz;
+        char* b = static_cast<char*>(arena);
+        e->row_ptr = reinterpret_cast<int64_t*>(b + o_rowptr);
+        e->rank = reinterpret_cast<int32_t*>(b + o_rank);
+        e->cum = reinterpret_cast<int64_t*>(b + o_cum);
+        e->total = reinterpret_cast<double*>(b + o_total);
+        e->lo = reinterpret_cast<int32_t*>(b + o_lo);
+        e->hi = reinterpret_cast<int32_t*>(b + o_hi);
+        e->len = reinterpret_cast<double*>(b + o_len);
+        e->len32 = reinterpret_cast<float*>(b + o_len32);
+        e->len_hi = reinterpret_cast<uint16_t*>(b + o_lhi);
+        e->len_lo = reinterpret_cast<uint16_t*>(b + o_llo);
+        e->sw = reinterpret_cast<double*>(b + o_sw);
+        e->wu = reinterpret_cast<double*>(b + o_wu);
+        e->wu32 = reinterpret_cast<double*>(b + o_wu32);
+        e->wub = reinterpret_cast<double*>(b + o_wub);
+        int32_t* ppos = reinterpret_cast<int32_t*>(b + o_ppos);
+        int32_t* tpos = reinterpret_cast<int32_t*>(b + o_tpos);
+        double* dd64 = reinterpret_cast<double*>(b + o_d64);
+        double* dd32 = reinterpret_cast<double*>(b + o_d32);
+        double* ddbf = reinterpret_cast<double*>(b + o_dbf);
+        auto cleanup = [&](uf_status code) {
+            (void)hipFree(arena);
+            e->arena = nullptr;
+            return code;
+        };
+        // synchronous copies (pageable host memory), then the scalar kernel
+        auto H2D = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+            if (bytes == 0) return hipSuccess;
+            return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        };
+        hipError_t rc = hipSuccess;
+        if (rc == hipSuccess) rc = H2D(e->row_ptr, tb->row_ptr.data(), size_t(n + 1) * 8);
+        if (rc == hipSuccess) rc = H2D(e->rank, tb->rank.data(), size_t(nnz) * 4);
+        if (rc == hipSuccess) rc = H2D(e->cum, cum.data(), size_t(nnz + n) * 8);
+        if (rc == hipSuccess) rc = H2D(e->total, total.data(), size_t(n) * 8);
+        if (rc == hipSuccess) rc = H2D(e->lo, t->lo.data(), size_t(m) * 4);
+        if (rc == hipSuccess) rc = H2D(e->hi, t->hi.data(), size_t(m) * 4);
+        if (rc == hipSuccess) rc = H2D(e->len, t->len.data(), size_t(nb) * 8);
+        if (rc == hipSuccess) rc = H2D(e->len32, len32.data(), size_t(nb_pad) * 4);
+        if (rc == hipSuccess) rc = H2D(e->len_hi, lhi.data(), size_t(nb_pad) * 2);
+        if (rc == hipSuccess) rc = H2D(e->len_lo, llo.data(), size_t(nb_pad) * 2);
+        if (rc == hipSuccess) rc = H2D(ppos, t->parent_pos.data(), size_t(m) * 4);
+        if (rc == hipSuccess) rc = H2D(tpos, t->tip_pos.data(), size_t(t->n_tips) * 4);
+        if (rc == hipSuccess) rc = H2D(dd64, d64.data(), size_t(m) * 8);
+        if (rc == hipSuccess) rc = H2D(dd32, d32.data(), size_t(m) * 8);
+        if (rc == hipSuccess) rc = H2D(ddbf, dbf.data(), size_t(m) * 8);
+        if (rc != hipSuccess) return cleanup(hip_fail(rc, "upload of the embedding inputs"));
+        if (n > 0) {
+            rc = ufk::sample_scalars(*e, ppos, tpos, dd64, dd32, ddbf, s);
+            if (rc != hipSuccess) return cleanup(hip_fail(rc, "sample scalar kernel launch"));
+        }
+        rc = hipStreamSynchronize(s);
+        if (rc != hipSuccess) return cleanup(hip_fail(rc, "sample scalar kernel"));
+        *out = guard.release();
+        return UF_OK;
+    });
+}
+
+int64_t uf_embedding_n_samples(const uf_embedding* e) { return e ? e->n : -1; }
+
+uf_status uf_embedding_scalars(const uf_embedding* e, double* sw, double* wu) {
+    return guarded([&]() -> uf_status {
+        if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+        if (sw && e->n) UF_HIP(hipMemcpy(sw, e->sw, size_t(e->n) * 8, hipMemcpyDeviceToHost));
+        if (wu && e->n) UF_HIP(hipMemcpy(wu, e->wu, size_t(e->n) * 8, hipMemcpyDeviceToHost));
+        return UF_OK;
+    });
+}
+
+void uf_free_embedding(uf_embedding* e) {
+    if (!e) return;
+    if (e->arena) (void)hipFree(e->arena);
+    delete e;
+}
+
+// ------------------------------------------------------------------ workspace
+uf_status uf_workspace_size(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
+                            int64_t se, int want_row_stats, size_t* bytes) {
+    return guarded([&]() -> uf_status {
+        if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
+        Plan p;
+        uf_status st = make_plan(e, weighted ? 1 : 0, prec, sb, se, want_row_stats != 0, &p);
+        if (st != UF_OK) return st;
+        *bytes = p.total;
+        return UF_OK;
+    });
+}
+
+// ------------------------------------------------------------------ distances
+uf_status uf_dm_unweighted(const uf_embedding* e, uf_precision prec, uf_out_dtype odt, void* out,
+                           double* row_means, double* grand_mean, void* ws, size_t ws_bytes,
+                           void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+        return run_dm(e, 0, prec, 0, e->n / 2, UF_CONDENSED, odt, out, row_means, grand_mean,
+                      true, ws, ws_bytes, stream);
+    });
+}
+
+uf_status uf_dm_weighted_normalized(const uf_embedding* e, uf_precision prec, uf_out_dtype odt,
+                                    void* out, double* row_means, double* grand_mean, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+        return run_dm(e, 1, prec, 0, e->n / 2, UF_CONDENSED, odt, out, row_means, grand_mean,
+                      true, ws, ws_bytes, stream);
+    });
+}
+
+uf_status uf_dm_unweighted_stripes(const uf_embedding* e, uf_precision prec, int64_t sb,
+                                   int64_t se, uf_layout layout, uf_out_dtype odt, void* out,
+                                   double* row_sums, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&]() -> uf_status {
+        return run_dm(e, 0, prec, sb, se, layout, odt, out, row_sums, nullptr, false, ws,
+                      ws_bytes, stream);
+    });
+}
+
+uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* e, uf_precision prec, int64_t sb,
+                                            int64_t se, uf_layout layout, uf_out_dtype odt,
+                                            void* out, double* row_sums, void* ws,
+                                            size_t ws_bytes, void* stream) {
+    return guarded([&]() -> uf_status {
+        return run_dm(e, 1, prec, sb, se, layout, odt, out, row_sums, nullptr, false, ws,
+                      ws_bytes, stream);
+    });
+}
+
+}  // extern "C"

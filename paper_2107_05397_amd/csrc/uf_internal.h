@@ -1,0 +1,122 @@
+// Internal declarations shared by the host side (uf_host.hip) and the kernels
+// (uf_kernels.hip) of the striped UniFrac library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "uf.h"
+
+// ---------------------------------------------------------------------------
+// Host handles
+// ---------------------------------------------------------------------------
+
+// A validated rooted tree, re-indexed in depth-first postorder.  "Position"
+// k in [0, n_nodes) is the postorder rank; the root is the last position and
+// positions [0, n_nodes-1) are the branches in the order they are streamed.
+// Tips are ranked by position; node k covers the tip ranks [lo[k], hi[k]).
+struct uf_tree {
+    int64_t n_nodes = 0;
+    int64_t n_tips = 0;
+    std::vector<int64_t> node_at;     // node id at position k
+    std::vector<int64_t> pos_of;      // position of node id
+    std::vector<int32_t> parent_pos;  // parent position, -1 for the root
+    std::vector<double> len;          // branch length at position (root: 0)
+    std::vector<int32_t> lo, hi;      // tip-rank interval under position k
+    std::vector<int32_t> tip_rank;    // by node id, -1 for internal nodes
+    std::vector<int32_t> tip_pos;     // position of the tip with rank r
+};
+
+// A validated table: per sample, its nonzero entries sorted by tip rank.
+struct uf_table {
+    int64_t n_samples = 0;
+    int64_t n_tips = 0;               // of the tree it was validated against
+    std::vector<int64_t> row_ptr;     // [n_samples+1]
+    std::vector<int32_t> rank;        // tip rank of each entry, ascending per row
+    std::vector<int64_t> count;       // > 0
+    std::vector<int64_t> total;       // per sample, > 0
+};
+
+// Device-resident inputs of the distance calls.  All arrays are on `device`.
+struct uf_embedding {
+    int device = 0;
+    int64_t n = 0;          // samples
+    int64_t nb = 0;         // branches (non-root nodes) = positions [0, nb)
+    int64_t nnz = 0;
+    // table
+    int64_t* row_ptr = nullptr;   // [n+1]
+    int32_t* rank = nullptr;      // [nnz]
+    int64_t* cum = nullptr;       // [nnz + n]: exclusive prefix of counts, per row
+    double* total = nullptr;      // [n]  T_s as double (exact below 2^53)
+    // tree, by position
+    int32_t* lo = nullptr;        // [nb+1] (last entry: the root)
+    int32_t* hi = nullptr;        // [nb+1]
+    double* len = nullptr;        // [nb]
+    float* len32 = nullptr;       // [nb] FP32-rounded lengths
+    uint16_t* len_hi = nullptr;   // [nb] bf16 bits of RNE(len)
+    uint16_t* len_lo = nullptr;   // [nb] bf16 bits of RNE(len - hi)
+    // per-sample scalars (FP64)
+    double* sw = nullptr;         // sum_v l_v u_sv
+    double* wu = nullptr;         // sum_v l_v a_sv, FP64 lengths
+    double* wu32 = nullptr;       // same with FP32-rounded lengths
+    double* wub = nullptr;        // same with hi+lo bf16 lengths
+    void* arena = nullptr;        // one allocation holding all of the above
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (uf_kernels.hip).  All are asynchronous on `st` and return
+// the hipError_t of the launch.
+// ---------------------------------------------------------------------------
+namespace ufk {
+
+constexpr int kBandI = 128;       // samples per band tile
+constexpr int kBandS = 128;       // stripes per band tile
+constexpr int kGramT = 128;       // square tile of the MFMA Gram kernel
+constexpr int kGramK = 32;        // K step of the MFMA Gram kernel
+
+// Per-sample scalars from the postorder leaf intervals (one wave per sample).
+hipError_t sample_scalars(const uf_embedding& e, const int32_t* parent_pos,
+                          const int32_t* tip_pos, const double* d64, const double* d32,
+                          const double* dbf, hipStream_t st);
+
+// Node-major chunk E[k][s] for positions [k0, k0+kc): weighted -> T(l * c/T_s),
+// presence -> T(c > 0).
+hipError_t embed_node_major_f64(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
+                                double* out, hipStream_t st);
+hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
+                                float* out, hipStream_t st);
+// Sample-major BF16 0/1 presence P[s][k], k < kpad (zero beyond kc).
+hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
+                               uint16_t* out, hipStream_t st);
+
+// Band accumulation over one node chunk for stripes [sb, se):
+// weighted: acc += sum_k |E[k][i] - E[k][j]|;  unweighted: acc += sum_k l_k E[k][i] E[k][j].
+hipError_t band_f64(const double* E, const double* lenk, int64_t kc, int64_t n, int64_t sb,
+                    int64_t se, int weighted, int first, double* acc, hipStream_t st);
+hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, int64_t sb,
+                    int64_t se, int weighted, int first, float* acc, hipStream_t st);
+
+// MFMA Gram over one chunk: for every upper-triangle 128x128 tile (bi <= bj) that holds
+// a pair of stripes [sb, se), G_ij (+)= sum_k P_ik P_jk (hi_k + lo_k), scattered into the
+// FP32 stripe-major accumulator (first: overwrite, else add).
+hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
+                     int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st);
+
+// Distances from the accumulators.  kind 0: weighted (num / (s_i + s_j));
+// kind 1: unweighted Gram form ((w_i + w_j - 2G) / (w_i + w_j - G)), clamped to [0, 1].
+// acc_is_f64 selects the accumulator type.  q (nullable) receives -d^2/2 in FP64,
+// stripe-major.  layout/out dtype as in uf.h.
+hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
+                    int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
+                    hipStream_t st);
+
+// Row sums of -d^2/2 over the distinct pairs of stripes [sb, se): two fixed-order stages.
+hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* partial,
+                    int64_t n_parts, double scale, double* out, hipStream_t st);
+hipError_t grand_mean(const double* row_means, int64_t n, double* out, hipStream_t st);
+
+}  // namespace ufk

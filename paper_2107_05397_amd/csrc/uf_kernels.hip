@@ -1,0 +1,587 @@
+// HIP kernels of the striped UniFrac library, written for gfx950 (CDNA4):
+// 64-lane waves, 160 KB LDS per CU, MFMA matrix cores.
+//
+//   k_sample_scalars   per-sample FP64 scalars from the postorder leaf intervals
+//   k_embed_nm<T>      node-major chunk of the embedding (weighted or 0/1)
+//   k_embed_pres_bf16  sample-major BF16 0/1 presence for the MFMA Gram path
+//   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled)
+//   k_gram_mfma        unweighted Gram product on MFMA (split-precision lengths)
+//   k_finalize         FP64 division, output layouts, -d^2/2 for PCoA
+//   k_rowsum_*         fixed-order two-stage row sums; k_grand_mean
+#include <hip/hip_runtime.h>
+
+#include "uf_internal.h"
+
+namespace ufk {
+namespace {
+
+// ----------------------------------------------------------------------------
+// Embedded count of sample s on the branch at postorder position k: the sum
+// of the sample's counts on the tips whose rank lies in [lo_k, hi_k).  Rows
+// are sorted by tip rank and carry an exclusive prefix of the counts, so the
+// count is a difference of two prefix values found by binary search.  This
+// equals the postorder sum of the children's counts (a subtree is a contiguous
+// run of postorder positions), exactly, in integers.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lower_bound_rank(const int32_t* __restrict__ rank, int64_t a,
+                                                    int64_t b, int32_t key) {
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (rank[mid] < key) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+__device__ __forceinline__ int64_t embedded_count(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ rank,
+                                                  const int64_t* __restrict__ cum, int64_t s,
+                                                  int32_t lo, int32_t hi) {
+    const int64_t a = row_ptr[s], b = row_ptr[s + 1];
+    const int64_t p1 = lower_bound_rank(rank, a, b, lo);
+    const int64_t p2 = lower_bound_rank(rank, p1, b, hi);
+    return cum[p2 + s] - cum[p1 + s];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ----------------------------------------------------------------------------
+// Per-sample scalars, one wave per sample.
+//   sw = sum_t x_t D_t / T   (= sum_v l_v u_v: every branch above t counts x_t/T)
+//   w  = total length of the union of the root paths of the sample's tips
+//      = sum_k D(t_k) - sum_k D(lca(t_k, t_{k+1}))  for tips in rank order,
+// which is sum_v l_v a_v.  D is the root distance with FP64, FP32-rounded or
+// BF16 hi+lo lengths.  Lane sums and the wave reduction run in a fixed order.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample_scalars(
+    int64_t n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ rank,
+    const int64_t* __restrict__ cum, const double* __restrict__ total,
+    const int32_t* __restrict__ parent_pos, const int32_t* __restrict__ hi,
+    const int32_t* __restrict__ tip_pos, const double* __restrict__ d64,
+    const double* __restrict__ d32, const double* __restrict__ dbf, double* __restrict__ sw,
+    double* __restrict__ wu, double* __restrict__ wu32, double* __restrict__ wub) {
+    const int lane = threadIdx.x & 63;
+    const int64_t s = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (s >= n) return;
+    const int64_t a = row_ptr[s], b = row_ptr[s + 1];
+    double x = 0.0, w = 0.0, w32 = 0.0, wb = 0.0;
+    for (int64_t e = a + lane; e < b; e += 64) {
+        const int32_t r = rank[e];
+        const int32_t tp = tip_pos[r];
+        const double cnt = double(cum[e + 1 + s] - cum[e + s]);
+        x += cnt * d64[tp];
+        w += d64[tp];
+        w32 += d32[tp];
+        wb += dbf[tp];
+        if (e + 1 < b) {
+            const int32_t r2 = rank[e + 1];
+            int32_t p = tp;
+            while (hi[p] <= r2) p = parent_pos[p];   // first ancestor covering the next tip
+            w -= d64[p];
+            w32 -= d32[p];
+            wb -= dbf[p];
+        }
+    }
+    x = wave_sum(x);
+    w = wave_sum(w);
+    w32 = wave_sum(w32);
+    wb = wave_sum(wb);
+    if (lane == 0) {
+        sw[s] = x / total[s];
+        wu[s] = w;
+        wu32[s] = w32;
+        wub[s] = wb;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Node-major embedding chunk: out[k][s] for k in [0, kc), positions k0 + k.
+// Block (k, 256 samples): consecutive lanes write consecutive samples.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_embed_nm(
+    int64_t n, int64_t k0, int weighted, const int64_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
+    const double* __restrict__ total, const int32_t* __restrict__ lo,
+    const int32_t* __restrict__ hi, const double* __restrict__ len, T* __restrict__ out) {
+    const int64_t k = blockIdx.x;
+    const int64_t s = int64_t(blockIdx.y) * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int64_t pos = k0 + k;
+    const int64_t c = embedded_count(row_ptr, rank, cum, s, lo[pos], hi[pos]);
+    T v;
+    if (weighted) v = T(len[pos] * (double(c) / total[s]));
+    else v = c > 0 ? T(1) : T(0);
+    out[k * n + s] = v;
+}
+
+// Sample-major BF16 presence: out[s][k], k in [0, kpad); 0x3F80 = 1.0, zero past kc.
+__global__ __launch_bounds__(256) void k_embed_pres_bf16(
+    int64_t n, int64_t k0, int64_t kc, int64_t kpad, const int64_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
+    const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, uint16_t* __restrict__ out) {
+    const int64_t s = blockIdx.y;
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= kpad) return;
+    uint16_t v = 0;
+    if (k < kc) {
+        const int64_t pos = k0 + k;
+        v = embedded_count(row_ptr, rank, cum, s, lo[pos], hi[pos]) > 0 ? uint16_t(0x3F80) : 0;
+    }
+    out[s * kpad + k] = v;
+}
+
+// ----------------------------------------------------------------------------
+// Stripe-band accumulation (vector ALU).
+//
+// A block owns a band tile: samples i in [i0, i0+128) times stripes s in
+// [s0, s0+128); the partner of (s, i) is j = (i+s+1) mod N.  For each branch
+// k of the chunk it needs E[k][i] for its 128 samples and E[k][j] for the
+// 255 partners, staged in LDS KS branches at a time.  Thread (ti, ts) keeps an
+// 8x8 register tile: samples i0+8ti+a, stripes s0+8ts+b; its partners are the
+// 15 consecutive window entries 8ti+8ts+(a+b).  Per branch and thread: 8+15
+// LDS reads for 64 pair updates, each update two VALU ops
+//   weighted:   acc += |x_i - x_j|   with x = l * u prescaled in the embedding
+//   unweighted: acc += (l * a_i) * a_j  (Gram form, one FMA; 8 extra multiplies)
+// Per-pair sums run over branches in postorder, independent of the tile
+// position, so any stripe range reproduces the full run bit for bit.
+// ----------------------------------------------------------------------------
+template <typename T, bool W>
+__global__ __launch_bounds__(256, 2) void k_band(const T* __restrict__ E,
+                                                 const T* __restrict__ lenk, int64_t kc,
+                                                 int64_t n, int64_t sb, int64_t se, int first,
+                                                 T* __restrict__ acc) {
+    constexpr int I = kBandI, S = kBandS, KS = 16, WJ = I + S;
+    __shared__ T wi[KS][I];
+    __shared__ T wj[KS][WJ];
+    __shared__ T wl[KS];
+    const int tid = threadIdx.x;
+    const int ti = tid & 15, ts = tid >> 4;
+    const int64_t i0 = int64_t(blockIdx.x) * I;
+    const int64_t s0 = sb + int64_t(blockIdx.y) * S;
+
+    T r[8][8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t s = s0 + ts * 8 + b;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int64_t i = i0 + ti * 8 + a;
+            r[a][b] = (!first && s < se && i < n) ? acc[(s - sb) * n + i] : T(0);
+        }
+    }
+
+    for (int64_t k0 = 0; k0 < kc; k0 += KS) {
+        __syncthreads();
+        for (int x = tid; x < KS * I; x += 256) {
+            const int kk = x / I, w = x % I;
+            const int64_t col = (i0 + w) % n;
+            wi[kk][w] = (k0 + kk < kc) ? E[(k0 + kk) * n + col] : T(0);
+        }
+        for (int x = tid; x < KS * WJ; x += 256) {
+            const int kk = x / WJ, w = x % WJ;
+            const int64_t col = (i0 + s0 + 1 + w) % n;
+            wj[kk][w] = (k0 + kk < kc) ? E[(k0 + kk) * n + col] : T(0);
+        }
+        if (!W && tid < KS) wl[tid] = (k0 + tid < kc) ? lenk[k0 + tid] : T(0);
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < KS; ++kk) {
+            T xi[8], xj[16];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) xi[a] = wi[kk][ti * 8 + a];
+#pragma unroll
+            for (int c = 0; c < 15; ++c) xj[c] = wj[kk][ti * 8 + ts * 8 + c];
+            if (W) {
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) r[a][b] += fabs(xi[a] - xj[a + b]);
+            } else {
+                const T l = wl[kk];
+#pragma unroll
+                for (int a = 0; a < 8; ++a) {
+                    const T li = l * xi[a];
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) r[a][b] = fma(li, xj[a + b], r[a][b]);
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int64_t s = s0 + ts * 8 + b;
+        if (s >= se) continue;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const int64_t i = i0 + ti * 8 + a;
+            if (i < n) acc[(s - sb) * n + i] = r[a][b];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Unweighted Gram product on MFMA: G = P diag(l) P^T with P the 0/1 presence
+// (exact in BF16) and l = l_hi + l_lo, both BF16; two MFMAs per K step share
+// the A fragment.  v_mfma_f32_32x32x16_bf16 accumulates in FP32.
+// Block = 4 waves in 2x2, tile 128x128 (wave 64x64 = 2x2 MFMA blocks of 32x32),
+// K step 32 staged in LDS (rows padded by 8 BF16 against bank conflicts).
+// Only upper-triangle tiles (bi <= bj) that hold a pair of the stripe range
+// run; each pair i<j of the range is written to its stripe-major slot.
+// ----------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bool tile_in_range(int64_t i0, int64_t j0, int64_t n, int64_t sb,
+                                              int64_t se) {
+    const int64_t S = n / 2;
+    const int64_t imax = min(i0 + kGramT, n) - 1;
+    const int64_t jmax = min(j0 + kGramT, n) - 1;
+    const int64_t dlo = max<int64_t>(1, j0 - imax);
+    const int64_t dhi = jmax - i0;
+    if (dhi < dlo) return false;
+    // partner offset d = j - i; stripe d-1 if d <= S, else n-d-1
+    const int64_t a1 = max(dlo, sb + 1), b1 = min(dhi, min(se, S));
+    const int64_t a2 = max(dlo, max(n - se, S + 1)), b2 = min(dhi, n - 1 - sb);
+    return a1 <= b1 || a2 <= b2;
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict__ P,
+                                                      const uint16_t* __restrict__ hiv,
+                                                      const uint16_t* __restrict__ lov,
+                                                      int64_t kpad, int64_t n, int64_t sb,
+                                                      int64_t se, int first,
+                                                      float* __restrict__ acc) {
+    constexpr int T = kGramT, KT = kGramK, LD = KT + 8;
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi) return;
+    const int64_t i0 = bi * T, j0 = bj * T;
+    if (!tile_in_range(i0, j0, n, sb, se)) return;
+
+    __shared__ __attribute__((aligned(16))) uint16_t As[T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bh[T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bl[T * LD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    floatx16 c[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
+
+    const int lrow = tid >> 1;          // staging: row of the tile
+    const int lseg = (tid & 1) * 16;    // staging: first of 16 K columns
+    const int64_t gi = i0 + lrow, gj = j0 + lrow;
+
+    for (int64_t k0 = 0; k0 < kpad; k0 += KT) {
+        uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
+        if (gi < n) {
+            const uint4* src = reinterpret_cast<const uint4*>(P + gi * kpad + k0 + lseg);
+            a0 = src[0];
+            a1 = src[1];
+        }
+        if (gj < n) {
+            const uint4* src = reinterpret_cast<const uint4*>(P + gj * kpad + k0 + lseg);
+            b0 = src[0];
+            b1 = src[1];
+        }
+        const uint4* hsrc = reinterpret_cast<const uint4*>(hiv + k0 + lseg);
+        const uint4* lsrc = reinterpret_cast<const uint4*>(lov + k0 + lseg);
+        const uint4 h0 = hsrc[0], h1 = hsrc[1], l0 = lsrc[0], l1 = lsrc[1];
+        // B = P (0 or 0x3F80 per BF16) masked onto the lengths
+        auto mask = [](unsigned p) -> unsigned {
+            const unsigned lo = (p & 0x0000FFFFu) ? 0x0000FFFFu : 0u;
+            const unsigned hi = (p & 0xFFFF0000u) ? 0xFFFF0000u : 0u;
+            return lo | hi;
+        };
+        const uint4 m0 = make_uint4(mask(b0.x), mask(b0.y), mask(b0.z), mask(b0.w));
+        const uint4 m1 = make_uint4(mask(b1.x), mask(b1.y), mask(b1.z), mask(b1.w));
+        __syncthreads();
+        uint4* ad = reinterpret_cast<uint4*>(As + lrow * LD + lseg);
+        uint4* hd = reinterpret_cast<uint4*>(Bh + lrow * LD + lseg);
+        uint4* ld = reinterpret_cast<uint4*>(Bl + lrow * LD + lseg);
+        ad[0] = a0;
+        ad[1] = a1;
+        hd[0] = make_uint4(h0.x & m0.x, h0.y & m0.y, h0.z & m0.z, h0.w & m0.w);
+        hd[1] = make_uint4(h1.x & m1.x, h1.y & m1.y, h1.z & m1.z, h1.w & m1.w);
+        ld[0] = make_uint4(l0.x & m0.x, l0.y & m0.y, l0.z & m0.z, l0.w & m0.w);
+        ld[1] = make_uint4(l1.x & m1.x, l1.y & m1.y, l1.z & m1.z, l1.w & m1.w);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KT; kk += 16) {
+            const int kq = kk + 8 * (lane >> 5);
+            bf16x8 fa[2], fh[2], fl[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int row = wi * 64 + x * 32 + (lane & 31);
+                fa[x] = *reinterpret_cast<const bf16x8*>(As + row * LD + kq);
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int col = wj * 64 + y * 32 + (lane & 31);
+                fh[y] = *reinterpret_cast<const bf16x8*>(Bh + col * LD + kq);
+                fl[y] = *reinterpret_cast<const bf16x8*>(Bl + col * LD + kq);
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fh[y], c[x][y], 0, 0, 0);
+                    c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fl[y], c[x][y], 0, 0, 0);
+                }
+        }
+    }
+
+    // epilogue: D[i][j] for 32x32 block: lane holds column lane%32 and rows
+    // 8*(r/4) + 4*(lane/32) + r%4 for r = 0..15
+    const int64_t S = n / 2;
+    const bool even = (n & 1) == 0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = i0 + wi * 64 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t j = j0 + wj * 64 + y * 32 + (lane & 31);
+                if (!(i < j && j < n)) continue;
+                const int64_t d = j - i;
+                const float g = c[x][y][r];
+                int64_t s, slot;
+                if (d <= S) { s = d - 1; slot = i; }
+                else { s = n - d - 1; slot = j; }
+                if (s < sb || s >= se) continue;
+                const int64_t idx = (s - sb) * n + slot;
+                acc[idx] = first ? g : acc[idx] + g;
+                if (even && d == S) {  // the last stripe of an even N holds the pair twice
+                    const int64_t idx2 = (s - sb) * n + j;
+                    acc[idx2] = first ? g : acc[idx2] + g;
+                }
+            }
+}
+
+// ----------------------------------------------------------------------------
+// Finalize: distance from the accumulator of (s, i), output layout, -d^2/2.
+// ----------------------------------------------------------------------------
+template <typename A>
+__global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict__ acc,
+                                                  const double* __restrict__ scal, int64_t n,
+                                                  int64_t sb, int64_t se, int layout, int out_f32,
+                                                  void* __restrict__ out, double* __restrict__ q) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const bool even = (n & 1) == 0;
+    for (int64_t s = sb + blockIdx.y; s < se; s += gridDim.y) {
+        const int64_t j = (i + s + 1) % n;
+        const double num = double(acc[(s - sb) * n + i]);
+        double d;
+        if (kind == 0) {
+            const double den = scal[i] + scal[j];
+            d = den > 0.0 ? num / den : 0.0;
+        } else {
+            const double sum = scal[i] + scal[j];
+            const double orr = sum - num;
+            const double xr = sum - 2.0 * num;
+            d = orr > 0.0 ? xr / orr : 0.0;
+        }
+        d = fmin(fmax(d, 0.0), 1.0);
+        if (q) q[(s - sb) * n + i] = -0.5 * d * d;
+        int64_t idx;
+        if (layout == UF_STRIPES) {
+            idx = (s - sb) * n + i;
+        } else {
+            if (even && s == n / 2 - 1 && i >= n / 2) continue;
+            const int64_t a = i < j ? i : j, b = i < j ? j : i;
+            idx = a * n - a * (a + 1) / 2 + (b - a - 1);
+        }
+        if (out_f32) static_cast<float*>(out)[idx] = float(d);
+        else static_cast<double*>(out)[idx] = d;
+    }
+}
+
+// Row sums, stage 1: part p sums stripes [sb + 256p, sb + 256(p+1)) for sample i,
+// taking each distinct pair once: (i, i+s+1) at column i and (i-s-1, i) at
+// column i-s-1 (skipped on the duplicated last stripe of an even N).
+__global__ __launch_bounds__(256) void k_rowsum_part(const double* __restrict__ q, int64_t n,
+                                                     int64_t sb, int64_t se,
+                                                     double* __restrict__ part) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = blockIdx.y;
+    const int64_t a = sb + p * 256, b = min(se, a + 256);
+    const bool even = (n & 1) == 0;
+    double acc = 0.0;
+    for (int64_t s = a; s < b; ++s) {
+        const double* row = q + (s - sb) * n;
+        acc += row[i];
+        if (!(even && s == n / 2 - 1)) {
+            int64_t jj = (i - s - 1) % n;
+            if (jj < 0) jj += n;
+            acc += row[jj];
+        }
+    }
+    part[p * n + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_rowsum_final(const double* __restrict__ part,
+                                                      int64_t n_parts, int64_t n, double scale,
+                                                      double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t p = 0; p < n_parts; ++p) acc += part[p * n + i];
+    out[i] = acc * scale;
+}
+
+__global__ __launch_bounds__(256) void k_grand_mean(const double* __restrict__ rm, int64_t n,
+                                                    double* __restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += rm[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] / double(n);
+}
+
+inline unsigned grid_y(int64_t v) { return unsigned(v < 65535 ? (v < 1 ? 1 : v) : 65535); }
+
+}  // namespace
+
+// ============================================================================
+// launchers
+// ============================================================================
+hipError_t sample_scalars(const uf_embedding& e, const int32_t* parent_pos, const int32_t* tip_pos,
+                          const double* d64, const double* d32, const double* dbf,
+                          hipStream_t st) {
+    const unsigned blocks = unsigned((e.n + 3) / 4);
+    hipLaunchKernelGGL(k_sample_scalars, dim3(blocks), dim3(256), 0, st, e.n, e.row_ptr, e.rank,
+                       e.cum, e.total, parent_pos, e.hi, tip_pos, d64, d32, dbf, e.sw, e.wu,
+                       e.wu32, e.wub);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t embed_nm(const uf_embedding& e, int64_t k0, int64_t kc, int weighted, T* out,
+                           hipStream_t st) {
+    if (kc <= 0 || e.n <= 0) return hipSuccess;
+    dim3 grid(unsigned(kc), unsigned((e.n + 255) / 256));
+    hipLaunchKernelGGL(k_embed_nm<T>, grid, dim3(256), 0, st, e.n, k0, weighted, e.row_ptr,
+                       e.rank, e.cum, e.total, e.lo, e.hi, e.len, out);
+    return hipGetLastError();
+}
+
+hipError_t embed_node_major_f64(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
+                                double* out, hipStream_t st) {
+    return embed_nm<double>(e, k0, kc, weighted, out, st);
+}
+hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
+                                float* out, hipStream_t st) {
+    return embed_nm<float>(e, k0, kc, weighted, out, st);
+}
+
+hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
+                               uint16_t* out, hipStream_t st) {
+    if (kpad <= 0 || e.n <= 0) return hipSuccess;
+    if (e.n > 65535) {
+        // one launch per 65535 samples keeps grid.y in range
+        for (int64_t s0 = 0; s0 < e.n; s0 += 65535) {
+            const int64_t ns = std::min<int64_t>(65535, e.n - s0);
+            dim3 grid(unsigned((kpad + 255) / 256), unsigned(ns));
+            hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, ns, k0, kc, kpad,
+                               e.row_ptr + s0, e.rank, e.cum + s0, e.lo, e.hi,
+                               out + s0 * kpad);
+            hipError_t err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    dim3 grid(unsigned((kpad + 255) / 256), unsigned(e.n));
+    hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, e.n, k0, kc, kpad, e.row_ptr,
+                       e.rank, e.cum, e.lo, e.hi, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t band(const T* E, const T* lenk, int64_t kc, int64_t n, int64_t sb, int64_t se,
+                       int weighted, int first, T* acc, hipStream_t st) {
+    if (se <= sb || n <= 0) return hipSuccess;
+    const int64_t by = (se - sb + kBandS - 1) / kBandS;
+    if (by > 65535) return hipErrorInvalidValue;
+    dim3 grid(unsigned((n + kBandI - 1) / kBandI), unsigned(by));
+    if (weighted)
+        hipLaunchKernelGGL((k_band<T, true>), grid, dim3(256), 0, st, E, lenk, kc, n, sb, se,
+                           first, acc);
+    else
+        hipLaunchKernelGGL((k_band<T, false>), grid, dim3(256), 0, st, E, lenk, kc, n, sb, se,
+                           first, acc);
+    return hipGetLastError();
+}
+
+hipError_t band_f64(const double* E, const double* lenk, int64_t kc, int64_t n, int64_t sb,
+                    int64_t se, int weighted, int first, double* acc, hipStream_t st) {
+    return band<double>(E, lenk, kc, n, sb, se, weighted, first, acc, st);
+}
+hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, int64_t sb,
+                    int64_t se, int weighted, int first, float* acc, hipStream_t st) {
+    return band<float>(E, lenk, kc, n, sb, se, weighted, first, acc, st);
+}
+
+hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
+                     int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st) {
+    if (se <= sb || n <= 0) return hipSuccess;
+    const int64_t nblk = (n + kGramT - 1) / kGramT;
+    if (nblk > 65535 || (kpad % kGramK) != 0) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(nblk), unsigned(nblk), 1u};
+    hipLaunchKernelGGL(k_gram_mfma, grid, dim3(256), 0, st, P, hi, lo, kpad, n, sb, se, first,
+                       acc);
+    return hipGetLastError();
+}
+
+hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
+                    int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
+                    hipStream_t st) {
+    if (se <= sb || n <= 0) return hipSuccess;
+    dim3 grid(unsigned((n + 255) / 256), grid_y(se - sb));
+    if (acc_is_f64)
+        hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, st, kind,
+                           static_cast<const double*>(acc), scal, n, sb, se, layout, out_f32, out,
+                           q);
+    else
+        hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, st, kind,
+                           static_cast<const float*>(acc), scal, n, sb, se, layout, out_f32, out,
+                           q);
+    return hipGetLastError();
+}
+
+hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* partial,
+                    int64_t n_parts, double scale, double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (n_parts > 65535) return hipErrorInvalidValue;
+    dim3 g1(unsigned((n + 255) / 256), unsigned(n_parts));
+    hipLaunchKernelGGL(k_rowsum_part, g1, dim3(256), 0, st, q, n, sb, se, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowsum_final, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, partial,
+                       n_parts, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t grand_mean(const double* row_means, int64_t n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_grand_mean, dim3(1), dim3(256), 0, st, row_means, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace ufk
