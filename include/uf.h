@@ -165,6 +165,47 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* emb, uf_precisio
                                             void* out, double* row_sums, void* ws,
                                             size_t ws_bytes, void* hip_stream);
 
+/* ---- batches: many tables on one tree --------------------------------------- */
+
+/* Many tables of uneven size on one tree -- e.g. rarefied replicates of a study
+ * -- computed together: weighted normalized, FP32 accumulation, FP64 division,
+ * condensed FP32 output per table.  Per node chunk, one kernel embeds every
+ * table and one persistent kernel (#CU x wgs_per_cu resident blocks) drains
+ * the (table, band tile) items of all tables from per-XCD atomic queues; the
+ * whole sequence (all chunks, then finalize of every table) is captured once
+ * into a hipGraph and replayed with one launch.  Per-pair values are bitwise
+ * equal to uf_dm_weighted_normalized(UF_FP32) on each table alone.
+ *
+ * uf_batch_create: tables must have been loaded against `tree`; they are
+ * concatenated and uploaded (library-owned device memory; synchronises
+ * `hip_stream`).  tune_cache (nullable; else $UF_TUNE_CACHE, else defaults):
+ * JSON written by uf_autotune; its entry for the batch's size bucket
+ * ceil(log2(mean N)) sets the launch configuration.
+ * Errors: UF_ERR_ARG, UF_ERR_NOMEM, UF_ERR_DEVICE. */
+typedef struct uf_batch uf_batch;
+uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
+                          const char* tune_cache, void* hip_stream, uf_batch** out);
+int64_t uf_batch_n_tables(const uf_batch* batch);
+uf_status uf_batch_workspace_size(const uf_batch* batch, size_t* bytes);
+/* Current launch configuration: branches staged per LDS block (8, 16 or 32),
+ * resident blocks per CU, and branches per chunk. */
+uf_status uf_batch_config(const uf_batch* batch, int* stage_branches, int* wgs_per_cu,
+                          int64_t* chunk_nodes);
+uf_status uf_batch_set_config(uf_batch* batch, int stage_branches, int wgs_per_cu);
+/* Compute every table: outs[r] is a device buffer of N_r(N_r-1)/2 floats
+ * (NULL allowed for tables with fewer than 2 samples).  use_graph: replay the
+ * captured graph (captured on first use and again whenever ws or outs change)
+ * instead of launching kernel by kernel.  Asynchronous on hip_stream. */
+uf_status uf_batch_run(uf_batch* batch, float* const* outs, int use_graph, void* ws,
+                       size_t ws_bytes, void* hip_stream);
+/* Time every valid (stage_branches, wgs_per_cu) on the batch's first chunk,
+ * keep the fastest (results are identical for all), and record it in the JSON
+ * cache at tune_cache (nullable; else $UF_TUNE_CACHE; no file if neither).
+ * best_ms (nullable) receives the winner's time.  Synchronises hip_stream. */
+uf_status uf_autotune(uf_batch* batch, void* ws, size_t ws_bytes, const char* tune_cache,
+                      void* hip_stream, double* best_ms);
+void uf_free_batch(uf_batch* batch);
+
 /* ---- kernel timing --------------------------------------------------------- */
 
 /* Per-kernel timing with HIP events recorded on the call's stream around each

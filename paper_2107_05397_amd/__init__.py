@@ -27,7 +27,7 @@ __all__ = [
     "UFError", "lib", "Tree", "Table", "Embedding", "workspace_size", "dm", "dm_unweighted",
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
-    "profile_read",
+    "profile_read", "Batch",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -80,6 +80,17 @@ _SIGS = {
     "uf_free_tree": (None, [_vp]),
     "uf_free_table": (None, [_vp]),
     "uf_free_embedding": (None, [_vp]),
+    "uf_batch_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, ctypes.c_char_p, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "uf_batch_n_tables": (_i64, [_vp]),
+    "uf_batch_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), _i64p]),
+    "uf_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "uf_batch_run": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t,
+                                    _vp]),
+    "uf_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_char_p, _vp, _f64p]),
+    "uf_free_batch": (None, [_vp]),
     "uf_profile_enable": (None, [ctypes.c_int]),
     "uf_profile_reset": (None, []),
     "uf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _f64p, _i64p]),
@@ -342,3 +353,67 @@ def dm_stripes(emb: Embedding, variant: str, precision: str, stripe_begin: int, 
               LAYOUT[layout], 1 if out.dtype == torch.float32 else 0, _tptr(out), _tptr(rs),
               _tptr(ws), ws.numel() * ws.element_size(), _stream_ptr(stream)))
     return out[:need].view(shape), (rs[:n] if rs is not None else None)
+
+
+class Batch(_Handle):
+    """Many tables on one tree: weighted normalized FP32, one graph replay per run."""
+    _free = "uf_free_batch"
+
+    def __init__(self, tree: Tree, tables, tune_cache: Optional[str] = None, stream=None):
+        super().__init__()
+        self.tree = tree
+        self.tables = list(tables)
+        arr = (_vp * len(self.tables))(*[t.handle.value for t in self.tables])
+        _check(lib().uf_batch_create(tree.handle, arr, len(self.tables),
+                                     tune_cache.encode() if tune_cache else None,
+                                     _stream_ptr(stream), ctypes.byref(self._h)))
+        self._ws = None
+        self._outs = None
+
+    @property
+    def n_tables(self) -> int:
+        return int(lib().uf_batch_n_tables(self._h))
+
+    def workspace_size(self) -> int:
+        out = ctypes.c_size_t(0)
+        _check(lib().uf_batch_workspace_size(self._h, ctypes.byref(out)))
+        return int(out.value)
+
+    def config(self):
+        ks, w, kc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
+        _check(lib().uf_batch_config(self._h, ctypes.byref(ks), ctypes.byref(w), ctypes.byref(kc)))
+        return int(ks.value), int(w.value), int(kc.value)
+
+    def set_config(self, stage_branches: int, wgs_per_cu: int) -> None:
+        _check(lib().uf_batch_set_config(self._h, int(stage_branches), int(wgs_per_cu)))
+
+    def _workspace(self, workspace):
+        if workspace is not None:
+            return _workspace(self.workspace_size(), workspace)
+        if self._ws is None:
+            self._ws = _workspace(self.workspace_size(), None)
+        return self._ws
+
+    def outputs(self):
+        """Per-table condensed FP32 output tensors (allocated once, reused)."""
+        import torch
+        if self._outs is None:
+            self._outs = [torch.empty(max(t.n_samples * (t.n_samples - 1) // 2, 1),
+                                      dtype=torch.float32, device="cuda") for t in self.tables]
+        return self._outs
+
+    def run(self, use_graph: bool = True, outs=None, workspace=None, stream=None):
+        outs = outs if outs is not None else self.outputs()
+        ws = self._workspace(workspace)
+        arr = (_vp * len(outs))(*[o.data_ptr() for o in outs])
+        _check(lib().uf_batch_run(self._h, arr, 1 if use_graph else 0, _tptr(ws),
+                                  ws.numel() * ws.element_size(), _stream_ptr(stream)))
+        return [o[: t.n_samples * (t.n_samples - 1) // 2] for o, t in zip(outs, self.tables)]
+
+    def autotune(self, tune_cache: Optional[str] = None, workspace=None, stream=None) -> float:
+        ws = self._workspace(workspace)
+        ms = ctypes.c_double(0.0)
+        _check(lib().uf_autotune(self._h, _tptr(ws), ws.numel() * ws.element_size(),
+                                 tune_cache.encode() if tune_cache else None,
+                                 _stream_ptr(stream), ctypes.byref(ms)))
+        return float(ms.value)

@@ -520,8 +520,11 @@ int64_t uf_table_n_samples(const uf_table* t) { return t ? t->n_samples : -1; }
 void uf_free_table(uf_table* t) { delete t; }
 
 // ------------------------------------------------------------------ embedding
-uf_status uf_embed(const uf_tree* t, const uf_table* tb, void* stream, uf_embedding** out) {
-    return guarded([&]() -> uf_status {
+}  // extern "C"
+
+namespace {
+uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embedding** out) {
+    {
         if (!out) return fail(UF_ERR_ARG, "out is NULL");
         *out = nullptr;
         if (!t || !tb) return fail(UF_ERR_ARG, "tree or table is NULL");
@@ -649,7 +652,14 @@ uf_status uf_embed(const uf_tree* t, const uf_table* tb, void* stream, uf_embedd
         if (rc != hipSuccess) return cleanup(hip_fail(rc, "sample scalar kernel"));
         *out = guard.release();
         return UF_OK;
-    });
+    }
+}
+}  // namespace
+
+extern "C" {
+
+uf_status uf_embed(const uf_tree* t, const uf_table* tb, void* stream, uf_embedding** out) {
+    return guarded([&]() -> uf_status { return embed_impl(t, tb, stream, out); });
 }
 
 int64_t uf_embedding_n_samples(const uf_embedding* e) { return e ? e->n : -1; }
@@ -721,5 +731,373 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* e, uf_precision 
                       ws_bytes, stream);
     });
 }
+
+}  // extern "C"
+
+// =========================================================================
+// Batches: many tables on one tree (weighted normalized, FP32), one graph
+// =========================================================================
+struct uf_batch {
+    uf_embedding* emb = nullptr;              // concatenated tables, device
+    int64_t n_tables = 0;
+    std::vector<BatchTable> tabs;        // host copy
+    std::vector<int64_t> acc_elems;           // per table
+    int64_t n_items = 0;
+    int64_t kc = 0, n_chunks = 0;
+    int stage_branches = 16, wgs_per_cu = 2, n_cu = 256;
+    int64_t n_bucket = 0;
+    void* arena = nullptr;                    // descs, tab_of, items, queue bounds
+    BatchTable* d_tabs = nullptr;
+    int32_t* d_tab_of = nullptr;
+    int2* d_items = nullptr;
+    int64_t* d_qbeg = nullptr;
+    int64_t* d_qend = nullptr;
+    size_t off_E = 0, off_acc = 0, off_cnt = 0, ws_total = 0;
+    hipStream_t cap = nullptr;                // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> graph_key;         // workspace + outputs the graph was built for
+
+    ~uf_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (arena) (void)hipFree(arena);
+        uf_free_embedding(emb);
+    }
+};
+
+namespace {
+
+const int kBatchStages[] = {8, 16, 32};
+
+bool config_valid(int ks, int w) {
+    // one CU holds at most 160 KB of LDS and 512 VGPRs x 4 SIMDs
+    const int lds_kb = ks == 8 ? 25 : (ks == 16 ? 49 : 97);
+    const int max_w = ks == 8 ? 3 : (ks == 16 ? 2 : 1);
+    return w >= 1 && w <= max_w && w * lds_kb <= 160;
+}
+
+std::string cache_key_arch() { return "gfx950"; }
+
+// Cache file: {"gfx950": {"weighted_normalized_fp32": {"n_bucket_B": {"stage_branches": K,
+// "wgs_per_cu": W, "ms": T}, ...}}}.  Entries are parsed leniently by pattern.
+struct TuneEntry {
+    int ks, w;
+    double ms;
+};
+std::map<int64_t, TuneEntry> read_tune_cache(const char* path) {
+    std::map<int64_t, TuneEntry> m;
+    if (!path) return m;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return m;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    size_t pos = 0;
+    while ((pos = text.find("\"n_bucket_", pos)) != std::string::npos) {
+        long long b = 0;
+        int ks = 0, w = 0;
+        double ms = 0;
+        if (std::sscanf(text.c_str() + pos,
+                        "\"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, \"ms\": %lf",
+                        &b, &ks, &w, &ms) == 4 &&
+            config_valid(ks, w))
+            m[b] = TuneEntry{ks, w, ms};
+        pos += 10;
+    }
+    return m;
+}
+
+bool write_tune_cache(const char* path, const std::map<int64_t, TuneEntry>& m) {
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\"%s\": {\"weighted_normalized_fp32\": {", cache_key_arch().c_str());
+    bool firstc = true;
+    for (const auto& kv : m) {
+        std::fprintf(f, "%s\n  \"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, \"ms\": %.6f}",
+                     firstc ? "" : ",", (long long)kv.first, kv.second.ks, kv.second.w, kv.second.ms);
+        firstc = false;
+    }
+    std::fprintf(f, "\n}}}\n");
+    std::fclose(f);
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+const char* tune_path(const char* p) { return p ? p : std::getenv("UF_TUNE_CACHE"); }
+
+// enqueue the whole batch on stream s (also used under graph capture)
+uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t s) {
+    float* E = reinterpret_cast<float*>(base + b->off_E);
+    float* acc = reinterpret_cast<float*>(base + b->off_acc);
+    unsigned* cnt = reinterpret_cast<unsigned*>(base + b->off_cnt);
+    const uf_embedding& e = *b->emb;
+    const int nblk = b->n_cu * b->wgs_per_cu;
+    UF_HIP(ufk::zero_u32(cnt, std::max<int64_t>(b->n_chunks, 1) * 8, s));
+    for (int64_t c = 0; c < b->n_chunks; ++c) {
+        const int64_t k0 = c * b->kc;
+        const int64_t kc = std::min<int64_t>(b->kc, e.nb - k0);
+        UF_HIP(ufk::embed_batch_f32(e, b->d_tabs, b->d_tab_of, k0, kc, E, s));
+        if (b->n_items > 0)
+            UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend,
+                                            cnt + c * 8, kc, c == 0, acc, b->stage_branches, nblk, s));
+    }
+    for (int64_t r = 0; r < b->n_tables; ++r) {
+        const BatchTable& t = b->tabs[r];
+        if (t.n < 2) continue;
+        if (b->n_chunks == 0) {
+            UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(acc + t.acc_off), (t.n / 2) * t.n, s));
+        }
+        UF_HIP(ufk::finalize(0, acc + t.acc_off, 0, e.sw + t.off, t.n, 0, t.n / 2, UF_CONDENSED, 1,
+                             outs[r], nullptr, s));
+    }
+    return UF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
+                          const char* tune_cache, void* stream, uf_batch** out) {
+    return guarded([&]() -> uf_status {
+        if (!out) return fail(UF_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        if (!tree || !tables || n_tables < 1) return fail(UF_ERR_ARG, "need a tree and >= 1 table");
+        // concatenate the tables on the host
+        uf_table cat;
+        cat.n_tips = tree->n_tips;
+        cat.row_ptr.push_back(0);
+        for (int64_t r = 0; r < n_tables; ++r) {
+            const uf_table* t = tables[r];
+            if (!t) return fail(UF_ERR_ARG, "table pointer is NULL");
+            if (t->n_tips != tree->n_tips) return fail(UF_ERR_ARG, "table loaded against another tree");
+            const int64_t base = int64_t(cat.rank.size());
+            cat.rank.insert(cat.rank.end(), t->rank.begin(), t->rank.end());
+            cat.count.insert(cat.count.end(), t->count.begin(), t->count.end());
+            cat.total.insert(cat.total.end(), t->total.begin(), t->total.end());
+            for (int64_t sidx = 1; sidx <= t->n_samples; ++sidx) cat.row_ptr.push_back(base + t->row_ptr[sidx]);
+        }
+        cat.n_samples = int64_t(cat.total.size());
+        auto b = new uf_batch();
+        std::unique_ptr<uf_batch> guard(b);
+        uf_status st = embed_impl(tree, &cat, stream, &b->emb);
+        if (st != UF_OK) return st;
+        b->n_tables = n_tables;
+        int dev = 0;
+        UF_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        UF_HIP(hipGetDeviceProperties(&prop, dev));
+        b->n_cu = prop.multiProcessorCount;
+        // chunk length: 16 GiB of embedding for all tables, or the process-wide setting
+        const int64_t n_all = std::max<int64_t>(cat.n_samples, 1);
+        int64_t kc = g_chunk_nodes.load();
+        if (kc <= 0) kc = int64_t(16.0 * 1024 * 1024 * 1024 / (double(n_all) * 4.0));
+        kc = std::min<int64_t>(std::max<int64_t>(kc, 32), std::max<int64_t>(b->emb->nb, 1));
+        b->kc = kc;
+        b->n_chunks = b->emb->nb > 0 ? (b->emb->nb + kc - 1) / kc : 0;
+        // per-table layout and work items
+        int64_t off = 0, eoff = 0, aoff = 0;
+        std::vector<int2> items;
+        std::vector<int32_t> tab_of(size_t(n_all), 0);
+        double mean_n = 0;
+        for (int64_t r = 0; r < n_tables; ++r) {
+            BatchTable t;
+            t.n = tables[r]->n_samples;
+            t.off = off;
+            t.e_off = eoff;
+            t.acc_off = aoff;
+            t.n_iblk = (t.n + ufk::kBandI - 1) / ufk::kBandI;
+            b->tabs.push_back(t);
+            for (int64_t i = 0; i < t.n; ++i) tab_of[size_t(off + i)] = int32_t(r);
+            const int64_t S = t.n / 2;
+            const int64_t n_sblk = (S + ufk::kBandS - 1) / ufk::kBandS;
+            if (t.n >= 2)
+                for (int64_t tt = 0; tt < t.n_iblk * n_sblk; ++tt) items.push_back(make_int2(int(r), int(tt)));
+            off += t.n;
+            eoff += kc * t.n;
+            aoff += ((S * t.n + 63) / 64) * 64;
+            mean_n += double(t.n) / double(n_tables);
+        }
+        b->n_items = int64_t(items.size());
+        b->n_bucket = mean_n > 1 ? int64_t(std::ceil(std::log2(mean_n))) : 0;
+        std::vector<int64_t> qb(8), qe(8);
+        for (int q = 0; q < 8; ++q) {
+            qb[q] = b->n_items * q / 8;
+            qe[q] = b->n_items * (q + 1) / 8;
+        }
+        Carver c;
+        const size_t o_tabs = c.take(sizeof(BatchTable) * size_t(n_tables));
+        const size_t o_tabof = c.take(size_t(n_all) * 4);
+        const size_t o_items = c.take(sizeof(int2) * size_t(std::max<int64_t>(b->n_items, 1)));
+        const size_t o_qb = c.take(8 * 8);
+        const size_t o_qe = c.take(8 * 8);
+        if (hipMalloc(&b->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "batch descriptors");
+        char* base = static_cast<char*>(b->arena);
+        b->d_tabs = reinterpret_cast<BatchTable*>(base + o_tabs);
+        b->d_tab_of = reinterpret_cast<int32_t*>(base + o_tabof);
+        b->d_items = reinterpret_cast<int2*>(base + o_items);
+        b->d_qbeg = reinterpret_cast<int64_t*>(base + o_qb);
+        b->d_qend = reinterpret_cast<int64_t*>(base + o_qe);
+        UF_HIP(hipMemcpy(b->d_tabs, b->tabs.data(), sizeof(BatchTable) * size_t(n_tables), hipMemcpyHostToDevice));
+        UF_HIP(hipMemcpy(b->d_tab_of, tab_of.data(), size_t(n_all) * 4, hipMemcpyHostToDevice));
+        if (b->n_items) UF_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * size_t(b->n_items), hipMemcpyHostToDevice));
+        UF_HIP(hipMemcpy(b->d_qbeg, qb.data(), 64, hipMemcpyHostToDevice));
+        UF_HIP(hipMemcpy(b->d_qend, qe.data(), 64, hipMemcpyHostToDevice));
+        Carver w;
+        b->off_E = w.take(size_t(eoff) * 4);
+        b->off_acc = w.take(size_t(aoff) * 4);
+        b->off_cnt = w.take(size_t(std::max<int64_t>(b->n_chunks, 1)) * 8 * 4);
+        b->ws_total = w.off + 256;
+        // launch configuration from the tuning cache, if it has this size bucket
+        auto cache = read_tune_cache(tune_path(tune_cache));
+        auto it = cache.find(b->n_bucket);
+        if (it != cache.end()) {
+            b->stage_branches = it->second.ks;
+            b->wgs_per_cu = it->second.w;
+        }
+        UF_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        *out = guard.release();
+        return UF_OK;
+    });
+}
+
+int64_t uf_batch_n_tables(const uf_batch* b) { return b ? b->n_tables : -1; }
+
+uf_status uf_batch_workspace_size(const uf_batch* b, size_t* bytes) {
+    if (!b || !bytes) return fail(UF_ERR_ARG, "NULL argument");
+    *bytes = b->ws_total;
+    return UF_OK;
+}
+
+uf_status uf_batch_config(const uf_batch* b, int* stage_branches, int* wgs_per_cu, int64_t* chunk_nodes) {
+    if (!b) return fail(UF_ERR_ARG, "batch is NULL");
+    if (stage_branches) *stage_branches = b->stage_branches;
+    if (wgs_per_cu) *wgs_per_cu = b->wgs_per_cu;
+    if (chunk_nodes) *chunk_nodes = b->kc;
+    return UF_OK;
+}
+
+uf_status uf_batch_set_config(uf_batch* b, int stage_branches, int wgs_per_cu) {
+    if (!b) return fail(UF_ERR_ARG, "batch is NULL");
+    if (!config_valid(stage_branches, wgs_per_cu))
+        return fail(UF_ERR_ARG, "unsupported (stage_branches, wgs_per_cu)");
+    b->stage_branches = stage_branches;
+    b->wgs_per_cu = wgs_per_cu;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->graph_key.clear();
+    }
+    return UF_OK;
+}
+
+uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws, size_t ws_bytes,
+                       void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!b || !outs) return fail(UF_ERR_ARG, "NULL argument");
+        if (!ws || ws_bytes < b->ws_total) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
+        for (int64_t r = 0; r < b->n_tables; ++r)
+            if (!outs[r] && b->tabs[r].n >= 2) return fail(UF_ERR_ARG, "output pointer is NULL");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (!use_graph) return batch_enqueue(b, outs, base, s);
+        std::vector<uintptr_t> key;
+        key.push_back(reinterpret_cast<uintptr_t>(base));
+        for (int64_t r = 0; r < b->n_tables; ++r) key.push_back(reinterpret_cast<uintptr_t>(outs[r]));
+        if (!b->exec || key != b->graph_key) {
+            if (b->exec) {
+                (void)hipGraphExecDestroy(b->exec);
+                (void)hipGraphDestroy(b->graph);
+                b->exec = nullptr;
+                b->graph = nullptr;
+            }
+            UF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+            uf_status est = batch_enqueue(b, outs, base, b->cap);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(b->cap, &g);
+            if (est != UF_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return est;
+            }
+            if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+            hipGraphExec_t ex = nullptr;
+            hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return hip_fail(ie, "hipGraphInstantiate");
+            }
+            b->graph = g;
+            b->exec = ex;
+            b->graph_key = key;
+        }
+        UF_HIP(hipGraphLaunch(b->exec, s));
+        return UF_OK;
+    });
+}
+
+uf_status uf_autotune(uf_batch* b, void* ws, size_t ws_bytes, const char* tune_cache,
+                      void* stream, double* best_ms) {
+    return guarded([&]() -> uf_status {
+        if (!b) return fail(UF_ERR_ARG, "batch is NULL");
+        if (!ws || ws_bytes < b->ws_total) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+        float* E = reinterpret_cast<float*>(base + b->off_E);
+        float* acc = reinterpret_cast<float*>(base + b->off_acc);
+        unsigned* cnt = reinterpret_cast<unsigned*>(base + b->off_cnt);
+        const uf_embedding& e = *b->emb;
+        if (b->n_chunks == 0 || b->n_items == 0) return UF_OK;
+        const int64_t kc = std::min<int64_t>(b->kc, e.nb);
+        UF_HIP(ufk::embed_batch_f32(e, b->d_tabs, b->d_tab_of, 0, kc, E, s));
+        hipEvent_t e0, e1;
+        UF_HIP(hipEventCreate(&e0));
+        UF_HIP(hipEventCreate(&e1));
+        TuneEntry best{b->stage_branches, b->wgs_per_cu, 1e300};
+        for (int ks : kBatchStages) {
+            for (int w = 1; w <= 3; ++w) {
+                if (!config_valid(ks, w) || (w == 1 && ks != 32)) continue;
+                double tmin = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {
+                    UF_HIP(ufk::zero_u32(cnt, 8, s));
+                    UF_HIP(hipEventRecord(e0, s));
+                    UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend, cnt,
+                                                    kc, 1, acc, ks, b->n_cu * w, s));
+                    UF_HIP(hipEventRecord(e1, s));
+                    UF_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    UF_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    tmin = std::min(tmin, double(ms));
+                }
+                if (tmin < best.ms) best = TuneEntry{ks, w, tmin};
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best_ms) *best_ms = best.ms;
+        st = uf_batch_set_config(b, best.ks, best.w);
+        if (st != UF_OK) return st;
+        const char* path = tune_path(tune_cache);
+        if (path) {
+            auto cache = read_tune_cache(path);
+            cache[b->n_bucket] = best;
+            if (!write_tune_cache(path, cache)) return fail(UF_ERR_ARG, "cannot write the tuning cache");
+        }
+        return UF_OK;
+    });
+}
+
+void uf_free_batch(uf_batch* b) { delete b; }
 
 }  // extern "C"

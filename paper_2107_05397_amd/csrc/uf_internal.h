@@ -67,6 +67,15 @@ struct uf_embedding {
     void* arena = nullptr;        // one allocation holding all of the above
 };
 
+// One table of a batch, as the batched kernels see it.
+struct BatchTable {
+    int64_t n;        // samples
+    int64_t off;      // first sample in the concatenated table
+    int64_t e_off;    // element offset of its node-major chunk block [kc][n]
+    int64_t acc_off;  // element offset of its stripe-major accumulator [n/2][n]
+    int64_t n_iblk;   // 128-sample blocks
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (uf_kernels.hip).  All are asynchronous on `st` and return
 // the hipError_t of the launch.
@@ -118,5 +127,19 @@ hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* sca
 hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* partial,
                     int64_t n_parts, double scale, double* out, hipStream_t st);
 hipError_t grand_mean(const double* row_means, int64_t n, double* out, hipStream_t st);
+
+// ---- batches (many tables on one tree, weighted normalized, FP32) --------
+// Node-major chunk of every table: table r's block at e_off, row stride n_r.
+hipError_t embed_batch_f32(const uf_embedding& e, const BatchTable* tabs, const int32_t* tab_of,
+                           int64_t k0, int64_t kc, float* out, hipStream_t st);
+// Persistent band kernel over (table, tile) items.  items: int32 pairs; queue q
+// holds items [qbeg[q], qend[q]) and its counter counters[q] (8 queues, one per
+// XCD; exhausted queues are stolen from).  stage_branches in {8, 16, 32}.
+hipError_t band_persistent_f32(const float* E, const BatchTable* tabs, const int2* items,
+                               const int64_t* qbeg, const int64_t* qend, unsigned* counters,
+                               int64_t kc, int first, float* acc, int stage_branches,
+                               int n_blocks, hipStream_t st);
+// Zero n unsigned counters (a kernel, so that graph replays stay valid).
+hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t st);
 
 }  // namespace ufk

@@ -100,23 +100,48 @@ __global__ __launch_bounds__(256) void k_sample_scalars(
 
 // ----------------------------------------------------------------------------
 // Node-major embedding chunk: out[k][s] for k in [0, kc), positions k0 + k.
-// Block (k, 256 samples): consecutive lanes write consecutive samples.
+// A block covers 256 consecutive branches x TS samples.  The counts are found
+// sample by sample (all lanes search the same row, which stays in L1), kept in
+// an LDS tile, then written branch-row by branch-row (TS consecutive samples
+// per row: coalesced).
 // ----------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_embed_nm(
-    int64_t n, int64_t k0, int weighted, const int64_t* __restrict__ row_ptr,
+    int64_t n, int64_t k0, int64_t kc, int weighted, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
     const double* __restrict__ total, const int32_t* __restrict__ lo,
     const int32_t* __restrict__ hi, const double* __restrict__ len, T* __restrict__ out) {
-    const int64_t k = blockIdx.x;
-    const int64_t s = int64_t(blockIdx.y) * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int64_t pos = k0 + k;
-    const int64_t c = embedded_count(row_ptr, rank, cum, s, lo[pos], hi[pos]);
-    T v;
-    if (weighted) v = T(len[pos] * (double(c) / total[s]));
-    else v = c > 0 ? T(1) : T(0);
-    out[k * n + s] = v;
+    constexpr int TK = 256, TS = 256 / int(sizeof(T));   // FP32: 64 samples, FP64: 32
+    __shared__ T tile[TK][TS + 1];
+    const int tid = threadIdx.x;
+    const int64_t kb = int64_t(blockIdx.x) * TK;
+    const int64_t sb = int64_t(blockIdx.y) * TS;
+    const int64_t k = kb + tid;
+    const bool kin = k < kc;
+    int32_t lk = 0, hk = 0;
+    double lv = 0.0;
+    if (kin) {
+        lk = lo[k0 + k];
+        hk = hi[k0 + k];
+        lv = len[k0 + k];
+    }
+    for (int j = 0; j < TS; ++j) {
+        const int64_t s = sb + j;
+        T v = T(0);
+        if (kin && s < n) {
+            const int64_t c = embedded_count(row_ptr, rank, cum, s, lk, hk);
+            if (weighted) v = T(lv * (double(c) / total[s]));
+            else v = c > 0 ? T(1) : T(0);
+        }
+        tile[tid][j] = v;
+    }
+    __syncthreads();
+    constexpr int ROWS_PER_PASS = 256 / TS;
+    for (int r = tid / TS; r < TK; r += ROWS_PER_PASS) {
+        const int64_t kk = kb + r;
+        const int64_t s = sb + (tid % TS);
+        if (kk < kc && s < n) out[kk * n + s] = tile[r][tid % TS];
+    }
 }
 
 // Sample-major BF16 presence: out[s][k], k in [0, kpad); 0x3F80 = 1.0, zero past kc.
@@ -141,28 +166,91 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
 // A block owns a band tile: samples i in [i0, i0+128) times stripes s in
 // [s0, s0+128); the partner of (s, i) is j = (i+s+1) mod N.  For each branch
 // k of the chunk it needs E[k][i] for its 128 samples and E[k][j] for the
-// 255 partners, staged in LDS KS branches at a time.  Thread (ti, ts) keeps an
-// 8x8 register tile: samples i0+8ti+a, stripes s0+8ts+b; its partners are the
-// 15 consecutive window entries 8ti+8ts+(a+b).  Per branch and thread: 8+15
-// LDS reads for 64 pair updates, each update two VALU ops
+// 255 partners.  Thread (ti, ts) keeps an 8x8 register tile: samples
+// i0+8ti+a, stripes s0+8ts+b; its partners are the 15 consecutive window
+// entries 8ti+8ts+(a+b).  Per branch and thread: 8+15 LDS reads for 64 pair
+// updates, each update two VALU ops
 //   weighted:   acc += |x_i - x_j|   with x = l * u prescaled in the embedding
 //   unweighted: acc += (l * a_i) * a_j  (Gram form, one FMA; 8 extra multiplies)
+// Staging: KS branches at a time, double-buffered in LDS and filled by direct
+// global->LDS loads (no registers), issued for block b+1 before block b is
+// computed.  Column offsets (mod N) are computed once per thread.
 // Per-pair sums run over branches in postorder, independent of the tile
 // position, so any stripe range reproduces the full run bit for bit.
 // ----------------------------------------------------------------------------
-template <typename T, bool W>
-__global__ __launch_bounds__(256, 2) void k_band(const T* __restrict__ E,
-                                                 const T* __restrict__ lenk, int64_t kc,
-                                                 int64_t n, int64_t sb, int64_t se, int first,
-                                                 T* __restrict__ acc) {
-    constexpr int I = kBandI, S = kBandS, KS = 16, WJ = I + S;
-    __shared__ T wi[KS][I];
-    __shared__ T wj[KS][WJ];
-    __shared__ T wl[KS];
-    const int tid = threadIdx.x;
+template <typename T>
+struct BandCfg;
+template <>
+struct BandCfg<float> {
+    static constexpr int KS = 16;
+};
+template <>
+struct BandCfg<double> {
+    static constexpr int KS = 8;
+};
+
+// Hardware hands block b to XCD b mod 8.  Remap so each XCD runs a contiguous
+// range of tiles (i-block fastest): neighbouring i-blocks of one stripe block
+// share most of their partner window, so those loads hit the XCD's own L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n_tiles) {
+    const int64_t x = b & 7, local = b >> 3;
+    const int64_t per = n_tiles >> 3, rem = n_tiles & 7;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+// LDS of one band tile: two staging buffers of KS branches.
+template <typename T, int KS>
+struct BandLds {
+    T wi[2][KS][kBandI];
+    T wj[2][KS][kBandI + kBandS];
+    T wl[2][KS];
+};
+
+// One band tile: samples [i0, i0+128) x stripes [s0, s0+128) of a matrix with
+// n samples, over the kc branches of node-major E (row stride n).
+template <typename T, bool W, int KS>
+__device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict__ E,
+                                          const T* __restrict__ lenk, int64_t kc, int64_t n,
+                                          int64_t sb, int64_t se, int64_t i0, int64_t s0,
+                                          int first, T* __restrict__ acc) {
+    constexpr int I = kBandI, WJ = kBandI + kBandS;
+    constexpr int DW = int(sizeof(T) / 4);          // dwords per element
+    constexpr int EPS = 64 / DW;                    // elements per 64-dword segment
+    constexpr int SEG_I = I / EPS, SEG_J = WJ / EPS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ti = tid & 15, ts = tid >> 4;
-    const int64_t i0 = int64_t(blockIdx.x) * I;
-    const int64_t s0 = sb + int64_t(blockIdx.y) * S;
+
+    // lane -> (element of its segment, dword of that element)
+    const int part = lane % DW;
+    int64_t coli[SEG_I], colj[SEG_J];
+#pragma unroll
+    for (int p = 0; p < SEG_I; ++p) coli[p] = ((i0 + p * EPS + lane / DW) % n) * DW + part;
+#pragma unroll
+    for (int p = 0; p < SEG_J; ++p) colj[p] = ((i0 + s0 + 1 + p * EPS + lane / DW) % n) * DW + part;
+
+    auto stage = [&](int buf, int64_t k0) {
+#pragma unroll
+        for (int kk = wave; kk < KS; kk += 4) {
+            const int64_t row = k0 + kk;
+            uint32_t* di = reinterpret_cast<uint32_t*>(&L.wi[buf][kk][0]);
+            uint32_t* dj = reinterpret_cast<uint32_t*>(&L.wj[buf][kk][0]);
+            if (row < kc) {
+                const uint32_t* src = reinterpret_cast<const uint32_t*>(E + row * n);
+#pragma unroll
+                for (int p = 0; p < SEG_I; ++p)
+                    __builtin_amdgcn_global_load_lds(src + coli[p], di + p * 64, 4, 0, 0);
+#pragma unroll
+                for (int p = 0; p < SEG_J; ++p)
+                    __builtin_amdgcn_global_load_lds(src + colj[p], dj + p * 64, 4, 0, 0);
+            } else {
+#pragma unroll
+                for (int p = 0; p < SEG_I; ++p) di[p * 64 + lane] = 0u;
+#pragma unroll
+                for (int p = 0; p < SEG_J; ++p) dj[p * 64 + lane] = 0u;
+            }
+        }
+        if (!W && tid < KS) L.wl[buf][tid] = (k0 + tid < kc) ? lenk[k0 + tid] : T(0);
+    };
 
     T r[8][8];
 #pragma unroll
@@ -175,34 +263,27 @@ __global__ __launch_bounds__(256, 2) void k_band(const T* __restrict__ E,
         }
     }
 
-    for (int64_t k0 = 0; k0 < kc; k0 += KS) {
-        __syncthreads();
-        for (int x = tid; x < KS * I; x += 256) {
-            const int kk = x / I, w = x % I;
-            const int64_t col = (i0 + w) % n;
-            wi[kk][w] = (k0 + kk < kc) ? E[(k0 + kk) * n + col] : T(0);
-        }
-        for (int x = tid; x < KS * WJ; x += 256) {
-            const int kk = x / WJ, w = x % WJ;
-            const int64_t col = (i0 + s0 + 1 + w) % n;
-            wj[kk][w] = (k0 + kk < kc) ? E[(k0 + kk) * n + col] : T(0);
-        }
-        if (!W && tid < KS) wl[tid] = (k0 + tid < kc) ? lenk[k0 + tid] : T(0);
-        __syncthreads();
+    const int64_t nblk = (kc + KS - 1) / KS;
+    stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        const int cur = int(blk & 1);
+        if (blk + 1 < nblk) stage(cur ^ 1, (blk + 1) * KS);
 #pragma unroll 2
         for (int kk = 0; kk < KS; ++kk) {
             T xi[8], xj[16];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) xi[a] = wi[kk][ti * 8 + a];
+            for (int a = 0; a < 8; ++a) xi[a] = L.wi[cur][kk][ti * 8 + a];
 #pragma unroll
-            for (int c = 0; c < 15; ++c) xj[c] = wj[kk][ti * 8 + ts * 8 + c];
+            for (int c = 0; c < 15; ++c) xj[c] = L.wj[cur][kk][ti * 8 + ts * 8 + c];
             if (W) {
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
 #pragma unroll
                     for (int b = 0; b < 8; ++b) r[a][b] += fabs(xi[a] - xj[a + b]);
             } else {
-                const T l = wl[kk];
+                const T l = L.wl[cur][kk];
 #pragma unroll
                 for (int a = 0; a < 8; ++a) {
                     const T li = l * xi[a];
@@ -211,6 +292,8 @@ __global__ __launch_bounds__(256, 2) void k_band(const T* __restrict__ E,
                 }
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
 
 #pragma unroll
@@ -223,6 +306,20 @@ __global__ __launch_bounds__(256, 2) void k_band(const T* __restrict__ E,
             if (i < n) acc[(s - sb) * n + i] = r[a][b];
         }
     }
+}
+
+template <typename T, bool W>
+__global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
+                                              const T* __restrict__ lenk, int64_t kc,
+                                              int64_t n, int64_t sb, int64_t se, int64_t n_iblk,
+                                              int first, T* __restrict__ acc) {
+    constexpr int KS = BandCfg<T>::KS;
+    __shared__ __attribute__((aligned(16))) BandLds<T, KS> L;
+    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
+    const int64_t i0 = (tile % n_iblk) * kBandI;
+    const int64_t s0 = sb + (tile / n_iblk) * kBandS;
+    band_tile<T, W, KS>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
 }
 
 // ----------------------------------------------------------------------------
@@ -456,6 +553,87 @@ __global__ __launch_bounds__(256) void k_grand_mean(const double* __restrict__ r
     if (threadIdx.x == 0) out[0] = red[0] / double(n);
 }
 
+// ----------------------------------------------------------------------------
+// Batches: many tables on one tree.
+// ----------------------------------------------------------------------------
+// Node-major chunk of every table; global sample g belongs to table tab_of[g].
+__global__ __launch_bounds__(256) void k_embed_batch_f32(
+    int64_t n_all, int64_t k0, int64_t kc, const BatchTable* __restrict__ tabs,
+    const int32_t* __restrict__ tab_of, const int64_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
+    const double* __restrict__ total, const int32_t* __restrict__ lo,
+    const int32_t* __restrict__ hi, const double* __restrict__ len, float* __restrict__ out) {
+    constexpr int TK = 256, TS = 64;
+    __shared__ float tile[TK][TS + 1];
+    const int tid = threadIdx.x;
+    const int64_t kb = int64_t(blockIdx.x) * TK;
+    const int64_t gb = int64_t(blockIdx.y) * TS;
+    const int64_t k = kb + tid;
+    const bool kin = k < kc;
+    int32_t lk = 0, hk = 0;
+    double lv = 0.0;
+    if (kin) {
+        lk = lo[k0 + k];
+        hk = hi[k0 + k];
+        lv = len[k0 + k];
+    }
+    for (int j = 0; j < TS; ++j) {
+        const int64_t g = gb + j;
+        float v = 0.0f;
+        if (kin && g < n_all) {
+            const int64_t c = embedded_count(row_ptr, rank, cum, g, lk, hk);
+            v = float(lv * (double(c) / total[g]));
+        }
+        tile[tid][j] = v;
+    }
+    __syncthreads();
+    for (int r = tid / TS; r < TK; r += 256 / TS) {
+        const int64_t kk = kb + r;
+        const int64_t g = gb + (tid % TS);
+        if (kk < kc && g < n_all) {
+            const BatchTable t = tabs[tab_of[g]];
+            out[t.e_off + kk * t.n + (g - t.off)] = tile[r][tid % TS];
+        }
+    }
+}
+
+// Persistent band kernel: the grid stays resident and pulls (table, tile)
+// items from per-XCD queues (block b runs on XCD b mod 8 and drains queue
+// b mod 8 first, then steals from the others).  Every queue is finite, so
+// every block exits once all queues are exhausted.
+template <int KS>
+__global__ __launch_bounds__(256) void k_band_persistent_f32(
+    const float* __restrict__ E, const BatchTable* __restrict__ tabs,
+    const int2* __restrict__ items, const int64_t* __restrict__ qbeg,
+    const int64_t* __restrict__ qend, unsigned* __restrict__ counters, int64_t kc, int first,
+    float* __restrict__ acc) {
+    __shared__ __attribute__((aligned(16))) BandLds<float, KS> L;
+    __shared__ int64_t next_item;
+    const int xcd = int(blockIdx.x & 7);
+    for (int q = 0; q < 8; ++q) {
+        const int queue = (xcd + q) & 7;
+        const int64_t end = qend[queue];
+        for (;;) {
+            if (threadIdx.x == 0) next_item = qbeg[queue] + int64_t(atomicAdd(&counters[queue], 1u));
+            __syncthreads();
+            const int64_t item = next_item;
+            __syncthreads();
+            if (item >= end) break;
+            const int2 it = items[item];
+            const BatchTable t = tabs[it.x];
+            const int64_t i0 = (int64_t(it.y) % t.n_iblk) * kBandI;
+            const int64_t s0 = (int64_t(it.y) / t.n_iblk) * kBandS;
+            band_tile<float, true, KS>(L, E + t.e_off, nullptr, kc, t.n, 0, t.n / 2, i0, s0,
+                                       first, acc + t.acc_off);
+        }
+    }
+}
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 inline unsigned grid_y(int64_t v) { return unsigned(v < 65535 ? (v < 1 ? 1 : v) : 65535); }
 
 }  // namespace
@@ -477,8 +655,11 @@ template <typename T>
 static hipError_t embed_nm(const uf_embedding& e, int64_t k0, int64_t kc, int weighted, T* out,
                            hipStream_t st) {
     if (kc <= 0 || e.n <= 0) return hipSuccess;
-    dim3 grid(unsigned(kc), unsigned((e.n + 255) / 256));
-    hipLaunchKernelGGL(k_embed_nm<T>, grid, dim3(256), 0, st, e.n, k0, weighted, e.row_ptr,
+    constexpr int TS = 256 / int(sizeof(T));
+    const int64_t gy = (e.n + TS - 1) / TS;
+    if (gy > 65535) return hipErrorInvalidValue;
+    dim3 grid(unsigned((kc + 255) / 256), unsigned(gy));
+    hipLaunchKernelGGL(k_embed_nm<T>, grid, dim3(256), 0, st, e.n, k0, kc, weighted, e.row_ptr,
                        e.rank, e.cum, e.total, e.lo, e.hi, e.len, out);
     return hipGetLastError();
 }
@@ -518,15 +699,16 @@ template <typename T>
 static hipError_t band(const T* E, const T* lenk, int64_t kc, int64_t n, int64_t sb, int64_t se,
                        int weighted, int first, T* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
-    const int64_t by = (se - sb + kBandS - 1) / kBandS;
-    if (by > 65535) return hipErrorInvalidValue;
-    dim3 grid(unsigned((n + kBandI - 1) / kBandI), unsigned(by));
+    const int64_t n_iblk = (n + kBandI - 1) / kBandI;
+    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(n_tiles), 1u, 1u};
     if (weighted)
         hipLaunchKernelGGL((k_band<T, true>), grid, dim3(256), 0, st, E, lenk, kc, n, sb, se,
-                           first, acc);
+                           n_iblk, first, acc);
     else
         hipLaunchKernelGGL((k_band<T, false>), grid, dim3(256), 0, st, E, lenk, kc, n, sb, se,
-                           first, acc);
+                           n_iblk, first, acc);
     return hipGetLastError();
 }
 
@@ -581,6 +763,49 @@ hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* 
 
 hipError_t grand_mean(const double* row_means, int64_t n, double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_grand_mean, dim3(1), dim3(256), 0, st, row_means, n, out);
+    return hipGetLastError();
+}
+
+hipError_t embed_batch_f32(const uf_embedding& e, const BatchTable* tabs, const int32_t* tab_of,
+                           int64_t k0, int64_t kc, float* out, hipStream_t st) {
+    if (kc <= 0 || e.n <= 0) return hipSuccess;
+    const int64_t gy = (e.n + 63) / 64;
+    if (gy > 65535) {
+        return hipErrorInvalidValue;
+    }
+    dim3 grid(unsigned((kc + 255) / 256), unsigned(gy));
+    hipLaunchKernelGGL(k_embed_batch_f32, grid, dim3(256), 0, st, e.n, k0, kc, tabs, tab_of,
+                       e.row_ptr, e.rank, e.cum, e.total, e.lo, e.hi, e.len, out);
+    return hipGetLastError();
+}
+
+hipError_t band_persistent_f32(const float* E, const BatchTable* tabs, const int2* items,
+                               const int64_t* qbeg, const int64_t* qend, unsigned* counters,
+                               int64_t kc, int first, float* acc, int stage_branches,
+                               int n_blocks, hipStream_t st) {
+    const dim3 grid{unsigned(n_blocks), 1u, 1u};
+    switch (stage_branches) {
+        case 8:
+            hipLaunchKernelGGL(k_band_persistent_f32<8>, grid, dim3(256), 0, st, E, tabs, items,
+                               qbeg, qend, counters, kc, first, acc);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_band_persistent_f32<16>, grid, dim3(256), 0, st, E, tabs, items,
+                               qbeg, qend, counters, kc, first, acc);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_band_persistent_f32<32>, grid, dim3(256), 0, st, E, tabs, items,
+                               qbeg, qend, counters, kc, first, acc);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -260,16 +260,28 @@ def config(name: str, n_samples: Optional[int] = None, n_tips: Optional[int] = N
     return tree, table
 
 
+def _one_batch_table(args):
+    n, n_tips, nnz, depth, tseed = args
+    t = gen_table_zipf(int(n), np.arange(n_tips, dtype=np.int64), min(nnz, n_tips), tseed)
+    return rarefy(t, depth, tseed)
+
+
 def batch_tables(n_tips: int = 100000, n_tables: int = 64, n_min: int = 2000,
                  n_max: int = 20000, nnz: int = 1000, depth: int = 5000,
-                 seed: int = 104):
-    """Tree + ``n_tables`` rarefied tables of uneven size (the batching workload)."""
+                 seed: int = 104, processes: int = 1):
+    """Tree + ``n_tables`` rarefied tables of uneven size (the batching workload).
+
+    Table r uses its own seed, so the result does not depend on ``processes``
+    (worker processes are forked; call this before any GPU is initialised).
+    """
     tree = gen_tree(n_tips, CONFIGS["C4"]["mean_len"], seed)
     rng = _rng(seed, 5)
     sizes = rng.integers(n_min, n_max + 1, size=n_tables)
-    tip_ids = np.arange(n_tips, dtype=np.int64)
-    tables = []
-    for r, n in enumerate(sizes):
-        t = gen_table_zipf(int(n), tip_ids, min(nnz, n_tips), seed * 1000 + r)
-        tables.append(rarefy(t, depth, seed * 1000 + r))
+    jobs = [(int(n), n_tips, nnz, depth, seed * 1000 + r) for r, n in enumerate(sizes)]
+    if processes > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(processes) as pool:
+            tables = pool.map(_one_batch_table, jobs, chunksize=1)
+    else:
+        tables = [_one_batch_table(j) for j in jobs]
     return tree, tables
