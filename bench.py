@@ -187,12 +187,41 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_placement(args) -> int:
+    """Learned placement: train the encoder on a 25,000-sample reference table
+    (exact weighted-normalized targets), place 10,000 new samples."""
+    import numpy as np
+    import synth
+    c = synth.CONFIGS["C5"]
+    log("generating reference and query tables")
+    tree, ref = synth.config("C2", n_samples=c["n_ref"])
+    query = synth.gen_table_zipf(c["n_query"], np.arange(tree.n_tips), c["nnz"], c["query_seed"])
+    import torch
+    from paper_2107_05397_amd import placement
+    torch.cuda.set_device(0)
+    res = placement.experiment(tree, ref, query, epochs=args.epochs, log=log)
+    rec = {
+        "metric": "placement queries/s (1 GPU) with recall@10 against exact UniFrac",
+        "value": c["n_query"] / res["placement_s"], "unit": "queries/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": res["placement_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"C5: {res['n_ref']} reference + {res['n_query']} query samples "
+                               f"on the {tree.n_nodes}-node tree; encoder {res['dims']}",
+                   "parallelism": "single-gpu"},
+        "extra": res,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4"])
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--epochs", type=int, default=5, help="C5: training epochs")
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
     ap.add_argument("--tune-cache", default=None, help="C4: autotuner cache path")
     ap.add_argument("--samples", type=int, default=None, help="override the sample count")
@@ -215,6 +244,8 @@ def main() -> int:
 
     if args.workload == "C4":
         return bench_batch(args)
+    if args.workload == "C5":
+        return bench_placement(args)
 
     import numpy as np
     import torch

@@ -206,6 +206,94 @@ uf_status uf_autotune(uf_batch* batch, void* ws, size_t ws_bytes, const char* tu
                       void* hip_stream, double* best_ms);
 void uf_free_batch(uf_batch* batch);
 
+/* ---- learned placement -------------------------------------------------------- */
+
+/* Placing new samples against an existing reference set (the paper's
+ * introduction: data reuse places new sample collections into the context of
+ * existing data).  A sample's embedded proportions are projected, an MLP maps
+ * them to a space whose Euclidean distances approximate weighted-normalized
+ * UniFrac, the nearest references there are candidates, and the exact
+ * distance re-ranks them.
+ *
+ * uf_project: x = scale * R (l * u) with R[d, v] = signs[v][j] / 2 at d = dims[v][j],
+ * j < per_node (scale > 0 sets the input scale of the network); dims/signs are HOST arrays indexed by node id
+ * ([n_nodes][per_node]; the root's row is ignored).  out_bf16: device
+ * [N][out_dim] bfloat16.  Sums are exact fixed point (2^-40), so the result
+ * is deterministic.  Synchronises hip_stream. */
+uf_status uf_project(const uf_tree* tree, const uf_embedding* emb, const int32_t* dims,
+                     const int8_t* signs, int64_t per_node, int64_t out_dim, double scale,
+                     void* out_bf16, void* hip_stream);
+
+/* A multilayer perceptron d0 -> d1 -> ... -> dL (ReLU between layers, none
+ * after the last): BF16 weights and activations on MFMA with FP32
+ * accumulation, FP32 master weights, biases and Adam moments.  Widths must be
+ * multiples of 32; max_rows bounds the rows of one forward pass (2 x pairs
+ * for training).  skip != 0 adds a trainable linear path: z = MLP(x) + S x
+ * with S [dL][d0] (layer index n_layers in uf_mlp_set / uf_mlp_get).
+ * Parameters start at zero; set them with uf_mlp_set. */
+typedef struct uf_mlp uf_mlp;
+uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows, int skip,
+                        uf_mlp** out);
+/* Host FP32 weights [d_{l+1}][d_l] and bias [d_{l+1}] of one layer (either
+ * may be NULL; for the linear path only w).  Synchronous. */
+uf_status uf_mlp_set(uf_mlp* mlp, int64_t layer, const float* w, const float* b);
+/* Copy out one layer: what 0 = parameters, 1 = gradients, 2 = Adam first
+ * moments, 3 = second moments.  Synchronous. */
+uf_status uf_mlp_get(const uf_mlp* mlp, int64_t layer, int what, float* w, float* b);
+/* z[i] = MLP(x[rows ? rows[i] : i]) for i < n; x: device BF16 rows of stride
+ * ldx (>= d0, multiple of 8); z: device FP32 [n][dL]. */
+uf_status uf_mlp_forward(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const int32_t* rows,
+                         int64_t n, float* z, void* hip_stream);
+/* Loss mean_p (w_p (||z_a - z_b||_2 - target_p))^2 over n_pairs pairs
+ * (device index arrays into x), written to loss (device, 1 float); w_p = 1,
+ * or 1 / max(target_p, rel_floor) when rel_floor > 0 (relative error, which
+ * weights the near pairs a nearest-neighbour search depends on).  The
+ * gradients of every weight and bias are left in the MLP for uf_mlp_adam /
+ * uf_mlp_get. */
+uf_status uf_mlp_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const int32_t* pair_a,
+                           const int32_t* pair_b, const float* target, int64_t n_pairs,
+                           float rel_floor, float* loss, void* hip_stream);
+/* One Adam step (bias-corrected, step >= 1) on every parameter, with
+ * decoupled weight decay on the weight matrices (weight_decay = 0: plain
+ * Adam). */
+uf_status uf_mlp_adam(uf_mlp* mlp, float lr, float beta1, float beta2, float eps,
+                      float weight_decay, int64_t step, void* hip_stream);
+void uf_free_mlp(uf_mlp* mlp);
+
+/* out[i][j] = ||a_i - b_j||^2 (FP32, device [na][dim], [nb][dim] -> [na][nb]). */
+uf_status uf_sqdist(const float* a, int64_t na, const float* b, int64_t nb, int64_t dim,
+                    float* out, void* hip_stream);
+/* The k smallest entries of each row of a non-negative FP32 matrix, sorted,
+ * ties to the smaller column (exact radix select); 1 <= k <= 128 <= ... cols.
+ * idx: device [rows][k]; vals (nullable): device [rows][k]. */
+uf_status uf_topk_rows(const float* values, int64_t rows, int64_t cols, int64_t k, int32_t* idx,
+                       float* vals, void* hip_stream);
+/* Read a condensed matrix of n samples (dtype F64/F32): a dense FP32 block
+ * out[r][c] = d(row_off + r, col_off + c) (+inf on the diagonal), or the
+ * entries d(a_p, b_p) of a pair list (0 where a_p = b_p). */
+uf_status uf_condensed_block(const void* cond, uf_out_dtype dtype, int64_t n, int64_t row_off,
+                             int64_t n_rows, int64_t col_off, int64_t n_cols, float* out,
+                             void* hip_stream);
+uf_status uf_gather_pairs(const void* cond, uf_out_dtype dtype, int64_t n, const int32_t* a,
+                          const int32_t* b, int64_t count, float* out, void* hip_stream);
+
+/* Per-sample lists of the branches a sample touches, with l_v u_sv in FP64
+ * (library-owned device memory).  Synchronises hip_stream. */
+typedef struct uf_sparse uf_sparse;
+uf_status uf_sparse_build(const uf_embedding* emb, void* hip_stream, uf_sparse** out);
+int64_t uf_sparse_nnz(const uf_sparse* sparse);
+void uf_free_sparse(uf_sparse* sparse);
+/* Exact weighted-normalized distances across two tables on the same tree:
+ * out[i][c] = d(queries[query_ids[i]], refs[cand[i][c]]) in FP64, for
+ * i < n_queries, c < k (device arrays).  Uses sum|x-y| = s_x + s_y -
+ * 2 sum min(x, y), the min being nonzero only where both samples touch a
+ * branch.  ws: device workspace of uf_rerank_workspace_size bytes. */
+uf_status uf_rerank_workspace_size(const uf_sparse* queries, int64_t n_queries, size_t* bytes);
+uf_status uf_dm_rerank_weighted_normalized(const uf_sparse* queries, const uf_sparse* refs,
+                                           const int32_t* query_ids, const int32_t* cand,
+                                           int64_t n_queries, int64_t k, double* out, void* ws,
+                                           size_t ws_bytes, void* hip_stream);
+
 /* ---- kernel timing --------------------------------------------------------- */
 
 /* Per-kernel timing with HIP events recorded on the call's stream around each

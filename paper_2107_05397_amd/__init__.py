@@ -27,7 +27,8 @@ __all__ = [
     "UFError", "lib", "Tree", "Table", "Embedding", "workspace_size", "dm", "dm_unweighted",
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
-    "profile_read", "Batch",
+    "profile_read", "Batch", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
+    "gather_pairs", "Sparse", "rerank",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -91,6 +92,26 @@ _SIGS = {
                                     _vp]),
     "uf_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_char_p, _vp, _f64p]),
     "uf_free_batch": (None, [_vp]),
+    "uf_project": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
+    "uf_mlp_create": (ctypes.c_int, [_i64, _i64p, _i64, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "uf_mlp_set": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+    "uf_mlp_get": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp]),
+    "uf_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "uf_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, ctypes.c_float, _vp,
+                                        _vp]),
+    "uf_mlp_adam": (ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, _i64, _vp]),
+    "uf_free_mlp": (None, [_vp]),
+    "uf_sqdist": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i64, _vp, _vp]),
+    "uf_topk_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp, _vp]),
+    "uf_condensed_block": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _i64, _i64, _vp, _vp]),
+    "uf_gather_pairs": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _vp, _vp, _i64, _vp, _vp]),
+    "uf_sparse_build": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(_vp)]),
+    "uf_sparse_nnz": (_i64, [_vp]),
+    "uf_free_sparse": (None, [_vp]),
+    "uf_rerank_workspace_size": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_dm_rerank_weighted_normalized": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp,
+                                                        ctypes.c_size_t, _vp]),
     "uf_profile_enable": (None, [ctypes.c_int]),
     "uf_profile_reset": (None, []),
     "uf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _f64p, _i64p]),
@@ -417,3 +438,164 @@ class Batch(_Handle):
                                  tune_cache.encode() if tune_cache else None,
                                  _stream_ptr(stream), ctypes.byref(ms)))
         return float(ms.value)
+
+
+# ---------------------------------------------------------------------------
+# learned placement
+# ---------------------------------------------------------------------------
+def project(tree: Tree, emb: Embedding, dims, signs, out_dim: int = 4096, scale: float = 1.0,
+            out=None, stream=None):
+    """Sparse random projection of l*u: device bfloat16 [N][out_dim]."""
+    import torch
+    d = _as(dims, np.int32)
+    sg = _as(signs, np.int8)
+    if d.ndim != 2 or d.shape != sg.shape or d.shape[0] != tree.n_nodes:
+        raise UFError(1, "dims/signs must be [n_nodes, per_node]")
+    n = emb.n_samples
+    if out is None:
+        out = torch.empty((max(n, 1), out_dim), dtype=torch.bfloat16, device="cuda")
+    _check(lib().uf_project(tree.handle, emb.handle, d.ctypes.data_as(_vp), sg.ctypes.data_as(_vp),
+                            d.shape[1], out_dim, float(scale), _tptr(out), _stream_ptr(stream)))
+    return out[:n]
+
+
+class MLP(_Handle):
+    """d0 -> ... -> dL perceptron trained by the library's BF16 MFMA kernels."""
+    _free = "uf_free_mlp"
+
+    def __init__(self, dims, max_rows: int, params=None, skip=None):
+        """params: [(W, b)] per layer; skip: None, or the initial S [dL][d0] of a
+        trainable linear path z = MLP(x) + S x."""
+        super().__init__()
+        self.dims = [int(x) for x in dims]
+        self.max_rows = int(max_rows)
+        self.has_skip = skip is not None
+        arr = np.asarray(self.dims, dtype=np.int64)
+        _check(lib().uf_mlp_create(len(self.dims) - 1, _ptr(arr, ctypes.c_int64), self.max_rows,
+                                   1 if self.has_skip else 0, ctypes.byref(self._h)))
+        if params is not None:
+            for l, (w, b) in enumerate(params):
+                self.set(l, w, b)
+        if self.has_skip:
+            self.set(self.n_layers, skip)
+
+    @property
+    def n_layers(self) -> int:
+        return len(self.dims) - 1
+
+    def set(self, layer: int, w=None, b=None):
+        wa = _as(w, np.float32) if w is not None else None
+        ba = _as(b, np.float32) if b is not None else None
+        _check(lib().uf_mlp_set(self._h, layer, wa.ctypes.data_as(_vp) if wa is not None else None,
+                                ba.ctypes.data_as(_vp) if ba is not None else None))
+
+    def get(self, layer: int, what: str = "params"):
+        """(w, b) of a layer; layer == n_layers is the linear path (b is None)."""
+        sel = {"params": 0, "grads": 1, "adam_m": 2, "adam_v": 3}[what]
+        if layer == self.n_layers:
+            w = np.zeros((self.dims[-1], self.dims[0]), dtype=np.float32)
+            _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), None))
+            return w, None
+        w = np.zeros((self.dims[layer + 1], self.dims[layer]), dtype=np.float32)
+        b = np.zeros(self.dims[layer + 1], dtype=np.float32)
+        _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), b.ctypes.data_as(_vp)))
+        return w, b
+
+    def forward(self, x, rows=None, out=None, stream=None):
+        import torch
+        n = int(rows.numel()) if rows is not None else int(x.shape[0])
+        if out is None:
+            out = torch.empty((max(n, 1), self.dims[-1]), dtype=torch.float32, device="cuda")
+        _check(lib().uf_mlp_forward(self._h, _tptr(x), x.stride(0), _tptr(rows), n, _tptr(out),
+                                    _stream_ptr(stream)))
+        return out[:n]
+
+    def loss_grad(self, x, pair_a, pair_b, target, loss=None, rel_floor: float = 0.0, stream=None):
+        import torch
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().uf_mlp_loss_grad(self._h, _tptr(x), x.stride(0), _tptr(pair_a), _tptr(pair_b),
+                                      _tptr(target), int(pair_a.numel()), float(rel_floor),
+                                      _tptr(loss), _stream_ptr(stream)))
+        return loss
+
+    def adam(self, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, weight_decay: float = 0.0, stream=None):
+        _check(lib().uf_mlp_adam(self._h, lr, beta1, beta2, eps, weight_decay, int(step),
+                                 _stream_ptr(stream)))
+
+
+def sqdist(a, b, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((a.shape[0], b.shape[0]), dtype=torch.float32, device="cuda")
+    _check(lib().uf_sqdist(_tptr(a), a.shape[0], _tptr(b), b.shape[0], a.shape[1], _tptr(out),
+                           _stream_ptr(stream)))
+    return out
+
+
+def topk_rows(values, k: int, stream=None):
+    """(idx int32 [rows][k], vals FP32 [rows][k]): the k smallest per row, sorted."""
+    import torch
+    rows, cols = values.shape
+    idx = torch.empty((max(rows, 1), k), dtype=torch.int32, device="cuda")
+    vals = torch.empty((max(rows, 1), k), dtype=torch.float32, device="cuda")
+    _check(lib().uf_topk_rows(_tptr(values), rows, cols, k, _tptr(idx), _tptr(vals),
+                              _stream_ptr(stream)))
+    return idx[:rows], vals[:rows]
+
+
+def _cond_dtype(cond):
+    import torch
+    if cond.dtype == torch.float64:
+        return 0
+    if cond.dtype == torch.float32:
+        return 1
+    raise UFError(1, "condensed matrix must be float32 or float64")
+
+
+def condensed_block(cond, n: int, row_off: int, n_rows: int, col_off: int, n_cols: int,
+                    stream=None):
+    import torch
+    out = torch.empty((max(n_rows, 1), max(n_cols, 1)), dtype=torch.float32, device="cuda")
+    _check(lib().uf_condensed_block(_tptr(cond), _cond_dtype(cond), n, row_off, n_rows, col_off,
+                                    n_cols, _tptr(out), _stream_ptr(stream)))
+    return out[:n_rows, :n_cols]
+
+
+def gather_pairs(cond, n: int, a, b, stream=None):
+    import torch
+    out = torch.empty(max(int(a.numel()), 1), dtype=torch.float32, device="cuda")
+    _check(lib().uf_gather_pairs(_tptr(cond), _cond_dtype(cond), n, _tptr(a), _tptr(b),
+                                 int(a.numel()), _tptr(out), _stream_ptr(stream)))
+    return out[: int(a.numel())]
+
+
+class Sparse(_Handle):
+    """Per-sample lists of touched branches (l*u in FP64), for exact re-ranking."""
+    _free = "uf_free_sparse"
+
+    def __init__(self, emb: Embedding, stream=None):
+        super().__init__()
+        self.emb = emb
+        _check(lib().uf_sparse_build(emb.handle, _stream_ptr(stream), ctypes.byref(self._h)))
+
+    @property
+    def nnz(self) -> int:
+        return int(lib().uf_sparse_nnz(self._h))
+
+
+def rerank(queries: Sparse, refs: Sparse, query_ids, cand, out=None, workspace=None, stream=None):
+    """Exact weighted-normalized d(queries[query_ids[i]], refs[cand[i][c]]): FP64 [nq][k]."""
+    import torch
+    nq, k = int(cand.shape[0]), int(cand.shape[1])
+    if out is None:
+        out = torch.empty((max(nq, 1), k), dtype=torch.float64, device="cuda")
+    need = ctypes.c_size_t(0)
+    _check(lib().uf_rerank_workspace_size(queries.handle, nq, ctypes.byref(need)))
+    ws = _workspace(int(need.value), workspace)
+    _check(lib().uf_dm_rerank_weighted_normalized(queries.handle, refs.handle, _tptr(query_ids),
+                                                  _tptr(cand), nq, k, _tptr(out),
+                                                  _tptr(ws), ws.numel() * ws.element_size(),
+                                                  _stream_ptr(stream)))
+    return out[:nq]

@@ -303,6 +303,12 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
 
 }  // namespace
 
+namespace ufh {
+uf_status fail(uf_status st, const std::string& msg) { return ::fail(st, msg); }
+uf_status hip_fail(hipError_t e, const char* what) { return ::hip_fail(e, what); }
+uf_status check_device(int* dev_out) { return ::check_device(dev_out); }
+}  // namespace ufh
+
 // =========================================================================
 // C ABI
 // =========================================================================
@@ -614,6 +620,8 @@ uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embe
         e->wub = reinterpret_cast<double*>(b + o_wub);
         int32_t* ppos = reinterpret_cast<int32_t*>(b + o_ppos);
         int32_t* tpos = reinterpret_cast<int32_t*>(b + o_tpos);
+        e->parent_pos = ppos;
+        e->tip_pos = tpos;
         double* dd64 = reinterpret_cast<double*>(b + o_d64);
         double* dd32 = reinterpret_cast<double*>(b + o_d32);
         double* ddbf = reinterpret_cast<double*>(b + o_dbf);

@@ -64,8 +64,18 @@ struct uf_embedding {
     double* wu = nullptr;         // sum_v l_v a_sv, FP64 lengths
     double* wu32 = nullptr;       // same with FP32-rounded lengths
     double* wub = nullptr;        // same with hi+lo bf16 lengths
+    int32_t* parent_pos = nullptr;  // [nb+1], -1 for the root
+    int32_t* tip_pos = nullptr;     // [n_tips] position of the tip with rank r
     void* arena = nullptr;        // one allocation holding all of the above
 };
+
+// Shared host helpers (uf_host.hip): record a thread-local error message and
+// return the status; check that a gfx950 device is current.
+namespace ufh {
+uf_status fail(uf_status st, const std::string& msg);
+uf_status hip_fail(hipError_t e, const char* what);
+uf_status check_device(int* dev_out);
+}  // namespace ufh
 
 // One table of a batch, as the batched kernels see it.
 struct BatchTable {

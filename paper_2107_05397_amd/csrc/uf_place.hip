@@ -1,0 +1,711 @@
+// HIP kernels of the learned placement encoder (gfx950):
+//
+//   k_project          sparse random projection of l*u (fixed-point LDS sums)
+//   k_gemm_bf16<..>    BF16 MFMA GEMM, FP32 accumulate, three operand layouts
+//                      (forward X W^T, backward-data dY W, weight-grad dY^T X)
+//                      with fused bias / ReLU / ReLU-mask epilogues
+//   k_colsum_*         bias gradients (fixed-order FP64 column sums)
+//   k_pairloss         (||z_a - z_b|| - d)^2 and its gradient
+//   k_adam             Adam on FP32 master weights + BF16 copy
+//   k_sqdist           FP32 pairwise squared distances (kNN)
+//   k_topk_rows        exact k smallest per row (radix select, ties by index)
+//   k_sparse_*         per-sample lists of (branch, l*u) for nonzero branches
+//   k_rerank           exact weighted-normalized distance across two tables
+//   k_condensed_block, k_gather_pairs   reads of a condensed matrix
+#include <hip/hip_runtime.h>
+
+#include "uf_internal.h"
+#include "uf_place.h"
+
+namespace ufp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);     // round to nearest even (finite inputs)
+    return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ int64_t lower_bound_rank(const int32_t* __restrict__ rank, int64_t a,
+                                                    int64_t b, int32_t key) {
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (rank[mid] < key) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+// count of sample s on the branch covering tip ranks [lo, hi)
+__device__ __forceinline__ int64_t count_in(const int64_t* __restrict__ row_ptr,
+                                            const int32_t* __restrict__ rank,
+                                            const int64_t* __restrict__ cum, int64_t s, int32_t lo,
+                                            int32_t hi) {
+    const int64_t a = row_ptr[s], b = row_ptr[s + 1];
+    const int64_t p1 = lower_bound_rank(rank, a, b, lo);
+    const int64_t p2 = lower_bound_rank(rank, p1, b, hi);
+    return cum[p2 + s] - cum[p1 + s];
+}
+
+// ----------------------------------------------------------------------------
+// Nonzero branches of a sample, each exactly once: walking up from the tip of
+// entry e, a branch v is reported by e when the previous tip of the row
+// (rank[e-1]) lies outside v's subtree, i.e. lo_v > rank[e-1]; the walk stops
+// at the first ancestor that also covers the previous tip (reported already).
+// ----------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void for_each_branch_of_entry(const Emb& e, int64_t entry,
+                                                         int64_t row_start, F&& f) {
+    const int32_t r = e.rank[entry];
+    const int32_t prev = entry > row_start ? e.rank[entry - 1] : -1;
+    int32_t v = e.tip_pos[r];
+    while (v < e.root_pos && e.lo[v] > prev) {
+        f(v);
+        v = e.parent_pos[v];
+    }
+}
+
+// x[s] = sum_v l_v u_sv * sign/2 at dims: one block per sample, int64 fixed
+// point (2^-40) sums in LDS so the result does not depend on atomic order.
+__global__ __launch_bounds__(256) void k_project(Emb e, const int32_t* __restrict__ dims,
+                                                 const int8_t* __restrict__ signs, int per_node,
+                                                 int out_dim, double scale,
+                                                 uint16_t* __restrict__ out) {
+    extern __shared__ unsigned long long acc[];
+    const int64_t s = blockIdx.x;
+    for (int d = threadIdx.x; d < out_dim; d += 256) acc[d] = 0ull;
+    __syncthreads();
+    const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
+    const double inv_t = 1.0 / e.total[s];
+    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        for_each_branch_of_entry(e, ent, a, [&](int32_t v) {
+            const int64_t c = count_in(e.row_ptr, e.rank, e.cum, s, e.lo[v], e.hi[v]);
+            const double y = e.len[v] * (double(c) * inv_t) * 0.5 * scale;
+            const long long q = llrint(y * 1099511627776.0);   // 2^40
+            for (int j = 0; j < per_node; ++j) {
+                const long long sq = signs[int64_t(v) * per_node + j] > 0 ? q : -q;
+                atomicAdd(&acc[dims[int64_t(v) * per_node + j]], (unsigned long long)sq);
+            }
+        });
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < out_dim; d += 256) {
+        const double x = double((long long)acc[d]) * (1.0 / 1099511627776.0);
+        out[s * out_dim + d] = f2bf(float(x));
+    }
+}
+
+// ----------------------------------------------------------------------------
+// BF16 GEMM on MFMA: C[m][n] = sum_k A(m, k) B(n, k), FP32 accumulation.
+// Layout 0 (row): element (m, k) at P[src(m) * ld + k]   (k contiguous)
+// Layout 1 (col): element (m, k) at P[src(k) * ld + m]   (m contiguous)
+// src() applies the optional row-index array (a gather of source rows).
+// Tile 128x128, 4 waves (2x2, 64x64 each = 2x2 v_mfma_f32_32x32x16_bf16), K step
+// 32 staged in LDS as [row][k] (padded), transposing layout-1 sources.
+// ----------------------------------------------------------------------------
+template <int LAY>
+__device__ __forceinline__ void stage_operand(uint16_t* __restrict__ S,
+                                              const uint16_t* __restrict__ P, int64_t ld,
+                                              const int32_t* __restrict__ rows, int64_t r0,
+                                              int64_t R, int64_t k0, int64_t K) {
+    constexpr int LD = 40;
+    const int tid = threadIdx.x;
+    if (LAY == 0) {
+        const int r = tid >> 1, seg = (tid & 1) * 16;
+        const int64_t gr = r0 + r;
+        uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+        if (gr < R) {
+            const int64_t src = rows ? rows[gr] : gr;
+            const uint4* p = reinterpret_cast<const uint4*>(P + src * ld + k0 + seg);
+            v0 = p[0];
+            v1 = p[1];
+        }
+        uint4* d = reinterpret_cast<uint4*>(S + r * LD + seg);
+        d[0] = v0;
+        d[1] = v1;
+    } else {
+        const int kk = tid >> 3, seg = (tid & 7) * 16;
+        const int64_t gk = k0 + kk;
+        uint16_t v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = 0;
+        if (gk < K) {
+            const int64_t src = rows ? rows[gk] : gk;
+            const uint16_t* p = P + src * ld + r0 + seg;
+            if (r0 + seg + 16 <= R) {
+                const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+                const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+                const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    v[2 * e] = uint16_t(w[e] & 0xFFFFu);
+                    v[2 * e + 1] = uint16_t(w[e] >> 16);
+                }
+            } else {
+                for (int e = 0; e < 16; ++e)
+                    if (r0 + seg + e < R) v[e] = p[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) S[(seg + e) * LD + kk] = v[e];
+    }
+}
+
+template <int LA, int LB, int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16(
+    const uint16_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ arow,
+    const uint16_t* __restrict__ B, int64_t ldb, const int32_t* __restrict__ brow, int64_t M,
+    int64_t N, int64_t K, const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+    int64_t ldm, void* __restrict__ C, int64_t ldc) {
+    constexpr int T = 128, KT = 32, LD = 40;
+    __shared__ __attribute__((aligned(16))) uint16_t As[T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LD];
+    const int64_t m0 = int64_t(blockIdx.y) * T, n0 = int64_t(blockIdx.x) * T;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave & 1, wj = wave >> 1;
+    floatx16 c[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
+    for (int64_t k0 = 0; k0 < K; k0 += KT) {
+        __syncthreads();
+        stage_operand<LA>(As, A, lda, arow, m0, M, k0, K);
+        stage_operand<LB>(Bs, B, ldb, brow, n0, N, k0, K);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KT; kk += 16) {
+            const int kq = kk + 8 * (lane >> 5);
+            bf16x8 fa[2], fb[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+                fa[x] = *reinterpret_cast<const bf16x8*>(As + (wi * 64 + x * 32 + (lane & 31)) * LD + kq);
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+                fb[y] = *reinterpret_cast<const bf16x8*>(Bs + (wj * 64 + y * 32 + (lane & 31)) * LD + kq);
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[y], c[x][y], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = m0 + wi * 64 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t j = n0 + wj * 64 + y * 32 + (lane & 31);
+                if (i >= M || j >= N) continue;
+                const float v = c[x][y][r];
+                if (EPI == EPI_F32) {
+                    static_cast<float*>(C)[i * ldc + j] = v;
+                } else if (EPI == EPI_ACC_F32) {
+                    static_cast<float*>(C)[i * ldc + j] += v;
+                } else if (EPI == EPI_BIAS_RELU_BF16) {
+                    static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(fmaxf(v + bias[j], 0.0f));
+                } else if (EPI == EPI_BIAS_F32) {
+                    static_cast<float*>(C)[i * ldc + j] = v + bias[j];
+                } else if (EPI == EPI_MASK_BF16) {
+                    static_cast<uint16_t*>(C)[i * ldc + j] = mask[i * ldm + j] != 0 ? f2bf(v) : uint16_t(0);
+                } else {
+                    static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(v);
+                }
+            }
+}
+
+// column sums in FP64, rows in order (deterministic)
+__global__ __launch_bounds__(256) void k_colsum_f32(const float* __restrict__ X, int64_t rows,
+                                                    int64_t cols, float* __restrict__ out) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < rows; ++i) s += X[i * cols + j];
+    out[j] = float(s);
+}
+__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t* __restrict__ X, int64_t rows,
+                                                     int64_t cols, float* __restrict__ out) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < rows; ++i) s += bf2f(X[i * cols + j]);
+    out[j] = float(s);
+}
+
+// one wave per pair; Z rows [0, P) are the a-ends, [P, 2P) the b-ends
+// rel_floor > 0 selects the relative loss ((delta - d) / max(d, rel_floor))^2
+__global__ __launch_bounds__(256) void k_pairloss(const float* __restrict__ Z, int64_t P, int D,
+                                                  const float* __restrict__ target, float rel_floor,
+                                                  uint16_t* __restrict__ dZ,
+                                                  float* __restrict__ loss) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const float* za = Z + p * D;
+    const float* zb = Z + (P + p) * D;
+    float s = 0.0f;
+    for (int d = lane; d < D; d += 64) {
+        const float df = za[d] - zb[d];
+        s = fmaf(df, df, s);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const float delta = sqrtf(s);
+    const float w = rel_floor > 0.0f ? 1.0f / fmaxf(target[p], rel_floor) : 1.0f;
+    const float r = (delta - target[p]) * w;
+    const float coef = delta > 0.0f ? 2.0f * r * w / delta / float(P) : 0.0f;
+    for (int d = lane; d < D; d += 64) {
+        const float g = coef * (za[d] - zb[d]);
+        dZ[p * D + d] = f2bf(g);
+        dZ[(P + p) * D + d] = f2bf(-g);
+    }
+    if (lane == 0) loss[p] = r * r;
+}
+
+__global__ __launch_bounds__(256) void k_mean(const float* __restrict__ x, int64_t n,
+                                              float* __restrict__ out) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) a += x[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = float(red[0] / double(n > 0 ? n : 1));
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float bc1, float bc2, float wd,
+                                              uint16_t* __restrict__ pbf) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    // decoupled weight decay (AdamW): wd = 0 gives plain Adam
+    const float pi = p[i] - lr * ((mi / bc1) / (sqrtf(vi / bc2) + eps) + wd * p[i]);
+    p[i] = pi;
+    if (pbf) pbf[i] = f2bf(pi);
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ x, int64_t n,
+                                                     uint16_t* __restrict__ y) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// out[i][j] = sum_d (a_i[d] - b_j[d])^2 ; 64x64 tiles, 4x4 per thread
+__global__ __launch_bounds__(256) void k_sqdist(const float* __restrict__ A, int64_t na,
+                                                const float* __restrict__ B, int64_t nb, int64_t D,
+                                                float* __restrict__ out) {
+    __shared__ float as[32][65];
+    __shared__ float bs[32][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t i0 = int64_t(blockIdx.y) * 64, j0 = int64_t(blockIdx.x) * 64;
+    float acc[4][4] = {};
+    for (int64_t d0 = 0; d0 < D; d0 += 32) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < 64 * 32; t += 256) {
+            const int r = t / 32, dd = t % 32;
+            as[dd][r] = (i0 + r < na && d0 + dd < D) ? A[(i0 + r) * D + d0 + dd] : 0.0f;
+            bs[dd][r] = (j0 + r < nb && d0 + dd < D) ? B[(j0 + r) * D + d0 + dd] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int dd = 0; dd < 32; ++dd) {
+            float a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = as[dd][ty * 4 + u];
+                b[u] = bs[dd][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const float df = a[u] - b[w];
+                    acc[u][w] = fmaf(df, df, acc[u][w]);
+                }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int64_t i = i0 + ty * 4 + u, j = j0 + tx * 4 + w;
+            if (i < na && j < nb) out[i * nb + j] = acc[u][w];
+        }
+}
+
+// ----------------------------------------------------------------------------
+// k smallest of each row (values >= 0), ties by the smaller column: radix
+// select on the FP32 bit pattern (monotone for non-negative floats) in four
+// 8-bit passes, then collect below-threshold entries plus the first equal
+// ones in column order, then sort the k pairs (bits, column) in LDS.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_topk_rows(const float* __restrict__ vals, int64_t cols,
+                                                   int k, int32_t* __restrict__ idx_out,
+                                                   float* __restrict__ val_out) {
+    __shared__ unsigned hist[256];
+    __shared__ unsigned s_prefix, s_mask, s_remaining, s_nless, s_neq;
+    __shared__ unsigned cb[kTopkMax];
+    __shared__ int ci[kTopkMax];
+    __shared__ unsigned wave_cnt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float* v = vals + int64_t(blockIdx.x) * cols;
+    if (tid == 0) {
+        s_prefix = 0;
+        s_mask = 0;
+        s_remaining = unsigned(k);
+        s_nless = 0;
+        s_neq = 0;
+    }
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0;
+        __syncthreads();
+        const unsigned prefix = s_prefix, mask = s_mask;
+        for (int64_t c = tid; c < cols; c += 256) {
+            const unsigned bits = __float_as_uint(v[c]);
+            if ((bits & mask) == prefix) atomicAdd(&hist[(bits >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned cum = 0, rem = s_remaining;
+            int d = 0;
+            for (; d < 256; ++d) {
+                if (cum + hist[d] >= rem) break;
+                cum += hist[d];
+            }
+            s_remaining = rem - cum;
+            s_prefix = prefix | (unsigned(d) << shift);
+            s_mask = mask | (255u << shift);
+        }
+        __syncthreads();
+    }
+    const unsigned thr = s_prefix;
+    const unsigned take_eq = s_remaining;            // equal entries to keep
+    const unsigned n_less = unsigned(k) - take_eq;
+    // entries strictly below the threshold (any order; sorted below)
+    for (int64_t c = tid; c < cols; c += 256) {
+        const unsigned bits = __float_as_uint(v[c]);
+        if (bits < thr) {
+            const unsigned slot = atomicAdd(&s_nless, 1u);
+            cb[slot] = bits;
+            ci[slot] = int(c);
+        }
+    }
+    __syncthreads();
+    // equal entries: the first take_eq in column order
+    for (int64_t base = 0; base < cols; base += 256) {
+        if (s_neq >= take_eq) break;
+        const int64_t c = base + tid;
+        const bool eq = c < cols && __float_as_uint(v[c]) == thr;
+        const unsigned long long bal = __ballot(eq);
+        if (lane == 0) wave_cnt[wave] = unsigned(__popcll(bal));
+        __syncthreads();
+        unsigned before = s_neq;
+        for (int w = 0; w < wave; ++w) before += wave_cnt[w];
+        before += unsigned(__popcll(bal & ((1ull << lane) - 1ull)));
+        if (eq && before < take_eq) {
+            cb[n_less + before] = thr;
+            ci[n_less + before] = int(c);
+        }
+        __syncthreads();
+        if (tid == 0) s_neq += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+        __syncthreads();
+    }
+    // pad to kTopkMax and bitonic-sort (bits, column)
+    for (int t = tid; t < kTopkMax; t += 256)
+        if (t >= k) {
+            cb[t] = 0xFFFFFFFFu;
+            ci[t] = 0x7FFFFFFF;
+        }
+    __syncthreads();
+    for (int size = 2; size <= kTopkMax; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < kTopkMax; t += 256) {
+                const int partner = t ^ stride;
+                if (partner > t) {
+                    const bool up = (t & size) == 0;
+                    const bool gt = cb[t] > cb[partner] || (cb[t] == cb[partner] && ci[t] > ci[partner]);
+                    if (gt == up) {
+                        const unsigned tb = cb[t];
+                        cb[t] = cb[partner];
+                        cb[partner] = tb;
+                        const int tc = ci[t];
+                        ci[t] = ci[partner];
+                        ci[partner] = tc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = tid; t < k; t += 256) {
+        idx_out[int64_t(blockIdx.x) * k + t] = ci[t];
+        if (val_out) val_out[int64_t(blockIdx.x) * k + t] = __uint_as_float(cb[t]);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Sparse per-sample branch lists (position, l*u in FP64)
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sparse_count(Emb e, int64_t* __restrict__ cnt) {
+    const int64_t s = blockIdx.x;
+    const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
+    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        int64_t c = 0;
+        for_each_branch_of_entry(e, ent, a, [&](int32_t) { ++c; });
+        cnt[ent] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sparse_fill(Emb e, const int64_t* __restrict__ off,
+                                                     int32_t* __restrict__ pos,
+                                                     double* __restrict__ val) {
+    const int64_t s = blockIdx.x;
+    const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
+    const double inv_t = 1.0 / e.total[s];
+    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        int64_t o = off[ent];
+        for_each_branch_of_entry(e, ent, a, [&](int32_t v) {
+            const int64_t c = count_in(e.row_ptr, e.rank, e.cum, s, e.lo[v], e.hi[v]);
+            pos[o] = v;
+            val[o] = e.len[v] * (double(c) * inv_t);
+            ++o;
+        });
+    }
+}
+
+// Exact weighted-normalized distance of query q against each candidate r:
+// sum_v |x_q - x_r| = s_q + s_r - 2 sum_v min(x_q, x_r), where the min is
+// nonzero only on branches both samples touch.  The query is scattered into
+// a dense FP64 row (one per resident block, left zeroed afterwards); each
+// candidate's list gathers from it.  Persistent grid over queries.
+__global__ __launch_bounds__(256) void k_rerank(SparseView q, SparseView rf,
+                                                const int32_t* __restrict__ qids,
+                                                const int32_t* __restrict__ cand, int64_t nq,
+                                                int kc, int64_t nb, double* __restrict__ scratch,
+                                                double* __restrict__ out) {
+    __shared__ double red[256];
+    double* row = scratch + int64_t(blockIdx.x) * nb;
+    for (int64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+        const int64_t qs = qids[qi];
+        const int64_t qa = q.off[qs], qb = q.off[qs + 1];
+        for (int64_t t = qa + threadIdx.x; t < qb; t += 256) row[q.pos[t]] = q.val[t];
+        __syncthreads();
+        for (int c = 0; c < kc; ++c) {
+            const int64_t r = cand[qi * kc + c];
+            const int64_t ra = rf.off[r], rb = rf.off[r + 1];
+            double acc = 0.0;
+            for (int64_t t = ra + threadIdx.x; t < rb; t += 256) acc += fmin(row[rf.pos[t]], rf.val[t]);
+            red[threadIdx.x] = acc;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const double den = q.s[qs] + rf.s[r];
+                double d = den > 0.0 ? (den - 2.0 * red[0]) / den : 0.0;
+                out[qi * kc + c] = fmin(fmax(d, 0.0), 1.0);
+            }
+            __syncthreads();
+        }
+        for (int64_t t = qa + threadIdx.x; t < qb; t += 256) row[q.pos[t]] = 0.0;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <typename V>
+__device__ __forceinline__ float cond_at(const V* __restrict__ c, int64_t n, int64_t i, int64_t j) {
+    if (i == j) return __builtin_inff();
+    const int64_t a = i < j ? i : j, b = i < j ? j : i;
+    return float(c[a * n - a * (a + 1) / 2 + (b - a - 1)]);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_condensed_block(const V* __restrict__ c, int64_t n,
+                                                         int64_t row_off, int64_t n_rows,
+                                                         int64_t col_off, int64_t n_cols,
+                                                         float* __restrict__ out) {
+    const int64_t r = blockIdx.y;
+    for (int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x; j < n_cols; j += int64_t(gridDim.x) * 256)
+        out[r * n_cols + j] = cond_at(c, n, row_off + r, col_off + j);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_gather_pairs(const V* __restrict__ c, int64_t n,
+                                                      const int32_t* __restrict__ a,
+                                                      const int32_t* __restrict__ b, int64_t cnt,
+                                                      float* __restrict__ out) {
+    const int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= cnt) return;
+    const float v = cond_at(c, n, a[p], b[p]);
+    out[p] = a[p] == b[p] ? 0.0f : v;
+}
+
+}  // namespace
+
+// ============================================================================
+// launchers
+// ============================================================================
+hipError_t project(const Emb& e, const int32_t* dims, const int8_t* signs, int per_node,
+                   int out_dim, double scale, uint16_t* out, hipStream_t st) {
+    if (e.n <= 0) return hipSuccess;
+    const size_t lds = size_t(out_dim) * 8;
+    hipLaunchKernelGGL(k_project, dim3(unsigned(e.n)), dim3(256), lds, st, e, dims, signs,
+                       per_node, out_dim, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, const int32_t* arow,
+                     const uint16_t* B, int64_t ldb, const int32_t* brow, int64_t M, int64_t N,
+                     int64_t K, const float* bias, const uint16_t* mask, int64_t ldm, void* C,
+                     int64_t ldc, hipStream_t st) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const dim3 grid{unsigned((N + 127) / 128), unsigned((M + 127) / 128), 1u};
+#define UF_GEMM(LA_, LB_, EPI_)                                                                 \
+    if (la == LA_ && lb == LB_ && epi == EPI_) {                                                \
+        hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_>), grid, dim3(256), 0, st, A, lda, arow, \
+                           B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc);                     \
+        return hipGetLastError();                                                               \
+    }
+    UF_GEMM(0, 0, EPI_BIAS_RELU_BF16)
+    UF_GEMM(0, 0, EPI_BIAS_F32)
+    UF_GEMM(0, 0, EPI_F32)
+    UF_GEMM(0, 0, EPI_ACC_F32)
+    UF_GEMM(0, 1, EPI_MASK_BF16)
+    UF_GEMM(0, 1, EPI_F32)
+    UF_GEMM(1, 1, EPI_F32)
+#undef UF_GEMM
+    return hipErrorInvalidValue;
+}
+
+hipError_t colsum_f32(const float* X, int64_t rows, int64_t cols, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum_f32, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, st, X, rows,
+                       cols, out);
+    return hipGetLastError();
+}
+hipError_t colsum_bf16(const uint16_t* X, int64_t rows, int64_t cols, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_colsum_bf16, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, st, X,
+                       rows, cols, out);
+    return hipGetLastError();
+}
+
+hipError_t pairloss(const float* Z, int64_t P, int D, const float* target, float rel_floor,
+                    uint16_t* dZ, float* loss_per_pair, float* loss_mean, hipStream_t st) {
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairloss, dim3(unsigned((P + 3) / 4)), dim3(256), 0, st, Z, P, D, target,
+                       rel_floor, dZ, loss_per_pair);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, loss_per_pair, P, loss_mean);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                float b2, float eps, float bc1, float bc2, float wd, uint16_t* pbf, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr,
+                       b1, b2, eps, bc1, bc2, wd, pbf);
+    return hipGetLastError();
+}
+
+hipError_t f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t sqdist(const float* A, int64_t na, const float* B, int64_t nb, int64_t D, float* out,
+                  hipStream_t st) {
+    if (na <= 0 || nb <= 0) return hipSuccess;
+    if ((na + 63) / 64 > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sqdist, dim3(unsigned((nb + 63) / 64), unsigned((na + 63) / 64)), dim3(256),
+                       0, st, A, na, B, nb, D, out);
+    return hipGetLastError();
+}
+
+hipError_t topk_rows(const float* vals, int64_t rows, int64_t cols, int k, int32_t* idx,
+                     float* val, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    if (k < 1 || k > kTopkMax || cols < k || rows > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_topk_rows, dim3(unsigned(rows)), dim3(256), 0, st, vals, cols, k, idx, val);
+    return hipGetLastError();
+}
+
+hipError_t sparse_count(const Emb& e, int64_t* cnt, hipStream_t st) {
+    if (e.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sparse_count, dim3(unsigned(e.n)), dim3(256), 0, st, e, cnt);
+    return hipGetLastError();
+}
+
+hipError_t sparse_fill(const Emb& e, const int64_t* off, int32_t* pos, double* val, hipStream_t st) {
+    if (e.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sparse_fill, dim3(unsigned(e.n)), dim3(256), 0, st, e, off, pos, val);
+    return hipGetLastError();
+}
+
+hipError_t rerank(const SparseView& q, const SparseView& r, const int32_t* qids,
+                  const int32_t* cand, int64_t nq, int kc, int64_t nb, double* scratch,
+                  int64_t n_rows, double* out, hipStream_t st) {
+    if (nq <= 0 || kc <= 0) return hipSuccess;
+    const int64_t grid = nq < n_rows ? nq : n_rows;
+    hipLaunchKernelGGL(k_rerank, dim3(unsigned(grid)), dim3(256), 0, st, q, r, qids, cand, nq, kc,
+                       nb, scratch, out);
+    return hipGetLastError();
+}
+
+hipError_t zero_f64(double* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t condensed_block(const void* c, int is_f32, int64_t n, int64_t row_off, int64_t n_rows,
+                           int64_t col_off, int64_t n_cols, float* out, hipStream_t st) {
+    if (n_rows <= 0 || n_cols <= 0) return hipSuccess;
+    if (n_rows > 65535) return hipErrorInvalidValue;
+    const int64_t gx = (n_cols + 255) / 256 < 64 ? (n_cols + 255) / 256 : 64;
+    if (is_f32)
+        hipLaunchKernelGGL(k_condensed_block<float>, dim3(unsigned(gx), unsigned(n_rows)), dim3(256),
+                           0, st, static_cast<const float*>(c), n, row_off, n_rows, col_off, n_cols, out);
+    else
+        hipLaunchKernelGGL(k_condensed_block<double>, dim3(unsigned(gx), unsigned(n_rows)), dim3(256),
+                           0, st, static_cast<const double*>(c), n, row_off, n_rows, col_off, n_cols, out);
+    return hipGetLastError();
+}
+
+hipError_t gather_pairs(const void* c, int is_f32, int64_t n, const int32_t* a, const int32_t* b,
+                        int64_t cnt, float* out, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    if (is_f32)
+        hipLaunchKernelGGL(k_gather_pairs<float>, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st,
+                           static_cast<const float*>(c), n, a, b, cnt, out);
+    else
+        hipLaunchKernelGGL(k_gather_pairs<double>, dim3(unsigned((cnt + 255) / 256)), dim3(256), 0, st,
+                           static_cast<const double*>(c), n, a, b, cnt, out);
+    return hipGetLastError();
+}
+
+}  // namespace ufp

@@ -285,3 +285,66 @@ def batch_tables(n_tips: int = 100000, n_tables: int = 64, n_min: int = 2000,
     else:
         tables = [_one_batch_table(j) for j in jobs]
     return tree, tables
+
+
+# ---------------------------------------------------------------------------
+# Random inputs of the learned placement encoder.  The encoder's random
+# numbers are drawn here and passed to both the GPU library and the oracle.
+# ---------------------------------------------------------------------------
+def sparse_projection(n_nodes: int, out_dim: int = 4096, per_node: int = 4, seed: int = 7):
+    """A fixed sparse random projection: node v (by id) feeds ``per_node``
+    distinct output dims with signs +-1 (the projection weight is sign/2).
+    Returns (dims int32 [n_nodes, per_node], signs int8 [n_nodes, per_node])."""
+    rng = _rng(seed, 6)
+    dims = rng.integers(0, out_dim, size=(n_nodes, per_node)).astype(np.int32)
+    while True:                         # redraw the rows that repeat a dim
+        srt = np.sort(dims, axis=1)
+        dup = np.any(srt[:, 1:] == srt[:, :-1], axis=1)
+        if not dup.any():
+            break
+        dims[dup] = rng.integers(0, out_dim, size=(int(dup.sum()), per_node))
+    signs = np.where(rng.random((n_nodes, per_node)) < 0.5, -1, 1).astype(np.int8)
+    return dims, signs
+
+
+def bf16_grid(x: np.ndarray) -> np.ndarray:
+    """Values already on the bfloat16 grid (truncate float32 mantissas), so that
+    random inputs are exactly representable by either side."""
+    f = np.asarray(x, dtype=np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    return f.view(np.float32)
+
+
+def mlp_init(dims, seed: int = 11):
+    """He-uniform initial weights on the bfloat16 grid and zero biases.
+    dims = (d0, d1, ..., dL); returns [(W1 [d1, d0], b1), ...] as float32."""
+    rng = _rng(seed, 7)
+    out = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        bound = np.sqrt(6.0 / a)
+        w = bf16_grid(rng.uniform(-bound, bound, size=(b, a)).astype(np.float32))
+        out.append((w, np.zeros(b, dtype=np.float32)))
+    return out
+
+
+def placement_pairs(n: int, n_uniform: int, neighbours: np.ndarray, n_near: int, seed: int = 13):
+    """Training pairs: ``n_uniform`` uniform random pairs (i != j) plus ``n_near``
+    pairs drawn from each sample's nearest-neighbour lists ``neighbours`` [n, k]."""
+    rng = _rng(seed, 8)
+    a = rng.integers(0, n, size=n_uniform)
+    b = (a + rng.integers(1, n, size=n_uniform)) % n
+    k = neighbours.shape[1]
+    rows = rng.integers(0, n, size=n_near)
+    cols = rng.integers(0, k, size=n_near)
+    a2 = rows
+    b2 = neighbours[rows, cols]
+    pa = np.concatenate([a, a2]).astype(np.int32)
+    pb = np.concatenate([b, b2]).astype(np.int32)
+    perm = rng.permutation(pa.shape[0])
+    return pa[perm], pb[perm]
+
+
+def gaussian_matrix(rows: int, cols: int, seed: int = 17) -> np.ndarray:
+    """Standard normal entries on the bfloat16 grid (a Johnson-Lindenstrauss map
+    when scaled), float32 [rows, cols]."""
+    rng = _rng(seed, 9)
+    return bf16_grid(rng.standard_normal(size=(rows, cols)).astype(np.float32))

@@ -1,0 +1,137 @@
+"""Pins of the placement-encoder oracle (oracle/placement.py) on the CPU.
+
+* analytic FP64 gradients vs central finite differences of the loss
+* the same loss and gradients through torch's CPU autograd (FP64) -- an
+  independent library implementation of the same definition
+* Adam vs torch.optim.Adam (FP64)
+* kNN / top-k vs scipy.spatial.distance.cdist + a stable sort
+* projection: a one-dim-per-node projection of a star tree is l*u/2 exactly;
+  linearity in the counts' proportions
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.distance import cdist
+
+import synth
+from oracle import placement as op
+from oracle import unifrac
+from tests import _util
+
+
+def _problem(seed=0, dims=(16, 12, 8, 4), n=10, p=7):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, dims[0]))
+    params = [(rng.normal(size=(b, a)) / np.sqrt(a), rng.normal(size=b) * 0.1)
+              for a, b in zip(dims[:-1], dims[1:])]
+    pa = rng.integers(0, n, size=p)
+    pb = (pa + rng.integers(1, n, size=p)) % n
+    target = rng.random(p)
+    return x, params, pa, pb, target
+
+
+def test_gradients_match_finite_differences():
+    x, params, pa, pb, t = _problem()
+    loss, grads = op.loss_and_grads(x, params, pa, pb, t)
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for l, (w, b) in enumerate(params):
+        for _ in range(6):
+            i, j = rng.integers(w.shape[0]), rng.integers(w.shape[1])
+            wp = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wm = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wp[l][0][i, j] += h
+            wm[l][0][i, j] -= h
+            fd = (op.loss_only(x, wp, pa, pb, t) - op.loss_only(x, wm, pa, pb, t)) / (2 * h)
+            assert grads[l][0][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+        i = rng.integers(b.shape[0])
+        bp = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bm = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bp[l][1][i] += h
+        bm[l][1][i] -= h
+        fd = (op.loss_only(x, bp, pa, pb, t) - op.loss_only(x, bm, pa, pb, t)) / (2 * h)
+        assert grads[l][1][i] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+def test_loss_and_gradients_match_torch_autograd():
+    x, params, pa, pb, t = _problem(seed=3)
+    loss, grads = op.loss_and_grads(x, params, pa, pb, t)
+    tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for w, b in params]
+    h = torch.tensor(x)
+    rows = np.concatenate([pa, pb])
+    h = h[rows]
+    for l, (w, b) in enumerate(tp):
+        h = h @ w.T + b
+        if l < len(tp) - 1:
+            h = torch.relu(h)
+    p = len(pa)
+    dist = torch.sqrt(((h[:p] - h[p:]) ** 2).sum(1))
+    tl = ((dist - torch.tensor(t)) ** 2).mean()
+    tl.backward()
+    assert float(tl) == pytest.approx(loss, rel=1e-12)
+    for (w, b), (gw, gb) in zip(tp, grads):
+        assert np.allclose(w.grad.numpy(), gw, rtol=1e-10, atol=1e-12)
+        assert np.allclose(b.grad.numpy(), gb, rtol=1e-10, atol=1e-12)
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(size=20)
+    grads = [rng.normal(size=20) for _ in range(3)]
+    tp = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(20), np.zeros(20)
+    for step, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = op.adam(p, g, m, v, 1e-2, 0.9, 0.999, 1e-8, step)
+        assert np.allclose(tp.detach().numpy(), p, rtol=1e-12, atol=1e-14)
+
+
+def test_knn_and_topk_match_cdist():
+    rng = np.random.default_rng(7)
+    zq = rng.integers(0, 4, size=(9, 3)).astype(float)     # many ties
+    zr = rng.integers(0, 4, size=(40, 3)).astype(float)
+    idx, d = op.knn(zq, zr, 7)
+    full = cdist(zq, zr, "sqeuclidean")
+    for q in range(9):
+        order = sorted(range(40), key=lambda r: (full[q, r], r))[:7]
+        assert list(idx[q]) == order
+        assert np.allclose(d[q], full[q, order])
+    idx2, v2 = op.topk_rows(full, 7)
+    assert np.array_equal(idx2, idx)
+
+
+def test_projection_of_a_star_tree_is_half_l_u():
+    n_tips = 12
+    t = _util.tree([n_tips] * n_tips + [-1], list(np.arange(1, n_tips + 1) * 0.5) + [0.0])
+    rows = [{0: 3, 5: 1}, {2: 4, 11: 4, 7: 2}]
+    tab = _util.table(rows)
+    dims = np.arange(n_tips + 1, dtype=np.int32).reshape(-1, 1)   # node v -> dim v
+    signs = np.ones((n_tips + 1, 1), dtype=np.int8)
+    signs[3, 0] = -1
+    x = op.project(t, tab, dims, signs, n_tips + 1)
+    u, a, length, nonroot = unifrac.embedding(t, tab)
+    want = (u * length) / 2.0
+    want[:, 3] *= -1
+    want[:, n_tips] = 0.0                    # the root contributes nothing
+    assert np.allclose(x, want, atol=1e-15)
+
+
+def test_projection_is_linear_in_embedding():
+    tr = synth.gen_tree(50, 0.2, seed=2)
+    tab = synth.gen_table_uniform(5, np.arange(50), 8, seed=3)
+    dims, signs = synth.sparse_projection(tr.n_nodes, out_dim=32, per_node=4, seed=1)
+    x = op.project(tr, tab, dims, signs, 32)
+    u, a, length, nonroot = unifrac.embedding(tr, tab)
+    R = np.zeros((32, tr.n_nodes))
+    for j in range(4):
+        np.add.at(R, (dims[:, j], np.arange(tr.n_nodes)), np.where(nonroot, signs[:, j] / 2.0, 0))
+    assert np.allclose(x, (u * length) @ R.T, atol=1e-14)
+
+
+def test_recall_helper():
+    exact = np.array([[0.1, 0.2, 0.3, 0.4], [0.5, 0.1, 0.1, 0.9]])
+    assert op.recall_at_k(np.array([[0, 1], [1, 2]]), exact, 2) == 1.0
+    assert op.recall_at_k(np.array([[0, 3], [1, 0]]), exact, 2) == 0.5
