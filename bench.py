@@ -225,7 +225,8 @@ def main() -> int:
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
     ap.add_argument("--tune-cache", default=None, help="C4: autotuner cache path")
     ap.add_argument("--samples", type=int, default=None, help="override the sample count")
-    ap.add_argument("--weighted-precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--weighted-precision", default="fp32", choices=["fp32", "fp64", "fp32_split"])
+    ap.add_argument("--split-threshold", type=float, default=0.05)
     ap.add_argument("--unweighted-precision", default="mfma", choices=["mfma", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -276,6 +277,13 @@ def main() -> int:
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     wp, up = args.weighted_precision, args.unweighted_precision
+    split = None
+    if wp == "fp32_split":
+        uf.set_split_threshold(args.split_threshold)
+        t_split = time.perf_counter()
+        split = uf.split_stats(emb)        # builds the split once, outside the timed steps
+        log(f"split: {split[0]} dense branches, {split[1]} shared lists, {split[2]:.3e} pairs "
+            f"({time.perf_counter() - t_split:.2f}s)")
     out_w = torch.empty(pairs, dtype=torch.float64, device="cuda")
     out_u = torch.empty(pairs, dtype=torch.float64, device="cuda")
     ws_w = torch.empty(uf.workspace_size(emb, "weighted_normalized", wp, row_stats=True),
@@ -311,19 +319,21 @@ def main() -> int:
 
     kern = {}
     for name in ("embed_nm", "embed_pres", "band_wn_f32", "band_wn_f64", "band_uw_f32",
-                 "band_uw_f64", "gram_mfma", "finalize", "row_sums"):
+                 "band_uw_f64", "gram_mfma", "rare_pairs", "finalize", "row_sums"):
         tot, cnt = uf.profile_read(name)
         if cnt:
             kern[name] = {"total_ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
                           "avg_ms_per_launch": tot / cnt}
-    band = "band_wn_f32" if wp == "fp32" else "band_wn_f64"
+    band = "band_wn_f64" if wp == "fp64" else "band_wn_f32"
     band_ms = kern[band]["total_ms_per_step"]
     # weighted stripe kernel: 2 VALU slots per update (subtract, add |.|); reported in
-    # FMA-equivalent TFLOP/s (2 flops per slot) against the published vector peak
-    slots = 2 * U / (band_ms / 1e3)
-    peak_slots = PEAK_VALU_SLOTS[wp]
+    # FMA-equivalent TFLOP/s (2 flops per slot) against the published vector peak.
+    # With the split the band kernel visits only the dense branches.
+    band_updates = U if split is None else pairs * split[0]
+    slots = 2 * band_updates / (band_ms / 1e3)
+    peak_slots = PEAK_VALU_SLOTS["fp64" if wp == "fp64" else "fp32"]
     traffic = measured_traffic(band, args.workload)
-    roofline = {"bound": "alu", "kernel": f"k_band<{'float' if wp == 'fp32' else 'double'},weighted>",
+    roofline = {"bound": "alu", "kernel": f"k_band<{'double' if wp == 'fp64' else 'float'},weighted>",
                 "achieved": 2 * slots / 1e12, "peak": 2 * peak_slots / 1e12,
                 "unit": "TFLOP/s", "frac": slots / peak_slots, "traffic": traffic,
                 "avg_launch_ms": kern[band]["avg_ms_per_launch"],
@@ -332,6 +342,12 @@ def main() -> int:
                         "slot counted as 2 flops (FMA-equivalent) so the peak is the published "
                         "vector rate: FP32 157.3, FP64 78.6 TFLOP/s (256 CU, 2.4 GHz)"}
     extra = {"kernels": kern}
+    if split is not None:
+        r_ms = kern.get("rare_pairs", {}).get("total_ms_per_step", 0.0)
+        extra["split"] = {"threshold": args.split_threshold, "dense_branches": split[0],
+                          "shared_lists": split[1], "pairs_enumerated": split[2],
+                          "band_updates_per_step": band_updates,
+                          "rare_pair_atomics_per_s": split[2] / (r_ms / 1e3) if r_ms else None}
     if "gram_mfma" in kern:
         g_ms = kern["gram_mfma"]["total_ms_per_step"]
         extra["mfma_roofline"] = {"bound": "mfma", "achieved": 4 * U / (g_ms / 1e3) / 1e12,

@@ -66,8 +66,14 @@ typedef enum {
 typedef enum {
     UF_FP64 = 0,        /* FP64 embedding and FP64 accumulation (vector ALU)           */
     UF_FP32 = 1,        /* FP32 embedding and FP32 accumulation, FP64 final division   */
-    UF_MFMA_BF16X2 = 2  /* unweighted only: Gram product on MFMA, 0/1 x (l_hi + l_lo)  */
+    UF_MFMA_BF16X2 = 2, /* unweighted only: Gram product on MFMA, 0/1 x (l_hi + l_lo)  */
                         /* in BF16 with FP32 accumulation, FP64 final division         */
+    UF_FP32_SPLIT = 3   /* weighted only, sparse aware (the paper's "sparse-aware      */
+                        /* optimizations", section II): branches touched by more than  */
+                        /* a threshold fraction of the samples on the FP32 stripe      */
+                        /* kernel; on every other branch only pairs that both touch it */
+                        /* are visited, via sum|x-y| = sum x + sum y - 2 sum min(x,y), */
+                        /* summed exactly in 2^-40 fixed point                         */
 } uf_precision;
 
 typedef enum { UF_CONDENSED = 0, UF_STRIPES = 1 } uf_layout;
@@ -125,6 +131,16 @@ uf_status uf_workspace_size(const uf_embedding* emb, int weighted, uf_precision 
 /* Number of branches streamed per chunk (0 = automatic: as many as fit in
  * 8 GiB of chunk buffer).  Process-wide; affects later workspace sizes. */
 void uf_set_chunk_nodes(int64_t nodes);
+
+/* UF_FP32_SPLIT: the dense set is the branches touched by more than
+ * `fraction` x N samples (default 0.05; process-wide).  The split of an
+ * embedding is built on first use and rebuilt when the fraction changes. */
+void uf_set_split_threshold(double fraction);
+/* Size of the split of `emb` at the current threshold: dense branches, shared
+ * non-dense branches, and sample pairs enumerated over them (builds the split
+ * if needed; synchronous). */
+uf_status uf_split_stats(const uf_embedding* emb, int64_t* n_dense, int64_t* n_lists,
+                         int64_t* n_pairs);
 
 /* ---- distance matrices --------------------------------------------------- */
 

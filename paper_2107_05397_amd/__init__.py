@@ -27,7 +27,7 @@ __all__ = [
     "UFError", "lib", "Tree", "Table", "Embedding", "workspace_size", "dm", "dm_unweighted",
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
-    "profile_read", "Batch", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
+    "profile_read", "Batch", "set_split_threshold", "split_stats", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
     "gather_pairs", "Sparse", "rerank",
 ]
 
@@ -35,7 +35,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libuf.so")
 HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "uf.h")
 
-PRECISION = {"fp64": 0, "fp32": 1, "mfma": 2, "mfma_bf16x2": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "mfma": 2, "mfma_bf16x2": 2, "fp32_split": 3}
 LAYOUT = {"condensed": 0, "stripes": 1}
 STATUS = {0: "UF_OK", 1: "UF_ERR_ARG", 2: "UF_ERR_TREE", 3: "UF_ERR_TABLE",
           4: "UF_ERR_EMPTY_SAMPLE", 5: "UF_ERR_RANGE", 6: "UF_ERR_NOMEM", 7: "UF_ERR_DEVICE",
@@ -67,6 +67,8 @@ _SIGS = {
     "uf_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "uf_set_chunk_nodes": (None, [_i64]),
+    "uf_set_split_threshold": (None, [ctypes.c_double]),
+    "uf_split_stats": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p]),
     "uf_dm_unweighted": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
                                         ctypes.c_size_t, _vp]),
     "uf_dm_weighted_normalized": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
@@ -168,6 +170,18 @@ def condensed_index(n: int, i: int, j: int) -> int:
 def set_chunk_nodes(nodes: int) -> None:
     """Branches per streamed chunk (0 = automatic, 8 GiB of chunk buffer)."""
     lib().uf_set_chunk_nodes(int(nodes))
+
+
+def set_split_threshold(fraction: float) -> None:
+    """Dense-set threshold of the sparse-aware split (fraction of samples)."""
+    lib().uf_set_split_threshold(float(fraction))
+
+
+def split_stats(emb) -> Tuple[int, int, int]:
+    """(dense branches, shared non-dense branches, enumerated pairs) of the split."""
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().uf_split_stats(emb.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
 
 
 def profile_enable(on: bool = True) -> None:

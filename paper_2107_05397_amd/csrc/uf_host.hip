@@ -18,11 +18,13 @@
 #include <vector>
 
 #include "uf_internal.h"
+#include "uf_split.h"
 
 namespace {
 
 thread_local std::string g_last_error;
 std::atomic<int64_t> g_chunk_nodes{0};
+std::atomic<double> g_split_threshold{0.05};
 
 uf_status fail(uf_status st, const std::string& msg) {
     g_last_error = msg;
@@ -158,6 +160,115 @@ struct Carver {
     }
 };
 
+// ------------------------------------------------------------------ sparse split
+ufp::Emb emb_view(const uf_embedding& e) {
+    ufp::Emb v;
+    v.n = e.n;
+    v.row_ptr = e.row_ptr;
+    v.rank = e.rank;
+    v.cum = e.cum;
+    v.total = e.total;
+    v.lo = e.lo;
+    v.hi = e.hi;
+    v.len = e.len;
+    v.parent_pos = e.parent_pos;
+    v.tip_pos = e.tip_pos;
+    v.root_pos = int32_t(e.nb);
+    return v;
+}
+
+void free_split(SplitCache* sc) {
+    if (!sc) return;
+    if (sc->arena) (void)hipFree(sc->arena);
+    delete sc;
+}
+
+// Build (or rebuild for a new threshold) the dense set and the shared
+// non-dense branch lists of an embedding.  Synchronous on `stream`.
+uf_status ensure_split(const uf_embedding* ce, void* stream) {
+    uf_embedding* e = const_cast<uf_embedding*>(ce);   // the cache is internal state
+    std::lock_guard<std::mutex> lk(e->split_mu);
+    const double thr = g_split_threshold.load();
+    if (e->split && e->split->threshold == thr) return UF_OK;
+    free_split(e->split);
+    e->split = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = e->n, nb = e->nb;
+    const ufp::Emb ev = emb_view(*e);
+    int32_t* dcnt = nullptr;
+    if (hipMalloc(&dcnt, size_t(std::max<int64_t>(nb, 1)) * 4) != hipSuccess)
+        return fail(UF_ERR_NOMEM, "branch counts");
+    std::unique_ptr<void, void (*)(void*)> gc(dcnt, [](void* q) { (void)hipFree(q); });
+    UF_HIP(hipMemsetAsync(dcnt, 0, size_t(std::max<int64_t>(nb, 1)) * 4, s));
+    UF_HIP(ufs::branch_count(ev, dcnt, s));
+    std::vector<int32_t> cnt(size_t(std::max<int64_t>(nb, 1)), 0);
+    UF_HIP(hipStreamSynchronize(s));
+    if (nb) UF_HIP(hipMemcpy(cnt.data(), dcnt, size_t(nb) * 4, hipMemcpyDeviceToHost));
+    auto sc = std::unique_ptr<SplitCache>(new SplitCache());
+    sc->threshold = thr;
+    std::vector<int32_t> cls(size_t(std::max<int64_t>(nb, 1)), ufs::kClassAlone), dense;
+    std::vector<int64_t> roff(1, 0);
+    std::vector<ufs::RareItem> items;
+    const double lim = thr * double(n);
+    constexpr int64_t kPairsPerItem = 1 << 15;
+    for (int64_t v = 0; v < nb; ++v) {
+        const int64_t c = cnt[size_t(v)];
+        if (double(c) > lim) {
+            cls[size_t(v)] = ufs::kClassDense;
+            dense.push_back(int32_t(v));
+        } else if (c >= 2) {
+            const int64_t li = int64_t(roff.size()) - 1;
+            cls[size_t(v)] = int32_t(li);
+            roff.push_back(roff.back() + c);
+            const int64_t np = c * (c - 1) / 2;
+            for (int64_t p0 = 0; p0 < np; p0 += kPairsPerItem)
+                items.push_back(ufs::RareItem{li, p0, std::min(np, p0 + kPairsPerItem)});
+            sc->n_pairs += np;
+        }
+    }
+    sc->n_dense = int64_t(dense.size());
+    sc->n_lists = int64_t(roff.size()) - 1;
+    sc->n_entries = roff.back();
+    sc->n_items = int64_t(items.size());
+    Carver c;
+    const size_t o_dense = c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4);
+    const size_t o_cls = c.take(size_t(std::max<int64_t>(nb, 1)) * 4);
+    const size_t o_roff = c.take(roff.size() * 8);
+    const size_t o_rs = c.take(size_t(std::max<int64_t>(sc->n_entries, 1)) * 4);
+    const size_t o_rq = c.take(size_t(std::max<int64_t>(sc->n_entries, 1)) * 8);
+    const size_t o_sig = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+    const size_t o_items = c.take(sizeof(ufs::RareItem) * size_t(std::max<int64_t>(sc->n_items, 1)));
+    const size_t o_fill = c.take(size_t(std::max<int64_t>(sc->n_lists, 1)) * 4);
+    if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
+    char* b = static_cast<char*>(sc->arena);
+    sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
+    sc->cls = reinterpret_cast<int32_t*>(b + o_cls);
+    sc->roff = reinterpret_cast<int64_t*>(b + o_roff);
+    sc->rs = reinterpret_cast<int32_t*>(b + o_rs);
+    sc->rq = reinterpret_cast<int64_t*>(b + o_rq);
+    sc->sigma = reinterpret_cast<unsigned long long*>(b + o_sig);
+    sc->items = b + o_items;
+    int32_t* fill = reinterpret_cast<int32_t*>(b + o_fill);
+    auto fail_free = [&](uf_status code) {
+        (void)hipFree(sc->arena);
+        sc->arena = nullptr;
+        return code;
+    };
+    hipError_t rc = hipSuccess;
+    if (sc->n_dense) rc = hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice);
+    if (rc == hipSuccess && nb) rc = hipMemcpy(sc->cls, cls.data(), size_t(nb) * 4, hipMemcpyHostToDevice);
+    if (rc == hipSuccess) rc = hipMemcpy(sc->roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice);
+    if (rc == hipSuccess && sc->n_items)
+        rc = hipMemcpy(sc->items, items.data(), sizeof(ufs::RareItem) * size_t(sc->n_items), hipMemcpyHostToDevice);
+    if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, size_t(std::max<int64_t>(sc->n_lists, 1)) * 4, s);
+    if (rc == hipSuccess) rc = hipMemsetAsync(sc->sigma, 0, size_t(std::max<int64_t>(n, 1)) * 8, s);
+    if (rc == hipSuccess) rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, sc->rs, sc->rq, sc->sigma, s);
+    if (rc == hipSuccess) rc = hipStreamSynchronize(s);
+    if (rc != hipSuccess) return fail_free(hip_fail(rc, "sparse split build"));
+    e->split = sc.release();
+    return UF_OK;
+}
+
 // ------------------------------------------------------------------ planning
 struct Plan {
     int64_t n = 0, S = 0, sb = 0, se = 0, sr = 0;
@@ -166,17 +277,20 @@ struct Plan {
     bool rowstats = false;
     int64_t kc = 0, nchunks = 0, kpad = 0;
     int64_t n_parts = 0;
-    size_t off_acc = 0, off_q = 0, off_chunk = 0, off_part = 0, off_rm = 0, total = 0;
+    size_t off_acc = 0, off_q = 0, off_chunk = 0, off_part = 0, off_rm = 0, off_m = 0, total = 0;
 };
 
 uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
                     int64_t se, bool rowstats, Plan* p) {
     if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
-    if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2)
+    if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2 && prec != UF_FP32_SPLIT)
         return fail(UF_ERR_ARG, "unknown precision");
     if (weighted && prec == UF_MFMA_BF16X2)
         return fail(UF_ERR_UNSUPPORTED,
                     "the MFMA Gram path exists for the unweighted variant only");
+    if (!weighted && prec == UF_FP32_SPLIT)
+        return fail(UF_ERR_UNSUPPORTED,
+                    "the sparse-aware split exists for the weighted-normalized variant only");
     const int64_t n = e->n;
     const int64_t S = n / 2;
     if (sb < 0 || se < sb || se > S)
@@ -189,8 +303,8 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     p->weighted = weighted;
     p->prec = prec;
     p->rowstats = rowstats;
-    const int64_t nb = e->nb;
-    const size_t elem = prec == UF_FP64 ? 8 : (prec == UF_FP32 ? 4 : 2);
+    const int64_t nb = (prec == UF_FP32_SPLIT) ? e->split->n_dense : e->nb;
+    const size_t elem = prec == UF_FP64 ? 8 : (prec == UF_MFMA_BF16X2 ? 2 : 4);
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
         const double budget = 8.0 * 1024 * 1024 * 1024;
@@ -213,6 +327,7 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
         p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
     p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
     p->off_rm = rowstats ? c.take(size_t(n) * 8) : 0;
+    p->off_m = prec == UF_FP32_SPLIT ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
     p->total = c.off + 256;
     return UF_OK;
 }
@@ -225,6 +340,10 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     if (odt != UF_OUT_F64 && odt != UF_OUT_F32) return fail(UF_ERR_ARG, "bad output dtype");
     const bool rowstats = row_out != nullptr || grand_mean != nullptr;
     Plan p;
+    if (prec == UF_FP32_SPLIT && weighted) {
+        uf_status sst = ensure_split(e, stream);
+        if (sst != UF_OK) return sst;
+    }
     uf_status st = make_plan(e, weighted, prec, sb, se, rowstats, &p);
     if (st != UF_OK) return st;
     if (!ws || ws_bytes < p.total)
@@ -244,6 +363,46 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     double* q = rowstats ? reinterpret_cast<double*>(base + p.off_q) : nullptr;
     void* chunk = base + p.off_chunk;
     const int64_t nb = e->nb;
+
+    if (prec == UF_FP32_SPLIT) {
+        const SplitCache& sc = *e->split;
+        const ufp::Emb ev = emb_view(*e);
+        for (int64_t c = 0; c < p.nchunks; ++c) {
+            const int64_t k0 = c * p.kc;
+            const int64_t kc = std::min<int64_t>(p.kc, sc.n_dense - k0);
+            float* E = static_cast<float*>(chunk);
+            {
+                ProfScope ps("embed_nm", s);
+                UF_HIP(ufs::embed_list_f32(ev, sc.dense, k0, kc, E, s));
+            }
+            ProfScope ps("band_wn_f32", s);
+            UF_HIP(ufk::band_f32(E, nullptr, kc, p.n, p.sb, p.se, 1, c == 0,
+                                 static_cast<float*>(acc), s));
+        }
+        if (p.nchunks == 0)
+            UF_HIP(ufk::zero_u32(static_cast<unsigned*>(acc), p.sr * p.n, s));
+        unsigned long long* M = reinterpret_cast<unsigned long long*>(base + p.off_m);
+        UF_HIP(ufs::zero_u64(M, p.sr * p.n, s));
+        {
+            ProfScope ps("rare_pairs", s);
+            UF_HIP(ufs::rare_pairs(sc.roff, sc.rs, sc.rq, static_cast<const ufs::RareItem*>(sc.items),
+                                   sc.n_items, p.n, p.sb, p.se, M, s));
+        }
+        {
+            ProfScope ps("finalize", s);
+            UF_HIP(ufk::finalize(0, acc, 0, e->sw, p.n, p.sb, p.se, layout, odt == UF_OUT_F32 ? 1 : 0,
+                                 out, q, s, M, sc.sigma));
+        }
+        if (rowstats) {
+            ProfScope ps("row_sums", s);
+            double* part = reinterpret_cast<double*>(base + p.off_part);
+            double* rm = row_out ? row_out : reinterpret_cast<double*>(base + p.off_rm);
+            const double scale = full_means ? 1.0 / double(p.n) : 1.0;
+            UF_HIP(ufk::row_sums(q, p.n, p.sb, p.se, part, p.n_parts, scale, rm, s));
+            if (grand_mean) UF_HIP(ufk::grand_mean(rm, p.n, grand_mean, s));
+        }
+        return UF_OK;
+    }
 
     for (int64_t c = 0; c < p.nchunks; ++c) {
         const int64_t k0 = c * p.kc;
@@ -341,6 +500,23 @@ int64_t uf_condensed_index(int64_t n, int64_t i, int64_t j) {
 }
 
 void uf_set_chunk_nodes(int64_t nodes) { g_chunk_nodes.store(nodes < 0 ? 0 : nodes); }
+
+void uf_set_split_threshold(double fraction) {
+    g_split_threshold.store(fraction >= 0.0 && fraction <= 1.0 ? fraction : 0.05);
+}
+
+uf_status uf_split_stats(const uf_embedding* e, int64_t* n_dense, int64_t* n_lists,
+                         int64_t* n_pairs) {
+    return guarded([&]() -> uf_status {
+        if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+        uf_status st = ensure_split(e, nullptr);
+        if (st != UF_OK) return st;
+        if (n_dense) *n_dense = e->split->n_dense;
+        if (n_lists) *n_lists = e->split->n_lists;
+        if (n_pairs) *n_pairs = e->split->n_pairs;
+        return UF_OK;
+    });
+}
 
 void uf_profile_enable(int on) { g_prof_on.store(on ? 1 : 0); }
 
@@ -683,6 +859,7 @@ uf_status uf_embedding_scalars(const uf_embedding* e, double* sw, double* wu) {
 
 void uf_free_embedding(uf_embedding* e) {
     if (!e) return;
+    free_split(e->split);
     if (e->arena) (void)hipFree(e->arena);
     delete e;
 }
@@ -692,6 +869,10 @@ uf_status uf_workspace_size(const uf_embedding* e, int weighted, uf_precision pr
                             int64_t se, int want_row_stats, size_t* bytes) {
     return guarded([&]() -> uf_status {
         if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
+        if (e && weighted && prec == UF_FP32_SPLIT) {
+            uf_status sst = ensure_split(e, nullptr);
+            if (sst != UF_OK) return sst;
+        }
         Plan p;
         uf_status st = make_plan(e, weighted ? 1 : 0, prec, sb, se, want_row_stats != 0, &p);
         if (st != UF_OK) return st;

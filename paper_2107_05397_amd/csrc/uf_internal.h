@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,24 @@ struct uf_table {
     std::vector<int64_t> total;       // per sample, > 0
 };
 
+// Sparse-aware split of one embedding at one threshold (uf_host.hip).
+struct SplitCache {
+    double threshold = 0.0;
+    int64_t n_dense = 0;          // branches in the dense set
+    int64_t n_lists = 0;          // shared non-dense branches (>= 2 samples)
+    int64_t n_entries = 0;        // entries of their sample lists
+    int64_t n_items = 0;          // pair-range work items
+    int64_t n_pairs = 0;          // pairs enumerated over all lists
+    void* arena = nullptr;
+    int32_t* dense = nullptr;     // [n_dense] positions, ascending
+    int32_t* cls = nullptr;       // [nb] class per position
+    int64_t* roff = nullptr;      // [n_lists+1]
+    int32_t* rs = nullptr;        // [n_entries] sample of each list entry
+    int64_t* rq = nullptr;        // [n_entries] l*u in 2^-40 fixed point
+    unsigned long long* sigma = nullptr;   // [n] fixed-point sum over non-dense branches
+    void* items = nullptr;        // [n_items] pair ranges (ufs::RareItem)
+};
+
 // Device-resident inputs of the distance calls.  All arrays are on `device`.
 struct uf_embedding {
     int device = 0;
@@ -64,6 +83,9 @@ struct uf_embedding {
     double* wu = nullptr;         // sum_v l_v a_sv, FP64 lengths
     double* wu32 = nullptr;       // same with FP32-rounded lengths
     double* wub = nullptr;        // same with hi+lo bf16 lengths
+    // sparse-aware split, built on first use (guarded by split_mu)
+    struct SplitCache* split = nullptr;
+    std::mutex split_mu;
     int32_t* parent_pos = nullptr;  // [nb+1], -1 for the root
     int32_t* tip_pos = nullptr;     // [n_tips] position of the tip with rank r
     void* arena = nullptr;        // one allocation holding all of the above
@@ -131,7 +153,8 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 // stripe-major.  layout/out dtype as in uf.h.
 hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
                     int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
-                    hipStream_t st);
+                    hipStream_t st, const unsigned long long* split_m = nullptr,
+                    const unsigned long long* sigma = nullptr);
 
 // Row sums of -d^2/2 over the distinct pairs of stripes [sb, se): two fixed-order stages.
 hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* partial,

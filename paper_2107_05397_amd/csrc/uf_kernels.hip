@@ -469,17 +469,26 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
 // ----------------------------------------------------------------------------
 // Finalize: distance from the accumulator of (s, i), output layout, -d^2/2.
 // ----------------------------------------------------------------------------
+// With the sparse-aware split (split_m != NULL) the weighted numerator adds the
+// exact fixed-point part sigma_i + sigma_j - 2 M_ij (2^-40 units) of the branches
+// outside the dense set.
 template <typename A>
 __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict__ acc,
                                                   const double* __restrict__ scal, int64_t n,
                                                   int64_t sb, int64_t se, int layout, int out_f32,
-                                                  void* __restrict__ out, double* __restrict__ q) {
+                                                  void* __restrict__ out, double* __restrict__ q,
+                                                  const unsigned long long* __restrict__ split_m,
+                                                  const unsigned long long* __restrict__ sigma) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n) return;
     const bool even = (n & 1) == 0;
     for (int64_t s = sb + blockIdx.y; s < se; s += gridDim.y) {
         const int64_t j = (i + s + 1) % n;
-        const double num = double(acc[(s - sb) * n + i]);
+        double num = double(acc[(s - sb) * n + i]);
+        if (split_m) {
+            const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
+            num += double(r) * (1.0 / 1099511627776.0);
+        }
         double d;
         if (kind == 0) {
             const double den = scal[i] + scal[j];
@@ -734,17 +743,18 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 
 hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
                     int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
-                    hipStream_t st) {
+                    hipStream_t st, const unsigned long long* split_m,
+                    const unsigned long long* sigma) {
     if (se <= sb || n <= 0) return hipSuccess;
     dim3 grid(unsigned((n + 255) / 256), grid_y(se - sb));
     if (acc_is_f64)
         hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, st, kind,
                            static_cast<const double*>(acc), scal, n, sb, se, layout, out_f32, out,
-                           q);
+                           q, split_m, sigma);
     else
         hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, st, kind,
                            static_cast<const float*>(acc), scal, n, sb, se, layout, out_f32, out,
-                           q);
+                           q, split_m, sigma);
     return hipGetLastError();
 }
 

@@ -217,4 +217,16 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
     ri = torch.as_tensor(rng.integers(0, nr, 20000), device="cuda")
     approx = torch.sqrt(((z_q[qi] - z_ref[ri]) ** 2).sum(1))
     out["mean_abs_dist_err_random_pairs"] = float((approx - cross[qi, ri]).abs().mean().item())
+    # the projection as a distance estimate, with its best single scale (least
+    # squares on the training pairs)
+    sel = torch.arange(min(20000, len(pa)), device="cuda")
+    pa_t = torch.as_tensor(pa, device="cuda")[sel].long()
+    pb_t = torch.as_tensor(pb, device="cuda")[sel].long()
+    dxt = (xr[pa_t] - xr[pb_t]).norm(dim=1).double()
+    scale = float((dxt * tg[sel].double()).sum() / (dxt * dxt).sum().clamp_min(1e-300))
+    dq = (xq[qi] - xr[ri]).norm(dim=1).double() * scale
+    out["projection_only_mean_abs_dist_err_random_pairs"] = float(
+        (dq - cross[qi, ri].double()).abs().mean().item())
+    out["knn_dims_encoder"] = int(dims[-1])
+    out["knn_dims_projection_only"] = int(dims[0])
     return out

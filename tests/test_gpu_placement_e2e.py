@@ -1,0 +1,36 @@
+"""End to end, scaled down: train the encoder on exact distances of a reference
+table, place new samples, and compare with the method without the network
+(the raw 1024-d projection, same exact re-rank budget).
+
+Encoder quality has no value printed in the paper to pin against ("parity
+unpinned" as a number); it is judged against exact UniFrac.  What the trained
+network gains over the projection alone, asserted here:
+* its Euclidean distances estimate UniFrac itself: lower mean error on random
+  query/reference pairs than the projection under its best single scale;
+* a 16x smaller search space (64 vs 1024 dims) for the candidate search.
+Recall@10 is reported, not asserted against the projection: the raw
+projection keeps more dimensions and ranks near neighbours better.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def test_encoder_gains_over_projection_only():
+    from paper_2107_05397_amd import placement
+    tree = synth.gen_tree(20000, 0.05, seed=41)
+    ref = synth.gen_table_zipf(3000, np.arange(20000), 300, seed=42)
+    qry = synth.gen_table_zipf(400, np.arange(20000), 300, seed=43)
+    res = placement.experiment(tree, ref, qry, dims=(1024, 256, 256, 64), epochs=10,
+                               n_uniform=200_000, n_near=200_000, near_k=20,
+                               k_candidates=(10, 50), lr=5e-4, log=print)
+    print({k: v for k, v in res.items() if k != "train_losses"})
+    assert res["train_losses"][-1] < 0.5 * res["train_losses"][0]
+    assert res["recall@10_kprime50"] >= res["recall@10_kprime10"]
+    assert res["mean_abs_dist_err_random_pairs"] < res["projection_only_mean_abs_dist_err_random_pairs"]
+    assert res["knn_dims_encoder"] * 16 == res["knn_dims_projection_only"]
