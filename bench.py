@@ -227,7 +227,8 @@ def main() -> int:
     ap.add_argument("--samples", type=int, default=None, help="override the sample count")
     ap.add_argument("--weighted-precision", default="fp32", choices=["fp32", "fp64", "fp32_split"])
     ap.add_argument("--split-threshold", type=float, default=0.05)
-    ap.add_argument("--unweighted-precision", default="mfma", choices=["mfma", "fp32", "fp64"])
+    ap.add_argument("--unweighted-precision", default="mfma",
+                    choices=["mfma", "mfma_split", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -278,7 +279,7 @@ def main() -> int:
 
     wp, up = args.weighted_precision, args.unweighted_precision
     split = None
-    if wp == "fp32_split":
+    if wp == "fp32_split" or up == "mfma_split":
         uf.set_split_threshold(args.split_threshold)
         t_split = time.perf_counter()
         split = uf.split_stats(emb)        # builds the split once, outside the timed steps
@@ -329,7 +330,7 @@ def main() -> int:
     # weighted stripe kernel: 2 VALU slots per update (subtract, add |.|); reported in
     # FMA-equivalent TFLOP/s (2 flops per slot) against the published vector peak.
     # With the split the band kernel visits only the dense branches.
-    band_updates = U if split is None else pairs * split[0]
+    band_updates = pairs * split[0] if wp == "fp32_split" else U
     slots = 2 * band_updates / (band_ms / 1e3)
     peak_slots = PEAK_VALU_SLOTS["fp64" if wp == "fp64" else "fp32"]
     traffic = measured_traffic(band, args.workload)
@@ -347,12 +348,14 @@ def main() -> int:
         extra["split"] = {"threshold": args.split_threshold, "dense_branches": split[0],
                           "shared_lists": split[1], "pairs_enumerated": split[2],
                           "band_updates_per_step": band_updates,
-                          "rare_pair_atomics_per_s": split[2] / (r_ms / 1e3) if r_ms else None}
+                          "rare_pair_atomics_per_s": (split[2] * ((wp == "fp32_split") + (up == "mfma_split"))
+                                                      / (r_ms / 1e3)) if r_ms else None}
     if "gram_mfma" in kern:
         g_ms = kern["gram_mfma"]["total_ms_per_step"]
-        extra["mfma_roofline"] = {"bound": "mfma", "achieved": 4 * U / (g_ms / 1e3) / 1e12,
+        g_upd = pairs * split[0] if up == "mfma_split" else U
+        extra["mfma_roofline"] = {"bound": "mfma", "achieved": 4 * g_upd / (g_ms / 1e3) / 1e12,
                                   "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                                  "frac": 4 * U / (g_ms / 1e3) / PEAK_BF16_MFMA,
+                                  "frac": 4 * g_upd / (g_ms / 1e3) / PEAK_BF16_MFMA,
                                   "note": "2 BF16 MACs (l_hi, l_lo) = 4 flops per update"}
 
     # sampled parity against the oracle (pairs drawn at random)

@@ -68,12 +68,17 @@ typedef enum {
     UF_FP32 = 1,        /* FP32 embedding and FP32 accumulation, FP64 final division   */
     UF_MFMA_BF16X2 = 2, /* unweighted only: Gram product on MFMA, 0/1 x (l_hi + l_lo)  */
                         /* in BF16 with FP32 accumulation, FP64 final division         */
-    UF_FP32_SPLIT = 3   /* weighted only, sparse aware (the paper's "sparse-aware      */
+    UF_FP32_SPLIT = 3,  /* weighted only, sparse aware (the paper's "sparse-aware      */
                         /* optimizations", section II): branches touched by more than  */
                         /* a threshold fraction of the samples on the FP32 stripe      */
                         /* kernel; on every other branch only pairs that both touch it */
                         /* are visited, via sum|x-y| = sum x + sum y - 2 sum min(x,y), */
                         /* summed exactly in 2^-40 fixed point                         */
+    UF_MFMA_SPLIT = 4   /* unweighted only, sparse aware: the dense branches as in     */
+                        /* UF_MFMA_BF16X2; the Gram terms of every other branch, l for */
+                        /* each pair of samples that both touch it, summed exactly in  */
+                        /* 2^-40 fixed point.  Lengths are l_hi + l_lo throughout, as  */
+                        /* in UF_MFMA_BF16X2                                           */
 } uf_precision;
 
 typedef enum { UF_CONDENSED = 0, UF_STRIPES = 1 } uf_layout;
@@ -132,7 +137,7 @@ uf_status uf_workspace_size(const uf_embedding* emb, int weighted, uf_precision 
  * 8 GiB of chunk buffer).  Process-wide; affects later workspace sizes. */
 void uf_set_chunk_nodes(int64_t nodes);
 
-/* UF_FP32_SPLIT: the dense set is the branches touched by more than
+/* UF_FP32_SPLIT, UF_MFMA_SPLIT: the dense set is the branches touched by more than
  * `fraction` x N samples (default 0.05; process-wide).  The split of an
  * embedding is built on first use and rebuilt when the fraction changes. */
 void uf_set_split_threshold(double fraction);

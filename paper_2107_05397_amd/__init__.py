@@ -35,7 +35,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libuf.so")
 HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "uf.h")
 
-PRECISION = {"fp64": 0, "fp32": 1, "mfma": 2, "mfma_bf16x2": 2, "fp32_split": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "mfma": 2, "mfma_bf16x2": 2, "fp32_split": 3, "mfma_split": 4}
 LAYOUT = {"condensed": 0, "stripes": 1}
 STATUS = {0: "UF_OK", 1: "UF_ERR_ARG", 2: "UF_ERR_TREE", 3: "UF_ERR_TABLE",
           4: "UF_ERR_EMPTY_SAMPLE", 5: "UF_ERR_RANGE", 6: "UF_ERR_NOMEM", 7: "UF_ERR_DEVICE",

@@ -239,6 +239,10 @@ uf_status ensure_split(const uf_embedding* ce, void* stream) {
     const size_t o_sig = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
     const size_t o_items = c.take(sizeof(ufs::RareItem) * size_t(std::max<int64_t>(sc->n_items, 1)));
     const size_t o_fill = c.take(size_t(std::max<int64_t>(sc->n_lists, 1)) * 4);
+    sc->n_dense_pad = (sc->n_dense + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    const size_t o_dhi = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
+    const size_t o_dlo = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
+    const size_t o_rl = c.take(size_t(std::max<int64_t>(sc->n_lists, 1)) * 8);
     if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
     char* b = static_cast<char*>(sc->arena);
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
@@ -249,6 +253,9 @@ uf_status ensure_split(const uf_embedding* ce, void* stream) {
     sc->sigma = reinterpret_cast<unsigned long long*>(b + o_sig);
     sc->items = b + o_items;
     int32_t* fill = reinterpret_cast<int32_t*>(b + o_fill);
+    sc->dlen_hi = reinterpret_cast<uint16_t*>(b + o_dhi);
+    sc->dlen_lo = reinterpret_cast<uint16_t*>(b + o_dlo);
+    sc->rl = reinterpret_cast<int64_t*>(b + o_rl);
     auto fail_free = [&](uf_status code) {
         (void)hipFree(sc->arena);
         sc->arena = nullptr;
@@ -263,6 +270,9 @@ uf_status ensure_split(const uf_embedding* ce, void* stream) {
     if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, size_t(std::max<int64_t>(sc->n_lists, 1)) * 4, s);
     if (rc == hipSuccess) rc = hipMemsetAsync(sc->sigma, 0, size_t(std::max<int64_t>(n, 1)) * 8, s);
     if (rc == hipSuccess) rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, sc->rs, sc->rq, sc->sigma, s);
+    if (rc == hipSuccess)
+        rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
+                                e->len_lo, sc->dlen_hi, sc->dlen_lo, sc->rl, s);
     if (rc == hipSuccess) rc = hipStreamSynchronize(s);
     if (rc != hipSuccess) return fail_free(hip_fail(rc, "sparse split build"));
     e->split = sc.release();
@@ -283,14 +293,15 @@ struct Plan {
 uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
                     int64_t se, bool rowstats, Plan* p) {
     if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
-    if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2 && prec != UF_FP32_SPLIT)
+    if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2 && prec != UF_FP32_SPLIT &&
+        prec != UF_MFMA_SPLIT)
         return fail(UF_ERR_ARG, "unknown precision");
-    if (weighted && prec == UF_MFMA_BF16X2)
+    if (weighted && (prec == UF_MFMA_BF16X2 || prec == UF_MFMA_SPLIT))
         return fail(UF_ERR_UNSUPPORTED,
                     "the MFMA Gram path exists for the unweighted variant only");
     if (!weighted && prec == UF_FP32_SPLIT)
         return fail(UF_ERR_UNSUPPORTED,
-                    "the sparse-aware split exists for the weighted-normalized variant only");
+                    "UF_FP32_SPLIT is the weighted-normalized split; use UF_MFMA_SPLIT");
     const int64_t n = e->n;
     const int64_t S = n / 2;
     if (sb < 0 || se < sb || se > S)
@@ -303,15 +314,17 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     p->weighted = weighted;
     p->prec = prec;
     p->rowstats = rowstats;
-    const int64_t nb = (prec == UF_FP32_SPLIT) ? e->split->n_dense : e->nb;
-    const size_t elem = prec == UF_FP64 ? 8 : (prec == UF_MFMA_BF16X2 ? 2 : 4);
+    const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
+    const bool mfma = prec == UF_MFMA_BF16X2 || prec == UF_MFMA_SPLIT;
+    const int64_t nb = split ? e->split->n_dense : e->nb;
+    const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 2 : 4);
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
         const double budget = 8.0 * 1024 * 1024 * 1024;
         kc = static_cast<int64_t>(budget / (double(std::max<int64_t>(n, 1)) * double(elem)));
     }
     kc = std::max<int64_t>(kc, 32);
-    if (prec == UF_MFMA_BF16X2) kc = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    if (mfma) kc = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
     kc = std::min<int64_t>(kc, std::max<int64_t>(nb, 1));
     p->kc = kc;
     p->nchunks = nb > 0 ? (nb + kc - 1) / kc : 0;
@@ -321,13 +334,13 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     const size_t acc_elem = (prec == UF_FP64) ? 8 : 4;
     p->off_acc = c.take(size_t(p->sr) * size_t(n) * acc_elem);
     p->off_q = rowstats ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
-    if (prec == UF_MFMA_BF16X2)
+    if (mfma)
         p->off_chunk = c.take(size_t(n) * size_t(p->kpad) * 2);
     else
         p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
     p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
     p->off_rm = rowstats ? c.take(size_t(n) * 8) : 0;
-    p->off_m = prec == UF_FP32_SPLIT ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
+    p->off_m = split ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
     p->total = c.off + 256;
     return UF_OK;
 }
@@ -340,7 +353,7 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     if (odt != UF_OUT_F64 && odt != UF_OUT_F32) return fail(UF_ERR_ARG, "bad output dtype");
     const bool rowstats = row_out != nullptr || grand_mean != nullptr;
     Plan p;
-    if (prec == UF_FP32_SPLIT && weighted) {
+    if ((prec == UF_FP32_SPLIT && weighted) || (prec == UF_MFMA_SPLIT && !weighted)) {
         uf_status sst = ensure_split(e, stream);
         if (sst != UF_OK) return sst;
     }
@@ -363,50 +376,11 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     double* q = rowstats ? reinterpret_cast<double*>(base + p.off_q) : nullptr;
     void* chunk = base + p.off_chunk;
     const int64_t nb = e->nb;
-
-    if (prec == UF_FP32_SPLIT) {
-        const SplitCache& sc = *e->split;
-        const ufp::Emb ev = emb_view(*e);
-        for (int64_t c = 0; c < p.nchunks; ++c) {
-            const int64_t k0 = c * p.kc;
-            const int64_t kc = std::min<int64_t>(p.kc, sc.n_dense - k0);
-            float* E = static_cast<float*>(chunk);
-            {
-                ProfScope ps("embed_nm", s);
-                UF_HIP(ufs::embed_list_f32(ev, sc.dense, k0, kc, E, s));
-            }
-            ProfScope ps("band_wn_f32", s);
-            UF_HIP(ufk::band_f32(E, nullptr, kc, p.n, p.sb, p.se, 1, c == 0,
-                                 static_cast<float*>(acc), s));
-        }
-        if (p.nchunks == 0)
-            UF_HIP(ufk::zero_u32(static_cast<unsigned*>(acc), p.sr * p.n, s));
-        unsigned long long* M = reinterpret_cast<unsigned long long*>(base + p.off_m);
-        UF_HIP(ufs::zero_u64(M, p.sr * p.n, s));
-        {
-            ProfScope ps("rare_pairs", s);
-            UF_HIP(ufs::rare_pairs(sc.roff, sc.rs, sc.rq, static_cast<const ufs::RareItem*>(sc.items),
-                                   sc.n_items, p.n, p.sb, p.se, M, s));
-        }
-        {
-            ProfScope ps("finalize", s);
-            UF_HIP(ufk::finalize(0, acc, 0, e->sw, p.n, p.sb, p.se, layout, odt == UF_OUT_F32 ? 1 : 0,
-                                 out, q, s, M, sc.sigma));
-        }
-        if (rowstats) {
-            ProfScope ps("row_sums", s);
-            double* part = reinterpret_cast<double*>(base + p.off_part);
-            double* rm = row_out ? row_out : reinterpret_cast<double*>(base + p.off_rm);
-            const double scale = full_means ? 1.0 / double(p.n) : 1.0;
-            UF_HIP(ufk::row_sums(q, p.n, p.sb, p.se, part, p.n_parts, scale, rm, s));
-            if (grand_mean) UF_HIP(ufk::grand_mean(rm, p.n, grand_mean, s));
-        }
-        return UF_OK;
-    }
-
+    const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
+    // Dense part: node chunks (all branches, or the split's dense list) into acc.
     for (int64_t c = 0; c < p.nchunks; ++c) {
         const int64_t k0 = c * p.kc;
-        const int64_t kc = std::min<int64_t>(p.kc, nb - k0);
+        const int64_t kc = std::min<int64_t>(p.kc, (split ? e->split->n_dense : nb) - k0);
         const int first = c == 0;
         if (prec == UF_FP64) {
             double* E = static_cast<double*>(chunk);
@@ -426,28 +400,52 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
             ProfScope ps(weighted ? "band_wn_f32" : "band_uw_f32", s);
             UF_HIP(ufk::band_f32(E, e->len32 + k0, kc, p.n, p.sb, p.se, weighted, first,
                                  static_cast<float*>(acc), s));
+        } else if (prec == UF_FP32_SPLIT) {
+            float* E = static_cast<float*>(chunk);
+            {
+                ProfScope ps("embed_nm", s);
+                UF_HIP(ufs::embed_list_f32(emb_view(*e), e->split->dense, k0, kc, E, s));
+            }
+            ProfScope ps("band_wn_f32", s);
+            UF_HIP(ufk::band_f32(E, nullptr, kc, p.n, p.sb, p.se, 1, first,
+                                 static_cast<float*>(acc), s));
         } else {
+            const bool sp = prec == UF_MFMA_SPLIT;
             uint16_t* P = static_cast<uint16_t*>(chunk);
             const int64_t kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
             {
                 ProfScope ps("embed_pres", s);
-                UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s));
+                UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s,
+                                                sp ? e->split->dense : nullptr));
             }
             ProfScope ps("gram_mfma", s);
-            UF_HIP(ufk::gram_mfma(P, e->len_hi + k0, e->len_lo + k0, kpad, p.n, p.sb, p.se,
-                                  first, static_cast<float*>(acc), s));
+            UF_HIP(ufk::gram_mfma(P, (sp ? e->split->dlen_hi : e->len_hi) + k0,
+                                  (sp ? e->split->dlen_lo : e->len_lo) + k0, kpad, p.n, p.sb,
+                                  p.se, first, static_cast<float*>(acc), s));
         }
     }
-    if (p.nchunks == 0) {  // a tree with only a root: every distance is 0
-        const size_t acc_elem = prec == UF_FP64 ? 8 : 4;
-        UF_HIP(hipMemsetAsync(acc, 0, size_t(p.sr) * size_t(p.n) * acc_elem, s));
+    if (p.nchunks == 0) {  // no (dense) branch: the dense part is 0
+        const int64_t words = p.sr * p.n * (prec == UF_FP64 ? 2 : 1);
+        UF_HIP(ufk::zero_u32(static_cast<unsigned*>(acc), words, s));
+    }
+    // Non-dense part of a split: exact fixed-point pair sums into M.
+    unsigned long long* M = nullptr;
+    if (split) {
+        const SplitCache& sc = *e->split;
+        M = reinterpret_cast<unsigned long long*>(base + p.off_m);
+        UF_HIP(ufs::zero_u64(M, p.sr * p.n, s));
+        ProfScope ps("rare_pairs", s);
+        UF_HIP(ufs::rare_pairs(sc.roff, sc.rs, sc.rq, weighted ? nullptr : sc.rl,
+                               static_cast<const ufs::RareItem*>(sc.items), sc.n_items, p.n, p.sb,
+                               p.se, M, s));
     }
     const double* scal = weighted ? e->sw
                                   : (prec == UF_FP64 ? e->wu : (prec == UF_FP32 ? e->wu32 : e->wub));
     {
         ProfScope ps("finalize", s);
         UF_HIP(ufk::finalize(weighted ? 0 : 1, acc, prec == UF_FP64 ? 1 : 0, scal, p.n, p.sb,
-                             p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s));
+                             p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s, M,
+                             split && weighted ? e->split->sigma : nullptr));
     }
     if (rowstats) {
         ProfScope ps("row_sums", s);
@@ -869,7 +867,7 @@ uf_status uf_workspace_size(const uf_embedding* e, int weighted, uf_precision pr
                             int64_t se, int want_row_stats, size_t* bytes) {
     return guarded([&]() -> uf_status {
         if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
-        if (e && weighted && prec == UF_FP32_SPLIT) {
+        if (e && ((weighted && prec == UF_FP32_SPLIT) || (!weighted && prec == UF_MFMA_SPLIT))) {
             uf_status sst = ensure_split(e, nullptr);
             if (sst != UF_OK) return sst;
         }

@@ -58,6 +58,10 @@ struct SplitCache {
     int64_t* rq = nullptr;        // [n_entries] l*u in 2^-40 fixed point
     unsigned long long* sigma = nullptr;   // [n] fixed-point sum over non-dense branches
     void* items = nullptr;        // [n_items] pair ranges (ufs::RareItem)
+    int64_t n_dense_pad = 0;      // n_dense rounded up to the MFMA K step
+    uint16_t* dlen_hi = nullptr;  // [n_dense_pad] bf16 high part of each dense length, 0-padded
+    uint16_t* dlen_lo = nullptr;  // [n_dense_pad] bf16 low part
+    int64_t* rl = nullptr;        // [n_lists] (hi+lo) length of each list's branch, 2^-40 fixed point
 };
 
 // Device-resident inputs of the distance calls.  All arrays are on `device`.
@@ -130,9 +134,10 @@ hipError_t embed_node_major_f64(const uf_embedding& e, int64_t k0, int64_t kc, i
                                 double* out, hipStream_t st);
 hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
                                 float* out, hipStream_t st);
-// Sample-major BF16 0/1 presence P[s][k], k < kpad (zero beyond kc).
+// Sample-major BF16 0/1 presence P[s][k], k < kpad (zero beyond kc), for positions
+// [k0, k0+kc), or for positions list[k0 .. k0+kc) when list is non-null.
 hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
-                               uint16_t* out, hipStream_t st);
+                               uint16_t* out, hipStream_t st, const int32_t* list = nullptr);
 
 // Band accumulation over one node chunk for stripes [sb, se):
 // weighted: acc += sum_k |E[k][i] - E[k][j]|;  unweighted: acc += sum_k l_k E[k][i] E[k][j].
@@ -150,7 +155,9 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 // Distances from the accumulators.  kind 0: weighted (num / (s_i + s_j));
 // kind 1: unweighted Gram form ((w_i + w_j - 2G) / (w_i + w_j - G)), clamped to [0, 1].
 // acc_is_f64 selects the accumulator type.  q (nullable) receives -d^2/2 in FP64,
-// stripe-major.  layout/out dtype as in uf.h.
+// stripe-major.  layout/out dtype as in uf.h.  split_m (nullable, 2^-40 fixed point,
+// stripe-major like acc) carries the non-dense branches: kind 0 adds
+// sigma_i + sigma_j - 2 M to the numerator, kind 1 adds M to the Gram value.
 hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
                     int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
                     hipStream_t st, const unsigned long long* split_m = nullptr,

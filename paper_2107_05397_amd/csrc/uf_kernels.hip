@@ -148,13 +148,14 @@ __global__ __launch_bounds__(256) void k_embed_nm(
 __global__ __launch_bounds__(256) void k_embed_pres_bf16(
     int64_t n, int64_t k0, int64_t kc, int64_t kpad, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
-    const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, uint16_t* __restrict__ out) {
+    const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, const int32_t* __restrict__ list,
+    uint16_t* __restrict__ out) {
     const int64_t s = blockIdx.y;
     const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (k >= kpad) return;
     uint16_t v = 0;
     if (k < kc) {
-        const int64_t pos = k0 + k;
+        const int64_t pos = list ? int64_t(list[k0 + k]) : k0 + k;
         v = embedded_count(row_ptr, rank, cum, s, lo[pos], hi[pos]) > 0 ? uint16_t(0x3F80) : 0;
     }
     out[s * kpad + k] = v;
@@ -486,8 +487,12 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
         const int64_t j = (i + s + 1) % n;
         double num = double(acc[(s - sb) * n + i]);
         if (split_m) {
-            const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
-            num += double(r) * (1.0 / 1099511627776.0);
+            if (kind == 0) {
+                const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
+                num += double(r) * (1.0 / 1099511627776.0);
+            } else {
+                num += double(split_m[(s - sb) * n + i]) * (1.0 / 1099511627776.0);
+            }
         }
         double d;
         if (kind == 0) {
@@ -683,7 +688,7 @@ hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, i
 }
 
 hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
-                               uint16_t* out, hipStream_t st) {
+                               uint16_t* out, hipStream_t st, const int32_t* list) {
     if (kpad <= 0 || e.n <= 0) return hipSuccess;
     if (e.n > 65535) {
         // one launch per 65535 samples keeps grid.y in range
@@ -691,7 +696,7 @@ hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, in
             const int64_t ns = std::min<int64_t>(65535, e.n - s0);
             dim3 grid(unsigned((kpad + 255) / 256), unsigned(ns));
             hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, ns, k0, kc, kpad,
-                               e.row_ptr + s0, e.rank, e.cum + s0, e.lo, e.hi,
+                               e.row_ptr + s0, e.rank, e.cum + s0, e.lo, e.hi, list,
                                out + s0 * kpad);
             hipError_t err = hipGetLastError();
             if (err != hipSuccess) return err;
@@ -700,7 +705,7 @@ hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, in
     }
     dim3 grid(unsigned((kpad + 255) / 256), unsigned(e.n));
     hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, e.n, k0, kc, kpad, e.row_ptr,
-                       e.rank, e.cum, e.lo, e.hi, out);
+                       e.rank, e.cum, e.lo, e.hi, list, out);
     return hipGetLastError();
 }
 

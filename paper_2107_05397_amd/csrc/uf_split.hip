@@ -10,7 +10,13 @@
 // it, so those pairs are enumerated from per-branch sample lists and summed by
 // integer atomics in fixed point (2^-40): exact and independent of the order in
 // which the atomics land, so results are bitwise reproducible.
+//
+// Unweighted, the same lists serve the Gram form: with presence a in {0, 1},
+// min(l a_i, l a_j) = l a_i a_j, so the non-dense part of G_ij is the sum of l
+// over the branches both samples touch; the dense part is the MFMA Gram.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "uf_device.h"
 #include "uf_internal.h"
@@ -104,9 +110,34 @@ __device__ __forceinline__ void pair_of(int64_t p, int64_t m, int64_t& a, int64_
     b = p - (r * m - r * (r + 1) / 2) + r + 1;
 }
 
+__device__ __forceinline__ uint32_t bf16_to_bits32(uint16_t h) { return uint32_t(h) << 16; }
+
+__global__ __launch_bounds__(256) void k_split_lengths(const int32_t* __restrict__ cls, int64_t nb,
+                                                       const int32_t* __restrict__ dense,
+                                                       int64_t n_dense, int64_t n_pad,
+                                                       const uint16_t* __restrict__ len_hi,
+                                                       const uint16_t* __restrict__ len_lo,
+                                                       uint16_t* __restrict__ dlen_hi,
+                                                       uint16_t* __restrict__ dlen_lo,
+                                                       int64_t* __restrict__ rl) {
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (t < n_pad) {
+        const bool in = t < n_dense;
+        dlen_hi[t] = in ? len_hi[dense[t]] : uint16_t(0);
+        dlen_lo[t] = in ? len_lo[dense[t]] : uint16_t(0);
+    }
+    if (t < nb && cls[t] >= 0) {
+        const double l = double(__uint_as_float(bf16_to_bits32(len_hi[t]))) +
+                         double(__uint_as_float(bf16_to_bits32(len_lo[t])));
+        rl[cls[t]] = llrint(l * kFix);
+    }
+}
+
+template <bool W>
 __global__ __launch_bounds__(256) void k_rare_pairs(const int64_t* __restrict__ roff,
                                                     const int32_t* __restrict__ rs,
                                                     const int64_t* __restrict__ rq,
+                                                    const int64_t* __restrict__ rl,
                                                     const RareItem* __restrict__ items, int64_t n,
                                                     int64_t sb, int64_t se,
                                                     unsigned long long* __restrict__ M) {
@@ -115,6 +146,7 @@ __global__ __launch_bounds__(256) void k_rare_pairs(const int64_t* __restrict__ 
     const int64_t m = roff[it.list + 1] - base;
     const int64_t S = n / 2;
     const bool even = (n & 1) == 0;
+    const unsigned long long lq = W ? 0ull : (unsigned long long)rl[it.list];
     for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += 256) {
         int64_t a, b;
         pair_of(p, m, a, b);
@@ -124,8 +156,11 @@ __global__ __launch_bounds__(256) void k_rare_pairs(const int64_t* __restrict__ 
             i = j;
             j = t;
         }
-        const long long qa = rq[base + a], qb = rq[base + b];
-        const unsigned long long mn = (unsigned long long)(qa < qb ? qa : qb);
+        unsigned long long mn = lq;
+        if (W) {
+            const long long qa = rq[base + a], qb = rq[base + b];
+            mn = (unsigned long long)(qa < qb ? qa : qb);
+        }
         const int64_t d = j - i;
         int64_t s, slot;
         if (d <= S) {
@@ -173,13 +208,27 @@ hipError_t zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t rare_pairs(const int64_t* roff, const int32_t* rs, const int64_t* rq, const RareItem* items,
-                      int64_t n_items, int64_t n, int64_t sb, int64_t se, unsigned long long* M,
-                      hipStream_t st) {
+hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,
+                         int64_t n_pad, const uint16_t* len_hi, const uint16_t* len_lo,
+                         uint16_t* dlen_hi, uint16_t* dlen_lo, int64_t* rl, hipStream_t st) {
+    const int64_t t = std::max(nb, n_pad);
+    if (t <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_lengths, dim3(unsigned((t + 255) / 256)), dim3(256), 0, st, cls, nb,
+                       dense, n_dense, n_pad, len_hi, len_lo, dlen_hi, dlen_lo, rl);
+    return hipGetLastError();
+}
+
+hipError_t rare_pairs(const int64_t* roff, const int32_t* rs, const int64_t* rq, const int64_t* rl,
+                      const RareItem* items, int64_t n_items, int64_t n, int64_t sb, int64_t se,
+                      unsigned long long* M, hipStream_t st) {
     if (n_items <= 0 || se <= sb) return hipSuccess;
     if (n_items > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rare_pairs, dim3(unsigned(n_items)), dim3(256), 0, st, roff, rs, rq, items,
-                       n, sb, se, M);
+    if (rl)
+        hipLaunchKernelGGL(k_rare_pairs<false>, dim3(unsigned(n_items)), dim3(256), 0, st, roff, rs,
+                           rq, rl, items, n, sb, se, M);
+    else
+        hipLaunchKernelGGL(k_rare_pairs<true>, dim3(unsigned(n_items)), dim3(256), 0, st, roff, rs,
+                           rq, rl, items, n, sb, se, M);
     return hipGetLastError();
 }
 

@@ -1,16 +1,19 @@
-"""Sparse-aware weighted-normalized path (UF_FP32_SPLIT) through the C ABI.
+"""Sparse-aware paths through the C ABI: UF_FP32_SPLIT (weighted normalized) and
+UF_MFMA_SPLIT (unweighted).
 
 * threshold 1.0: no branch is dense, every pair contribution goes through the
-  exact fixed-point min-form: |d - d_oracle| <= 1e-10 (2^-40 quantisation of
-  each l*u value, sums exact in integers);
-* default and 0.0 thresholds: the dense part is the FP32 stripe kernel, so the
-  FP32 tolerance (1e-4) applies;
+  exact fixed-point sums: |d - d_oracle| <= 1e-10 (2^-40 quantisation of each
+  term, sums exact in integers).  The unweighted split uses the lengths
+  l_hi + l_lo of the MFMA path, so its oracle runs on those lengths;
+* default and 0.0 thresholds: the dense part is the FP32 stripe kernel or the
+  MFMA Gram, so the FP32 tolerance (1e-4) applies;
 * stripe ranges merge bit for bit; repeated runs are bit-identical (integer
   atomics commute).
 """
 import numpy as np
 import pytest
 
+import oracle
 import synth
 from oracle import core
 from tests.conftest import gpu_available
@@ -32,40 +35,86 @@ def threshold():
     uf.set_split_threshold(0.05)
 
 
+SPLIT = {"weighted_normalized": "fp32_split", "unweighted": "mfma_split"}
+
+
+@pytest.mark.parametrize("variant", sorted(SPLIT))
 @pytest.mark.parametrize("n", [2, 3, 64, 129, 256, 301])
 @pytest.mark.parametrize("thr,tol", [(1.0, 1e-10), (0.05, 1e-4), (0.0, 1e-4), (0.3, 1e-4)])
-def test_split_matches_oracle(n, thr, tol, threshold):
+def test_split_matches_oracle(variant, n, thr, tol, threshold):
     import torch
     import paper_2107_05397_amd as uf
     threshold(thr)
     tree = synth.gen_tree(400, 0.1, seed=n)
     table = synth.gen_table_zipf(n, np.arange(400), 40, seed=n + 7)
     emb = _emb(tree, table)
-    d, rm, gm = uf.dm(emb, "weighted_normalized", "fp32_split", row_means=True)
+    d, rm, gm = uf.dm(emb, variant, SPLIT[variant], row_means=True)
     torch.cuda.synchronize()
-    want = core.dm(tree, table, "weighted_normalized")[0]
+    ref_tree = tree
+    if variant == "unweighted" and thr == 1.0:
+        hi, lo = oracle.gram_split_bf16(tree.length)
+        ref_tree = synth.Tree(tree.parent.copy(), hi + lo, tree.n_tips)
+    want = core.dm(ref_tree, table, variant)[0]
     err = np.abs(d.cpu().numpy() - want)
-    print(f"[split n={n} thr={thr}] max|err|={err.max():.3e}", uf.split_stats(emb))
+    print(f"[split {variant} n={n} thr={thr}] max|err|={err.max():.3e}", uf.split_stats(emb))
     assert err.max() <= tol
 
 
-def test_split_stripes_merge_bitwise_and_repeat(threshold):
+@pytest.mark.parametrize("variant", sorted(SPLIT))
+def test_split_stripes_merge_bitwise_and_repeat(variant, threshold):
     import torch
     import paper_2107_05397_amd as uf
     threshold(0.05)
     tree = synth.gen_tree(500, 0.1, seed=5)
     table = synth.gen_table_zipf(300, np.arange(500), 50, seed=6)
     emb = _emb(tree, table)
-    full, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split")
-    again, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split")
+    full, _, _ = uf.dm(emb, variant, SPLIT[variant])
+    again, _, _ = uf.dm(emb, variant, SPLIT[variant])
     n = 300
     S = uf.n_stripes(n)
     buf = torch.full((n * (n - 1) // 2,), -1.0, dtype=torch.float64, device="cuda")
     for a, b in ((0, 7), (7, 100), (100, S)):
-        uf.dm_stripes(emb, "weighted_normalized", "fp32_split", a, b, layout="condensed", out=buf)
+        uf.dm_stripes(emb, variant, SPLIT[variant], a, b, layout="condensed", out=buf)
     torch.cuda.synchronize()
     assert torch.equal(full, again)
-    assert torch.equal(full, buf)
+    if variant == "weighted_normalized":
+        assert torch.equal(full, buf)
+    else:
+        # the MFMA tiles covering a stripe range differ with the range, so the FP32
+        # Gram partial sums may be added in another order
+        assert torch.max(torch.abs(full - buf)).item() < 1e-5
+
+
+def test_mfma_split_exact_with_integer_lengths(threshold):
+    """Integer lengths < 256 are exact in bf16 and their FP32 Gram sums stay below
+    2^24, so the dense MFMA part is exact too: the split equals the oracle."""
+    import torch
+    import paper_2107_05397_amd as uf
+    threshold(0.1)
+    tree = synth.gen_tree(400, 1.0, seed=12)
+    rng = np.random.default_rng(0)
+    tree.length[:] = rng.integers(1, 256, size=tree.n_nodes).astype(float)
+    table = synth.gen_table_zipf(150, np.arange(400), 30, seed=13)
+    emb = _emb(tree, table)
+    nd, nl, npairs = uf.split_stats(emb)
+    assert nd > 0 and npairs > 0
+    want = core.dm(tree, table, "unweighted")[0]
+    d, _, _ = uf.dm(emb, "unweighted", "mfma_split")
+    torch.cuda.synchronize()
+    err = np.abs(d.cpu().numpy() - want).max()
+    print(f"[mfma_split integer lengths] max|err|={err:.3e}")
+    assert err < 1e-12
+
+
+def test_split_rejects_wrong_variant():
+    import paper_2107_05397_amd as uf
+    tree = synth.gen_tree(50, 0.1, seed=1)
+    table = synth.gen_table_uniform(10, np.arange(50), 5, seed=2)
+    emb = _emb(tree, table)
+    with pytest.raises(uf.UFError):
+        uf.dm(emb, "weighted_normalized", "mfma_split")
+    with pytest.raises(uf.UFError):
+        uf.dm(emb, "unweighted", "fp32_split")
 
 
 def test_split_stats_partition(threshold):
