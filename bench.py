@@ -10,12 +10,18 @@ branch lengths; 25,000 samples with ~1,000 distinct Zipf(1.1)-popular tips
 each and round(LogNormal(2, 1.5)) + 1 counts; seed 102.
 
 One step = the whole hot path over that table with the inputs resident on the
-device: the weighted-normalized matrix (FP32 stripe kernel) and the unweighted
-matrix (split-BF16 Gram product on MFMA), each with the chunked embedding,
-accumulation, FP64 finalize into a condensed FP64 matrix and the PCoA row
-means and grand mean.  Printed: one JSON line on stdout.
+device: the weighted-normalized matrix and the unweighted matrix, each with
+the chunked embedding, accumulation, FP64 finalize into a condensed FP64
+matrix and the PCoA row means and grand mean.  By default both run sparse
+aware: branches touched by many samples on the dense kernel (FP32 stripe
+kernel, weighted; split-BF16 Gram on MFMA, unweighted), every other branch
+as exact fixed-point sums over the sample pairs that share it, with the
+automatic dense-set cost model.  The split itself is built once per table
+before the timed steps.  Printed: one JSON line on stdout.
 
-    python bench.py [--steps K] [--warmup W] [--workload C2|C1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload C1|C2|C3|C4|C5]
+                    [--weighted-precision P] [--unweighted-precision P]
+                    [--split-threshold F] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -173,10 +179,12 @@ def bench_batch(args) -> int:
                                f"weighted normalized FP32, one hipGraph",
                    "n_tables": len(tables), "samples": sum(sizes), "pairs": pairs,
                    "updates_per_step": U, "parallelism": "single-gpu"},
-        "roofline": {"bound": "alu", "achieved": 2 * slots / 1e12,
-                     "peak": 2 * PEAK_VALU_SLOTS["fp32"] / 1e12, "unit": "TFLOP/s",
+        "roofline": {"bound": "alu", "achieved": slots / 1e12,
+                     "peak": PEAK_VALU_SLOTS["fp32"] / 1e12, "unit": "Tops/s",
                      "frac": slots / PEAK_VALU_SLOTS["fp32"], "traffic": None,
-                     "note": "whole batch (embed + persistent band + finalize) per step"},
+                     "note": "VALU lane-ops (2 per update) over the whole batch (embed + "
+                             "persistent band + finalize) per step; peak 256 CU x 128 lanes/clk "
+                             "x 2.4 GHz"},
         "extra": {"graph_s": graph_s, "eager_batch_s": eager_s,
                   "separate_single_table_calls_s": separate_s,
                   "autotuned_config": dict(zip(("stage_branches", "wgs_per_cu", "chunk_nodes"),
@@ -225,9 +233,11 @@ def main() -> int:
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
     ap.add_argument("--tune-cache", default=None, help="C4: autotuner cache path")
     ap.add_argument("--samples", type=int, default=None, help="override the sample count")
-    ap.add_argument("--weighted-precision", default="fp32", choices=["fp32", "fp64", "fp32_split"])
-    ap.add_argument("--split-threshold", type=float, default=0.05)
-    ap.add_argument("--unweighted-precision", default="mfma",
+    ap.add_argument("--weighted-precision", default="fp32_split",
+                    choices=["fp32_split", "fp32", "fp64"])
+    ap.add_argument("--split-threshold", type=float, default=None,
+                    help="dense-set fraction of the sparse-aware split (default: automatic)")
+    ap.add_argument("--unweighted-precision", default="mfma_split",
                     choices=["mfma", "mfma_split", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -278,13 +288,14 @@ def main() -> int:
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     wp, up = args.weighted_precision, args.unweighted_precision
-    split = None
-    if wp == "fp32_split" or up == "mfma_split":
-        uf.set_split_threshold(args.split_threshold)
-        t_split = time.perf_counter()
-        split = uf.split_stats(emb)        # builds the split once, outside the timed steps
-        log(f"split: {split[0]} dense branches, {split[1]} shared lists, {split[2]:.3e} pairs "
-            f"({time.perf_counter() - t_split:.2f}s)")
+    splits = {}
+    uf.set_split_threshold(args.split_threshold)
+    for var, prec in (("weighted_normalized", wp), ("unweighted", up)):
+        if prec.endswith("_split"):
+            t_split = time.perf_counter()
+            splits[var] = uf.split_stats(emb, var)   # built once, outside the timed steps
+            log(f"split {var}: {splits[var][0]} dense branches, {splits[var][1]} shared lists, "
+                f"{splits[var][2]:.3e} pairs ({time.perf_counter() - t_split:.2f}s)")
     out_w = torch.empty(pairs, dtype=torch.float64, device="cuda")
     out_u = torch.empty(pairs, dtype=torch.float64, device="cuda")
     ws_w = torch.empty(uf.workspace_size(emb, "weighted_normalized", wp, row_stats=True),
@@ -319,40 +330,50 @@ def main() -> int:
     value = 2 * U / (ms_step / 1e3)
 
     kern = {}
-    for name in ("embed_nm", "embed_pres", "band_wn_f32", "band_wn_f64", "band_uw_f32",
+    for name in ("embed_nm", "embed_pres", "band_wn_u32", "band_wn_f32", "band_wn_f64", "band_uw_f32",
                  "band_uw_f64", "gram_mfma", "rare_pairs", "finalize", "row_sums"):
         tot, cnt = uf.profile_read(name)
         if cnt:
             kern[name] = {"total_ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
                           "avg_ms_per_launch": tot / cnt}
-    band = "band_wn_f64" if wp == "fp64" else "band_wn_f32"
+    # dominant kernel: the weighted stripe kernel (FP64, FP32, or the 32-bit
+    # fixed-point pass of the split).  Counted in VALU lane-ops: FP64/FP32 take 2 per
+    # update (subtract, add of |.|), fixed point 1 (v_sad_u32: |a - b| + acc).  The
+    # peak is 256 CU x 128 lanes/clk x 2.4 GHz = 78.6e12 lane-ops/s for 32-bit ops
+    # (the published 157.3 TFLOP/s FP32 counts an FMA as 2 flops), 39.3e12 for FP64.
+    # With the split the stripe kernel visits only the dense branches.
+    if wp == "fp64":
+        band, ops, peak_ops, kname = "band_wn_f64", 2, PEAK_VALU_SLOTS["fp64"], "k_band<double,weighted>"
+    elif "band_wn_u32" in kern:
+        band, ops, peak_ops, kname = "band_wn_u32", 1, PEAK_VALU_SLOTS["fp32"], "k_band<uint32_t,weighted>"
+    else:
+        band, ops, peak_ops, kname = "band_wn_f32", 2, PEAK_VALU_SLOTS["fp32"], "k_band<float,weighted>"
     band_ms = kern[band]["total_ms_per_step"]
-    # weighted stripe kernel: 2 VALU slots per update (subtract, add |.|); reported in
-    # FMA-equivalent TFLOP/s (2 flops per slot) against the published vector peak.
-    # With the split the band kernel visits only the dense branches.
-    band_updates = pairs * split[0] if wp == "fp32_split" else U
-    slots = 2 * band_updates / (band_ms / 1e3)
-    peak_slots = PEAK_VALU_SLOTS["fp64" if wp == "fp64" else "fp32"]
+    band_updates = pairs * splits["weighted_normalized"][0] if wp == "fp32_split" else U
+    lane_ops = ops * band_updates / (band_ms / 1e3)
     traffic = measured_traffic(band, args.workload)
-    roofline = {"bound": "alu", "kernel": f"k_band<{'double' if wp == 'fp64' else 'float'},weighted>",
-                "achieved": 2 * slots / 1e12, "peak": 2 * peak_slots / 1e12,
-                "unit": "TFLOP/s", "frac": slots / peak_slots, "traffic": traffic,
+    roofline = {"bound": "alu", "kernel": kname,
+                "achieved": lane_ops / 1e12, "peak": peak_ops / 1e12,
+                "unit": "Tops/s", "frac": lane_ops / peak_ops, "traffic": traffic,
                 "avg_launch_ms": kern[band]["avg_ms_per_launch"],
                 "launches_per_step": kern[band]["launches_per_step"],
-                "note": "2 VALU issue slots (subtract, add of |x|) per pair-node update, each "
-                        "slot counted as 2 flops (FMA-equivalent) so the peak is the published "
-                        "vector rate: FP32 157.3, FP64 78.6 TFLOP/s (256 CU, 2.4 GHz)"}
+                "updates_per_launch": band_updates / kern[band]["launches_per_step"],
+                "note": f"{ops} VALU lane-op(s) per pair-branch update; peak = 256 CU x 128 "
+                        "lanes/clk x 2.4 GHz (32-bit) or half that (FP64); one lane-op = "
+                        "one issue slot, i.e. half of an FMA's 2 flops"}
     extra = {"kernels": kern}
-    if split is not None:
+    if splits:
         r_ms = kern.get("rare_pairs", {}).get("total_ms_per_step", 0.0)
-        extra["split"] = {"threshold": args.split_threshold, "dense_branches": split[0],
-                          "shared_lists": split[1], "pairs_enumerated": split[2],
+        n_atomics = sum(v[2] for v in splits.values())
+        extra["split"] = {"threshold": args.split_threshold if args.split_threshold is not None
+                          else "automatic",
+                          **{var: {"dense_branches": v[0], "shared_lists": v[1],
+                                   "pairs_enumerated": v[2]} for var, v in splits.items()},
                           "band_updates_per_step": band_updates,
-                          "rare_pair_atomics_per_s": (split[2] * ((wp == "fp32_split") + (up == "mfma_split"))
-                                                      / (r_ms / 1e3)) if r_ms else None}
+                          "rare_pair_atomics_per_s": n_atomics / (r_ms / 1e3) if r_ms else None}
     if "gram_mfma" in kern:
         g_ms = kern["gram_mfma"]["total_ms_per_step"]
-        g_upd = pairs * split[0] if up == "mfma_split" else U
+        g_upd = pairs * splits["unweighted"][0] if up == "mfma_split" else U
         extra["mfma_roofline"] = {"bound": "mfma", "achieved": 4 * g_upd / (g_ms / 1e3) / 1e12,
                                   "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                                   "frac": 4 * g_upd / (g_ms / 1e3) / PEAK_BF16_MFMA,
@@ -389,6 +410,14 @@ def main() -> int:
             extra["mfma_speedup_over_plain_fp32"] = (extra["unweighted_plain_fp32"]["seconds"] /
                                                      (kern["gram_mfma"]["total_ms_per_step"] / 1e3))
 
+    # arithmetic types of the kernels that ran: weighted dense part, split pair sums,
+    # unweighted dense part
+    parts = [{"band_wn_u32": "u32", "band_wn_f32": "f32", "band_wn_f64": "f64"}[band]]
+    if splits:
+        parts.append("u64")
+    parts.append({"mfma": "bf16", "mfma_split": "bf16", "fp32": "f32", "fp64": "f64"}[up])
+    dtype = "+".join(dict.fromkeys(parts))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
@@ -405,7 +434,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: random-merge tree {tree.n_tips} tips "
                                f"({m} nodes), {n} samples, both variants, condensed FP64 "

@@ -137,15 +137,20 @@ uf_status uf_workspace_size(const uf_embedding* emb, int weighted, uf_precision 
  * 8 GiB of chunk buffer).  Process-wide; affects later workspace sizes. */
 void uf_set_chunk_nodes(int64_t nodes);
 
-/* UF_FP32_SPLIT, UF_MFMA_SPLIT: the dense set is the branches touched by more than
- * `fraction` x N samples (default 0.05; process-wide).  The split of an
- * embedding is built on first use and rebuilt when the fraction changes. */
-void uf_set_split_threshold(double fraction);
-/* Size of the split of `emb` at the current threshold: dense branches, shared
- * non-dense branches, and sample pairs enumerated over them (builds the split
- * if needed; synchronous). */
-uf_status uf_split_stats(const uf_embedding* emb, int64_t* n_dense, int64_t* n_lists,
-                         int64_t* n_pairs);
+/* UF_FP32_SPLIT (weighted != 0), UF_MFMA_SPLIT (weighted == 0): the dense set
+ * of that variant's split.  fraction in [0, 1]: a branch is dense when more
+ * than fraction x N samples touch it.  fraction < 0 (the default): automatic,
+ * a branch is dense when its c(c-1)/2 sample pairs would take longer as
+ * fixed-point atomics than one pass of the variant's dense kernel over all
+ * N x floor(N/2) stripe slots (rates measured on MI355X).  Process-wide; the
+ * split of an embedding is built on first use and rebuilt when its variant's
+ * threshold changes.  UF_ERR_ARG for fraction > 1 or NaN. */
+uf_status uf_set_split_threshold(int weighted, double fraction);
+/* Size of the split of `emb` for one variant at its current threshold: dense
+ * branches, shared non-dense branches, and sample pairs enumerated over them
+ * (builds the split if needed; synchronous). */
+uf_status uf_split_stats(const uf_embedding* emb, int weighted, int64_t* n_dense,
+                         int64_t* n_lists, int64_t* n_pairs);
 
 /* ---- distance matrices --------------------------------------------------- */
 

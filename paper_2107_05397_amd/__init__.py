@@ -67,8 +67,8 @@ _SIGS = {
     "uf_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "uf_set_chunk_nodes": (None, [_i64]),
-    "uf_set_split_threshold": (None, [ctypes.c_double]),
-    "uf_split_stats": (ctypes.c_int, [_vp, _i64p, _i64p, _i64p]),
+    "uf_set_split_threshold": (ctypes.c_int, [ctypes.c_int, ctypes.c_double]),
+    "uf_split_stats": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, _i64p, _i64p]),
     "uf_dm_unweighted": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp,
                                         ctypes.c_size_t, _vp]),
     "uf_dm_weighted_normalized": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
@@ -172,15 +172,19 @@ def set_chunk_nodes(nodes: int) -> None:
     lib().uf_set_chunk_nodes(int(nodes))
 
 
-def set_split_threshold(fraction: float) -> None:
-    """Dense-set threshold of the sparse-aware split (fraction of samples)."""
-    lib().uf_set_split_threshold(float(fraction))
+def set_split_threshold(fraction: Optional[float] = None, variant: Optional[str] = None) -> None:
+    """Dense-set threshold of the sparse-aware split, as a fraction of the samples
+    (None: automatic cost model), for one variant or (variant None) both."""
+    f = -1.0 if fraction is None else float(fraction)
+    for v in ((variant,) if variant else ("unweighted", "weighted_normalized")):
+        _check(lib().uf_set_split_threshold(_variant(v), f))
 
 
-def split_stats(emb) -> Tuple[int, int, int]:
+def split_stats(emb, variant: str = "weighted_normalized") -> Tuple[int, int, int]:
     """(dense branches, shared non-dense branches, enumerated pairs) of the split."""
     a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
-    _check(lib().uf_split_stats(emb.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    _check(lib().uf_split_stats(emb.handle, _variant(variant), ctypes.byref(a), ctypes.byref(b),
+                                ctypes.byref(c)))
     return int(a.value), int(b.value), int(c.value)
 
 

@@ -24,7 +24,17 @@ namespace {
 
 thread_local std::string g_last_error;
 std::atomic<int64_t> g_chunk_nodes{0};
-std::atomic<double> g_split_threshold{0.05};
+// Dense-set thresholds of the sparse-aware split, [0] unweighted, [1] weighted;
+// negative = automatic (cost model in ensure_split).
+std::atomic<double> g_split_threshold[2] = {{-1.0}, {-1.0}};
+
+// Measured MI355X rates of the split's two halves (pair updates per second,
+// chunk embedding included, C2-sized inputs): the weighted dense stripe pass
+// (32-bit fixed point; FP32 is within 10%), the BF16x2 MFMA Gram, and the
+// marginal rate of the slot kernel over the pairs that share a non-dense branch.
+constexpr double kRateBandDense = 2.9e13;
+constexpr double kRateGramMfma = 1.55e14;
+constexpr double kRatePairs = 3.5e11;
 
 uf_status fail(uf_status st, const std::string& msg) {
     g_last_error = msg;
@@ -183,23 +193,66 @@ void free_split(SplitCache* sc) {
     delete sc;
 }
 
+// Scale Q of the 32-bit fixed-point dense pass of the weighted split (0: use FP32).
+// x_int = rint(x Q) is off by at most 1/(2Q) per value, so a pair's numerator is off
+// by at most (nnz_i + nnz_j) / (2Q) (nnz: dense branches of nonzero length touched),
+// and d by at most that over s_i + s_j <= max_s(nnz_s / s_s) / (2Q).  Q keeps every
+// pair sum, Q (m_i + m_j) plus rounding, below 2^32 (m: dense mass of a sample);
+// the fixed-point pass is taken when the bound on d is at most 1e-5.
+double fixed_point_scale(const std::vector<double>& sw, const std::vector<unsigned long long>& sigma,
+                         const std::vector<int32_t>& nnz, int64_t n_dense) {
+    constexpr double kMaxDistErr = 1e-5;
+    if (n_dense >= (int64_t(1) << 22)) return 0.0;
+    double m_max = 0.0, ratio = 0.0;
+    for (size_t s = 0; s < nnz.size(); ++s) {
+        const double m = std::max(sw[s] - double(sigma[s]) * 0x1p-40, 0.0);
+        m_max = std::max(m_max, m);
+        if (nnz[s] > 0) {
+            if (!(sw[s] > 0.0)) return 0.0;
+            ratio = std::max(ratio, double(nnz[s]) / sw[s]);
+        }
+    }
+    if (m_max <= 0.0) return 1.0;   // every dense value is 0
+    const double q = (0x1p32 - 0x1p23) / (2.0 * m_max);
+    return ratio / (2.0 * q) <= kMaxDistErr ? q : 0.0;
+}
+
 // Build (or rebuild for a new threshold) the dense set and the shared
 // non-dense branch lists of an embedding.  Synchronous on `stream`.
-uf_status ensure_split(const uf_embedding* ce, void* stream) {
+//
+// A branch touched by c samples costs c(c-1)/2 pair atomics when left out of the
+// dense set, and one pass over all N*floor(N/2) stripe slots of the dense kernel
+// when put in it.  With a fixed threshold f it is dense when c > f*N; with the
+// automatic one when c(c-1)/2 / kRatePairs > N*floor(N/2) / rate of the
+// variant's dense kernel, i.e. when it is cheaper in the dense kernel.
+uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     uf_embedding* e = const_cast<uf_embedding*>(ce);   // the cache is internal state
+    const int w = weighted ? 1 : 0;
     std::lock_guard<std::mutex> lk(e->split_mu);
-    const double thr = g_split_threshold.load();
-    if (e->split && e->split->threshold == thr) return UF_OK;
-    free_split(e->split);
-    e->split = nullptr;
+    const double thr = g_split_threshold[w].load();
+    if (e->split[w] && e->split[w]->threshold == thr) return UF_OK;
+    free_split(e->split[w]);
+    e->split[w] = nullptr;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = e->n, nb = e->nb;
     const ufp::Emb ev = emb_view(*e);
-    int32_t* dcnt = nullptr;
-    if (hipMalloc(&dcnt, size_t(std::max<int64_t>(nb, 1)) * 4) != hipSuccess)
-        return fail(UF_ERR_NOMEM, "branch counts");
-    std::unique_ptr<void, void (*)(void*)> gc(dcnt, [](void* q) { (void)hipFree(q); });
-    UF_HIP(hipMemsetAsync(dcnt, 0, size_t(std::max<int64_t>(nb, 1)) * 4, s));
+    // temporaries: branch counts, unsorted lists, list fill and per-sample cursors
+    std::vector<void*> tmp;
+    auto tmp_alloc = [&](size_t bytes) -> void* {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+        tmp.push_back(q);
+        return q;
+    };
+    struct Freer {
+        std::vector<void*>& v;
+        ~Freer() {
+            for (void* q : v) (void)hipFree(q);
+        }
+    } freer{tmp};
+    int32_t* dcnt = static_cast<int32_t*>(tmp_alloc(size_t(nb) * 4));
+    if (!dcnt) return fail(UF_ERR_NOMEM, "branch counts");
+    UF_HIP(hipMemsetAsync(dcnt, 0, std::max<size_t>(size_t(nb) * 4, 256), s));
     UF_HIP(ufs::branch_count(ev, dcnt, s));
     std::vector<int32_t> cnt(size_t(std::max<int64_t>(nb, 1)), 0);
     UF_HIP(hipStreamSynchronize(s));
@@ -208,41 +261,40 @@ uf_status ensure_split(const uf_embedding* ce, void* stream) {
     sc->threshold = thr;
     std::vector<int32_t> cls(size_t(std::max<int64_t>(nb, 1)), ufs::kClassAlone), dense;
     std::vector<int64_t> roff(1, 0);
-    std::vector<ufs::RareItem> items;
     const double lim = thr * double(n);
-    constexpr int64_t kPairsPerItem = 1 << 15;
+    const double pair_lim = 2.0 * double(n) * double(n / 2) * kRatePairs /
+                            (weighted ? kRateBandDense : kRateGramMfma);
     for (int64_t v = 0; v < nb; ++v) {
         const int64_t c = cnt[size_t(v)];
-        if (double(c) > lim) {
+        const bool is_dense = thr >= 0.0 ? double(c) > lim : double(c) * double(c - 1) > pair_lim;
+        if (is_dense) {
             cls[size_t(v)] = ufs::kClassDense;
             dense.push_back(int32_t(v));
         } else if (c >= 2) {
-            const int64_t li = int64_t(roff.size()) - 1;
-            cls[size_t(v)] = int32_t(li);
+            cls[size_t(v)] = int32_t(roff.size()) - 1;
             roff.push_back(roff.back() + c);
-            const int64_t np = c * (c - 1) / 2;
-            for (int64_t p0 = 0; p0 < np; p0 += kPairsPerItem)
-                items.push_back(ufs::RareItem{li, p0, std::min(np, p0 + kPairsPerItem)});
-            sc->n_pairs += np;
+            sc->n_pairs += c * (c - 1) / 2;
         }
     }
     sc->n_dense = int64_t(dense.size());
     sc->n_lists = int64_t(roff.size()) - 1;
     sc->n_entries = roff.back();
-    sc->n_items = int64_t(items.size());
+    sc->n_dense_pad = (sc->n_dense + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    const size_t ne = size_t(std::max<int64_t>(sc->n_entries, 1));
+    const size_t nl = size_t(std::max<int64_t>(sc->n_lists, 1));
     Carver c;
     const size_t o_dense = c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4);
     const size_t o_cls = c.take(size_t(std::max<int64_t>(nb, 1)) * 4);
     const size_t o_roff = c.take(roff.size() * 8);
-    const size_t o_rs = c.take(size_t(std::max<int64_t>(sc->n_entries, 1)) * 4);
-    const size_t o_rq = c.take(size_t(std::max<int64_t>(sc->n_entries, 1)) * 8);
+    const size_t o_rs = c.take(ne * 4);
+    const size_t o_rq = c.take(ne * 8);
     const size_t o_sig = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
-    const size_t o_items = c.take(sizeof(ufs::RareItem) * size_t(std::max<int64_t>(sc->n_items, 1)));
-    const size_t o_fill = c.take(size_t(std::max<int64_t>(sc->n_lists, 1)) * 4);
-    sc->n_dense_pad = (sc->n_dense + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
     const size_t o_dhi = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
     const size_t o_dlo = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
-    const size_t o_rl = c.take(size_t(std::max<int64_t>(sc->n_lists, 1)) * 8);
+    const size_t o_rl = c.take(nl * 8);
+    const size_t o_soff = c.take(size_t(n + 1) * 8);
+    const size_t o_sll = c.take(ne * 4);
+    const size_t o_slp = c.take(ne * 4);
     if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
     char* b = static_cast<char*>(sc->arena);
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
@@ -251,31 +303,61 @@ uf_status ensure_split(const uf_embedding* ce, void* stream) {
     sc->rs = reinterpret_cast<int32_t*>(b + o_rs);
     sc->rq = reinterpret_cast<int64_t*>(b + o_rq);
     sc->sigma = reinterpret_cast<unsigned long long*>(b + o_sig);
-    sc->items = b + o_items;
-    int32_t* fill = reinterpret_cast<int32_t*>(b + o_fill);
     sc->dlen_hi = reinterpret_cast<uint16_t*>(b + o_dhi);
     sc->dlen_lo = reinterpret_cast<uint16_t*>(b + o_dlo);
     sc->rl = reinterpret_cast<int64_t*>(b + o_rl);
+    sc->soff = reinterpret_cast<int64_t*>(b + o_soff);
+    sc->sl_list = reinterpret_cast<int32_t*>(b + o_sll);
+    sc->sl_pos = reinterpret_cast<int32_t*>(b + o_slp);
     auto fail_free = [&](uf_status code) {
         (void)hipFree(sc->arena);
         sc->arena = nullptr;
         return code;
     };
+    int32_t* rs_tmp = static_cast<int32_t*>(tmp_alloc(ne * 4));
+    int64_t* rq_tmp = static_cast<int64_t*>(tmp_alloc(ne * 8));
+    int32_t* fill = static_cast<int32_t*>(tmp_alloc(nl * 4));
+    int32_t* scnt = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
+    int32_t* scur = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
+    int32_t* dnnz = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
+    if (!rs_tmp || !rq_tmp || !fill || !scnt || !scur || !dnnz)
+        return fail_free(fail(UF_ERR_NOMEM, "split temporaries"));
     hipError_t rc = hipSuccess;
     if (sc->n_dense) rc = hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice);
     if (rc == hipSuccess && nb) rc = hipMemcpy(sc->cls, cls.data(), size_t(nb) * 4, hipMemcpyHostToDevice);
     if (rc == hipSuccess) rc = hipMemcpy(sc->roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice);
-    if (rc == hipSuccess && sc->n_items)
-        rc = hipMemcpy(sc->items, items.data(), sizeof(ufs::RareItem) * size_t(sc->n_items), hipMemcpyHostToDevice);
-    if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, size_t(std::max<int64_t>(sc->n_lists, 1)) * 4, s);
+    if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, nl * 4, s);
+    if (rc == hipSuccess) rc = hipMemsetAsync(scnt, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
+    if (rc == hipSuccess) rc = hipMemsetAsync(scur, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
+    if (rc == hipSuccess) rc = hipMemsetAsync(dnnz, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
     if (rc == hipSuccess) rc = hipMemsetAsync(sc->sigma, 0, size_t(std::max<int64_t>(n, 1)) * 8, s);
-    if (rc == hipSuccess) rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, sc->rs, sc->rq, sc->sigma, s);
+    if (rc == hipSuccess)
+        rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz, s);
+    const size_t nn = size_t(std::max<int64_t>(n, 1));
+    std::vector<int32_t> hcnt(nn, 0), hdnnz(nn, 0);
+    std::vector<double> hsw(nn, 0.0);
+    std::vector<unsigned long long> hsig(nn, 0);
+    if (rc == hipSuccess) rc = hipStreamSynchronize(s);
+    if (rc == hipSuccess && n) rc = hipMemcpy(hcnt.data(), scnt, size_t(n) * 4, hipMemcpyDeviceToHost);
+    if (rc == hipSuccess && n) rc = hipMemcpy(hdnnz.data(), dnnz, size_t(n) * 4, hipMemcpyDeviceToHost);
+    if (rc == hipSuccess && n) rc = hipMemcpy(hsw.data(), e->sw, size_t(n) * 8, hipMemcpyDeviceToHost);
+    if (rc == hipSuccess && n)
+        rc = hipMemcpy(hsig.data(), sc->sigma, size_t(n) * 8, hipMemcpyDeviceToHost);
+    if (rc == hipSuccess && weighted) sc->q_scale = fixed_point_scale(hsw, hsig, hdnnz, sc->n_dense);
+    std::vector<int64_t> soff(size_t(n + 1), 0);
+    for (int64_t i = 0; i < n; ++i) soff[size_t(i + 1)] = soff[size_t(i)] + hcnt[size_t(i)];
+    if (rc == hipSuccess && soff[size_t(n)] != sc->n_entries)
+        return fail_free(fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree"));
+    if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
+    if (rc == hipSuccess)
+        rc = ufs::sort_lists(sc->roff, sc->n_lists, rs_tmp, rq_tmp, sc->rs, sc->rq, sc->soff, scur,
+                             sc->sl_list, sc->sl_pos, s);
     if (rc == hipSuccess)
         rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
                                 e->len_lo, sc->dlen_hi, sc->dlen_lo, sc->rl, s);
     if (rc == hipSuccess) rc = hipStreamSynchronize(s);
     if (rc != hipSuccess) return fail_free(hip_fail(rc, "sparse split build"));
-    e->split = sc.release();
+    e->split[w] = sc.release();
     return UF_OK;
 }
 
@@ -316,7 +398,7 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     p->rowstats = rowstats;
     const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
     const bool mfma = prec == UF_MFMA_BF16X2 || prec == UF_MFMA_SPLIT;
-    const int64_t nb = split ? e->split->n_dense : e->nb;
+    const int64_t nb = split ? e->split[weighted ? 1 : 0]->n_dense : e->nb;
     const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 2 : 4);
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
@@ -354,7 +436,7 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     const bool rowstats = row_out != nullptr || grand_mean != nullptr;
     Plan p;
     if ((prec == UF_FP32_SPLIT && weighted) || (prec == UF_MFMA_SPLIT && !weighted)) {
-        uf_status sst = ensure_split(e, stream);
+        uf_status sst = ensure_split(e, weighted, stream);
         if (sst != UF_OK) return sst;
     }
     uf_status st = make_plan(e, weighted, prec, sb, se, rowstats, &p);
@@ -377,10 +459,11 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     void* chunk = base + p.off_chunk;
     const int64_t nb = e->nb;
     const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
+    const SplitCache* sp = split ? e->split[weighted ? 1 : 0] : nullptr;
     // Dense part: node chunks (all branches, or the split's dense list) into acc.
     for (int64_t c = 0; c < p.nchunks; ++c) {
         const int64_t k0 = c * p.kc;
-        const int64_t kc = std::min<int64_t>(p.kc, (split ? e->split->n_dense : nb) - k0);
+        const int64_t kc = std::min<int64_t>(p.kc, (sp ? sp->n_dense : nb) - k0);
         const int first = c == 0;
         if (prec == UF_FP64) {
             double* E = static_cast<double*>(chunk);
@@ -400,27 +483,35 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
             ProfScope ps(weighted ? "band_wn_f32" : "band_uw_f32", s);
             UF_HIP(ufk::band_f32(E, e->len32 + k0, kc, p.n, p.sb, p.se, weighted, first,
                                  static_cast<float*>(acc), s));
+        } else if (prec == UF_FP32_SPLIT && sp->q_scale > 0.0) {
+            uint32_t* E = static_cast<uint32_t*>(chunk);
+            {
+                ProfScope ps("embed_nm", s);
+                UF_HIP(ufs::embed_list_u32(emb_view(*e), sp->dense, k0, kc, sp->q_scale, E, s));
+            }
+            ProfScope ps("band_wn_u32", s);
+            UF_HIP(ufk::band_u32(E, kc, p.n, p.sb, p.se, first, static_cast<uint32_t*>(acc), s));
         } else if (prec == UF_FP32_SPLIT) {
             float* E = static_cast<float*>(chunk);
             {
                 ProfScope ps("embed_nm", s);
-                UF_HIP(ufs::embed_list_f32(emb_view(*e), e->split->dense, k0, kc, E, s));
+                UF_HIP(ufs::embed_list_f32(emb_view(*e), sp->dense, k0, kc, E, s));
             }
             ProfScope ps("band_wn_f32", s);
             UF_HIP(ufk::band_f32(E, nullptr, kc, p.n, p.sb, p.se, 1, first,
                                  static_cast<float*>(acc), s));
         } else {
-            const bool sp = prec == UF_MFMA_SPLIT;
+            const bool ms = prec == UF_MFMA_SPLIT;
             uint16_t* P = static_cast<uint16_t*>(chunk);
             const int64_t kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
             {
                 ProfScope ps("embed_pres", s);
                 UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s,
-                                                sp ? e->split->dense : nullptr));
+                                                ms ? sp->dense : nullptr));
             }
             ProfScope ps("gram_mfma", s);
-            UF_HIP(ufk::gram_mfma(P, (sp ? e->split->dlen_hi : e->len_hi) + k0,
-                                  (sp ? e->split->dlen_lo : e->len_lo) + k0, kpad, p.n, p.sb,
+            UF_HIP(ufk::gram_mfma(P, (ms ? sp->dlen_hi : e->len_hi) + k0,
+                                  (ms ? sp->dlen_lo : e->len_lo) + k0, kpad, p.n, p.sb,
                                   p.se, first, static_cast<float*>(acc), s));
         }
     }
@@ -428,24 +519,24 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
         const int64_t words = p.sr * p.n * (prec == UF_FP64 ? 2 : 1);
         UF_HIP(ufk::zero_u32(static_cast<unsigned*>(acc), words, s));
     }
-    // Non-dense part of a split: exact fixed-point pair sums into M.
+    // Non-dense part of a split: exact fixed-point pair sums into M (every
+    // element of the range written).
     unsigned long long* M = nullptr;
-    if (split) {
-        const SplitCache& sc = *e->split;
+    if (sp) {
         M = reinterpret_cast<unsigned long long*>(base + p.off_m);
-        UF_HIP(ufs::zero_u64(M, p.sr * p.n, s));
         ProfScope ps("rare_pairs", s);
-        UF_HIP(ufs::rare_pairs(sc.roff, sc.rs, sc.rq, weighted ? nullptr : sc.rl,
-                               static_cast<const ufs::RareItem*>(sc.items), sc.n_items, p.n, p.sb,
-                               p.se, M, s));
+        UF_HIP(ufs::rare_slots(sp->roff, sp->rs, sp->rq, weighted ? nullptr : sp->rl, sp->soff,
+                               sp->sl_list, sp->sl_pos, p.n, p.sb, p.se, M, s));
     }
     const double* scal = weighted ? e->sw
                                   : (prec == UF_FP64 ? e->wu : (prec == UF_FP32 ? e->wu32 : e->wub));
     {
         ProfScope ps("finalize", s);
-        UF_HIP(ufk::finalize(weighted ? 0 : 1, acc, prec == UF_FP64 ? 1 : 0, scal, p.n, p.sb,
-                             p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s, M,
-                             split && weighted ? e->split->sigma : nullptr));
+        const bool fixed = sp && weighted && sp->q_scale > 0.0;
+        const int acc_type = prec == UF_FP64 ? ufk::kAccF64 : (fixed ? ufk::kAccU32 : ufk::kAccF32);
+        UF_HIP(ufk::finalize(weighted ? 0 : 1, acc, acc_type, fixed ? 1.0 / sp->q_scale : 1.0, scal,
+                             p.n, p.sb, p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s, M,
+                             sp && weighted ? sp->sigma : nullptr));
     }
     if (rowstats) {
         ProfScope ps("row_sums", s);
@@ -499,19 +590,22 @@ int64_t uf_condensed_index(int64_t n, int64_t i, int64_t j) {
 
 void uf_set_chunk_nodes(int64_t nodes) { g_chunk_nodes.store(nodes < 0 ? 0 : nodes); }
 
-void uf_set_split_threshold(double fraction) {
-    g_split_threshold.store(fraction >= 0.0 && fraction <= 1.0 ? fraction : 0.05);
+uf_status uf_set_split_threshold(int weighted, double fraction) {
+    if (!(fraction <= 1.0)) return fail(UF_ERR_ARG, "split threshold must be <= 1 (or < 0: automatic)");
+    g_split_threshold[weighted ? 1 : 0].store(fraction < 0.0 ? -1.0 : fraction);
+    return UF_OK;
 }
 
-uf_status uf_split_stats(const uf_embedding* e, int64_t* n_dense, int64_t* n_lists,
+uf_status uf_split_stats(const uf_embedding* e, int weighted, int64_t* n_dense, int64_t* n_lists,
                          int64_t* n_pairs) {
     return guarded([&]() -> uf_status {
         if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
-        uf_status st = ensure_split(e, nullptr);
+        uf_status st = ensure_split(e, weighted, nullptr);
         if (st != UF_OK) return st;
-        if (n_dense) *n_dense = e->split->n_dense;
-        if (n_lists) *n_lists = e->split->n_lists;
-        if (n_pairs) *n_pairs = e->split->n_pairs;
+        const SplitCache* sc = e->split[weighted ? 1 : 0];
+        if (n_dense) *n_dense = sc->n_dense;
+        if (n_lists) *n_lists = sc->n_lists;
+        if (n_pairs) *n_pairs = sc->n_pairs;
         return UF_OK;
     });
 }
@@ -857,7 +951,8 @@ uf_status uf_embedding_scalars(const uf_embedding* e, double* sw, double* wu) {
 
 void uf_free_embedding(uf_embedding* e) {
     if (!e) return;
-    free_split(e->split);
+    free_split(e->split[0]);
+    free_split(e->split[1]);
     if (e->arena) (void)hipFree(e->arena);
     delete e;
 }
@@ -868,7 +963,7 @@ uf_status uf_workspace_size(const uf_embedding* e, int weighted, uf_precision pr
     return guarded([&]() -> uf_status {
         if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
         if (e && ((weighted && prec == UF_FP32_SPLIT) || (!weighted && prec == UF_MFMA_SPLIT))) {
-            uf_status sst = ensure_split(e, nullptr);
+            uf_status sst = ensure_split(e, weighted, nullptr);
             if (sst != UF_OK) return sst;
         }
         Plan p;
@@ -1038,8 +1133,8 @@ uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t
         if (b->n_chunks == 0) {
             UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(acc + t.acc_off), (t.n / 2) * t.n, s));
         }
-        UF_HIP(ufk::finalize(0, acc + t.acc_off, 0, e.sw + t.off, t.n, 0, t.n / 2, UF_CONDENSED, 1,
-                             outs[r], nullptr, s));
+        UF_HIP(ufk::finalize(0, acc + t.acc_off, ufk::kAccF32, 1.0, e.sw + t.off, t.n, 0, t.n / 2,
+                             UF_CONDENSED, 1, outs[r], nullptr, s));
     }
     return UF_OK;
 }

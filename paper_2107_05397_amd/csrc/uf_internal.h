@@ -44,24 +44,26 @@ struct uf_table {
 
 // Sparse-aware split of one embedding at one threshold (uf_host.hip).
 struct SplitCache {
-    double threshold = 0.0;
+    double threshold = 0.0;       // requested fraction, < 0 for the cost model
     int64_t n_dense = 0;          // branches in the dense set
     int64_t n_lists = 0;          // shared non-dense branches (>= 2 samples)
     int64_t n_entries = 0;        // entries of their sample lists
-    int64_t n_items = 0;          // pair-range work items
-    int64_t n_pairs = 0;          // pairs enumerated over all lists
+    int64_t n_pairs = 0;          // sample pairs over all lists
     void* arena = nullptr;
     int32_t* dense = nullptr;     // [n_dense] positions, ascending
-    int32_t* cls = nullptr;       // [nb] class per position
+    int32_t* cls = nullptr;       // [nb] class per position (list id, or ufs::kClass*)
     int64_t* roff = nullptr;      // [n_lists+1]
-    int32_t* rs = nullptr;        // [n_entries] sample of each list entry
+    int32_t* rs = nullptr;        // [n_entries] sample of each list entry, ascending per list
     int64_t* rq = nullptr;        // [n_entries] l*u in 2^-40 fixed point
     unsigned long long* sigma = nullptr;   // [n] fixed-point sum over non-dense branches
-    void* items = nullptr;        // [n_items] pair ranges (ufs::RareItem)
     int64_t n_dense_pad = 0;      // n_dense rounded up to the MFMA K step
     uint16_t* dlen_hi = nullptr;  // [n_dense_pad] bf16 high part of each dense length, 0-padded
     uint16_t* dlen_lo = nullptr;  // [n_dense_pad] bf16 low part
     int64_t* rl = nullptr;        // [n_lists] (hi+lo) length of each list's branch, 2^-40 fixed point
+    int64_t* soff = nullptr;      // [n+1] per-sample rows of the two arrays below
+    int32_t* sl_list = nullptr;   // [n_entries] a list the sample is in
+    int32_t* sl_pos = nullptr;    // [n_entries] the sample's position in that list
+    double q_scale = 0.0;         // weighted: 32-bit fixed-point scale of the dense pass (0: FP32)
 };
 
 // Device-resident inputs of the distance calls.  All arrays are on `device`.
@@ -88,7 +90,7 @@ struct uf_embedding {
     double* wu32 = nullptr;       // same with FP32-rounded lengths
     double* wub = nullptr;        // same with hi+lo bf16 lengths
     // sparse-aware split, built on first use (guarded by split_mu)
-    struct SplitCache* split = nullptr;
+    struct SplitCache* split[2] = {nullptr, nullptr};   // [0] unweighted, [1] weighted
     std::mutex split_mu;
     int32_t* parent_pos = nullptr;  // [nb+1], -1 for the root
     int32_t* tip_pos = nullptr;     // [n_tips] position of the tip with rank r
@@ -145,6 +147,10 @@ hipError_t band_f64(const double* E, const double* lenk, int64_t kc, int64_t n, 
                     int64_t se, int weighted, int first, double* acc, hipStream_t st);
 hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, int64_t sb,
                     int64_t se, int weighted, int first, float* acc, hipStream_t st);
+// Weighted only, 32-bit fixed point: acc += sum_k |E[k][i] - E[k][j]| (exact integers;
+// the caller keeps the sum below 2^32).
+hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_t se, int first,
+                    uint32_t* acc, hipStream_t st);
 
 // MFMA Gram over one chunk: for every upper-triangle 128x128 tile (bi <= bj) that holds
 // a pair of stripes [sb, se), G_ij (+)= sum_k P_ik P_jk (hi_k + lo_k), scattered into the
@@ -154,12 +160,14 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 
 // Distances from the accumulators.  kind 0: weighted (num / (s_i + s_j));
 // kind 1: unweighted Gram form ((w_i + w_j - 2G) / (w_i + w_j - G)), clamped to [0, 1].
-// acc_is_f64 selects the accumulator type.  q (nullable) receives -d^2/2 in FP64,
-// stripe-major.  layout/out dtype as in uf.h.  split_m (nullable, 2^-40 fixed point,
-// stripe-major like acc) carries the non-dense branches: kind 0 adds
-// sigma_i + sigma_j - 2 M to the numerator, kind 1 adds M to the Gram value.
-hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
-                    int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
+// acc_type (kAcc*) selects the accumulator type; its values are multiplied by
+// acc_scale.  q (nullable) receives -d^2/2 in FP64, stripe-major.  layout/out dtype
+// as in uf.h.  split_m (nullable, 2^-40 fixed point, stripe-major like acc) carries
+// the non-dense branches: kind 0 adds sigma_i + sigma_j - 2 M to the numerator,
+// kind 1 adds M to the Gram value.
+constexpr int kAccF32 = 0, kAccF64 = 1, kAccU32 = 2;
+hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, const double* scal,
+                    int64_t n, int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
                     hipStream_t st, const unsigned long long* split_m = nullptr,
                     const unsigned long long* sigma = nullptr);
 

@@ -4,11 +4,15 @@
 //   k_sample_scalars   per-sample FP64 scalars from the postorder leaf intervals
 //   k_embed_nm<T>      node-major chunk of the embedding (weighted or 0/1)
 //   k_embed_pres_bf16  sample-major BF16 0/1 presence for the MFMA Gram path
-//   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled)
+//   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled);
+//                      T = uint32_t: weighted, 32-bit fixed point, one v_sad_u32
+//                      (|a - b| + acc) per update
 //   k_gram_mfma        unweighted Gram product on MFMA (split-precision lengths)
 //   k_finalize         FP64 division, output layouts, -d^2/2 for PCoA
 //   k_rowsum_*         fixed-order two-stage row sums; k_grand_mean
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "uf_internal.h"
 
@@ -189,6 +193,17 @@ template <>
 struct BandCfg<double> {
     static constexpr int KS = 8;
 };
+template <>
+struct BandCfg<uint32_t> {
+    static constexpr int KS = 16;
+};
+
+// |a - b| + c on unsigned 32-bit integers in one VALU op
+__device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
 
 // Hardware hands block b to XCD b mod 8.  Remap so each XCD runs a contiguous
 // range of tiles (i-block fastest): neighbouring i-blocks of one stripe block
@@ -278,7 +293,12 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict
             for (int a = 0; a < 8; ++a) xi[a] = L.wi[cur][kk][ti * 8 + a];
 #pragma unroll
             for (int c = 0; c < 15; ++c) xj[c] = L.wj[cur][kk][ti * 8 + ts * 8 + c];
-            if (W) {
+            if constexpr (std::is_same<T, uint32_t>::value) {
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) r[a][b] = sad_u32(xi[a], xj[a + b], r[a][b]);
+            } else if constexpr (W) {
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -475,6 +495,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
 // outside the dense set.
 template <typename A>
 __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict__ acc,
+                                                  double acc_scale,
                                                   const double* __restrict__ scal, int64_t n,
                                                   int64_t sb, int64_t se, int layout, int out_f32,
                                                   void* __restrict__ out, double* __restrict__ q,
@@ -485,7 +506,7 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
     const bool even = (n & 1) == 0;
     for (int64_t s = sb + blockIdx.y; s < se; s += gridDim.y) {
         const int64_t j = (i + s + 1) % n;
-        double num = double(acc[(s - sb) * n + i]);
+        double num = double(acc[(s - sb) * n + i]) * acc_scale;
         if (split_m) {
             if (kind == 0) {
                 const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
@@ -735,6 +756,18 @@ hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, in
     return band<float>(E, lenk, kc, n, sb, se, weighted, first, acc, st);
 }
 
+hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_t se, int first,
+                    uint32_t* acc, hipStream_t st) {
+    if (se <= sb || n <= 0) return hipSuccess;
+    const int64_t n_iblk = (n + kBandI - 1) / kBandI;
+    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(n_tiles), 1u, 1u};
+    hipLaunchKernelGGL((k_band<uint32_t, true>), grid, dim3(256), 0, st, E, nullptr, kc, n, sb, se,
+                       n_iblk, first, acc);
+    return hipGetLastError();
+}
+
 hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
                      int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
@@ -746,20 +779,24 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
     return hipGetLastError();
 }
 
-hipError_t finalize(int kind, const void* acc, int acc_is_f64, const double* scal, int64_t n,
-                    int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
+hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, const double* scal,
+                    int64_t n, int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
                     hipStream_t st, const unsigned long long* split_m,
                     const unsigned long long* sigma) {
     if (se <= sb || n <= 0) return hipSuccess;
     dim3 grid(unsigned((n + 255) / 256), grid_y(se - sb));
-    if (acc_is_f64)
+    if (acc_type == kAccF64)
         hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, st, kind,
-                           static_cast<const double*>(acc), scal, n, sb, se, layout, out_f32, out,
-                           q, split_m, sigma);
+                           static_cast<const double*>(acc), acc_scale, scal, n, sb, se, layout,
+                           out_f32, out, q, split_m, sigma);
+    else if (acc_type == kAccU32)
+        hipLaunchKernelGGL(k_finalize<uint32_t>, grid, dim3(256), 0, st, kind,
+                           static_cast<const uint32_t*>(acc), acc_scale, scal, n, sb, se, layout,
+                           out_f32, out, q, split_m, sigma);
     else
         hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, st, kind,
-                           static_cast<const float*>(acc), scal, n, sb, se, layout, out_f32, out,
-                           q, split_m, sigma);
+                           static_cast<const float*>(acc), acc_scale, scal, n, sb, se, layout,
+                           out_f32, out, q, split_m, sigma);
     return hipGetLastError();
 }
 

@@ -1,15 +1,20 @@
-// Sparse-aware weighted-normalized numerator (gfx950).
+// Sparse-aware split of the UniFrac numerators (gfx950).
 //
 //   sum_v |x_iv - x_jv| = sum_{v in D} |x_iv - x_jv|
 //                         + sigma_i + sigma_j - 2 sum_{v not in D} min(x_iv, x_jv),
 //   sigma_s = sum_{v not in D} x_sv,  x = l * u.
 //
-// D ("dense") holds the branches that more than a set fraction of the samples
-// touch; they go through the stripe-band kernel (uf_kernels.hip) unchanged.  On
-// every other branch min(x_i, x_j) is nonzero only for the pairs that both touch
-// it, so those pairs are enumerated from per-branch sample lists and summed by
-// integer atomics in fixed point (2^-40): exact and independent of the order in
-// which the atomics land, so results are bitwise reproducible.
+// D ("dense") holds the branches that many samples touch; they go through the
+// stripe-band kernel or the MFMA Gram (uf_kernels.hip) unchanged.  On every
+// other branch min(x_i, x_j) is nonzero only for the pairs that both touch it.
+// Those branches keep a list of the samples touching them, sorted by sample,
+// and every sample keeps the lists it is in.  The slot kernel gives one
+// workgroup to one sample i and a range of stripes: for each list of i it walks
+// the members j that follow i cyclically at distance d = (j - i) mod N inside
+// the stripe window (stripe d - 1), and adds min(x_i, x_j) into an LDS row
+// indexed by stripe.  Sums are in 2^-40 fixed point: exact, so the order of the
+// additions does not matter and the result is bitwise reproducible.  Each
+// accumulator element of the range is written once, by its sample's workgroup.
 //
 // Unweighted, the same lists serve the Gram form: with presence a in {0, 1},
 // min(l a_i, l a_j) = l a_i a_j, so the non-dense part of G_ij is the sum of l
@@ -17,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "uf_device.h"
 #include "uf_internal.h"
@@ -34,20 +40,29 @@ __global__ __launch_bounds__(256) void k_branch_count(ufp::Emb e, int32_t* __res
         ufd::for_each_branch(e, ent, a, [&](int32_t v) { atomicAdd(&cnt[v], 1); });
 }
 
+// Unsorted list fill: members of each shared non-dense branch's list (sample,
+// fixed-point l*u), sigma per sample, the number of lists of each sample, and the
+// number of dense branches of nonzero length it touches.
 __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* __restrict__ cls,
                                                     const int64_t* __restrict__ roff,
                                                     int32_t* __restrict__ rfill,
                                                     int32_t* __restrict__ rs,
                                                     int64_t* __restrict__ rq,
-                                                    unsigned long long* __restrict__ sigma) {
+                                                    unsigned long long* __restrict__ sigma,
+                                                    int32_t* __restrict__ scnt,
+                                                    int32_t* __restrict__ dnnz) {
     const int64_t s = blockIdx.x;
     const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
     const double inv_t = 1.0 / e.total[s];
     unsigned long long part = 0;
+    int32_t lists = 0, dense = 0;
     for (int64_t ent = a + threadIdx.x; ent < b; ent += 256)
         ufd::for_each_branch(e, ent, a, [&](int32_t v) {
             const int32_t c = cls[v];
-            if (c == kClassDense) return;
+            if (c == kClassDense) {
+                dense += e.len[v] > 0.0;
+                return;
+            }
             const int64_t cn = ufd::count_in(e, s, e.lo[v], e.hi[v]);
             const long long q = llrint(e.len[v] * (double(cn) * inv_t) * kFix);
             part += (unsigned long long)q;
@@ -55,17 +70,74 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
                 const int32_t slot = atomicAdd(&rfill[c], 1);
                 rs[roff[c] + slot] = int32_t(s);
                 rq[roff[c] + slot] = q;
+                ++lists;
             }
         });
     atomicAdd(&sigma[s], part);
+    if (lists) atomicAdd(&scnt[s], lists);
+    if (dense) atomicAdd(&dnnz[s], dense);
 }
 
-// node-major FP32 chunk over a list of branch positions (the dense set)
-__global__ __launch_bounds__(256) void k_embed_list_f32(ufp::Emb e, const int32_t* __restrict__ list,
-                                                        int64_t k0, int64_t kc,
-                                                        float* __restrict__ out) {
+// Sort each list by sample: a member's new position is the number of members
+// with a smaller sample id (ids in a list are distinct).  Also records, in the
+// sample's row of the per-sample index, the list and the member's position.
+constexpr int kSortLds = 4096;
+
+__device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
+                                             int32_t r, const int64_t* __restrict__ rq_in,
+                                             int32_t* __restrict__ rs_out,
+                                             int64_t* __restrict__ rq_out,
+                                             const int64_t* __restrict__ soff,
+                                             int32_t* __restrict__ scur,
+                                             int32_t* __restrict__ sl_list,
+                                             int32_t* __restrict__ sl_pos) {
+    rs_out[base + r] = smp;
+    rq_out[base + r] = rq_in[base + k];
+    const int32_t slot = atomicAdd(&scur[smp], 1);
+    sl_list[soff[smp] + slot] = int32_t(L);
+    sl_pos[soff[smp] + slot] = r;
+}
+
+__global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff,
+                                                    const int32_t* __restrict__ rs_in,
+                                                    const int64_t* __restrict__ rq_in,
+                                                    int32_t* __restrict__ rs_out,
+                                                    int64_t* __restrict__ rq_out,
+                                                    const int64_t* __restrict__ soff,
+                                                    int32_t* __restrict__ scur,
+                                                    int32_t* __restrict__ sl_list,
+                                                    int32_t* __restrict__ sl_pos) {
+    __shared__ int32_t ks[kSortLds];
+    const int64_t L = blockIdx.x;
+    const int64_t base = roff[L];
+    const int64_t m = roff[L + 1] - base;
+    if (m <= kSortLds) {   // block-uniform
+        for (int64_t k = threadIdx.x; k < m; k += 256) ks[k] = rs_in[base + k];
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < m; k += 256) {
+            const int32_t smp = ks[k];
+            int32_t r = 0;
+            for (int64_t t = 0; t < m; ++t) r += ks[t] < smp;
+            place_member(L, base, k, smp, r, rq_in, rs_out, rq_out, soff, scur, sl_list, sl_pos);
+        }
+    } else {
+        for (int64_t k = threadIdx.x; k < m; k += 256) {
+            const int32_t smp = rs_in[base + k];
+            int32_t r = 0;
+            for (int64_t t = 0; t < m; ++t) r += rs_in[base + t] < smp;
+            place_member(L, base, k, smp, r, rq_in, rs_out, rq_out, soff, scur, sl_list, sl_pos);
+        }
+    }
+}
+
+// Node-major chunk over a list of branch positions (the dense set): x = l * c / T
+// as FP32, or as 32-bit fixed point rint(x * q) (T = uint32_t).
+template <typename T>
+__global__ __launch_bounds__(256) void k_embed_list(ufp::Emb e, const int32_t* __restrict__ list,
+                                                    int64_t k0, int64_t kc, double q,
+                                                    T* __restrict__ out) {
     constexpr int TK = 256, TS = 64;
-    __shared__ float tile[TK][TS + 1];
+    __shared__ T tile[TK][TS + 1];
     const int tid = threadIdx.x;
     const int64_t kb = int64_t(blockIdx.x) * TK;
     const int64_t sb = int64_t(blockIdx.y) * TS;
@@ -81,8 +153,12 @@ __global__ __launch_bounds__(256) void k_embed_list_f32(ufp::Emb e, const int32_
     }
     for (int j = 0; j < TS; ++j) {
         const int64_t s = sb + j;
-        float v = 0.0f;
-        if (kin && s < e.n) v = float(lv * (double(ufd::count_in(e, s, lk, hk)) / e.total[s]));
+        T v = T(0);
+        if (kin && s < e.n) {
+            const double x = lv * (double(ufd::count_in(e, s, lk, hk)) / e.total[s]);
+            if constexpr (std::is_same<T, uint32_t>::value) v = uint32_t(llrint(x * q));
+            else v = T(x);
+        }
         tile[tid][j] = v;
     }
     __syncthreads();
@@ -91,23 +167,6 @@ __global__ __launch_bounds__(256) void k_embed_list_f32(ufp::Emb e, const int32_
         const int64_t s = sb + (tid % TS);
         if (kk < kc && s < e.n) out[kk * e.n + s] = tile[r][tid % TS];
     }
-}
-
-__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
-
-// Pairs of one shared branch's sample list: pair index p in [0, m(m-1)/2)
-// maps to (a, b), a < b, row-major over the upper triangle.
-__device__ __forceinline__ void pair_of(int64_t p, int64_t m, int64_t& a, int64_t& b) {
-    const double t = double(2 * m - 1);
-    int64_t r = int64_t((t - sqrt(t * t - 8.0 * double(p))) * 0.5);
-    // fix rounding: first index of row r is r*m - r(r+1)/2
-    while (r > 0 && r * m - r * (r + 1) / 2 > p) --r;
-    while ((r + 1) * m - (r + 1) * (r + 2) / 2 <= p) ++r;
-    a = r;
-    b = p - (r * m - r * (r + 1) / 2) + r + 1;
 }
 
 __device__ __forceinline__ uint32_t bf16_to_bits32(uint16_t h) { return uint32_t(h) << 16; }
@@ -133,47 +192,91 @@ __global__ __launch_bounds__(256) void k_split_lengths(const int32_t* __restrict
     }
 }
 
+// Workgroup -> sample: consecutive samples on one XCD (blocks are dealt to the
+// 8 XCDs round-robin), so the column writes of neighbours share L2 lines.
+__device__ __forceinline__ int64_t xcd_sample(int64_t b, int64_t n) {
+    const int64_t per = n / 8, rem = n % 8;
+    const int64_t x = b % 8, k = b / 8;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+constexpr int kSlotThreads = 1024;
+constexpr int kSlotWaves = kSlotThreads / 64;
+constexpr int64_t kSegStripes = 8192;   // 64 KiB of LDS accumulators per workgroup
+
 template <bool W>
-__global__ __launch_bounds__(256) void k_rare_pairs(const int64_t* __restrict__ roff,
-                                                    const int32_t* __restrict__ rs,
-                                                    const int64_t* __restrict__ rq,
-                                                    const int64_t* __restrict__ rl,
-                                                    const RareItem* __restrict__ items, int64_t n,
-                                                    int64_t sb, int64_t se,
-                                                    unsigned long long* __restrict__ M) {
-    const RareItem it = items[blockIdx.x];
-    const int64_t base = roff[it.list];
-    const int64_t m = roff[it.list + 1] - base;
-    const int64_t S = n / 2;
-    const bool even = (n & 1) == 0;
-    const unsigned long long lq = W ? 0ull : (unsigned long long)rl[it.list];
-    for (int64_t p = it.p0 + threadIdx.x; p < it.p1; p += 256) {
-        int64_t a, b;
-        pair_of(p, m, a, b);
-        int64_t i = rs[base + a], j = rs[base + b];
-        if (i > j) {
-            const int64_t t = i;
-            i = j;
-            j = t;
+__global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
+    const int64_t* __restrict__ roff, const int32_t* __restrict__ rs,
+    const int64_t* __restrict__ rq, const int64_t* __restrict__ rl,
+    const int64_t* __restrict__ soff, const int32_t* __restrict__ sl_list,
+    const int32_t* __restrict__ sl_pos, int64_t n, int64_t sb, int64_t se, int64_t seg_len,
+    unsigned long long* __restrict__ M) {
+    __shared__ unsigned long long acc[kSegStripes];
+    const int64_t i = xcd_sample(blockIdx.x, n);
+    const int64_t g0 = sb + int64_t(blockIdx.y) * seg_len;
+    const int64_t g1 = min(se, g0 + seg_len);
+    const int64_t width = g1 - g0;
+    for (int64_t k = threadIdx.x; k < width; k += kSlotThreads) acc[k] = 0ull;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    // stripe s pairs i with its cyclic successor at distance d = s + 1; stripes
+    // run below floor(N/2), so the window is d in [g0 + 1, min(g1, N/2)]
+    const int64_t dlo = g0 + 1;
+    const int64_t dhi = min(g1, n / 2);
+    for (int64_t k = soff[i] + wave; k < soff[i + 1]; k += kSlotWaves) {
+        const int64_t L = sl_list[k];
+        const int64_t p = sl_pos[k];
+        const int64_t base = roff[L];
+        const int64_t m = roff[L + 1] - base;
+        const unsigned long long vi = W ? (unsigned long long)rq[base + p]
+                                        : (unsigned long long)rl[L];
+        // the c-th member after i (c in [0, m-1)), cyclically, sits at position
+        // (p + 1 + c) mod m; its distance from i grows with c
+        auto pos_of = [&](int64_t c) {
+            const int64_t q = p + 1 + c;
+            return q >= m ? q - m : q;
+        };
+        auto dist_of = [&](int64_t q) {
+            const int64_t d = int64_t(rs[base + q]) - i;
+            return d <= 0 ? d + n : d;
+        };
+        // first c whose distance reaches dlo: 64-way search, one probe per lane
+        // (answer in [lo, hi]; hi = m - 1 stands for "none")
+        int64_t lo = 0, hi = m - 1;
+        if (dlo > 1) {
+            while (lo < hi) {
+                const int64_t step = (hi - lo + 63) / 64;
+                const int64_t c = lo + int64_t(lane) * step;
+                const bool pred = c < hi && dist_of(pos_of(c)) >= dlo;
+                const unsigned long long ball = __ballot(pred);
+                if (ball) {
+                    const int64_t f = __ffsll((long long)ball) - 1;
+                    if (f == 0) {
+                        hi = lo;
+                    } else {
+                        hi = lo + f * step;
+                        lo = lo + (f - 1) * step + 1;
+                    }
+                } else {
+                    lo = lo + ((hi - 1 - lo) / step) * step + 1;
+                }
+            }
         }
-        unsigned long long mn = lq;
-        if (W) {
-            const long long qa = rq[base + a], qb = rq[base + b];
-            mn = (unsigned long long)(qa < qb ? qa : qb);
+        for (int64_t c = lo + lane; c < m - 1; c += 64) {
+            const int64_t q = pos_of(c);
+            const int64_t d = dist_of(q);
+            if (d > dhi) break;
+            unsigned long long v = vi;
+            if (W) {
+                const unsigned long long vj = (unsigned long long)rq[base + q];
+                v = vj < vi ? vj : vi;
+            }
+            atomicAdd(&acc[d - 1 - g0], v);
         }
-        const int64_t d = j - i;
-        int64_t s, slot;
-        if (d <= S) {
-            s = d - 1;
-            slot = i;
-        } else {
-            s = n - d - 1;
-            slot = j;
-        }
-        if (s < sb || s >= se) continue;
-        atomicAdd(&M[(s - sb) * n + slot], mn);
-        if (even && d == S) atomicAdd(&M[(s - sb) * n + j], mn);
     }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < width; k += kSlotThreads) M[(g0 + k - sb) * n + i] = acc[k];
 }
 
 }  // namespace
@@ -185,27 +288,43 @@ hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st) {
 }
 
 hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
-                      int32_t* rs, int64_t* rq, unsigned long long* sigma, hipStream_t st) {
+                      int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
+                      int32_t* dnnz, hipStream_t st) {
     if (e.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_split_fill, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff, rfill, rs,
-                       rq, sigma);
+                       rq, sigma, scnt, dnnz);
+    return hipGetLastError();
+}
+
+hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
+                      int32_t* rs_out, int64_t* rq_out, const int64_t* soff, int32_t* scur,
+                      int32_t* sl_list, int32_t* sl_pos, hipStream_t st) {
+    if (n_lists <= 0) return hipSuccess;
+    if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, rs_in, rq_in,
+                       rs_out, rq_out, soff, scur, sl_list, sl_pos);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t embed_list(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc,
+                             double q, T* out, hipStream_t st) {
+    if (kc <= 0 || e.n <= 0) return hipSuccess;
+    const int64_t gy = (e.n + 63) / 64;
+    if (gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_embed_list<T>, dim3(unsigned((kc + 255) / 256), unsigned(gy)), dim3(256), 0,
+                       st, e, list, k0, kc, q, out);
     return hipGetLastError();
 }
 
 hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, float* out,
                           hipStream_t st) {
-    if (kc <= 0 || e.n <= 0) return hipSuccess;
-    const int64_t gy = (e.n + 63) / 64;
-    if (gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_embed_list_f32, dim3(unsigned((kc + 255) / 256), unsigned(gy)), dim3(256), 0,
-                       st, e, list, k0, kc, out);
-    return hipGetLastError();
+    return embed_list<float>(e, list, k0, kc, 1.0, out, st);
 }
 
-hipError_t zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u64, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
-    return hipGetLastError();
+hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, double q,
+                          uint32_t* out, hipStream_t st) {
+    return embed_list<uint32_t>(e, list, k0, kc, q, out, st);
 }
 
 hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,
@@ -218,17 +337,21 @@ hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, i
     return hipGetLastError();
 }
 
-hipError_t rare_pairs(const int64_t* roff, const int32_t* rs, const int64_t* rq, const int64_t* rl,
-                      const RareItem* items, int64_t n_items, int64_t n, int64_t sb, int64_t se,
-                      unsigned long long* M, hipStream_t st) {
-    if (n_items <= 0 || se <= sb) return hipSuccess;
-    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
+hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const int64_t* rq, const int64_t* rl,
+                      const int64_t* soff, const int32_t* sl_list, const int32_t* sl_pos, int64_t n,
+                      int64_t sb, int64_t se, unsigned long long* M, hipStream_t st) {
+    if (se <= sb || n <= 0) return hipSuccess;
+    if (n > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t nseg = (se - sb + kSegStripes - 1) / kSegStripes;
+    const int64_t seg_len = (se - sb + nseg - 1) / nseg;
+    if (nseg > 65535) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(n), unsigned(nseg)};
     if (rl)
-        hipLaunchKernelGGL(k_rare_pairs<false>, dim3(unsigned(n_items)), dim3(256), 0, st, roff, rs,
-                           rq, rl, items, n, sb, se, M);
+        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), 0, st, roff, rs, rq, rl, soff,
+                           sl_list, sl_pos, n, sb, se, seg_len, M);
     else
-        hipLaunchKernelGGL(k_rare_pairs<true>, dim3(unsigned(n_items)), dim3(256), 0, st, roff, rs,
-                           rq, rl, items, n, sb, se, M);
+        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), 0, st, roff, rs, rq, rl, soff,
+                           sl_list, sl_pos, n, sb, se, seg_len, M);
     return hipGetLastError();
 }
 

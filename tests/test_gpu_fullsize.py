@@ -40,7 +40,7 @@ def _sampled(d, n, pairs):
     return d[idx].cpu().numpy()
 
 
-# the sparse-aware paths run at the dense-set threshold bench.py times (0.02)
+# the sparse-aware paths run with the automatic dense set, as bench.py times them
 @pytest.mark.parametrize("variant,precision,tol", [
     ("weighted_normalized", "fp32_split", 1e-4),
     ("unweighted", "mfma_split", 1e-4),
@@ -53,12 +53,8 @@ def test_c2_sampled_pairs_and_row_means(c2, variant, precision, tol):
     import paper_2107_05397_amd as uf
     tree, table, emb, pairs, want = c2
     n = table.n_samples
-    uf.set_split_threshold(0.02)
-    try:
-        d, rm, gm = uf.dm(emb, variant, precision, row_means=True)
-        torch.cuda.synchronize()
-    finally:
-        uf.set_split_threshold(0.05)
+    d, rm, gm = uf.dm(emb, variant, precision, row_means=True)
+    torch.cuda.synchronize()
     got = _sampled(d, n, pairs)
     err = np.abs(got - want[variant])
     print(f"[C2 {variant} {precision}] sampled max|err|={err.max():.3e}", flush=True)

@@ -5,7 +5,7 @@ UF_MFMA_SPLIT (unweighted).
   exact fixed-point sums: |d - d_oracle| <= 1e-10 (2^-40 quantisation of each
   term, sums exact in integers).  The unweighted split uses the lengths
   l_hi + l_lo of the MFMA path, so its oracle runs on those lengths;
-* default and 0.0 thresholds: the dense part is the FP32 stripe kernel or the
+* fixed thresholds 0.05, 0.3 and 0.0: the dense part is the FP32 stripe kernel or the
   MFMA Gram, so the FP32 tolerance (1e-4) applies;
 * stripe ranges merge bit for bit; repeated runs are bit-identical (integer
   atomics commute).
@@ -32,7 +32,7 @@ def _emb(tree, table):
 def threshold():
     import paper_2107_05397_amd as uf
     yield uf.set_split_threshold
-    uf.set_split_threshold(0.05)
+    uf.set_split_threshold(None)
 
 
 SPLIT = {"weighted_normalized": "fp32_split", "unweighted": "mfma_split"}
@@ -44,7 +44,7 @@ SPLIT = {"weighted_normalized": "fp32_split", "unweighted": "mfma_split"}
 def test_split_matches_oracle(variant, n, thr, tol, threshold):
     import torch
     import paper_2107_05397_amd as uf
-    threshold(thr)
+    threshold(thr, variant)
     tree = synth.gen_tree(400, 0.1, seed=n)
     table = synth.gen_table_zipf(n, np.arange(400), 40, seed=n + 7)
     emb = _emb(tree, table)
@@ -56,7 +56,7 @@ def test_split_matches_oracle(variant, n, thr, tol, threshold):
         ref_tree = synth.Tree(tree.parent.copy(), hi + lo, tree.n_tips)
     want = core.dm(ref_tree, table, variant)[0]
     err = np.abs(d.cpu().numpy() - want)
-    print(f"[split {variant} n={n} thr={thr}] max|err|={err.max():.3e}", uf.split_stats(emb))
+    print(f"[split {variant} n={n} thr={thr}] max|err|={err.max():.3e}", uf.split_stats(emb, variant))
     assert err.max() <= tol
 
 
@@ -96,7 +96,7 @@ def test_mfma_split_exact_with_integer_lengths(threshold):
     tree.length[:] = rng.integers(1, 256, size=tree.n_nodes).astype(float)
     table = synth.gen_table_zipf(150, np.arange(400), 30, seed=13)
     emb = _emb(tree, table)
-    nd, nl, npairs = uf.split_stats(emb)
+    nd, nl, npairs = uf.split_stats(emb, "unweighted")
     assert nd > 0 and npairs > 0
     want = core.dm(tree, table, "unweighted")[0]
     d, _, _ = uf.dm(emb, "unweighted", "mfma_split")
@@ -122,9 +122,86 @@ def test_split_stats_partition(threshold):
     tree = synth.gen_tree(300, 0.1, seed=8)
     table = synth.gen_table_zipf(100, np.arange(300), 30, seed=9)
     emb = _emb(tree, table)
-    threshold(1.0)
-    nd, nl, npairs = uf.split_stats(emb)
-    assert nd == 0 and nl > 0 and npairs > 0
+    for variant in SPLIT:
+        threshold(1.0, variant)
+        nd, nl, npairs = uf.split_stats(emb, variant)
+        assert nd == 0 and nl > 0 and npairs > 0
+        threshold(0.0, variant)
+        nd0, nl0, np0 = uf.split_stats(emb, variant)
+        assert nl0 == 0 and np0 == 0 and nd0 > 0
+
+
+def test_auto_threshold_per_variant(threshold):
+    """The automatic dense set follows the cost model: branches touched by more
+    samples are dense first, and the cheaper dense kernel (MFMA, unweighted)
+    takes at least as many branches as the stripe kernel (weighted)."""
+    import paper_2107_05397_amd as uf
+    tree = synth.gen_tree(3000, 0.05, seed=21)
+    table = synth.gen_table_zipf(2000, np.arange(3000), 100, seed=22)
+    emb = _emb(tree, table)
+    threshold(None)
+    nd_w, _, np_w = uf.split_stats(emb, "weighted_normalized")
+    nd_u, _, np_u = uf.split_stats(emb, "unweighted")
     threshold(0.0)
-    nd0, nl0, np0 = uf.split_stats(emb)
-    assert nl0 == 0 and np0 == 0 and nd0 > 0
+    nd_all = uf.split_stats(emb, "unweighted")[0]
+    print(f"[auto split] weighted dense={nd_w} pairs={np_w}; unweighted dense={nd_u} pairs={np_u}; "
+          f"touched={nd_all}")
+    assert 0 < nd_w <= nd_u < nd_all
+    assert np_u <= np_w
+    with pytest.raises(uf.UFError):
+        uf.set_split_threshold(1.5)
+
+
+def _dense_kernel_used(uf, emb):
+    uf.profile_reset()
+    uf.profile_enable(True)
+    try:
+        d, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split")
+    finally:
+        uf.profile_enable(False)
+    used = {k for k in ("band_wn_u32", "band_wn_f32") if uf.profile_read(k)[1] > 0}
+    return d, used
+
+
+def test_weighted_dense_pass_fixed_point(threshold):
+    """Homogeneous sample masses: the dense weighted pass runs in 32-bit fixed point
+    and stays within its stated bound (1e-5) of the oracle."""
+    import torch
+    import paper_2107_05397_amd as uf
+    threshold(0.1, "weighted_normalized")
+    tree = synth.gen_tree(600, 0.1, seed=31)
+    table = synth.gen_table_zipf(257, np.arange(600), 60, seed=32)
+    emb = _emb(tree, table)
+    assert uf.split_stats(emb, "weighted_normalized")[0] > 0
+    d, used = _dense_kernel_used(uf, emb)
+    torch.cuda.synchronize()
+    err = np.abs(d.cpu().numpy() - core.dm(tree, table, "weighted_normalized")[0]).max()
+    print(f"[fixed-point dense pass] kernels={used} max|err|={err:.3e}")
+    assert used == {"band_wn_u32"}
+    assert err <= 1e-5
+
+
+def test_weighted_dense_pass_falls_back_to_fp32(threshold):
+    """A sample whose whole mass sits on near-zero branch lengths makes the fixed-point
+    bound fail; the dense pass then runs in FP32 and still meets the FP32 tolerance."""
+    import torch
+    import paper_2107_05397_amd as uf
+    threshold(0.1, "weighted_normalized")
+    tree = synth.gen_tree(600, 0.1, seed=33)
+    table = synth.gen_table_zipf(200, np.arange(600), 60, seed=34)
+    # sample 0: one tip whose root path has lengths 1e-12
+    t = int(table.tips[table.indptr[0]])
+    v = t
+    while tree.parent[v] >= 0:
+        tree.length[v] = 1e-12
+        v = int(tree.parent[v])
+    table.tips = np.concatenate([[t], table.tips[table.indptr[1]:]])
+    table.counts = np.concatenate([[5], table.counts[table.indptr[1]:]])
+    table.indptr = np.concatenate([[0], table.indptr[1:] - table.indptr[1] + 1])
+    emb = _emb(tree, table)
+    d, used = _dense_kernel_used(uf, emb)
+    torch.cuda.synchronize()
+    err = np.abs(d.cpu().numpy() - core.dm(tree, table, "weighted_normalized")[0]).max()
+    print(f"[fp32 fallback dense pass] kernels={used} max|err|={err:.3e}")
+    assert used == {"band_wn_f32"}
+    assert err <= 1e-4
