@@ -44,10 +44,16 @@ PEAK_BF16_MFMA = 2.5e15                         # dense BF16 MFMA FLOP/s
 PEAK_HBM = 8.0e12
 
 
+KERNEL_SOURCES = ("uf_kernels.hip", "uf_split.hip", "uf_device.h", "uf_internal.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the distance-kernel sources the committed counter summaries were taken with."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2107_05397_amd", "csrc", "uf_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2107_05397_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -87,13 +93,16 @@ def cpu_baseline(tree, table, target_s: float):
         _, used = core.dm(tree, sub, "unweighted")
         return time.perf_counter() - t0, used
 
-    probe_n = 64
-    t_probe, _ = run(probe_n)
-    rate = 2 * probe_n * (probe_n - 1) / 2 * nb / max(t_probe, 1e-6)
-    want_pairs = rate * target_s / (2 * nb)
-    n = int(min(max((1 + (1 + 8 * want_pairs) ** 0.5) / 2, 96), 1500))
-    log(f"cpu baseline: probe {probe_n} samples {t_probe:.1f}s -> sample of {n} samples")
+    # pair work grows as n^2 and per-sample work as n: probe, then resize once if the
+    # first sample ran well short of the target
+    n = 64
     secs, used = run(n)
+    for _ in range(2):
+        if secs >= 0.5 * target_s:
+            break
+        n = int(min(n * (target_s / max(secs, 1e-3)) ** 0.5, 3000))
+        log(f"cpu baseline: resizing the sample to {n} samples")
+        secs, used = run(n)
     updates = 2 * n * (n - 1) / 2 * nb
     return {"value": updates / secs, "unit": "pair-node updates/s", "cores": int(used),
             "kind": "oracle",
