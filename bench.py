@@ -77,9 +77,17 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(tree, table, target_s: float):
+def sampled_error(tree, table, pairs, variant, got) -> float:
+    """Max |GPU - oracle| over sampled pairs (CPU leg only)."""
+    import numpy as np
+    import oracle
+    want = oracle.dm_pairs(tree, table, pairs, variant)
+    return float(np.max(np.abs(np.asarray(got) - want)))
+
+
+def cpu_baseline(tree, table, target_s: float, variants=("weighted_normalized", "unweighted")):
     """Time the C oracle (FP64, OpenMP on all host cores) on a bounded sample:
-    all pairs among the first n samples, both variants, full tree."""
+    all pairs among the first n samples, the given variants, full tree."""
     import numpy as np  # noqa: F401
     import synth
     from oracle import core
@@ -89,8 +97,8 @@ def cpu_baseline(tree, table, target_s: float):
     def run(n):
         sub = synth.subset_rows(table, np.arange(n))
         t0 = time.perf_counter()
-        _, used = core.dm(tree, sub, "weighted_normalized")
-        _, used = core.dm(tree, sub, "unweighted")
+        for v in variants:
+            _, used = core.dm(tree, sub, v)
         return time.perf_counter() - t0, used
 
     # pair work grows as n^2 and per-sample work as n: probe, then resize once if the
@@ -103,11 +111,12 @@ def cpu_baseline(tree, table, target_s: float):
         n = int(min(n * (target_s / max(secs, 1e-3)) ** 0.5, 3000))
         log(f"cpu baseline: resizing the sample to {n} samples")
         secs, used = run(n)
-    updates = 2 * n * (n - 1) / 2 * nb
+    updates = len(variants) * n * (n - 1) / 2 * nb
     return {"value": updates / secs, "unit": "pair-node updates/s", "cores": int(used),
             "kind": "oracle",
-            "sample": f"all {n * (n - 1) // 2} pairs among the first {n} samples, both variants, "
-                      f"full {tree.n_nodes}-node tree, FP64 C oracle; {secs:.1f} s",
+            "sample": f"all {n * (n - 1) // 2} pairs among the first {n} samples, "
+                      f"{' + '.join(variants)}, full {tree.n_nodes}-node tree, FP64 C oracle; "
+                      f"{secs:.1f} s",
             "seconds": secs, "host_cpus": os.cpu_count()}
 
 
@@ -159,23 +168,24 @@ def bench_batch(args) -> int:
     separate_s = time.perf_counter() - t2
     outs = b.run(use_graph=True, stream=stream)
     torch.cuda.synchronize()
-    par = {}
-    try:
-        import oracle
-        rng = np.random.default_rng(1)
-        errs = []
-        for r in rng.choice(len(tables), size=3, replace=False):
-            n = sizes[r]
-            ii = rng.choice(n, size=8, replace=False)
-            pr = [(int(min(a, c)), int(max(a, c))) for a, c in zip(ii[:4], ii[4:])]
-            want = oracle.dm_pairs(tree, tables[r], pr, "weighted_normalized")
-            idx = torch.tensor([uf.condensed_index(n, a, c) for a, c in pr], device="cuda")
-            got = outs[r][idx].double().cpu().numpy()
-            errs.append(float(np.max(np.abs(got - want))))
-        par = {"sampled_max_abs_err": max(errs)}
-        log(f"sampled parity vs oracle: {par}")
-    except Exception as ex:
-        par = {"error": repr(ex)}
+    # GPU values of a few sampled pairs, compared with the oracle in the CPU leg
+    rng = np.random.default_rng(1)
+    samples = []
+    for r in rng.choice(len(tables), size=3, replace=False):
+        n = sizes[r]
+        ii = rng.choice(n, size=8, replace=False)
+        pr = [(int(min(a, c)), int(max(a, c))) for a, c in zip(ii[:4], ii[4:])]
+        idx = torch.tensor([uf.condensed_index(n, a, c) for a, c in pr], device="cuda")
+        samples.append((int(r), pr, outs[r][idx].double().cpu().numpy()))
+    cpu = None
+    if not args.no_cpu_baseline:
+        # CPU leg: the oracle timed on a bounded sample of the smallest table, and the
+        # sampled GPU pairs checked against it
+        small = int(np.argmin(sizes))
+        cpu = cpu_baseline(tree, tables[small], args.cpu_seconds, variants=("weighted_normalized",))
+        cpu["sampled_parity_max_abs_err"] = max(
+            sampled_error(tree, tables[r], pr, "weighted_normalized", got) for r, pr, got in samples)
+        log(f"sampled parity vs oracle: {cpu['sampled_parity_max_abs_err']:.3e}")
     slots = 2 * U / graph_s
     rec = {
         "metric": "UniFrac pair-node updates/s (1 GPU), batched tables",
@@ -198,7 +208,8 @@ def bench_batch(args) -> int:
                   "separate_single_table_calls_s": separate_s,
                   "autotuned_config": dict(zip(("stage_branches", "wgs_per_cu", "chunk_nodes"),
                                                b.config())),
-                  "autotune_first_chunk_ms": tune_ms, "parity": par},
+                  "autotune_first_chunk_ms": tune_ms},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     return 0
@@ -253,7 +264,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the FP64 weighted and plain FP32 unweighted kernels once")
+                    help="also time the FP64 weighted kernel once")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the plain-kernel and all-branch MFMA comparison runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -388,36 +401,37 @@ def main() -> int:
                                   "frac": 4 * g_upd / (g_ms / 1e3) / PEAK_BF16_MFMA,
                                   "note": "2 BF16 MACs (l_hi, l_lo) = 4 flops per update"}
 
-    # sampled parity against the oracle (pairs drawn at random)
-    try:
-        import oracle
-        rng = np.random.default_rng(0)
-        ii = rng.choice(n, size=24, replace=False)
-        pr = [(int(min(a, b)), int(max(a, b))) for a, b in zip(ii[:12], ii[12:])]
-        idx = [uf.condensed_index(n, a, b) for a, b in pr]
-        par = {}
-        for name, out in (("weighted_normalized", out_w), ("unweighted", out_u)):
-            want = oracle.dm_pairs(tree, table, pr, name)
-            got = out[torch.tensor(idx, device="cuda")].cpu().numpy()
-            par[name] = float(np.max(np.abs(got - want)))
-        extra["sampled_parity_max_abs_err"] = par
-        log(f"sampled parity vs oracle: {par}")
-    except Exception as ex:  # reported, never hides the measurement
-        extra["sampled_parity_error"] = repr(ex)
+    # GPU values of sampled pairs (compared with the oracle in the CPU leg)
+    rng = np.random.default_rng(0)
+    ii = rng.choice(n, size=24, replace=False)
+    sampled_pairs = [(int(min(a, b)), int(max(a, b))) for a, b in zip(ii[:12], ii[12:])]
+    sidx = torch.tensor([uf.condensed_index(n, a, b) for a, b in sampled_pairs], device="cuda")
+    sampled_got = {"step_weighted_normalized": ("weighted_normalized", out_w[sidx].cpu().numpy()),
+                   "step_unweighted": ("unweighted", out_u[sidx].cpu().numpy())}
 
+    # Comparison runs, each a whole call over the full problem with the inputs resident:
+    # the unweighted plain stripe kernel (FP32) vs the MFMA Gram over all branches (the
+    # "MFMA vs plain" figure, both at <= 1e-4 error), and the plain weighted FP32 kernel
+    # (what the split replaces); --extra adds the FP64 weighted kernel.
+    comparisons = [("unweighted_plain_fp32", "unweighted", "fp32"),
+                   ("unweighted_mfma_all_branches", "unweighted", "mfma"),
+                   ("weighted_plain_fp32", "weighted_normalized", "fp32")]
     if args.extra:
-        for name, var, prec in (("weighted_fp64", "weighted_normalized", "fp64"),
-                                ("unweighted_plain_fp32", "unweighted", "fp32")):
+        comparisons.append(("weighted_fp64", "weighted_normalized", "fp64"))
+    if not args.no_comparisons:
+        for name, var, prec in comparisons:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             uf.dm(emb, var, prec, out=out_w, stream=stream)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             extra[name] = {"seconds": dt, "updates_per_s": U / dt}
-            log(f"extra {name}: {dt:.2f}s")
-        if "gram_mfma" in kern and "unweighted_plain_fp32" in extra:
-            extra["mfma_speedup_over_plain_fp32"] = (extra["unweighted_plain_fp32"]["seconds"] /
-                                                     (kern["gram_mfma"]["total_ms_per_step"] / 1e3))
+            sampled_got[name] = (var, out_w[sidx].cpu().numpy())
+            log(f"comparison {name}: {dt:.2f}s")
+        extra["mfma_speedup_over_plain_fp32"] = (extra["unweighted_plain_fp32"]["seconds"] /
+                                                 extra["unweighted_mfma_all_branches"]["seconds"])
+        t_all = extra["unweighted_mfma_all_branches"]["seconds"]
+        extra["unweighted_mfma_all_branches"]["mfma_frac_whole_call"] = 4 * U / t_all / PEAK_BF16_MFMA
 
     # arithmetic types of the kernels that ran: weighted dense part, split pair sums,
     # unweighted dense part
@@ -431,6 +445,9 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         cpu = cpu_baseline(tree, table, args.cpu_seconds)
+        cpu["sampled_parity_max_abs_err"] = {
+            k: sampled_error(tree, table, sampled_pairs, v, got) for k, (v, got) in sampled_got.items()}
+        log(f"sampled parity vs oracle: {cpu['sampled_parity_max_abs_err']}")
 
     rec = {
         "metric": "UniFrac pair-node updates/s (1 GPU)",
