@@ -257,6 +257,8 @@ def main() -> int:
                     choices=["fp32_split", "fp32", "fp64"])
     ap.add_argument("--split-threshold", type=float, default=None,
                     help="dense-set fraction of the sparse-aware split (default: automatic)")
+    ap.add_argument("--split-threshold-weighted", type=float, default=None)
+    ap.add_argument("--split-threshold-unweighted", type=float, default=None)
     ap.add_argument("--unweighted-precision", default="mfma_split",
                     choices=["mfma", "mfma_split", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -312,6 +314,10 @@ def main() -> int:
     wp, up = args.weighted_precision, args.unweighted_precision
     splits = {}
     uf.set_split_threshold(args.split_threshold)
+    if args.split_threshold_weighted is not None:
+        uf.set_split_threshold(args.split_threshold_weighted, "weighted_normalized")
+    if args.split_threshold_unweighted is not None:
+        uf.set_split_threshold(args.split_threshold_unweighted, "unweighted")
     for var, prec in (("weighted_normalized", wp), ("unweighted", up)):
         if prec.endswith("_split"):
             t_split = time.perf_counter()
@@ -353,46 +359,48 @@ def main() -> int:
 
     kern = {}
     for name in ("embed_nm", "embed_pres", "band_wn_u32", "band_wn_f32", "band_wn_f64", "band_uw_f32",
-                 "band_uw_f64", "gram_mfma", "rare_pairs", "finalize", "row_sums"):
+                 "band_uw_f64", "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize",
+                 "row_sums"):
         tot, cnt = uf.profile_read(name)
         if cnt:
             kern[name] = {"total_ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
                           "avg_ms_per_launch": tot / cnt}
     # dominant kernel: the weighted stripe kernel (FP64, FP32, or the 32-bit
-    # fixed-point pass of the split).  Counted in VALU lane-ops: FP64/FP32 take 2 per
-    # update (subtract, add of |.|), fixed point 1 (v_sad_u32: |a - b| + acc).  The
-    # peak is 256 CU x 128 lanes/clk x 2.4 GHz = 78.6e12 lane-ops/s for 32-bit ops
-    # (the published 157.3 TFLOP/s FP32 counts an FMA as 2 flops), 39.3e12 for FP64.
+    # fixed-point pass of the split), counted in VALU issue slots.  FP32/FP64 take 2
+    # full-rate ops per update (subtract, add of |.|); fixed point takes one v_sad_u32
+    # (|a - b| + acc), which issues at half the 32-bit rate, i.e. 2 slots as well.  The
+    # peak is 256 CU x 128 lanes/clk x 2.4 GHz = 78.6e12 slots/s for 32-bit ops (the
+    # published 157.3 TFLOP/s FP32 counts an FMA as 2 flops), half that for FP64.
     # With the split the stripe kernel visits only the dense branches.
     if wp == "fp64":
-        band, ops, peak_ops, kname = "band_wn_f64", 2, PEAK_VALU_SLOTS["fp64"], "k_band<double,weighted>"
+        band, peak_ops, kname = "band_wn_f64", PEAK_VALU_SLOTS["fp64"], "k_band<double,weighted>"
     elif "band_wn_u32" in kern:
-        band, ops, peak_ops, kname = "band_wn_u32", 1, PEAK_VALU_SLOTS["fp32"], "k_band<uint32_t,weighted>"
+        band, peak_ops, kname = "band_wn_u32", PEAK_VALU_SLOTS["fp32"], "k_band<uint32_t,weighted>"
     else:
-        band, ops, peak_ops, kname = "band_wn_f32", 2, PEAK_VALU_SLOTS["fp32"], "k_band<float,weighted>"
+        band, peak_ops, kname = "band_wn_f32", PEAK_VALU_SLOTS["fp32"], "k_band<float,weighted>"
     band_ms = kern[band]["total_ms_per_step"]
     band_updates = pairs * splits["weighted_normalized"][0] if wp == "fp32_split" else U
-    lane_ops = ops * band_updates / (band_ms / 1e3)
+    slots = 2 * band_updates / (band_ms / 1e3)
     traffic = measured_traffic(band, args.workload)
     roofline = {"bound": "alu", "kernel": kname,
-                "achieved": lane_ops / 1e12, "peak": peak_ops / 1e12,
-                "unit": "Tops/s", "frac": lane_ops / peak_ops, "traffic": traffic,
+                "achieved": slots / 1e12, "peak": peak_ops / 1e12,
+                "unit": "Tops/s", "frac": slots / peak_ops, "traffic": traffic,
                 "avg_launch_ms": kern[band]["avg_ms_per_launch"],
                 "launches_per_step": kern[band]["launches_per_step"],
                 "updates_per_launch": band_updates / kern[band]["launches_per_step"],
-                "note": f"{ops} VALU lane-op(s) per pair-branch update; peak = 256 CU x 128 "
-                        "lanes/clk x 2.4 GHz (32-bit) or half that (FP64); one lane-op = "
-                        "one issue slot, i.e. half of an FMA's 2 flops"}
+                "note": "VALU issue slots: 2 per pair-branch update (FP: subtract + add of |.|; "
+                        "fixed point: one half-rate v_sad_u32); peak = 256 CU x 128 lanes/clk "
+                        "x 2.4 GHz (32-bit), half that for FP64"}
     extra = {"kernels": kern}
     if splits:
-        r_ms = kern.get("rare_pairs", {}).get("total_ms_per_step", 0.0)
-        n_atomics = sum(v[2] for v in splits.values())
         extra["split"] = {"threshold": args.split_threshold if args.split_threshold is not None
-                          else "automatic",
-                          **{var: {"dense_branches": v[0], "shared_lists": v[1],
-                                   "pairs_enumerated": v[2]} for var, v in splits.items()},
-                          "band_updates_per_step": band_updates,
-                          "rare_pair_atomics_per_s": n_atomics / (r_ms / 1e3) if r_ms else None}
+                          else "automatic", "band_updates_per_step": band_updates}
+        for var, v in splits.items():
+            name = "rare_slots_wn" if var == "weighted_normalized" else "rare_slots_uw"
+            r_ms = kern.get(name, {}).get("total_ms_per_step", 0.0)
+            extra["split"][var] = {"dense_branches": v[0], "shared_lists": v[1],
+                                   "pairs_enumerated": v[2],
+                                   "slot_kernel_pairs_per_s": v[2] / (r_ms / 1e3) if r_ms else None}
     if "gram_mfma" in kern:
         g_ms = kern["gram_mfma"]["total_ms_per_step"]
         g_upd = pairs * splits["unweighted"][0] if up == "mfma_split" else U

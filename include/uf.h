@@ -324,8 +324,8 @@ uf_status uf_dm_rerank_weighted_normalized(const uf_sparse* queries, const uf_sp
 
 /* Per-kernel timing with HIP events recorded on the call's stream around each
  * launch (process-wide; off by default).  Names: "embed_nm", "embed_pres",
- * "band_wn_f64", "band_wn_f32", "band_uw_f64", "band_uw_f32", "gram_mfma",
- * "finalize", "row_sums".  uf_profile_read synchronises the recorded events
+ * "band_wn_f64", "band_wn_f32", "band_wn_u32", "band_uw_f64", "band_uw_f32",
+ * "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize", "row_sums".  uf_profile_read synchronises the recorded events
  * and returns the total milliseconds and launch count of one kernel name
  * since the last reset.  Errors: UF_ERR_ARG (NULL), UF_ERR_DEVICE. */
 void uf_profile_enable(int on);

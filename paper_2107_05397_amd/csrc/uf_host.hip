@@ -200,12 +200,12 @@ void free_split(SplitCache* sc) {
 // pair sum, Q (m_i + m_j) plus rounding, below 2^32 (m: dense mass of a sample);
 // the fixed-point pass is taken when the bound on d is at most 1e-5.
 double fixed_point_scale(const std::vector<double>& sw, const std::vector<unsigned long long>& sigma,
-                         const std::vector<int32_t>& nnz, int64_t n_dense) {
+                         double unit, const std::vector<int32_t>& nnz, int64_t n_dense) {
     constexpr double kMaxDistErr = 1e-5;
     if (n_dense >= (int64_t(1) << 22)) return 0.0;
     double m_max = 0.0, ratio = 0.0;
     for (size_t s = 0; s < nnz.size(); ++s) {
-        const double m = std::max(sw[s] - double(sigma[s]) * 0x1p-40, 0.0);
+        const double m = std::max(sw[s] - double(sigma[s]) * unit, 0.0);
         m_max = std::max(m_max, m);
         if (nnz[s] > 0) {
             if (!(sw[s] > 0.0)) return 0.0;
@@ -280,14 +280,28 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->n_lists = int64_t(roff.size()) - 1;
     sc->n_entries = roff.back();
     sc->n_dense_pad = (sc->n_dense + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    if (weighted) {
+        // packed members hold the sample in kSampleBits bits and the value in the
+        // other 40: choose the fixed-point step so that l * u <= max l stays below 2^40
+        if (n > (int64_t(1) << ufs::kSampleBits))
+            return fail(UF_ERR_UNSUPPORTED, "the weighted sparse split takes at most 2^24 samples");
+        std::vector<double> len(size_t(std::max<int64_t>(nb, 1)), 0.0);
+        if (nb) UF_HIP(hipMemcpy(len.data(), e->len, size_t(nb) * 8, hipMemcpyDeviceToHost));
+        double lmax = 0.0;
+        for (int64_t v = 0; v < nb; ++v)
+            if (cls[size_t(v)] != ufs::kClassDense) lmax = std::max(lmax, len[size_t(v)]);
+        int ex = 0;
+        while (lmax >= std::ldexp(1.0 - 0x1p-20, ex)) ++ex;
+        sc->unit = std::ldexp(1.0, ex - 40);
+    }
     const size_t ne = size_t(std::max<int64_t>(sc->n_entries, 1));
     const size_t nl = size_t(std::max<int64_t>(sc->n_lists, 1));
     Carver c;
     const size_t o_dense = c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4);
     const size_t o_cls = c.take(size_t(std::max<int64_t>(nb, 1)) * 4);
     const size_t o_roff = c.take(roff.size() * 8);
-    const size_t o_rs = c.take(ne * 4);
-    const size_t o_rq = c.take(ne * 8);
+    const size_t o_rs = weighted ? 0 : c.take(ne * 4);
+    const size_t o_rw = weighted ? c.take(ne * 8) : 0;
     const size_t o_sig = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
     const size_t o_dhi = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
     const size_t o_dlo = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
@@ -300,8 +314,8 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
     sc->cls = reinterpret_cast<int32_t*>(b + o_cls);
     sc->roff = reinterpret_cast<int64_t*>(b + o_roff);
-    sc->rs = reinterpret_cast<int32_t*>(b + o_rs);
-    sc->rq = reinterpret_cast<int64_t*>(b + o_rq);
+    sc->rs = weighted ? nullptr : reinterpret_cast<int32_t*>(b + o_rs);
+    sc->rw = weighted ? reinterpret_cast<unsigned long long*>(b + o_rw) : nullptr;
     sc->sigma = reinterpret_cast<unsigned long long*>(b + o_sig);
     sc->dlen_hi = reinterpret_cast<uint16_t*>(b + o_dhi);
     sc->dlen_lo = reinterpret_cast<uint16_t*>(b + o_dlo);
@@ -332,7 +346,8 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     if (rc == hipSuccess) rc = hipMemsetAsync(dnnz, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
     if (rc == hipSuccess) rc = hipMemsetAsync(sc->sigma, 0, size_t(std::max<int64_t>(n, 1)) * 8, s);
     if (rc == hipSuccess)
-        rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz, s);
+        rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz,
+                             1.0 / sc->unit, s);
     const size_t nn = size_t(std::max<int64_t>(n, 1));
     std::vector<int32_t> hcnt(nn, 0), hdnnz(nn, 0);
     std::vector<double> hsw(nn, 0.0);
@@ -343,14 +358,15 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     if (rc == hipSuccess && n) rc = hipMemcpy(hsw.data(), e->sw, size_t(n) * 8, hipMemcpyDeviceToHost);
     if (rc == hipSuccess && n)
         rc = hipMemcpy(hsig.data(), sc->sigma, size_t(n) * 8, hipMemcpyDeviceToHost);
-    if (rc == hipSuccess && weighted) sc->q_scale = fixed_point_scale(hsw, hsig, hdnnz, sc->n_dense);
+    if (rc == hipSuccess && weighted)
+        sc->q_scale = fixed_point_scale(hsw, hsig, sc->unit, hdnnz, sc->n_dense);
     std::vector<int64_t> soff(size_t(n + 1), 0);
     for (int64_t i = 0; i < n; ++i) soff[size_t(i + 1)] = soff[size_t(i)] + hcnt[size_t(i)];
     if (rc == hipSuccess && soff[size_t(n)] != sc->n_entries)
         return fail_free(fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree"));
     if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
     if (rc == hipSuccess)
-        rc = ufs::sort_lists(sc->roff, sc->n_lists, rs_tmp, rq_tmp, sc->rs, sc->rq, sc->soff, scur,
+        rc = ufs::sort_lists(sc->roff, sc->n_lists, rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur,
                              sc->sl_list, sc->sl_pos, s);
     if (rc == hipSuccess)
         rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
@@ -524,8 +540,8 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     unsigned long long* M = nullptr;
     if (sp) {
         M = reinterpret_cast<unsigned long long*>(base + p.off_m);
-        ProfScope ps("rare_pairs", s);
-        UF_HIP(ufs::rare_slots(sp->roff, sp->rs, sp->rq, weighted ? nullptr : sp->rl, sp->soff,
+        ProfScope ps(weighted ? "rare_slots_wn" : "rare_slots_uw", s);
+        UF_HIP(ufs::rare_slots(sp->roff, sp->rs, sp->rw, weighted ? nullptr : sp->rl, sp->soff,
                                sp->sl_list, sp->sl_pos, p.n, p.sb, p.se, M, s));
     }
     const double* scal = weighted ? e->sw
@@ -536,7 +552,8 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
         const int acc_type = prec == UF_FP64 ? ufk::kAccF64 : (fixed ? ufk::kAccU32 : ufk::kAccF32);
         UF_HIP(ufk::finalize(weighted ? 0 : 1, acc, acc_type, fixed ? 1.0 / sp->q_scale : 1.0, scal,
                              p.n, p.sb, p.se, layout, odt == UF_OUT_F32 ? 1 : 0, out, q, s, M,
-                             sp && weighted ? sp->sigma : nullptr));
+                             sp && weighted ? sp->sigma : nullptr,
+                             sp && weighted ? sp->unit : 0x1p-40));
     }
     if (rowstats) {
         ProfScope ps("row_sums", s);

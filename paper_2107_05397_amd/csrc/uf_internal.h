@@ -53,9 +53,10 @@ struct SplitCache {
     int32_t* dense = nullptr;     // [n_dense] positions, ascending
     int32_t* cls = nullptr;       // [nb] class per position (list id, or ufs::kClass*)
     int64_t* roff = nullptr;      // [n_lists+1]
-    int32_t* rs = nullptr;        // [n_entries] sample of each list entry, ascending per list
-    int64_t* rq = nullptr;        // [n_entries] l*u in 2^-40 fixed point
-    unsigned long long* sigma = nullptr;   // [n] fixed-point sum over non-dense branches
+    int32_t* rs = nullptr;        // unweighted: [n_entries] sample of each entry, ascending per list
+    unsigned long long* rw = nullptr;  // weighted: [n_entries] rint(l*u/unit) << 24 | sample
+    double unit = 0x1p-40;        // weighted: value of one fixed-point step of rw, sigma and M
+    unsigned long long* sigma = nullptr;   // [n] weighted: sum over non-dense branches, in unit
     int64_t n_dense_pad = 0;      // n_dense rounded up to the MFMA K step
     uint16_t* dlen_hi = nullptr;  // [n_dense_pad] bf16 high part of each dense length, 0-padded
     uint16_t* dlen_lo = nullptr;  // [n_dense_pad] bf16 low part
@@ -162,14 +163,14 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 // kind 1: unweighted Gram form ((w_i + w_j - 2G) / (w_i + w_j - G)), clamped to [0, 1].
 // acc_type (kAcc*) selects the accumulator type; its values are multiplied by
 // acc_scale.  q (nullable) receives -d^2/2 in FP64, stripe-major.  layout/out dtype
-// as in uf.h.  split_m (nullable, 2^-40 fixed point, stripe-major like acc) carries
-// the non-dense branches: kind 0 adds sigma_i + sigma_j - 2 M to the numerator,
-// kind 1 adds M to the Gram value.
+// as in uf.h.  split_m (nullable, fixed point with step split_unit, stripe-major
+// like acc) carries the non-dense branches: kind 0 adds sigma_i + sigma_j - 2 M to
+// the numerator, kind 1 adds M to the Gram value.
 constexpr int kAccF32 = 0, kAccF64 = 1, kAccU32 = 2;
 hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, const double* scal,
                     int64_t n, int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
                     hipStream_t st, const unsigned long long* split_m = nullptr,
-                    const unsigned long long* sigma = nullptr);
+                    const unsigned long long* sigma = nullptr, double split_unit = 0x1p-40);
 
 // Row sums of -d^2/2 over the distinct pairs of stripes [sb, se): two fixed-order stages.
 hipError_t row_sums(const double* q, int64_t n, int64_t sb, int64_t se, double* partial,

@@ -185,17 +185,18 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
 // ----------------------------------------------------------------------------
 template <typename T>
 struct BandCfg;
+// KS: branches per LDS stage; MS: stripes per thread (tile = 128 x 16*MS)
 template <>
 struct BandCfg<float> {
-    static constexpr int KS = 16;
+    static constexpr int KS = 16, MS = 8;
 };
 template <>
 struct BandCfg<double> {
-    static constexpr int KS = 8;
+    static constexpr int KS = 8, MS = 8;
 };
 template <>
 struct BandCfg<uint32_t> {
-    static constexpr int KS = 16;
+    static constexpr int KS = 16, MS = 16;
 };
 
 // |a - b| + c on unsigned 32-bit integers in one VALU op
@@ -214,22 +215,25 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n_tiles) {
     return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
-// LDS of one band tile: two staging buffers of KS branches.
-template <typename T, int KS>
+// LDS of one band tile of 16*MS stripes: two staging buffers of KS branches.
+template <typename T, int KS, int MS = 8>
 struct BandLds {
     T wi[2][KS][kBandI];
-    T wj[2][KS][kBandI + kBandS];
+    T wj[2][KS][kBandI + 16 * MS];
     T wl[2][KS];
 };
 
-// One band tile: samples [i0, i0+128) x stripes [s0, s0+128) of a matrix with
-// n samples, over the kc branches of node-major E (row stride n).
-template <typename T, bool W, int KS>
-__device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict__ E,
+// One band tile: samples [i0, i0+128) x stripes [s0, s0+16*MS) of a matrix with
+// n samples, over the kc branches of node-major E (row stride n).  Thread
+// (ti, ts) = (tid % 16, tid / 16) owns the 8 x MS register block of samples
+// i0 + 8ti + [0, 8) and stripes s0 + MS*ts + [0, MS); its partners are the
+// 8 + MS - 1 consecutive samples from i0 + s0 + 1 + 8ti + MS*ts.
+template <typename T, bool W, int KS, int MS = 8>
+__device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __restrict__ E,
                                           const T* __restrict__ lenk, int64_t kc, int64_t n,
                                           int64_t sb, int64_t se, int64_t i0, int64_t s0,
                                           int first, T* __restrict__ acc) {
-    constexpr int I = kBandI, WJ = kBandI + kBandS;
+    constexpr int I = kBandI, WJ = kBandI + 16 * MS;
     constexpr int DW = int(sizeof(T) / 4);          // dwords per element
     constexpr int EPS = 64 / DW;                    // elements per 64-dword segment
     constexpr int SEG_I = I / EPS, SEG_J = WJ / EPS;
@@ -268,10 +272,10 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict
         if (!W && tid < KS) L.wl[buf][tid] = (k0 + tid < kc) ? lenk[k0 + tid] : T(0);
     };
 
-    T r[8][8];
+    T r[8][MS];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int64_t s = s0 + ts * 8 + b;
+    for (int b = 0; b < MS; ++b) {
+        const int64_t s = s0 + ts * MS + b;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int64_t i = i0 + ti * 8 + a;
@@ -288,28 +292,28 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict
         if (blk + 1 < nblk) stage(cur ^ 1, (blk + 1) * KS);
 #pragma unroll 2
         for (int kk = 0; kk < KS; ++kk) {
-            T xi[8], xj[16];
+            T xi[8], xj[8 + MS];
 #pragma unroll
             for (int a = 0; a < 8; ++a) xi[a] = L.wi[cur][kk][ti * 8 + a];
 #pragma unroll
-            for (int c = 0; c < 15; ++c) xj[c] = L.wj[cur][kk][ti * 8 + ts * 8 + c];
+            for (int c = 0; c < 7 + MS; ++c) xj[c] = L.wj[cur][kk][ti * 8 + ts * MS + c];
             if constexpr (std::is_same<T, uint32_t>::value) {
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) r[a][b] = sad_u32(xi[a], xj[a + b], r[a][b]);
+                    for (int b = 0; b < MS; ++b) r[a][b] = sad_u32(xi[a], xj[a + b], r[a][b]);
             } else if constexpr (W) {
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) r[a][b] += fabs(xi[a] - xj[a + b]);
+                    for (int b = 0; b < MS; ++b) r[a][b] += fabs(xi[a] - xj[a + b]);
             } else {
                 const T l = L.wl[cur][kk];
 #pragma unroll
                 for (int a = 0; a < 8; ++a) {
                     const T li = l * xi[a];
 #pragma unroll
-                    for (int b = 0; b < 8; ++b) r[a][b] = fma(li, xj[a + b], r[a][b]);
+                    for (int b = 0; b < MS; ++b) r[a][b] = fma(li, xj[a + b], r[a][b]);
                 }
             }
         }
@@ -318,8 +322,8 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS>& L, const T* __restrict
     }
 
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const int64_t s = s0 + ts * 8 + b;
+    for (int b = 0; b < MS; ++b) {
+        const int64_t s = s0 + ts * MS + b;
         if (s >= se) continue;
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
@@ -334,13 +338,13 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
                                               const T* __restrict__ lenk, int64_t kc,
                                               int64_t n, int64_t sb, int64_t se, int64_t n_iblk,
                                               int first, T* __restrict__ acc) {
-    constexpr int KS = BandCfg<T>::KS;
-    __shared__ __attribute__((aligned(16))) BandLds<T, KS> L;
-    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    constexpr int KS = BandCfg<T>::KS, MS = BandCfg<T>::MS, TS = 16 * MS;
+    __shared__ __attribute__((aligned(16))) BandLds<T, KS, MS> L;
+    const int64_t n_tiles = n_iblk * ((se - sb + TS - 1) / TS);
     const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
     const int64_t i0 = (tile % n_iblk) * kBandI;
-    const int64_t s0 = sb + (tile / n_iblk) * kBandS;
-    band_tile<T, W, KS>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
+    const int64_t s0 = sb + (tile / n_iblk) * TS;
+    band_tile<T, W, KS, MS>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
 }
 
 // ----------------------------------------------------------------------------
@@ -369,6 +373,32 @@ __device__ __forceinline__ bool tile_in_range(int64_t i0, int64_t j0, int64_t n,
     return a1 <= b1 || a2 <= b2;
 }
 
+// Block -> tile of the Gram kernel.  Tiles are grouped in G x G super-tiles over
+// the upper triangle (super-row <= super-column); super-tile u runs on XCD u mod 8
+// (blocks are dealt to the 8 XCDs round-robin), so the ~2 blocks per CU of one XCD
+// cover one super-tile at a time and read each of its G row and G column panels
+// once into that XCD's L2 instead of once per tile.  Returns false for slots
+// outside the matrix or below the diagonal.
+constexpr int kGramGroup = 8;
+
+__device__ __forceinline__ bool gram_tile_of(int64_t b, int64_t nblk, int64_t& bi, int64_t& bj) {
+    constexpr int64_t G = kGramGroup, GG = G * G;
+    const int64_t ns = (nblk + G - 1) / G;
+    const int64_t x = b & 7, k = b >> 3;
+    int64_t u = (k / GG) * 8 + x;          // super-tile, upper triangle row-major
+    const int64_t w = k % GG;
+    int64_t si = 0;
+    while (si < ns && u >= ns - si) {
+        u -= ns - si;
+        ++si;
+    }
+    if (si >= ns) return false;
+    const int64_t sj = si + u;
+    bi = si * G + w / G;
+    bj = sj * G + w % G;
+    return bi < nblk && bj < nblk && bj >= bi;
+}
+
 __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict__ P,
                                                       const uint16_t* __restrict__ hiv,
                                                       const uint16_t* __restrict__ lov,
@@ -376,8 +406,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
                                                       int64_t se, int first,
                                                       float* __restrict__ acc) {
     constexpr int T = kGramT, KT = kGramK, LD = KT + 8;
-    const int64_t bi = blockIdx.y, bj = blockIdx.x;
-    if (bj < bi) return;
+    int64_t bi, bj;
+    if (!gram_tile_of(blockIdx.x, (n + T - 1) / T, bi, bj)) return;
     const int64_t i0 = bi * T, j0 = bj * T;
     if (!tile_in_range(i0, j0, n, sb, se)) return;
 
@@ -500,7 +530,8 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
                                                   int64_t sb, int64_t se, int layout, int out_f32,
                                                   void* __restrict__ out, double* __restrict__ q,
                                                   const unsigned long long* __restrict__ split_m,
-                                                  const unsigned long long* __restrict__ sigma) {
+                                                  const unsigned long long* __restrict__ sigma,
+                                                  double split_unit) {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n) return;
     const bool even = (n & 1) == 0;
@@ -510,9 +541,9 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
         if (split_m) {
             if (kind == 0) {
                 const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
-                num += double(r) * (1.0 / 1099511627776.0);
+                num += double(r) * split_unit;
             } else {
-                num += double(split_m[(s - sb) * n + i]) * (1.0 / 1099511627776.0);
+                num += double(split_m[(s - sb) * n + i]) * split_unit;
             }
         }
         double d;
@@ -734,8 +765,9 @@ template <typename T>
 static hipError_t band(const T* E, const T* lenk, int64_t kc, int64_t n, int64_t sb, int64_t se,
                        int weighted, int first, T* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
+    constexpr int64_t TS = 16 * BandCfg<T>::MS;
     const int64_t n_iblk = (n + kBandI - 1) / kBandI;
-    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    const int64_t n_tiles = n_iblk * ((se - sb + TS - 1) / TS);
     if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n_tiles), 1u, 1u};
     if (weighted)
@@ -759,8 +791,9 @@ hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, in
 hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_t se, int first,
                     uint32_t* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
+    constexpr int64_t TS = 16 * BandCfg<uint32_t>::MS;
     const int64_t n_iblk = (n + kBandI - 1) / kBandI;
-    const int64_t n_tiles = n_iblk * ((se - sb + kBandS - 1) / kBandS);
+    const int64_t n_tiles = n_iblk * ((se - sb + TS - 1) / TS);
     if (n_tiles > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n_tiles), 1u, 1u};
     hipLaunchKernelGGL((k_band<uint32_t, true>), grid, dim3(256), 0, st, E, nullptr, kc, n, sb, se,
@@ -773,7 +806,11 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
     if (se <= sb || n <= 0) return hipSuccess;
     const int64_t nblk = (n + kGramT - 1) / kGramT;
     if (nblk > 65535 || (kpad % kGramK) != 0) return hipErrorInvalidValue;
-    const dim3 grid{unsigned(nblk), unsigned(nblk), 1u};
+    const int64_t ns = (nblk + kGramGroup - 1) / kGramGroup;
+    const int64_t n_super = ns * (ns + 1) / 2;
+    const int64_t blocks = (n_super + 7) / 8 * 8 * kGramGroup * kGramGroup;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(blocks), 1u, 1u};
     hipLaunchKernelGGL(k_gram_mfma, grid, dim3(256), 0, st, P, hi, lo, kpad, n, sb, se, first,
                        acc);
     return hipGetLastError();
@@ -782,21 +819,21 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
 hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, const double* scal,
                     int64_t n, int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,
                     hipStream_t st, const unsigned long long* split_m,
-                    const unsigned long long* sigma) {
+                    const unsigned long long* sigma, double split_unit) {
     if (se <= sb || n <= 0) return hipSuccess;
     dim3 grid(unsigned((n + 255) / 256), grid_y(se - sb));
     if (acc_type == kAccF64)
         hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, st, kind,
                            static_cast<const double*>(acc), acc_scale, scal, n, sb, se, layout,
-                           out_f32, out, q, split_m, sigma);
+                           out_f32, out, q, split_m, sigma, split_unit);
     else if (acc_type == kAccU32)
         hipLaunchKernelGGL(k_finalize<uint32_t>, grid, dim3(256), 0, st, kind,
                            static_cast<const uint32_t*>(acc), acc_scale, scal, n, sb, se, layout,
-                           out_f32, out, q, split_m, sigma);
+                           out_f32, out, q, split_m, sigma, split_unit);
     else
         hipLaunchKernelGGL(k_finalize<float>, grid, dim3(256), 0, st, kind,
                            static_cast<const float*>(acc), acc_scale, scal, n, sb, se, layout,
-                           out_f32, out, q, split_m, sigma);
+                           out_f32, out, q, split_m, sigma, split_unit);
     return hipGetLastError();
 }
 

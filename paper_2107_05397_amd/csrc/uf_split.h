@@ -11,17 +11,20 @@ namespace ufs {
 
 constexpr int32_t kClassDense = -1;    // branch in the dense set
 constexpr int32_t kClassAlone = -2;    // touched by at most one sample: no pairs
+constexpr int kSampleBits = 24;         // packed weighted list member: value << 24 | sample
 
 hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st);
 // Unsorted list members (sample, fixed-point l*u), sigma, per-sample list counts
 // (scnt) and per-sample counts of dense branches of nonzero length (dnnz).
 hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
                       int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
-                      int32_t* dnnz, hipStream_t st);
-// Lists sorted by sample into rs_out/rq_out; per-sample index rows [soff[s], soff[s+1])
-// of (list, position) filled through the cursors scur (zeroed by the caller).
+                      int32_t* dnnz, double fix, hipStream_t st);
+// Lists sorted by sample, into rs_out (sample ids) or, when rw_out is non-null, into
+// rw_out as packed words rq << kSampleBits | sample; per-sample index rows
+// [soff[s], soff[s+1]) of (list, position) filled through the cursors scur (zeroed
+// by the caller).
 hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
-                      int32_t* rs_out, int64_t* rq_out, const int64_t* soff, int32_t* scur,
+                      int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       int32_t* sl_list, int32_t* sl_pos, hipStream_t st);
 // Node-major chunk E[k][s] over positions list[k0 .. k0+kc): x = l * c / T as FP32,
 // or as rint(x * q) in 32-bit fixed point.
@@ -35,10 +38,11 @@ hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, i
                          int64_t n_pad, const uint16_t* len_hi, const uint16_t* len_lo,
                          uint16_t* dlen_hi, uint16_t* dlen_lo, int64_t* rl, hipStream_t st);
 // M[(s-sb)*n + i] = sum over the pairs (i, (i+s+1) mod n), s in [sb, se), that share a
-// non-dense branch: rl == nullptr: weighted, min(rq_i, rq_j); else unweighted, rl[list].
-// Writes every element of the range (no clearing needed).
-hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const int64_t* rq, const int64_t* rl,
-                      const int64_t* soff, const int32_t* sl_list, const int32_t* sl_pos, int64_t n,
-                      int64_t sb, int64_t se, unsigned long long* M, hipStream_t st);
+// non-dense branch: rw non-null: weighted, min of the two packed values; else
+// unweighted (sample ids rs), rl[list].  Writes every element of the range.
+hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned long long* rw,
+                      const int64_t* rl, const int64_t* soff, const int32_t* sl_list,
+                      const int32_t* sl_pos, int64_t n, int64_t sb, int64_t se, unsigned long long* M,
+                      hipStream_t st);
 
 }  // namespace ufs

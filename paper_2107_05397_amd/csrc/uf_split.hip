@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
                                                     int64_t* __restrict__ rq,
                                                     unsigned long long* __restrict__ sigma,
                                                     int32_t* __restrict__ scnt,
-                                                    int32_t* __restrict__ dnnz) {
+                                                    int32_t* __restrict__ dnnz, double fix) {
     const int64_t s = blockIdx.x;
     const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
     const double inv_t = 1.0 / e.total[s];
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
                 return;
             }
             const int64_t cn = ufd::count_in(e, s, e.lo[v], e.hi[v]);
-            const long long q = llrint(e.len[v] * (double(cn) * inv_t) * kFix);
+            const long long q = llrint(e.len[v] * (double(cn) * inv_t) * fix);
             part += (unsigned long long)q;
             if (c >= 0) {
                 const int32_t slot = atomicAdd(&rfill[c], 1);
@@ -86,13 +86,15 @@ constexpr int kSortLds = 4096;
 __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
                                              int32_t r, const int64_t* __restrict__ rq_in,
                                              int32_t* __restrict__ rs_out,
-                                             int64_t* __restrict__ rq_out,
+                                             unsigned long long* __restrict__ rw_out,
                                              const int64_t* __restrict__ soff,
                                              int32_t* __restrict__ scur,
                                              int32_t* __restrict__ sl_list,
                                              int32_t* __restrict__ sl_pos) {
-    rs_out[base + r] = smp;
-    rq_out[base + r] = rq_in[base + k];
+    if (rw_out)
+        rw_out[base + r] = ((unsigned long long)rq_in[base + k] << kSampleBits) | unsigned(smp);
+    else
+        rs_out[base + r] = smp;
     const int32_t slot = atomicAdd(&scur[smp], 1);
     sl_list[soff[smp] + slot] = int32_t(L);
     sl_pos[soff[smp] + slot] = r;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ rs_in,
                                                     const int64_t* __restrict__ rq_in,
                                                     int32_t* __restrict__ rs_out,
-                                                    int64_t* __restrict__ rq_out,
+                                                    unsigned long long* __restrict__ rw_out,
                                                     const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ scur,
                                                     int32_t* __restrict__ sl_list,
@@ -118,14 +120,14 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
             const int32_t smp = ks[k];
             int32_t r = 0;
             for (int64_t t = 0; t < m; ++t) r += ks[t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rq_out, soff, scur, sl_list, sl_pos);
+            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, sl_list, sl_pos);
         }
     } else {
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = rs_in[base + k];
             int32_t r = 0;
             for (int64_t t = 0; t < m; ++t) r += rs_in[base + t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rq_out, soff, scur, sl_list, sl_pos);
+            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, sl_list, sl_pos);
         }
     }
 }
@@ -207,7 +209,7 @@ constexpr int64_t kSegStripes = 8192;   // 64 KiB of LDS accumulators per workgr
 template <bool W>
 __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     const int64_t* __restrict__ roff, const int32_t* __restrict__ rs,
-    const int64_t* __restrict__ rq, const int64_t* __restrict__ rl,
+    const unsigned long long* __restrict__ rw, const int64_t* __restrict__ rl,
     const int64_t* __restrict__ soff, const int32_t* __restrict__ sl_list,
     const int32_t* __restrict__ sl_pos, int64_t n, int64_t sb, int64_t se, int64_t seg_len,
     unsigned long long* __restrict__ M) {
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    constexpr unsigned long long kMask = (1ull << kSampleBits) - 1;
     // stripe s pairs i with its cyclic successor at distance d = s + 1; stripes
     // run below floor(N/2), so the window is d in [g0 + 1, min(g1, N/2)]
     const int64_t dlo = g0 + 1;
@@ -229,16 +232,19 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         const int64_t p = sl_pos[k];
         const int64_t base = roff[L];
         const int64_t m = roff[L + 1] - base;
-        const unsigned long long vi = W ? (unsigned long long)rq[base + p]
-                                        : (unsigned long long)rl[L];
+        const unsigned long long vi = W ? rw[base + p] >> kSampleBits : (unsigned long long)rl[L];
         // the c-th member after i (c in [0, m-1)), cyclically, sits at position
         // (p + 1 + c) mod m; its distance from i grows with c
         auto pos_of = [&](int64_t c) {
             const int64_t q = p + 1 + c;
             return q >= m ? q - m : q;
         };
+        auto sample_at = [&](int64_t q) -> int64_t {
+            if constexpr (W) return int64_t(rw[base + q] & kMask);
+            else return rs[base + q];
+        };
         auto dist_of = [&](int64_t q) {
-            const int64_t d = int64_t(rs[base + q]) - i;
+            const int64_t d = sample_at(q) - i;
             return d <= 0 ? d + n : d;
         };
         // first c whose distance reaches dlo: 64-way search, one probe per lane
@@ -265,13 +271,19 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         }
         for (int64_t c = lo + lane; c < m - 1; c += 64) {
             const int64_t q = pos_of(c);
-            const int64_t d = dist_of(q);
-            if (d > dhi) break;
             unsigned long long v = vi;
-            if (W) {
-                const unsigned long long vj = (unsigned long long)rq[base + q];
+            int64_t j;
+            if constexpr (W) {
+                const unsigned long long word = rw[base + q];
+                j = int64_t(word & kMask);
+                const unsigned long long vj = word >> kSampleBits;
                 v = vj < vi ? vj : vi;
+            } else {
+                j = rs[base + q];
             }
+            int64_t d = j - i;
+            if (d <= 0) d += n;
+            if (d > dhi) break;
             atomicAdd(&acc[d - 1 - g0], v);
         }
     }
@@ -289,20 +301,20 @@ hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st) {
 
 hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
                       int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
-                      int32_t* dnnz, hipStream_t st) {
+                      int32_t* dnnz, double fix, hipStream_t st) {
     if (e.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_split_fill, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff, rfill, rs,
-                       rq, sigma, scnt, dnnz);
+                       rq, sigma, scnt, dnnz, fix);
     return hipGetLastError();
 }
 
 hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
-                      int32_t* rs_out, int64_t* rq_out, const int64_t* soff, int32_t* scur,
+                      int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       int32_t* sl_list, int32_t* sl_pos, hipStream_t st) {
     if (n_lists <= 0) return hipSuccess;
     if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, rs_in, rq_in,
-                       rs_out, rq_out, soff, scur, sl_list, sl_pos);
+                       rs_out, rw_out, soff, scur, sl_list, sl_pos);
     return hipGetLastError();
 }
 
@@ -337,20 +349,21 @@ hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, i
     return hipGetLastError();
 }
 
-hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const int64_t* rq, const int64_t* rl,
-                      const int64_t* soff, const int32_t* sl_list, const int32_t* sl_pos, int64_t n,
-                      int64_t sb, int64_t se, unsigned long long* M, hipStream_t st) {
+hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned long long* rw,
+                      const int64_t* rl, const int64_t* soff, const int32_t* sl_list,
+                      const int32_t* sl_pos, int64_t n, int64_t sb, int64_t se, unsigned long long* M,
+                      hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
-    if (n > 0x7fffffff) return hipErrorInvalidValue;
+    if (n > 0x7fffffff || (rw && n > (int64_t(1) << kSampleBits))) return hipErrorInvalidValue;
     const int64_t nseg = (se - sb + kSegStripes - 1) / kSegStripes;
     const int64_t seg_len = (se - sb + nseg - 1) / nseg;
     if (nseg > 65535) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n), unsigned(nseg)};
-    if (rl)
-        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), 0, st, roff, rs, rq, rl, soff,
+    if (rw)
+        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), 0, st, roff, rs, rw, rl, soff,
                            sl_list, sl_pos, n, sb, se, seg_len, M);
     else
-        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), 0, st, roff, rs, rq, rl, soff,
+        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), 0, st, roff, rs, rw, rl, soff,
                            sl_list, sl_pos, n, sb, se, seg_len, M);
     return hipGetLastError();
 }
