@@ -204,7 +204,9 @@ __device__ __forceinline__ int64_t xcd_sample(int64_t b, int64_t n) {
 
 constexpr int kSlotThreads = 1024;
 constexpr int kSlotWaves = kSlotThreads / 64;
-constexpr int64_t kSegStripes = 8192;   // 64 KiB of LDS accumulators per workgroup
+// Stripes per workgroup segment: the LDS row takes 8 bytes per stripe, up to the
+// 160 KiB of a gfx950 CU.
+constexpr int64_t kSegStripes = 20480;
 
 template <bool W>
 __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     const int64_t* __restrict__ soff, const int32_t* __restrict__ sl_list,
     const int32_t* __restrict__ sl_pos, int64_t n, int64_t sb, int64_t se, int64_t seg_len,
     unsigned long long* __restrict__ M) {
-    __shared__ unsigned long long acc[kSegStripes];
+    extern __shared__ unsigned long long acc[];   // [seg_len]
     const int64_t i = xcd_sample(blockIdx.x, n);
     const int64_t g0 = sb + int64_t(blockIdx.y) * seg_len;
     const int64_t g1 = min(se, g0 + seg_len);
@@ -359,12 +361,21 @@ hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned lon
     const int64_t seg_len = (se - sb + nseg - 1) / nseg;
     if (nseg > 65535) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n), unsigned(nseg)};
+    const size_t lds = size_t(seg_len) * 8;
+    static const bool attr_ok = [] {
+        const int most = int(kSegStripes * 8);
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rare_slots<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, most) == hipSuccess &&
+               hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rare_slots<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, most) == hipSuccess;
+    }();
+    if (!attr_ok) return hipErrorInvalidValue;
     if (rw)
-        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), 0, st, roff, rs, rw, rl, soff,
-                           sl_list, sl_pos, n, sb, se, seg_len, M);
+        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), lds, st, roff, rs, rw, rl,
+                           soff, sl_list, sl_pos, n, sb, se, seg_len, M);
     else
-        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), 0, st, roff, rs, rw, rl, soff,
-                           sl_list, sl_pos, n, sb, se, seg_len, M);
+        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), lds, st, roff, rs, rw, rl,
+                           soff, sl_list, sl_pos, n, sb, se, seg_len, M);
     return hipGetLastError();
 }
 
