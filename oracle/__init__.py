@@ -13,6 +13,9 @@ Contents
              by walking parent pointers, with no postorder at all.
 ``core``     the same definitions in plain C (FP64, OpenMP over rows), used to
              time the CPU baseline and to check larger sample subsets.
+``pcoa``     principal coordinates: the exact eigendecomposition of the
+             double-centred matrix, and the randomized subspace iteration.
+``placement`` the learned-placement encoder (projection, MLP, loss, Adam, kNN).
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 (hand-computed worked example, closed forms, brute force, scipy library
@@ -23,3 +26,4 @@ from .unifrac import (  # noqa: F401
     embedding, dm, dm_pairs, pcoa_means, condensed_index, n_stripes,
     stripe_partner, to_stripes, gram_split_bf16,
 )
+from . import pcoa  # noqa: F401
