@@ -409,6 +409,30 @@ def main() -> int:
                                   "frac": 4 * g_upd / (g_ms / 1e3) / PEAK_BF16_MFMA,
                                   "note": "2 BF16 MACs (l_hi, l_lo) = 4 flops per update"}
 
+    # Principal coordinates of the weighted matrix (10 axes, 20-column test matrix,
+    # 3 power passes): 5 products B X, each reading the condensed matrix.
+    if not args.no_comparisons:
+        dims, cols, q = 10, 20, 3
+        omega = torch.tensor(synth.gaussian_matrix(n, cols, seed=17), dtype=torch.float64,
+                             device="cuda")
+        _, rw, gw = uf.dm(emb, "weighted_normalized", wp, out=out_w, row_means=True,
+                          workspace=ws_w, stream=stream)
+        uf.pcoa(out_w, n, dims, omega, power_iters=q, row_means=rw, grand_mean=gw, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, vals, tr = uf.pcoa(out_w, n, dims, omega, power_iters=q, row_means=rw, grand_mean=gw,
+                              stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        products = q + 2
+        extra["pcoa"] = {"seconds": dt, "dims": dims, "test_matrix_cols": cols, "power_iters": q,
+                         "products": products,
+                         "condensed_bytes_per_product": pairs * 8,
+                         "effective_GBps": products * pairs * 8 / dt / 1e9,
+                         "eigenvalues": [float(v) for v in vals[:5]],
+                         "proportion_explained": [float(v / tr) for v in vals[:5]]}
+        log(f"pcoa: {dt * 1e3:.1f} ms, top eigenvalues {vals[:3]}")
+
     # GPU values of sampled pairs (compared with the oracle in the CPU leg)
     rng = np.random.default_rng(0)
     ii = rng.choice(n, size=24, replace=False)

@@ -320,6 +320,41 @@ uf_status uf_dm_rerank_weighted_normalized(const uf_sparse* queries, const uf_sp
                                            int64_t n_queries, int64_t k, double* out, void* ws,
                                            size_t ws_bytes, void* hip_stream);
 
+/* ---- principal coordinates (PCoA) ----------------------------------------- */
+
+/* PCoA of a condensed distance matrix, the ordination the paper computes as
+ * part of the UniFrac job (section II).  Definition (Gower): A = -d^2/2,
+ * B = A - r 1^T - 1 r^T + g 11^T with r_i the row means of A (zero diagonal
+ * included) and g their mean; the principal coordinates are the top eigen-
+ * vectors v_k of B scaled by sqrt(max(lambda_k, 0)), lambda decreasing.  They are
+ * found by randomized subspace iteration with a Rayleigh-Ritz projection
+ * (Halko, Martinsson, Tropp 2011): Y = B Omega, power_iters passes of
+ * Q = orth(B Q), then the eigenpairs of Q^T B Q.  B is never formed; each
+ * product reads the condensed matrix once.
+ *
+ * dm:         device, condensed FP64 (length n(n-1)/2, SciPy order), read only.
+ * row_means, grand_mean: device FP64 [n] and [1] as returned by uf_dm_*, or both
+ *             NULL to have them computed here.
+ * dims:       coordinates wanted; n_cols: columns of the test matrix
+ *             (dims <= n_cols <= 48; oversampling n_cols - dims >= 5 advised).
+ * power_iters: 0..64 (each adds one pass over dm; 2-4 typical).
+ * omega:      device FP64 [n][n_cols], row major: the caller's random test matrix
+ *             (i.i.d. standard normal), read only.
+ * coords:     device FP64 [n][dims], row major, written; each column's largest-
+ *             magnitude entry (first on ties) is positive.
+ * eigvals:    host FP64 [dims], written (Ritz values, decreasing; 0 past the
+ *             numerical rank of B).
+ * trace:      host FP64 [1] or NULL: trace(B) = -n g, the sum of all eigenvalues
+ *             (for proportions explained).
+ * ws:         device workspace of uf_pcoa_workspace_size(n, n_cols) bytes.
+ * stream:     hipStream_t; the call returns after the stream has drained.
+ * Errors: UF_ERR_ARG (NULL pointers, sizes), UF_ERR_WORKSPACE, UF_ERR_DEVICE. */
+uf_status uf_pcoa_workspace_size(int64_t n, int64_t n_cols, size_t* bytes);
+uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const double* grand_mean,
+                  int64_t dims, int64_t n_cols, int power_iters, const double* omega,
+                  double* coords, double* eigvals, double* trace, void* ws, size_t ws_bytes,
+                  void* stream);
+
 /* ---- kernel timing --------------------------------------------------------- */
 
 /* Per-kernel timing with HIP events recorded on the call's stream around each

@@ -28,7 +28,7 @@ __all__ = [
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
     "profile_read", "Batch", "set_split_threshold", "split_stats", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
-    "gather_pairs", "Sparse", "rerank",
+    "gather_pairs", "Sparse", "rerank", "pcoa",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -114,6 +114,9 @@ _SIGS = {
     "uf_rerank_workspace_size": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_dm_rerank_weighted_normalized": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp,
                                                         ctypes.c_size_t, _vp]),
+    "uf_pcoa_workspace_size": (ctypes.c_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_pcoa": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
+                               _vp, ctypes.c_size_t, _vp]),
     "uf_profile_enable": (None, [ctypes.c_int]),
     "uf_profile_reset": (None, []),
     "uf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _f64p, _i64p]),
@@ -617,3 +620,27 @@ def rerank(queries: Sparse, refs: Sparse, query_ids, cand, out=None, workspace=N
                                                   _tptr(ws), ws.numel() * ws.element_size(),
                                                   _stream_ptr(stream)))
     return out[:nq]
+
+
+def pcoa(dm, n: int, dims: int, omega, power_iters: int = 3, row_means=None, grand_mean=None,
+         workspace=None, stream=None):
+    """Principal coordinates of a condensed FP64 distance matrix (device tensor).
+
+    omega: device FP64 [n][n_cols] standard-normal test matrix (n_cols >= dims).
+    row_means / grand_mean: device FP64 tensors from ``dm(..., row_means=True)``, or
+    None to have them computed.  Returns (coords [n][dims] device FP64,
+    eigenvalues numpy [dims], trace of the centred matrix)."""
+    import torch
+    n_cols = int(omega.shape[1])
+    need = ctypes.c_size_t(0)
+    _check(lib().uf_pcoa_workspace_size(int(n), n_cols, ctypes.byref(need)))
+    ws = _workspace(int(need.value), workspace)
+    coords = torch.empty((int(n), int(dims)), dtype=torch.float64, device="cuda")
+    vals = np.zeros(int(dims), dtype=np.float64)
+    tr = ctypes.c_double(0.0)
+    _check(lib().uf_pcoa(_tptr(dm), int(n), _tptr(row_means) if row_means is not None else None,
+                         _tptr(grand_mean) if grand_mean is not None else None, int(dims), n_cols,
+                         int(power_iters), _tptr(omega), _tptr(coords),
+                         vals.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tr), _tptr(ws),
+                         ws.numel() * ws.element_size(), _stream_ptr(stream)))
+    return coords, vals, float(tr.value)

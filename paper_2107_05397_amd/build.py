@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuf.so")
-SOURCES = ["uf_host.hip", "uf_kernels.hip", "uf_place.hip", "uf_place_host.hip", "uf_split.hip"]
+SOURCES = ["uf_host.hip", "uf_kernels.hip", "uf_place.hip", "uf_place_host.hip", "uf_split.hip",
+           "uf_pcoa.hip"]
 
 
 def hipcc() -> str:
