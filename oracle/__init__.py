@@ -16,6 +16,8 @@ Contents
 ``pcoa``     principal coordinates: the exact eigendecomposition of the
              double-centred matrix, and the randomized subspace iteration.
 ``placement`` the learned-placement encoder (projection, MLP, loss, Adam, kNN).
+``mantel``   the Mantel test: Pearson / Spearman statistics and permutation
+             p-values between two distance matrices.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 (hand-computed worked example, closed forms, brute force, scipy library
@@ -26,4 +28,4 @@ from .unifrac import (  # noqa: F401
     embedding, dm, dm_pairs, pcoa_means, condensed_index, n_stripes,
     stripe_partner, to_stripes, gram_split_bf16,
 )
-from . import pcoa  # noqa: F401
+from . import mantel, pcoa  # noqa: F401
