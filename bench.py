@@ -269,6 +269,8 @@ def main() -> int:
                     help="also time the FP64 weighted kernel once")
     ap.add_argument("--no-comparisons", action="store_true",
                     help="skip the plain-kernel and all-branch MFMA comparison runs")
+    ap.add_argument("--no-statistics", action="store_true",
+                    help="skip the PCoA and Mantel timings on the step's matrices")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -411,7 +413,7 @@ def main() -> int:
 
     # Principal coordinates of the weighted matrix (10 axes, 20-column test matrix,
     # 3 power passes): 5 products B X, each reading the condensed matrix.
-    if not args.no_comparisons:
+    if not args.no_statistics:
         dims, cols, q = 10, 20, 3
         omega = torch.tensor(synth.gaussian_matrix(n, cols, seed=17), dtype=torch.float64,
                              device="cuda")
@@ -432,6 +434,24 @@ def main() -> int:
                          "eigenvalues": [float(v) for v in vals[:5]],
                          "proportion_explained": [float(v / tr) for v in vals[:5]]}
         log(f"pcoa: {dt * 1e3:.1f} ms, top eigenvalues {vals[:3]}")
+        # Mantel test between the two matrices: 999 permutations (Pearson), 99 (Spearman)
+        _, _, _ = uf.dm(emb, "unweighted", up, out=out_u, row_means=True, workspace=ws_u,
+                        stream=stream)
+        prng = np.random.default_rng(23)
+        perms = torch.tensor(np.stack([prng.permutation(n) for _ in range(999)]).astype(np.int32),
+                             device="cuda")
+        extra["mantel"] = {}
+        for method, k in (("pearson", 999), ("spearman", 99)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r, pv, _ = uf.mantel(out_w, out_u, n, method, perms[:k], stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            extra["mantel"][method] = {"seconds": dt, "permutations": k, "statistic": r,
+                                       "p_value": pv,
+                                       "pair_products_per_s": (k + 1) * pairs / dt}
+            log(f"mantel {method}: {dt:.2f}s for {k} permutations, r={r:.4f} p={pv:.4f}")
+        del perms
 
     # GPU values of sampled pairs (compared with the oracle in the CPU leg)
     rng = np.random.default_rng(0)

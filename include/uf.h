@@ -355,6 +355,32 @@ uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const do
                   double* coords, double* eigvals, double* trace, void* ws, size_t ws_bytes,
                   void* stream);
 
+/* ---- Mantel test -------------------------------------------------------------- */
+
+/* Correlation between two distance matrices with a permutation p-value (the
+ * paper's section III).  Statistic: Pearson's r between the condensed vectors x
+ * and y, or Spearman's (Pearson's on their ranks, ties sharing the average
+ * rank).  Permutation b relabels the samples of the first matrix, rows and
+ * columns together: x'_ij = x_{perm_b(i) perm_b(j)}.  p = (number of permuted
+ * statistics at least as extreme as r, + 1) / (n_perm + 1); "as extreme" is
+ * |r_b| >= |r| (UF_TWO_SIDED), r_b >= r (UF_GREATER) or r_b <= r (UF_LESS).
+ *
+ * x, y:       device, condensed FP64, length n(n-1)/2 each, read only.
+ * perms:      device int32 [n_perm][n], each row a permutation of 0..n-1 drawn by
+ *             the caller (entries outside [0, n) are rejected with UF_ERR_ARG).
+ * stat, p_value: host, written.  perm_stats: host [n_perm] or NULL.
+ * ws:         device workspace of uf_mantel_workspace_size(n, method, n_perm)
+ *             bytes (holds x as a full n x n FP64 matrix).
+ * If either matrix is constant, r is undefined: stat = 0, p = 1.
+ * Errors: UF_ERR_ARG, UF_ERR_UNSUPPORTED (Spearman above 65,535 samples),
+ * UF_ERR_WORKSPACE, UF_ERR_DEVICE. */
+typedef enum { UF_MANTEL_PEARSON = 0, UF_MANTEL_SPEARMAN = 1 } uf_mantel_method;
+typedef enum { UF_TWO_SIDED = 0, UF_GREATER = 1, UF_LESS = 2 } uf_alternative;
+uf_status uf_mantel_workspace_size(int64_t n, int method, int64_t n_perm, size_t* bytes);
+uf_status uf_mantel(const double* x, const double* y, int64_t n, int method, const int32_t* perms,
+                    int64_t n_perm, int alternative, double* stat, double* p_value,
+                    double* perm_stats, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- kernel timing --------------------------------------------------------- */
 
 /* Per-kernel timing with HIP events recorded on the call's stream around each

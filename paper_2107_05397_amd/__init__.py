@@ -28,7 +28,7 @@ __all__ = [
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
     "profile_read", "Batch", "set_split_threshold", "split_stats", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
-    "gather_pairs", "Sparse", "rerank", "pcoa",
+    "gather_pairs", "Sparse", "rerank", "pcoa", "mantel",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -117,6 +117,10 @@ _SIGS = {
     "uf_pcoa_workspace_size": (ctypes.c_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_pcoa": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                _vp, ctypes.c_size_t, _vp]),
+    "uf_mantel_workspace_size": (ctypes.c_int, [_i64, ctypes.c_int, _i64,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_mantel": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp, _vp,
+                                 _vp, _vp, ctypes.c_size_t, _vp]),
     "uf_profile_enable": (None, [ctypes.c_int]),
     "uf_profile_reset": (None, []),
     "uf_profile_read": (ctypes.c_int, [ctypes.c_char_p, _f64p, _i64p]),
@@ -644,3 +648,26 @@ def pcoa(dm, n: int, dims: int, omega, power_iters: int = 3, row_means=None, gra
                          vals.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tr), _tptr(ws),
                          ws.numel() * ws.element_size(), _stream_ptr(stream)))
     return coords, vals, float(tr.value)
+
+
+MANTEL_METHOD = {"pearson": 0, "spearman": 1}
+ALTERNATIVE = {"two-sided": 0, "greater": 1, "less": 2}
+
+
+def mantel(x, y, n: int, method: str = "pearson", perms=None, alternative: str = "two-sided",
+           workspace=None, stream=None):
+    """Mantel test between condensed FP64 device matrices x and y.
+
+    perms: device int32 [n_perm][n] permutations of the first matrix's samples, or
+    None for none.  Returns (statistic, p-value, numpy [n_perm] permuted statistics)."""
+    n_perm = 0 if perms is None else int(perms.shape[0])
+    need = ctypes.c_size_t(0)
+    _check(lib().uf_mantel_workspace_size(int(n), MANTEL_METHOD[method], n_perm, ctypes.byref(need)))
+    ws = _workspace(int(need.value), workspace)
+    stat, pv = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    ps = np.zeros(max(n_perm, 1), dtype=np.float64)
+    _check(lib().uf_mantel(_tptr(x), _tptr(y), int(n), MANTEL_METHOD[method], _tptr(perms), n_perm,
+                           ALTERNATIVE[alternative], ctypes.byref(stat), ctypes.byref(pv),
+                           ps.ctypes.data_as(ctypes.c_void_p), _tptr(ws),
+                           ws.numel() * ws.element_size(), _stream_ptr(stream)))
+    return float(stat.value), float(pv.value), ps[:n_perm]

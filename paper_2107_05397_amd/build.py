@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuf.so")
 SOURCES = ["uf_host.hip", "uf_kernels.hip", "uf_place.hip", "uf_place_host.hip", "uf_split.hip",
-           "uf_pcoa.hip"]
+           "uf_pcoa.hip", "uf_mantel.hip"]
 
 
 def hipcc() -> str:

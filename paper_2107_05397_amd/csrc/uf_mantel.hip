@@ -1,0 +1,527 @@
+// Mantel test between two condensed distance matrices (gfx950).
+//
+// Statistic: Pearson's r between the condensed vectors x and y, or Spearman's
+// (Pearson's on the average-tie ranks).  With x' and y' centred and scaled to
+// unit norm, r = sum_k x'_k y'_k, and a relabelling pi of the first matrix's
+// samples gives r_pi = sum_{i<j} y'_ij x'_{pi(i) pi(j)} (the multiset of x' and
+// so its mean and norm do not change).  x' is expanded to a full square matrix
+// so that x'_{pi(i) pi(j)} is a gather inside row pi(i); one workgroup takes the
+// rows i and N-2-i (together N-1 partners) for a batch of permutations, reads
+// y' once for the batch and keeps one FP64 accumulator per permutation.  The
+// observed statistic runs through the same kernel with the identity, so the
+// comparisons behind the p-value see identical arithmetic.  Every reduction
+// runs in a fixed order.
+//
+// Ranks (Spearman): a stable LSD sort of the order-preserving 64-bit images of
+// the values, one bit per pass (a pass is an exclusive scan of the zero bits and
+// a scatter; passes whose bit is constant are skipped), then runs of equal keys
+// get the mean of the positions they span, plus one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "uf.h"
+#include "uf_internal.h"
+
+namespace ufm {
+namespace {
+
+constexpr int kPB = 8;                 // permutations per batch
+constexpr int64_t kChunk = 1 << 16;    // elements per partial sum
+constexpr int kScanBlock = 1024;       // elements per scan block (256 threads x 4)
+constexpr int kTile = 64;
+
+__device__ __forceinline__ int64_t cidx(int64_t n, int64_t a, int64_t b) {   // a < b
+    return a * n - a * (a + 1) / 2 + (b - a - 1);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double s = red[0];
+    __syncthreads();
+    return s;
+}
+
+// parts[b] = sum over chunk b of (v - shift)^power (power 1 or 2)
+__global__ __launch_bounds__(256) void k_chunk_sums(const double* __restrict__ v, int64_t m,
+                                                    double shift, int power,
+                                                    double* __restrict__ parts) {
+    __shared__ double red[256];
+    const int64_t a = int64_t(blockIdx.x) * kChunk, b = min(m, a + kChunk);
+    double s = 0.0;
+    for (int64_t k = a + threadIdx.x; k < b; k += 256) {
+        const double d = v[k] - shift;
+        s += power == 2 ? d * d : d;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+// out[k] = (v[k] - mean) * scale
+__global__ __launch_bounds__(256) void k_standardize(const double* __restrict__ v, int64_t m,
+                                                     double mean, double scale,
+                                                     double* __restrict__ out) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < m) out[k] = (v[k] - mean) * scale;
+}
+
+// Full square S[i][j] = (v_ij - mean) * scale for i != j, 0 on the diagonal.  Block
+// (bi, bj), bi <= bj: the tile is read from the condensed rows (contiguous in j)
+// and written to S[i][j] and, through LDS, to S[j][i], both coalesced.
+__global__ __launch_bounds__(256) void k_square(const double* __restrict__ v, int64_t n,
+                                                double mean, double scale,
+                                                double* __restrict__ S) {
+    __shared__ double t[kTile][kTile + 1];
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi) return;
+    const int64_t i0 = bi * kTile, j0 = bj * kTile;
+    for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+        const int r = e / kTile, c = e % kTile;
+        const int64_t i = i0 + r, j = j0 + c;
+        double x = 0.0;
+        if (i < n && j < n && i != j) {
+            const double d = i < j ? v[cidx(n, i, j)] : v[cidx(n, j, i)];
+            x = (d - mean) * scale;
+        }
+        t[r][c] = x;
+        if (i < n && j < n) S[i * n + j] = x;
+    }
+    if (bi == bj) return;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTile * kTile; e += 256) {
+        const int r = e / kTile, c = e % kTile;   // output row j0 + r, column i0 + c
+        const int64_t j = j0 + r, i = i0 + c;
+        if (i < n && j < n) S[j * n + i] = t[c][r];
+    }
+}
+
+// part[b][w] for permutations b0 + [0, nb) (perm == nullptr: identity, nb = 1):
+// sum over the rows w and n-2-w of sum_{j>i} y'_ij S[pi(i)][pi(j)].
+__global__ __launch_bounds__(256) void k_perm_rows(const double* __restrict__ S,
+                                                   const double* __restrict__ yv, int64_t n,
+                                                   const int32_t* __restrict__ perm, int64_t b0,
+                                                   int nb, int64_t n_pairs,
+                                                   double* __restrict__ part) {
+    __shared__ double red[256];
+    const int64_t w = blockIdx.x;
+    double acc[kPB];
+#pragma unroll
+    for (int q = 0; q < kPB; ++q) acc[q] = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        const int64_t i = side == 0 ? w : n - 2 - w;
+        if (side == 1 && i == w) break;
+        if (i < 0 || i >= n - 1) continue;
+        int64_t pi[kPB];
+#pragma unroll
+        for (int q = 0; q < kPB; ++q)
+            pi[q] = (q < nb) ? (perm ? int64_t(perm[(b0 + q) * n + i]) : i) : 0;
+        const int64_t base = cidx(n, i, i + 1);   // y'_{i, i+1 ..}
+        for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
+            const double y = yv[base + (j - i - 1)];
+#pragma unroll
+            for (int q = 0; q < kPB; ++q) {
+                if (q < nb) {
+                    const int64_t pj = perm ? int64_t(perm[(b0 + q) * n + j]) : j;
+                    acc[q] = fma(y, S[pi[q] * n + pj], acc[q]);
+                }
+            }
+        }
+    }
+    for (int q = 0; q < nb; ++q) {
+        const double s = block_sum(acc[q], red);
+        if (threadIdx.x == 0) part[(b0 + q) * n_pairs + w] = s;
+    }
+}
+
+// tot[b] = sum_w part[b][w] (one block per permutation, fixed order)
+__global__ __launch_bounds__(256) void k_perm_total(const double* __restrict__ part, int64_t n_pairs,
+                                                    double* __restrict__ tot) {
+    __shared__ double red[256];
+    const int64_t b = blockIdx.x;
+    double s = 0.0;
+    for (int64_t w = threadIdx.x; w < n_pairs; w += 256) s += part[b * n_pairs + w];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) tot[b] = s;
+}
+
+// ---------------------------------------------------------------- ranks
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    if (v == 0.0) v = 0.0;   // -0 and +0 are the same value
+    const unsigned long long u = __double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(256) void k_keys(const double* __restrict__ v, int64_t m,
+                                              unsigned long long* __restrict__ key,
+                                              uint32_t* __restrict__ idx) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < m) {
+        key[k] = order_key(v[k]);
+        idx[k] = uint32_t(k);
+    }
+}
+
+// z[k] = 1 if bit `bit` of key[k] is 0
+__global__ __launch_bounds__(256) void k_zero_bits(const unsigned long long* __restrict__ key,
+                                                   int64_t m, int bit, uint32_t* __restrict__ z) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < m) z[k] = ((key[k] >> bit) & 1ull) ? 0u : 1u;
+}
+
+// Block-level exclusive scan of kScanBlock elements; block totals to agg.
+__global__ __launch_bounds__(256) void k_scan_block(const uint32_t* __restrict__ in, int64_t m,
+                                                    uint32_t* __restrict__ out,
+                                                    uint32_t* __restrict__ agg) {
+    __shared__ uint32_t s[256];
+    const int64_t base = int64_t(blockIdx.x) * kScanBlock + threadIdx.x * 4;
+    uint32_t v[4];
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = base + q < m ? in[base + q] : 0u;
+        t += v[q];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele
+        const uint32_t add = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = s[threadIdx.x] - t;   // exclusive prefix of this thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (base + q < m) out[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 255) agg[blockIdx.x] = s[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, int64_t m,
+                                                  const uint32_t* __restrict__ off) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < m) out[k] += off[k / kScanBlock];
+}
+
+// stable split by the scanned zero flags
+__global__ __launch_bounds__(256) void k_split_scatter(const unsigned long long* __restrict__ key,
+                                                       const uint32_t* __restrict__ idx,
+                                                       const uint32_t* __restrict__ z,
+                                                       const uint32_t* __restrict__ zpos,
+                                                       int64_t m, uint32_t zeros,
+                                                       unsigned long long* __restrict__ key2,
+                                                       uint32_t* __restrict__ idx2) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= m) return;
+    const int64_t pos = z[k] ? int64_t(zpos[k]) : int64_t(zeros) + (k - int64_t(zpos[k]));
+    key2[pos] = key[k];
+    idx2[pos] = idx[k];
+}
+
+// run starts (flag) over sorted keys
+__global__ __launch_bounds__(256) void k_run_starts(const unsigned long long* __restrict__ key,
+                                                    int64_t m, uint32_t* __restrict__ f) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < m) f[k] = (k == 0 || key[k] != key[k - 1]) ? 1u : 0u;
+}
+
+// run r = (exclusive scan of starts) at its start, inclusive at any member; record
+// first and last positions of each run
+__global__ __launch_bounds__(256) void k_run_bounds(const unsigned long long* __restrict__ key,
+                                                    const uint32_t* __restrict__ f,
+                                                    const uint32_t* __restrict__ fpos, int64_t m,
+                                                    uint32_t* __restrict__ first,
+                                                    uint32_t* __restrict__ last) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t run = fpos[k] + f[k] - 1u;
+    if (f[k]) first[run] = uint32_t(k);
+    if (k == m - 1 || key[k] != key[k + 1]) last[run] = uint32_t(k);
+}
+
+__global__ __launch_bounds__(256) void k_assign_ranks(const uint32_t* __restrict__ idx,
+                                                      const uint32_t* __restrict__ f,
+                                                      const uint32_t* __restrict__ fpos,
+                                                      const uint32_t* __restrict__ first,
+                                                      const uint32_t* __restrict__ last, int64_t m,
+                                                      double* __restrict__ rank) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k >= m) return;
+    const uint32_t run = fpos[k] + f[k] - 1u;
+    rank[idx[k]] = 0.5 * (double(first[run]) + double(last[run])) + 1.0;
+}
+
+// bad[0] = 1 if any permutation entry lies outside [0, n)
+__global__ __launch_bounds__(256) void k_check_perms(const int32_t* __restrict__ perm, int64_t total,
+                                                     int64_t n, uint32_t* __restrict__ bad) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < total && (perm[k] < 0 || int64_t(perm[k]) >= n)) atomicOr(bad, 1u);
+}
+
+unsigned grid_of(int64_t m) { return unsigned((m + 255) / 256); }
+
+}  // namespace
+}  // namespace ufm
+
+using ufh::fail;
+using ufh::hip_fail;
+
+#define UFM_HIP(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+namespace {
+
+struct MantelPlan {
+    int64_t n = 0, m = 0, n_pairs = 0, n_perm = 0;
+    size_t off_sq = 0, off_y = 0, off_part = 0, off_tot = 0, off_cs = 0, off_rx = 0, off_ry = 0,
+           off_ka = 0, off_kb = 0, off_ia = 0, off_ib = 0, off_z = 0, off_zp = 0, off_agg = 0,
+           off_first = 0, off_last = 0, total = 0;
+    int64_t agg_len = 0;
+};
+
+size_t take(size_t& off, size_t bytes) {
+    const size_t at = (off + 255) & ~size_t(255);
+    off = at + bytes;
+    return at;
+}
+
+MantelPlan mantel_plan(int64_t n, int method, int64_t n_perm) {
+    MantelPlan p;
+    p.n = n;
+    p.m = n * (n - 1) / 2;
+    p.n_pairs = n / 2;   // row pairs (w, n-2-w) over rows 0..n-2: ceil((n-1)/2) = floor(n/2)
+    p.n_perm = n_perm;
+    size_t off = 0;
+    p.off_sq = take(off, size_t(n) * size_t(n) * 8);
+    p.off_y = take(off, size_t(p.m) * 8);
+    p.off_part = take(off, size_t(n_perm + 1) * size_t(p.n_pairs) * 8);
+    p.off_tot = take(off, size_t(n_perm + 1) * 8);
+    p.off_cs = take(off, size_t((p.m + ufm::kChunk - 1) / ufm::kChunk + 1) * 8);
+    if (method == UF_MANTEL_SPEARMAN) {
+        p.off_rx = take(off, size_t(p.m) * 8);
+        p.off_ry = take(off, size_t(p.m) * 8);
+        p.off_ka = take(off, size_t(p.m) * 8);
+        p.off_kb = take(off, size_t(p.m) * 8);
+        p.off_ia = take(off, size_t(p.m) * 4);
+        p.off_ib = take(off, size_t(p.m) * 4);
+        p.off_z = take(off, size_t(p.m) * 4);
+        p.off_zp = take(off, size_t(p.m) * 4);
+        // scan_u32 at a level of m values uses nb aggregates, and when nb > 1 their
+        // scan (nb) plus one spare slot, then the next level's space
+        int64_t len = 0, lv = p.m;
+        for (;;) {
+            const int64_t nb = (lv + ufm::kScanBlock - 1) / ufm::kScanBlock;
+            len += nb;
+            if (nb <= 1) break;
+            len += nb + 1;
+            lv = nb;
+        }
+        p.agg_len = len + 1;
+        p.off_agg = take(off, size_t(p.agg_len) * 4);
+        p.off_first = take(off, size_t(p.m) * 4);
+        p.off_last = take(off, size_t(p.m) * 4);
+    }
+    p.total = off + 256;
+    return p;
+}
+
+// exclusive scan of m uint32 values, recursive over block aggregates
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t m, uint32_t* agg, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = (m + ufm::kScanBlock - 1) / ufm::kScanBlock;
+    hipLaunchKernelGGL(ufm::k_scan_block, dim3(unsigned(nb)), dim3(256), 0, s, in, m, out, agg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nb == 1) return e;
+    uint32_t* agg_scan = agg + nb;   // exclusive scan of the aggregates, then the next level
+    e = scan_u32(agg, agg_scan, nb, agg_scan + nb + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ufm::k_scan_add, dim3(ufm::grid_of(m)), dim3(256), 0, s, out, m, agg_scan);
+    return hipGetLastError();
+}
+
+// fixed-order sum of (v - shift)^power over m values (host finishes the chunk sums)
+uf_status chunk_sum(const double* v, int64_t m, double shift, int power, double* parts, hipStream_t s,
+                    double* out) {
+    const int64_t nb = (m + ufm::kChunk - 1) / ufm::kChunk;
+    hipLaunchKernelGGL(ufm::k_chunk_sums, dim3(unsigned(nb)), dim3(256), 0, s, v, m, shift, power,
+                       parts);
+    UFM_HIP(hipGetLastError());
+    std::vector<double> h(static_cast<size_t>(nb));
+    UFM_HIP(hipMemcpyAsync(h.data(), parts, size_t(nb) * 8, hipMemcpyDeviceToHost, s));
+    UFM_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double x : h) t += x;
+    *out = t;
+    return UF_OK;
+}
+
+// average-tie ranks of v (m values) into rank
+uf_status ranks(const MantelPlan& p, char* base, const double* v, double* rank, hipStream_t s) {
+    using namespace ufm;
+    const int64_t m = p.m;
+    auto* ka = reinterpret_cast<unsigned long long*>(base + p.off_ka);
+    auto* kb = reinterpret_cast<unsigned long long*>(base + p.off_kb);
+    auto* ia = reinterpret_cast<uint32_t*>(base + p.off_ia);
+    auto* ib = reinterpret_cast<uint32_t*>(base + p.off_ib);
+    auto* z = reinterpret_cast<uint32_t*>(base + p.off_z);
+    auto* zp = reinterpret_cast<uint32_t*>(base + p.off_zp);
+    auto* agg = reinterpret_cast<uint32_t*>(base + p.off_agg);
+    auto* first = reinterpret_cast<uint32_t*>(base + p.off_first);
+    auto* last = reinterpret_cast<uint32_t*>(base + p.off_last);
+    hipLaunchKernelGGL(k_keys, dim3(grid_of(m)), dim3(256), 0, s, v, m, ka, ia);
+    UFM_HIP(hipGetLastError());
+    for (int bit = 0; bit < 64; ++bit) {
+        hipLaunchKernelGGL(k_zero_bits, dim3(grid_of(m)), dim3(256), 0, s, ka, m, bit, z);
+        UFM_HIP(hipGetLastError());
+        UFM_HIP(scan_u32(z, zp, m, agg, s));
+        uint32_t last_pos = 0, last_z = 0;
+        UFM_HIP(hipMemcpyAsync(&last_pos, zp + (m - 1), 4, hipMemcpyDeviceToHost, s));
+        UFM_HIP(hipMemcpyAsync(&last_z, z + (m - 1), 4, hipMemcpyDeviceToHost, s));
+        UFM_HIP(hipStreamSynchronize(s));
+        const uint64_t zeros = uint64_t(last_pos) + last_z;
+        if (zeros == 0 || zeros == uint64_t(m)) continue;   // bit constant: order unchanged
+        hipLaunchKernelGGL(k_split_scatter, dim3(grid_of(m)), dim3(256), 0, s, ka, ia, z, zp, m,
+                           uint32_t(zeros), kb, ib);
+        UFM_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(ia, ib);
+    }
+    hipLaunchKernelGGL(k_run_starts, dim3(grid_of(m)), dim3(256), 0, s, ka, m, z);
+    UFM_HIP(hipGetLastError());
+    UFM_HIP(scan_u32(z, zp, m, agg, s));
+    hipLaunchKernelGGL(k_run_bounds, dim3(grid_of(m)), dim3(256), 0, s, ka, z, zp, m, first, last);
+    UFM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_assign_ranks, dim3(grid_of(m)), dim3(256), 0, s, ia, z, zp, first, last, m,
+                       rank);
+    UFM_HIP(hipGetLastError());
+    return UF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uf_status uf_mantel_workspace_size(int64_t n, int method, int64_t n_perm, size_t* bytes) {
+    if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
+    if (n < 3) return fail(UF_ERR_ARG, "need at least 3 samples");
+    if (method != UF_MANTEL_PEARSON && method != UF_MANTEL_SPEARMAN)
+        return fail(UF_ERR_ARG, "unknown method");
+    if (method == UF_MANTEL_SPEARMAN && n > 65535)
+        return fail(UF_ERR_UNSUPPORTED, "Spearman ranks take at most 65,535 samples");
+    if (n_perm < 0) return fail(UF_ERR_ARG, "n_perm < 0");
+    *bytes = mantel_plan(n, method, n_perm).total;
+    return UF_OK;
+}
+
+uf_status uf_mantel(const double* x, const double* y, int64_t n, int method, const int32_t* perms,
+                    int64_t n_perm, int alternative, double* stat, double* p_value,
+                    double* perm_stats, void* ws, size_t ws_bytes, void* stream) {
+    using namespace ufm;
+    if (!x || !y || !stat || !p_value) return fail(UF_ERR_ARG, "NULL argument");
+    if (n < 3) return fail(UF_ERR_ARG, "need at least 3 samples");
+    if (method != UF_MANTEL_PEARSON && method != UF_MANTEL_SPEARMAN)
+        return fail(UF_ERR_ARG, "unknown method");
+    if (method == UF_MANTEL_SPEARMAN && n > 65535)
+        return fail(UF_ERR_UNSUPPORTED, "Spearman ranks take at most 65,535 samples");
+    if (alternative != UF_TWO_SIDED && alternative != UF_GREATER && alternative != UF_LESS)
+        return fail(UF_ERR_ARG, "unknown alternative");
+    if (n_perm < 0 || (n_perm > 0 && !perms)) return fail(UF_ERR_ARG, "permutations missing");
+    int dev = 0;
+    uf_status st = ufh::check_device(&dev);
+    if (st != UF_OK) return st;
+    const MantelPlan p = mantel_plan(n, method, n_perm);
+    if (!ws || ws_bytes < p.total) return fail(UF_ERR_WORKSPACE, "workspace missing or too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    double* S = reinterpret_cast<double*>(base + p.off_sq);
+    double* yv = reinterpret_cast<double*>(base + p.off_y);
+    double* part = reinterpret_cast<double*>(base + p.off_part);
+    double* tot = reinterpret_cast<double*>(base + p.off_tot);
+    double* cs = reinterpret_cast<double*>(base + p.off_cs);
+    const int64_t m = p.m;
+    if (n_perm > 0) {   // every permutation index must address a sample
+        uint32_t* bad = reinterpret_cast<uint32_t*>(base + p.off_tot);
+        UFM_HIP(hipMemsetAsync(bad, 0, 4, s));
+        hipLaunchKernelGGL(k_check_perms, dim3(grid_of(n_perm * n)), dim3(256), 0, s, perms, n_perm * n,
+                           n, bad);
+        UFM_HIP(hipGetLastError());
+        uint32_t hbad = 0;
+        UFM_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+        UFM_HIP(hipStreamSynchronize(s));
+        if (hbad) return fail(UF_ERR_ARG, "permutation entries must lie in [0, n)");
+    }
+
+    const double* xs = x;
+    const double* ys = y;
+    if (method == UF_MANTEL_SPEARMAN) {
+        double* rx = reinterpret_cast<double*>(base + p.off_rx);
+        double* ry = reinterpret_cast<double*>(base + p.off_ry);
+        st = ranks(p, base, x, rx, s);
+        if (st != UF_OK) return st;
+        st = ranks(p, base, y, ry, s);
+        if (st != UF_OK) return st;
+        xs = rx;
+        ys = ry;
+    }
+    // centre and scale both vectors to unit norm
+    double sx = 0.0, sy = 0.0, qx = 0.0, qy = 0.0;
+    if ((st = chunk_sum(xs, m, 0.0, 1, cs, s, &sx)) != UF_OK) return st;
+    if ((st = chunk_sum(ys, m, 0.0, 1, cs, s, &sy)) != UF_OK) return st;
+    const double mx = sx / double(m), my = sy / double(m);
+    if ((st = chunk_sum(xs, m, mx, 2, cs, s, &qx)) != UF_OK) return st;
+    if ((st = chunk_sum(ys, m, my, 2, cs, s, &qy)) != UF_OK) return st;
+    if (!(qx > 0.0) || !(qy > 0.0)) {   // a constant matrix: r undefined, reported as 0
+        *stat = 0.0;
+        *p_value = 1.0;
+        if (perm_stats) std::fill(perm_stats, perm_stats + n_perm, 0.0);
+        return UF_OK;
+    }
+    const int64_t nt = (n + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_square, dim3(unsigned(nt), unsigned(nt)), dim3(256), 0, s, xs, n, mx,
+                       1.0 / std::sqrt(qx), S);
+    UFM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_standardize, dim3(grid_of(m)), dim3(256), 0, s, ys, m, my, 1.0 / std::sqrt(qy),
+                       yv);
+    UFM_HIP(hipGetLastError());
+    // observed statistic (identity) in slot n_perm, then the permutations
+    hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(256), 0, s, S, yv, n,
+                       static_cast<const int32_t*>(nullptr), n_perm, 1, p.n_pairs, part);
+    UFM_HIP(hipGetLastError());
+    for (int64_t b0 = 0; b0 < n_perm; b0 += kPB) {
+        const int nb = int(std::min<int64_t>(kPB, n_perm - b0));
+        hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(256), 0, s, S, yv, n, perms, b0,
+                           nb, p.n_pairs, part);
+        UFM_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_perm_total, dim3(unsigned(n_perm + 1)), dim3(256), 0, s, part, p.n_pairs, tot);
+    UFM_HIP(hipGetLastError());
+    std::vector<double> h(static_cast<size_t>(n_perm + 1));
+    UFM_HIP(hipMemcpyAsync(h.data(), tot, h.size() * 8, hipMemcpyDeviceToHost, s));
+    UFM_HIP(hipStreamSynchronize(s));
+    const double r = h[size_t(n_perm)];
+    int64_t count = 0;
+    for (int64_t b = 0; b < n_perm; ++b) {
+        const double v = h[size_t(b)];
+        if (alternative == UF_TWO_SIDED) count += std::fabs(v) >= std::fabs(r);
+        else if (alternative == UF_GREATER) count += v >= r;
+        else count += v <= r;
+    }
+    *stat = r;
+    *p_value = double(count + 1) / double(n_perm + 1);
+    if (perm_stats) std::memcpy(perm_stats, h.data(), size_t(n_perm) * 8);
+    return UF_OK;
+}
+
+}  // extern "C"
