@@ -5,12 +5,14 @@
 // unit norm, r = sum_k x'_k y'_k, and a relabelling pi of the first matrix's
 // samples gives r_pi = sum_{i<j} y'_ij x'_{pi(i) pi(j)} (the multiset of x' and
 // so its mean and norm do not change).  x' is expanded to a full square matrix
-// so that x'_{pi(i) pi(j)} is a gather inside row pi(i); one workgroup takes the
-// rows i and N-2-i (together N-1 partners) for a batch of permutations, reads
-// y' once for the batch and keeps one FP64 accumulator per permutation.  The
-// observed statistic runs through the same kernel with the identity, so the
-// comparisons behind the p-value see identical arithmetic.  Every reduction
-// runs in a fixed order.
+// S so that x'_{pi(i) pi(j)} lies in row pi(i).  One workgroup takes the rows i
+// and N-2-i (together N-1 partners) for a batch of permutations, one permutation
+// after another: it holds its partners' y'_ij and pi(j) in registers, stages
+// row pi(i) of S in LDS part by part (coalesced), and gathers from LDS, so each
+// permutation streams S once in order and the random access stays inside LDS.
+// The observed statistic runs through the same kernel with the identity, so the
+// comparisons behind the p-value see identical arithmetic.  Every reduction runs
+// in a fixed order.
 //
 // Ranks (Spearman): a stable LSD sort of the order-preserving 64-bit images of
 // the values, one bit per pass (a pass is an exclusive scan of the zero bits and
@@ -30,6 +32,9 @@ namespace ufm {
 namespace {
 
 constexpr int kPB = 8;                 // permutations per batch
+constexpr int kRowThreads = 1024;      // threads of the permutation kernel
+constexpr int kJPT = 32;               // partners held in registers per thread
+constexpr int64_t kPartMax = 19456;    // LDS row part: 152 KiB, + 8 KiB for the reduction
 constexpr int64_t kChunk = 1 << 16;    // elements per partial sum
 constexpr int kScanBlock = 1024;       // elements per scan block (256 threads x 4)
 constexpr int kTile = 64;
@@ -105,39 +110,60 @@ __global__ __launch_bounds__(256) void k_square(const double* __restrict__ v, in
 
 // part[b][w] for permutations b0 + [0, nb) (perm == nullptr: identity, nb = 1):
 // sum over the rows w and n-2-w of sum_{j>i} y'_ij S[pi(i)][pi(j)].
-__global__ __launch_bounds__(256) void k_perm_rows(const double* __restrict__ S,
-                                                   const double* __restrict__ yv, int64_t n,
-                                                   const int32_t* __restrict__ perm, int64_t b0,
-                                                   int nb, int64_t n_pairs,
-                                                   double* __restrict__ part) {
-    __shared__ double red[256];
+// One block of kRowThreads threads per (row pair, batch).  The block keeps its
+// partners' y'_ij (up to kJPT per thread) and pi(j) in registers, stages the
+// permuted row S[pi(i)] in LDS part by part (coalesced reads of the row), and
+// gathers S[pi(i)][pi(j)] from LDS: each permutation reads S once, in order.
+__global__ __launch_bounds__(kRowThreads) void k_perm_rows(const double* __restrict__ S,
+                                                           const double* __restrict__ yv, int64_t n,
+                                                           const int32_t* __restrict__ perm,
+                                                           int64_t b0, int nb, int64_t n_pairs,
+                                                           int64_t part_len,
+                                                           double* __restrict__ part) {
+    extern __shared__ double row[];           // [part_len], then kRowThreads for the reduction
+    double* red = row + part_len;
     const int64_t w = blockIdx.x;
-    double acc[kPB];
+    const int tid = threadIdx.x;
+    for (int q = 0; q < nb; ++q) {            // one permutation at a time; y' rows stay in L2
+        const int32_t* pb = perm ? perm + (b0 + q) * n : nullptr;
+        double a = 0.0;
+        for (int side = 0; side < 2; ++side) {
+            const int64_t i = side == 0 ? w : n - 2 - w;
+            if (side == 1 && i == w) break;
+            if (i < 0 || i >= n - 1) continue;
+            const int64_t base = cidx(n, i, i + 1);   // y'_{i, i+1 ..}
+            const int64_t pi = pb ? int64_t(pb[i]) : i;
+            for (int64_t jc = i + 1; jc < n; jc += int64_t(kRowThreads) * kJPT) {
+                double yr[kJPT];
+                int32_t pr[kJPT];
 #pragma unroll
-    for (int q = 0; q < kPB; ++q) acc[q] = 0.0;
-    for (int side = 0; side < 2; ++side) {
-        const int64_t i = side == 0 ? w : n - 2 - w;
-        if (side == 1 && i == w) break;
-        if (i < 0 || i >= n - 1) continue;
-        int64_t pi[kPB];
+                for (int t = 0; t < kJPT; ++t) {
+                    const int64_t j = jc + tid + int64_t(kRowThreads) * t;
+                    yr[t] = j < n ? yv[base + (j - i - 1)] : 0.0;
+                    pr[t] = j < n ? (pb ? pb[j] : int32_t(j)) : -1;
+                }
+                for (int64_t lo = 0; lo < n; lo += part_len) {
+                    const int len = int(min(part_len, n - lo));
+                    __syncthreads();
+                    for (int k = tid; k < len; k += kRowThreads) row[k] = S[pi * n + lo + k];
+                    __syncthreads();
+                    const int lo32 = int(lo);
 #pragma unroll
-        for (int q = 0; q < kPB; ++q)
-            pi[q] = (q < nb) ? (perm ? int64_t(perm[(b0 + q) * n + i]) : i) : 0;
-        const int64_t base = cidx(n, i, i + 1);   // y'_{i, i+1 ..}
-        for (int64_t j = i + 1 + threadIdx.x; j < n; j += 256) {
-            const double y = yv[base + (j - i - 1)];
-#pragma unroll
-            for (int q = 0; q < kPB; ++q) {
-                if (q < nb) {
-                    const int64_t pj = perm ? int64_t(perm[(b0 + q) * n + j]) : j;
-                    acc[q] = fma(y, S[pi[q] * n + pj], acc[q]);
+                    for (int t = 0; t < kJPT; ++t) {
+                        const int c = pr[t] - lo32;
+                        if (c >= 0 && c < len) a = fma(yr[t], row[c], a);
+                    }
                 }
             }
         }
-    }
-    for (int q = 0; q < nb; ++q) {
-        const double s = block_sum(acc[q], red);
-        if (threadIdx.x == 0) part[(b0 + q) * n_pairs + w] = s;
+        red[tid] = a;
+        __syncthreads();
+        for (int s2 = kRowThreads / 2; s2 > 0; s2 >>= 1) {
+            if (tid < s2) red[tid] += red[tid + s2];
+            __syncthreads();
+        }
+        if (tid == 0) part[(b0 + q) * n_pairs + w] = red[0];
+        __syncthreads();
     }
 }
 
@@ -496,13 +522,21 @@ uf_status uf_mantel(const double* x, const double* y, int64_t n, int method, con
                        yv);
     UFM_HIP(hipGetLastError());
     // observed statistic (identity) in slot n_perm, then the permutations
-    hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(256), 0, s, S, yv, n,
-                       static_cast<const int32_t*>(nullptr), n_perm, 1, p.n_pairs, part);
+    const int64_t nparts = (n + kPartMax - 1) / kPartMax;
+    const int64_t part_len = (n + nparts - 1) / nparts;
+    const size_t lds = size_t(part_len + kRowThreads) * 8;
+    static const bool attr_ok =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_perm_rows),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int((kPartMax + kRowThreads) * 8)) == hipSuccess;
+    if (!attr_ok) return fail(UF_ERR_DEVICE, "cannot enable 160 KiB of LDS for the permutation kernel");
+    hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(kRowThreads), lds, s, S, yv, n,
+                       static_cast<const int32_t*>(nullptr), n_perm, 1, p.n_pairs, part_len, part);
     UFM_HIP(hipGetLastError());
     for (int64_t b0 = 0; b0 < n_perm; b0 += kPB) {
         const int nb = int(std::min<int64_t>(kPB, n_perm - b0));
-        hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(256), 0, s, S, yv, n, perms, b0,
-                           nb, p.n_pairs, part);
+        hipLaunchKernelGGL(k_perm_rows, dim3(unsigned(p.n_pairs)), dim3(kRowThreads), lds, s, S, yv, n,
+                           perms, b0, nb, p.n_pairs, part_len, part);
         UFM_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_perm_total, dim3(unsigned(n_perm + 1)), dim3(256), 0, s, part, p.n_pairs, tot);
