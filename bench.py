@@ -166,6 +166,35 @@ def bench_batch(args) -> int:
             uf.dm(emb, "weighted_normalized", "fp32", out_dtype=torch.float32, stream=stream)
     torch.cuda.synchronize()
     separate_s = time.perf_counter() - t2
+    # the same tables through the sparse-aware split, one call each (embeddings and
+    # splits built before the timed region, as for the batch)
+    embs = [uf.Embedding(ut, tu) for tu in uts if tu.n_samples >= 2]
+    uf.set_split_threshold(None)
+    for e in embs:
+        uf.split_stats(e, "weighted_normalized")
+    split_outs = [torch.empty(e.n_samples * (e.n_samples - 1) // 2, dtype=torch.float32, device="cuda")
+                  for e in embs]
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for e, o in zip(embs, split_outs):
+        uf.dm(e, "weighted_normalized", "fp32_split", out_dtype=torch.float32, out=o, stream=stream)
+    torch.cuda.synchronize()
+    split_s = time.perf_counter() - t3
+    log(f"per-table split calls: {split_s:.2f}s")
+    del embs, split_outs
+    # the batch itself in sparse-split mode: per-table splits on forked streams, one graph
+    bs = uf.Batch(ut, uts)
+    bs.set_precision("fp32_split")
+    split_tune_ms = bs.autotune()
+    bs.run(use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(max(args.steps, 1)):
+        bs.run(use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    split_graph_s = (time.perf_counter() - t4) / max(args.steps, 1)
+    log(f"split batch graph: {split_graph_s:.3f}s")
+    del bs
     outs = b.run(use_graph=True, stream=stream)
     torch.cuda.synchronize()
     # GPU values of a few sampled pairs, compared with the oracle in the CPU leg
@@ -206,6 +235,10 @@ def bench_batch(args) -> int:
                              "x 2.4 GHz"},
         "extra": {"graph_s": graph_s, "eager_batch_s": eager_s,
                   "separate_single_table_calls_s": separate_s,
+                  "separate_split_calls_s": split_s,
+                  "split_batch_graph_s": split_graph_s,
+                  "split_batch_updates_per_s": U / split_graph_s,
+                  "split_batch_autotune_ms": split_tune_ms,
                   "autotuned_config": dict(zip(("stage_branches", "wgs_per_cu", "chunk_nodes"),
                                                b.config())),
                   "autotune_first_chunk_ms": tune_ms},

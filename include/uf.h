@@ -218,6 +218,20 @@ uf_status uf_batch_workspace_size(const uf_batch* batch, size_t* bytes);
 uf_status uf_batch_config(const uf_batch* batch, int* stage_branches, int* wgs_per_cu,
                           int64_t* chunk_nodes);
 uf_status uf_batch_set_config(uf_batch* batch, int stage_branches, int wgs_per_cu);
+/* Arithmetic of the batch: UF_FP32 (default; the persistent stripe kernel above)
+ * or UF_FP32_SPLIT: every table through the sparse-aware split of
+ * uf_dm_weighted_normalized(UF_FP32_SPLIT) (results equal to that call on each
+ * table alone).  The split mode builds one embedding and split per table here
+ * (tables: the same ones, in the same order, as at creation; they and the tree
+ * must stay alive), then runs the tables on up to 8 streams forked from and
+ * joined back into the caller's stream, largest first, each stream with its own
+ * workspace slot; the graph captures that fork and join.  uf_autotune picks the
+ * stream count (1, 2, 4 or 8) in this mode.  The workspace size depends on the
+ * mode: query it after this call.  Synchronous.
+ * Errors: UF_ERR_ARG, UF_ERR_UNSUPPORTED (other precisions), UF_ERR_NOMEM,
+ * UF_ERR_DEVICE. */
+uf_status uf_batch_set_precision(uf_batch* batch, uf_precision prec, const uf_table* const* tables,
+                                 void* hip_stream);
 /* Compute every table: outs[r] is a device buffer of N_r(N_r-1)/2 floats
  * (NULL allowed for tables with fewer than 2 samples).  use_graph: replay the
  * captured graph (captured on first use and again whenever ws or outs change)

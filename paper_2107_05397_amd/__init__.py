@@ -90,6 +90,7 @@ _SIGS = {
     "uf_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int), _i64p]),
     "uf_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "uf_batch_set_precision": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "uf_batch_run": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t,
                                     _vp]),
     "uf_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_char_p, _vp, _f64p]),
@@ -432,6 +433,13 @@ class Batch(_Handle):
 
     def set_config(self, stage_branches: int, wgs_per_cu: int) -> None:
         _check(lib().uf_batch_set_config(self._h, int(stage_branches), int(wgs_per_cu)))
+
+    def set_precision(self, precision: str = "fp32", stream=None) -> None:
+        """"fp32" (persistent stripe kernel) or "fp32_split" (per-table sparse split on
+        forked streams); the workspace is re-sized on the next run."""
+        arr = (_vp * len(self.tables))(*[t.handle.value for t in self.tables])
+        _check(lib().uf_batch_set_precision(self._h, PRECISION[precision], arr, _stream_ptr(stream)))
+        self._ws = None
 
     def _workspace(self, workspace):
         if workspace is not None:

@@ -127,10 +127,13 @@ std::atomic<int> g_prof_on{0};
 std::vector<ProfRec> g_prof_pending;
 std::map<std::string, std::pair<double, int64_t>> g_prof_done;
 
+// set while a batch enqueues its per-table runs (possibly under graph capture)
+thread_local bool t_prof_suppress = false;
+
 class ProfScope {
   public:
     ProfScope(const char* name, hipStream_t s) : s_(s) {
-        if (!g_prof_on.load()) return;
+        if (!g_prof_on.load() || t_prof_suppress) return;
         rec_.name = name;
         if (hipEventCreate(&rec_.a) != hipSuccess || hipEventCreate(&rec_.b) != hipSuccess ||
             hipEventRecord(rec_.a, s) != hipSuccess) {
@@ -1037,6 +1040,7 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* e, uf_precision 
 // Batches: many tables on one tree (weighted normalized, FP32), one graph
 // =========================================================================
 struct uf_batch {
+    const uf_tree* tree = nullptr;            // caller's tree (must outlive the batch)
     uf_embedding* emb = nullptr;              // concatenated tables, device
     int64_t n_tables = 0;
     std::vector<BatchTable> tabs;        // host copy
@@ -1056,11 +1060,22 @@ struct uf_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> graph_key;         // workspace + outputs the graph was built for
+    // sparse-split mode: per-table embeddings, runs forked over `n_streams` streams
+    bool split = false;
+    std::vector<uf_embedding*> tembs;         // [n_tables], nullptr below 2 samples
+    std::vector<int64_t> order;               // tables by decreasing size
+    size_t slot_bytes = 0;                    // workspace per stream
+    int n_streams = 4;
+    std::vector<hipStream_t> streams;         // kMaxBatchStreams, default priority
+    std::vector<hipEvent_t> events;           // fork + one join event per stream
 
     ~uf_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
+        for (hipStream_t q : streams) (void)hipStreamDestroy(q);
+        for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+        for (uf_embedding* t : tembs) uf_free_embedding(t);
         if (arena) (void)hipFree(arena);
         uf_free_embedding(emb);
     }
@@ -1156,9 +1171,101 @@ uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t
     return UF_OK;
 }
 
+constexpr int kMaxBatchStreams = 8;
+
+// Sparse-split mode: table r runs on stream (rank of r by size) mod n_streams, in
+// decreasing size, each stream with its own workspace slot; the streams fork from
+// and join back into s (also under graph capture).
+uf_status batch_split_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t s) {
+    t_prof_suppress = true;
+    struct Reset {
+        ~Reset() { t_prof_suppress = false; }
+    } reset;
+    const int k = b->n_streams;
+    UF_HIP(hipEventRecord(b->events[0], s));
+    for (int q = 0; q < k; ++q) UF_HIP(hipStreamWaitEvent(b->streams[size_t(q)], b->events[0], 0));
+    for (size_t rank = 0; rank < b->order.size(); ++rank) {
+        const int64_t r = b->order[rank];
+        const uf_embedding* e = b->tembs[size_t(r)];
+        const int q = int(rank % size_t(k));
+        char* slot = base + size_t(q) * b->slot_bytes;
+        uf_status st = run_dm(e, 1, UF_FP32_SPLIT, 0, e->n / 2, UF_CONDENSED, UF_OUT_F32, outs[r],
+                              nullptr, nullptr, false, slot, b->slot_bytes, b->streams[size_t(q)]);
+        if (st != UF_OK) return st;
+    }
+    for (int q = 0; q < k; ++q) {
+        UF_HIP(hipEventRecord(b->events[size_t(q) + 1], b->streams[size_t(q)]));
+        UF_HIP(hipStreamWaitEvent(s, b->events[size_t(q) + 1], 0));
+    }
+    return UF_OK;
+}
+
+uf_status batch_enqueue_any(uf_batch* b, float* const* outs, char* base, hipStream_t s) {
+    return b->split ? batch_split_enqueue(b, outs, base, s) : batch_enqueue(b, outs, base, s);
+}
+
+void drop_graph(uf_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_key.clear();
+}
+
 }  // namespace
 
 extern "C" {
+
+uf_status uf_batch_set_precision(uf_batch* b, uf_precision prec, const uf_table* const* tables,
+                                 void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!b) return fail(UF_ERR_ARG, "batch is NULL");
+        if (prec == UF_FP32) {
+            b->split = false;
+            drop_graph(b);
+            return UF_OK;
+        }
+        if (prec != UF_FP32_SPLIT) return fail(UF_ERR_UNSUPPORTED, "batches run UF_FP32 or UF_FP32_SPLIT");
+        if (!tables) return fail(UF_ERR_ARG, "tables are NULL");
+        if (b->tembs.empty()) {
+            for (int64_t r = 0; r < b->n_tables; ++r)
+                if (!tables[r] || tables[r]->n_samples != b->tabs[size_t(r)].n)
+                    return fail(UF_ERR_ARG, "tables differ from the ones the batch was created with");
+            b->tembs.assign(size_t(b->n_tables), nullptr);
+            for (int64_t r = 0; r < b->n_tables; ++r) {
+                if (b->tabs[size_t(r)].n < 2) continue;
+                uf_status st = embed_impl(b->tree, tables[r], stream, &b->tembs[size_t(r)]);
+                if (st != UF_OK) return st;
+            }
+        }
+        size_t slot = 0;
+        b->order.clear();
+        for (int64_t r = 0; r < b->n_tables; ++r) {
+            const uf_embedding* e = b->tembs[size_t(r)];
+            if (!e) continue;
+            uf_status st = ensure_split(e, 1, stream);
+            if (st != UF_OK) return st;
+            Plan p;
+            st = make_plan(e, 1, UF_FP32_SPLIT, 0, e->n / 2, false, &p);
+            if (st != UF_OK) return st;
+            slot = std::max(slot, (p.total + 255) & ~size_t(255));
+            b->order.push_back(r);
+        }
+        std::stable_sort(b->order.begin(), b->order.end(), [&](int64_t x, int64_t y) {
+            return b->tabs[size_t(x)].n > b->tabs[size_t(y)].n;
+        });
+        b->slot_bytes = slot;
+        if (b->streams.empty()) {
+            b->streams.assign(kMaxBatchStreams, nullptr);
+            for (auto& q : b->streams) UF_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+            b->events.assign(kMaxBatchStreams + 1, nullptr);
+            for (auto& ev : b->events) UF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        }
+        b->split = true;
+        drop_graph(b);
+        return UF_OK;
+    });
+}
 
 uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
                           const char* tune_cache, void* stream, uf_batch** out) {
@@ -1183,6 +1290,7 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         cat.n_samples = int64_t(cat.total.size());
         auto b = new uf_batch();
         std::unique_ptr<uf_batch> guard(b);
+        b->tree = tree;
         uf_status st = embed_impl(tree, &cat, stream, &b->emb);
         if (st != UF_OK) return st;
         b->n_tables = n_tables;
@@ -1266,9 +1374,13 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
 
 int64_t uf_batch_n_tables(const uf_batch* b) { return b ? b->n_tables : -1; }
 
+size_t batch_ws_bytes(const uf_batch* b) {
+    return b->split ? b->slot_bytes * size_t(kMaxBatchStreams) + 256 : b->ws_total;
+}
+
 uf_status uf_batch_workspace_size(const uf_batch* b, size_t* bytes) {
     if (!b || !bytes) return fail(UF_ERR_ARG, "NULL argument");
-    *bytes = b->ws_total;
+    *bytes = batch_ws_bytes(b);
     return UF_OK;
 }
 
@@ -1300,7 +1412,7 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
                        void* stream) {
     return guarded([&]() -> uf_status {
         if (!b || !outs) return fail(UF_ERR_ARG, "NULL argument");
-        if (!ws || ws_bytes < b->ws_total) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
+        if (!ws || ws_bytes < batch_ws_bytes(b)) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
         for (int64_t r = 0; r < b->n_tables; ++r)
             if (!outs[r] && b->tabs[r].n >= 2) return fail(UF_ERR_ARG, "output pointer is NULL");
         int dev = 0;
@@ -1308,8 +1420,17 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
         if (st != UF_OK) return st;
         char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
         hipStream_t s = static_cast<hipStream_t>(stream);
-        if (!use_graph) return batch_enqueue(b, outs, base, s);
         std::vector<uintptr_t> key;
+        if (b->split) {
+            // splits are built outside any capture (a changed threshold rebuilds them)
+            for (int64_t r : b->order) {
+                st = ensure_split(b->tembs[size_t(r)], 1, stream);
+                if (st != UF_OK) return st;
+                key.push_back(reinterpret_cast<uintptr_t>(b->tembs[size_t(r)]->split[1]));
+            }
+            key.push_back(uintptr_t(b->n_streams));
+        }
+        if (!use_graph) return batch_enqueue_any(b, outs, base, s);
         key.push_back(reinterpret_cast<uintptr_t>(base));
         for (int64_t r = 0; r < b->n_tables; ++r) key.push_back(reinterpret_cast<uintptr_t>(outs[r]));
         if (!b->exec || key != b->graph_key) {
@@ -1320,7 +1441,7 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
                 b->graph = nullptr;
             }
             UF_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-            uf_status est = batch_enqueue(b, outs, base, b->cap);
+            uf_status est = batch_enqueue_any(b, outs, base, b->cap);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(b->cap, &g);
             if (est != UF_OK) {
@@ -1347,12 +1468,60 @@ uf_status uf_autotune(uf_batch* b, void* ws, size_t ws_bytes, const char* tune_c
                       void* stream, double* best_ms) {
     return guarded([&]() -> uf_status {
         if (!b) return fail(UF_ERR_ARG, "batch is NULL");
-        if (!ws || ws_bytes < b->ws_total) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
+        if (!ws || ws_bytes < batch_ws_bytes(b)) return fail(UF_ERR_WORKSPACE, "batch workspace too small");
         int dev = 0;
         uf_status st = check_device(&dev);
         if (st != UF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
         char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+        if (b->split) {
+            // sparse-split mode: time whole eager runs over 1, 2, 4 and 8 streams into
+            // scratch outputs in the workspace's slots (output sizes are the tables')
+            std::vector<void*> scratch(size_t(b->n_tables), nullptr);
+            struct Free {
+                std::vector<void*>& v;
+                ~Free() {
+                    for (void* q : v)
+                        if (q) (void)hipFree(q);
+                }
+            } fr{scratch};
+            for (int64_t r : b->order) {
+                const int64_t n = b->tabs[size_t(r)].n;
+                if (hipMalloc(&scratch[size_t(r)], size_t(n * (n - 1) / 2) * 4 + 256) != hipSuccess)
+                    return fail(UF_ERR_NOMEM, "autotune outputs");
+            }
+            std::vector<float*> outs(size_t(b->n_tables), nullptr);
+            for (int64_t r = 0; r < b->n_tables; ++r) outs[size_t(r)] = static_cast<float*>(scratch[size_t(r)]);
+            hipEvent_t e0, e1;
+            UF_HIP(hipEventCreate(&e0));
+            UF_HIP(hipEventCreate(&e1));
+            int best_k = b->n_streams;
+            double best_t = 1e300;
+            for (int k : {1, 2, 4, 8}) {
+                b->n_streams = k;
+                double tmin = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {
+                    UF_HIP(hipEventRecord(e0, s));
+                    st = batch_split_enqueue(b, outs.data(), base, s);
+                    if (st != UF_OK) return st;
+                    UF_HIP(hipEventRecord(e1, s));
+                    UF_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    UF_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    tmin = std::min(tmin, double(ms));
+                }
+                if (tmin < best_t) {
+                    best_t = tmin;
+                    best_k = k;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            b->n_streams = best_k;
+            drop_graph(b);
+            if (best_ms) *best_ms = best_t;
+            return UF_OK;
+        }
         float* E = reinterpret_cast<float*>(base + b->off_E);
         float* acc = reinterpret_cast<float*>(base + b->off_acc);
         unsigned* cnt = reinterpret_cast<unsigned*>(base + b->off_cnt);

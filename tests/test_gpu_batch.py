@@ -121,3 +121,51 @@ def test_tune_cache_is_read_back(batch, tmp_path):
         f"n_bucket_{bucket}": {"stage_branches": 8, "wgs_per_cu": 3, "ms": 1.0}}}}))
     b2 = uf.Batch(ut, uts, tune_cache=str(path))
     assert b2.config()[:2] == (8, 3)
+
+
+def test_split_mode_matches_single_split_calls(tmp_path):
+    """Sparse-split mode: every table equals uf_dm_weighted_normalized(UF_FP32_SPLIT)
+    on that table alone, bit for bit, and the oracle within 1e-4; graph replays
+    (with unrelated work between them), eager runs and every stream count agree."""
+    import torch
+    import paper_2107_05397_amd as uf
+    tree, tables = _tables()
+    ut = uf.Tree(tree.parent, tree.length)
+    uts = [uf.Table(ut, t.indptr, t.tips, t.counts) for t in tables]
+    b = uf.Batch(ut, uts)
+    b.set_precision("fp32_split")
+    ref = _copy(b.run(use_graph=True))
+    torch.cuda.synchronize()
+    for r, (t, tu) in enumerate(zip(tables, uts)):
+        n = t.n_samples
+        if n < 2:
+            continue
+        emb = uf.Embedding(ut, tu)
+        single, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split", out_dtype=torch.float32)
+        torch.cuda.synchronize()
+        assert torch.equal(ref[r], single[: n * (n - 1) // 2]), r
+        want = core.dm(tree, t, "weighted_normalized")[0]
+        err = np.abs(ref[r].cpu().numpy().astype(np.float64) - want)
+        print(f"[batch split table {r} n={n}] max|err|={err.max():.3e}")
+        assert err.max() <= 1e-4
+    x = torch.randn(512, 512, device="cuda")
+    for _ in range(3):
+        y = x @ x
+        got = b.run(use_graph=True)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, c) for a, c in zip(ref, got))
+    eager = b.run(use_graph=False)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(ref, eager))
+    del y
+    ms = b.autotune()
+    assert ms > 0
+    got = b.run(use_graph=True)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(ref, got))
+    b.set_precision("fp32")
+    dense = b.run(use_graph=True)
+    torch.cuda.synchronize()
+    for r, t in enumerate(tables):
+        if t.n_samples >= 2:
+            assert torch.max(torch.abs(dense[r] - ref[r])).item() <= 2e-4
