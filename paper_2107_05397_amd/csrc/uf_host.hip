@@ -310,8 +310,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     const size_t o_dlo = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
     const size_t o_rl = c.take(nl * 8);
     const size_t o_soff = c.take(size_t(n + 1) * 8);
-    const size_t o_sll = c.take(ne * 4);
-    const size_t o_slp = c.take(ne * 4);
+    const size_t o_ent = c.take(ne * sizeof(ufs::SlotEntry));
     if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
     char* b = static_cast<char*>(sc->arena);
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
@@ -324,8 +323,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->dlen_lo = reinterpret_cast<uint16_t*>(b + o_dlo);
     sc->rl = reinterpret_cast<int64_t*>(b + o_rl);
     sc->soff = reinterpret_cast<int64_t*>(b + o_soff);
-    sc->sl_list = reinterpret_cast<int32_t*>(b + o_sll);
-    sc->sl_pos = reinterpret_cast<int32_t*>(b + o_slp);
+    sc->entries = reinterpret_cast<ufs::SlotEntry*>(b + o_ent);
     auto fail_free = [&](uf_status code) {
         (void)hipFree(sc->arena);
         sc->arena = nullptr;
@@ -370,10 +368,11 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
     if (rc == hipSuccess)
         rc = ufs::sort_lists(sc->roff, sc->n_lists, rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur,
-                             sc->sl_list, sc->sl_pos, s);
+                             sc->entries, s);
     if (rc == hipSuccess)
         rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
                                 e->len_lo, sc->dlen_hi, sc->dlen_lo, sc->rl, s);
+    if (rc == hipSuccess && !weighted) rc = ufs::entry_lengths(sc->entries, sc->n_entries, sc->rl, s);
     if (rc == hipSuccess) rc = hipStreamSynchronize(s);
     if (rc != hipSuccess) return fail_free(hip_fail(rc, "sparse split build"));
     e->split[w] = sc.release();
@@ -544,8 +543,7 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     if (sp) {
         M = reinterpret_cast<unsigned long long*>(base + p.off_m);
         ProfScope ps(weighted ? "rare_slots_wn" : "rare_slots_uw", s);
-        UF_HIP(ufs::rare_slots(sp->roff, sp->rs, sp->rw, weighted ? nullptr : sp->rl, sp->soff,
-                               sp->sl_list, sp->sl_pos, p.n, p.sb, p.se, M, s));
+        UF_HIP(ufs::rare_slots(sp->rs, sp->rw, sp->soff, sp->entries, p.n, p.sb, p.se, M, s));
     }
     const double* scal = weighted ? e->sw
                                   : (prec == UF_FP64 ? e->wu : (prec == UF_FP32 ? e->wu32 : e->wub));

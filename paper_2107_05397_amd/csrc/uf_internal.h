@@ -43,6 +43,10 @@ struct uf_table {
 };
 
 // Sparse-aware split of one embedding at one threshold (uf_host.hip).
+namespace ufs {
+struct SlotEntry;
+}
+
 struct SplitCache {
     double threshold = 0.0;       // requested fraction, < 0 for the cost model
     int64_t n_dense = 0;          // branches in the dense set
@@ -61,9 +65,8 @@ struct SplitCache {
     uint16_t* dlen_hi = nullptr;  // [n_dense_pad] bf16 high part of each dense length, 0-padded
     uint16_t* dlen_lo = nullptr;  // [n_dense_pad] bf16 low part
     int64_t* rl = nullptr;        // [n_lists] (hi+lo) length of each list's branch, 2^-40 fixed point
-    int64_t* soff = nullptr;      // [n+1] per-sample rows of the two arrays below
-    int32_t* sl_list = nullptr;   // [n_entries] a list the sample is in
-    int32_t* sl_pos = nullptr;    // [n_entries] the sample's position in that list
+    int64_t* soff = nullptr;      // [n+1] per-sample rows of `entries`
+    ufs::SlotEntry* entries = nullptr;   // [n_entries] the sample's list memberships
     double q_scale = 0.0;         // weighted: 32-bit fixed-point scale of the dense pass (0: FP32)
 };
 

@@ -13,6 +13,17 @@ constexpr int32_t kClassDense = -1;    // branch in the dense set
 constexpr int32_t kClassAlone = -2;    // touched by at most one sample: no pairs
 constexpr int kSampleBits = 24;         // packed weighted list member: value << 24 | sample
 
+// One list membership of a sample, as the slot kernel reads it: the list's first
+// entry and length, the sample's position in it, and its value (weighted: the
+// sample's own l*u in the split's fixed-point step; unweighted: the branch length
+// l_hi + l_lo in 2^-40).
+struct SlotEntry {
+    int64_t base;
+    int32_t m;
+    int32_t p;
+    unsigned long long v;
+};
+
 hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st);
 // Unsorted list members (sample, fixed-point l*u), sigma, per-sample list counts
 // (scnt) and per-sample counts of dense branches of nonzero length (dnnz).
@@ -21,11 +32,13 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
                       int32_t* dnnz, double fix, hipStream_t st);
 // Lists sorted by sample, into rs_out (sample ids) or, when rw_out is non-null, into
 // rw_out as packed words rq << kSampleBits | sample; per-sample index rows
-// [soff[s], soff[s+1]) of (list, position) filled through the cursors scur (zeroed
-// by the caller).
+// [soff[s], soff[s+1]) of SlotEntry filled through the cursors scur (zeroed by the
+// caller); v holds the sample's value (weighted) or the list id (unweighted).
 hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
-                      int32_t* sl_list, int32_t* sl_pos, hipStream_t st);
+                      SlotEntry* se, hipStream_t st);
+// Unweighted: replace each entry's list id (left in v by sort_lists) by rl[list].
+hipError_t entry_lengths(SlotEntry* se, int64_t n_entries, const int64_t* rl, hipStream_t st);
 // Node-major chunk E[k][s] over positions list[k0 .. k0+kc): x = l * c / T as FP32,
 // or as rint(x * q) in 32-bit fixed point.
 hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, float* out,
@@ -38,11 +51,10 @@ hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, i
                          int64_t n_pad, const uint16_t* len_hi, const uint16_t* len_lo,
                          uint16_t* dlen_hi, uint16_t* dlen_lo, int64_t* rl, hipStream_t st);
 // M[(s-sb)*n + i] = sum over the pairs (i, (i+s+1) mod n), s in [sb, se), that share a
-// non-dense branch: rw non-null: weighted, min of the two packed values; else
-// unweighted (sample ids rs), rl[list].  Writes every element of the range.
-hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned long long* rw,
-                      const int64_t* rl, const int64_t* soff, const int32_t* sl_list,
-                      const int32_t* sl_pos, int64_t n, int64_t sb, int64_t se, unsigned long long* M,
-                      hipStream_t st);
+// non-dense branch: rw non-null: weighted, min of the two values; else unweighted
+// (sample ids rs), the branch length.  Writes every element of the range.
+hipError_t rare_slots(const int32_t* rs, const unsigned long long* rw, const int64_t* soff,
+                      const SlotEntry* entries, int64_t n, int64_t sb, int64_t se,
+                      unsigned long long* M, hipStream_t st);
 
 }  // namespace ufs

@@ -88,16 +88,20 @@ __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k,
                                              int32_t* __restrict__ rs_out,
                                              unsigned long long* __restrict__ rw_out,
                                              const int64_t* __restrict__ soff,
-                                             int32_t* __restrict__ scur,
-                                             int32_t* __restrict__ sl_list,
-                                             int32_t* __restrict__ sl_pos) {
+                                             int32_t* __restrict__ scur, int32_t m,
+                                             SlotEntry* __restrict__ se) {
+    const unsigned long long q = (unsigned long long)rq_in[base + k];
     if (rw_out)
-        rw_out[base + r] = ((unsigned long long)rq_in[base + k] << kSampleBits) | unsigned(smp);
+        rw_out[base + r] = (q << kSampleBits) | unsigned(smp);
     else
         rs_out[base + r] = smp;
     const int32_t slot = atomicAdd(&scur[smp], 1);
-    sl_list[soff[smp] + slot] = int32_t(L);
-    sl_pos[soff[smp] + slot] = r;
+    SlotEntry ent;
+    ent.base = base;
+    ent.m = m;
+    ent.p = r;
+    ent.v = rw_out ? q : (unsigned long long)L;
+    se[soff[smp] + slot] = ent;
 }
 
 __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff,
@@ -107,8 +111,7 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
                                                     unsigned long long* __restrict__ rw_out,
                                                     const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ scur,
-                                                    int32_t* __restrict__ sl_list,
-                                                    int32_t* __restrict__ sl_pos) {
+                                                    SlotEntry* __restrict__ se) {
     __shared__ int32_t ks[kSortLds];
     const int64_t L = blockIdx.x;
     const int64_t base = roff[L];
@@ -120,14 +123,14 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
             const int32_t smp = ks[k];
             int32_t r = 0;
             for (int64_t t = 0; t < m; ++t) r += ks[t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, sl_list, sl_pos);
+            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, int32_t(m), se);
         }
     } else {
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = rs_in[base + k];
             int32_t r = 0;
             for (int64_t t = 0; t < m; ++t) r += rs_in[base + t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, sl_list, sl_pos);
+            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, int32_t(m), se);
         }
     }
 }
@@ -194,6 +197,12 @@ __global__ __launch_bounds__(256) void k_split_lengths(const int32_t* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void k_entry_lengths(SlotEntry* __restrict__ se, int64_t n_entries,
+                                                       const int64_t* __restrict__ rl) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (k < n_entries) se[k].v = (unsigned long long)rl[se[k].v];
+}
+
 // Workgroup -> sample: consecutive samples on one XCD (blocks are dealt to the
 // 8 XCDs round-robin), so the column writes of neighbours share L2 lines.
 __device__ __forceinline__ int64_t xcd_sample(int64_t b, int64_t n) {
@@ -210,11 +219,9 @@ constexpr int64_t kSegStripes = 20480;
 
 template <bool W>
 __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
-    const int64_t* __restrict__ roff, const int32_t* __restrict__ rs,
-    const unsigned long long* __restrict__ rw, const int64_t* __restrict__ rl,
-    const int64_t* __restrict__ soff, const int32_t* __restrict__ sl_list,
-    const int32_t* __restrict__ sl_pos, int64_t n, int64_t sb, int64_t se, int64_t seg_len,
-    unsigned long long* __restrict__ M) {
+    const int32_t* __restrict__ rs, const unsigned long long* __restrict__ rw,
+    const int64_t* __restrict__ soff, const SlotEntry* __restrict__ entries, int64_t n,
+    int64_t sb, int64_t se, int64_t seg_len, unsigned long long* __restrict__ M) {
     extern __shared__ unsigned long long acc[];   // [seg_len]
     const int64_t i = xcd_sample(blockIdx.x, n);
     const int64_t g0 = sb + int64_t(blockIdx.y) * seg_len;
@@ -230,11 +237,11 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     const int64_t dlo = g0 + 1;
     const int64_t dhi = min(g1, n / 2);
     for (int64_t k = soff[i] + wave; k < soff[i + 1]; k += kSlotWaves) {
-        const int64_t L = sl_list[k];
-        const int64_t p = sl_pos[k];
-        const int64_t base = roff[L];
-        const int64_t m = roff[L + 1] - base;
-        const unsigned long long vi = W ? rw[base + p] >> kSampleBits : (unsigned long long)rl[L];
+        const SlotEntry ent = entries[k];
+        const int64_t base = ent.base;
+        const int64_t m = ent.m;
+        const int64_t p = ent.p;
+        const unsigned long long vi = ent.v;
         // the c-th member after i (c in [0, m-1)), cyclically, sits at position
         // (p + 1 + c) mod m; its distance from i grows with c
         auto pos_of = [&](int64_t c) {
@@ -312,11 +319,18 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
 
 hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
-                      int32_t* sl_list, int32_t* sl_pos, hipStream_t st) {
+                      SlotEntry* se, hipStream_t st) {
     if (n_lists <= 0) return hipSuccess;
     if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, rs_in, rq_in,
-                       rs_out, rw_out, soff, scur, sl_list, sl_pos);
+                       rs_out, rw_out, soff, scur, se);
+    return hipGetLastError();
+}
+
+hipError_t entry_lengths(SlotEntry* se, int64_t n_entries, const int64_t* rl, hipStream_t st) {
+    if (n_entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_lengths, dim3(unsigned((n_entries + 255) / 256)), dim3(256), 0, st, se,
+                       n_entries, rl);
     return hipGetLastError();
 }
 
@@ -351,10 +365,9 @@ hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, i
     return hipGetLastError();
 }
 
-hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned long long* rw,
-                      const int64_t* rl, const int64_t* soff, const int32_t* sl_list,
-                      const int32_t* sl_pos, int64_t n, int64_t sb, int64_t se, unsigned long long* M,
-                      hipStream_t st) {
+hipError_t rare_slots(const int32_t* rs, const unsigned long long* rw, const int64_t* soff,
+                      const SlotEntry* entries, int64_t n, int64_t sb, int64_t se,
+                      unsigned long long* M, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
     if (n > 0x7fffffff || (rw && n > (int64_t(1) << kSampleBits))) return hipErrorInvalidValue;
     const int64_t nseg = (se - sb + kSegStripes - 1) / kSegStripes;
@@ -371,11 +384,11 @@ hipError_t rare_slots(const int64_t* roff, const int32_t* rs, const unsigned lon
     }();
     if (!attr_ok) return hipErrorInvalidValue;
     if (rw)
-        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), lds, st, roff, rs, rw, rl,
-                           soff, sl_list, sl_pos, n, sb, se, seg_len, M);
+        hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), lds, st, rs, rw, soff,
+                           entries, n, sb, se, seg_len, M);
     else
-        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), lds, st, roff, rs, rw, rl,
-                           soff, sl_list, sl_pos, n, sb, se, seg_len, M);
+        hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), lds, st, rs, rw, soff,
+                           entries, n, sb, se, seg_len, M);
     return hipGetLastError();
 }
 
