@@ -126,7 +126,7 @@ namespace ufk {
 
 constexpr int kBandI = 128;       // samples per band tile
 constexpr int kBandS = 128;       // stripes per band tile
-constexpr int kGramT = 128;       // square tile of the MFMA Gram kernel
+constexpr int kGramT = 256;       // square tile of the MFMA Gram kernel
 constexpr int kGramK = 32;        // K step of the MFMA Gram kernel
 
 // Per-sample scalars from the postorder leaf intervals (one wave per sample).

@@ -351,8 +351,9 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
 // Unweighted Gram product on MFMA: G = P diag(l) P^T with P the 0/1 presence
 // (exact in BF16) and l = l_hi + l_lo, both BF16; two MFMAs per K step share
 // the A fragment.  v_mfma_f32_32x32x16_bf16 accumulates in FP32.
-// Block = 4 waves in 2x2, tile 128x128 (wave 64x64 = 2x2 MFMA blocks of 32x32),
-// K step 32 staged in LDS (rows padded by 8 BF16 against bank conflicts).
+// Block = 8 waves in 2x4, tile 256x256 (wave 128x64 = 4x2 MFMA blocks of 32x32),
+// K step 32 staged in two LDS stages (rows padded by 8 BF16 against bank
+// conflicts); the next step's global loads are in flight during the MFMAs.
 // Only upper-triangle tiles (bi <= bj) that hold a pair of the stripe range
 // run; each pair i<j of the range is written to its stripe-major slot.
 // ----------------------------------------------------------------------------
@@ -399,7 +400,7 @@ __device__ __forceinline__ bool gram_tile_of(int64_t b, int64_t nblk, int64_t& b
     return bi < nblk && bj < nblk && bj >= bi;
 }
 
-__global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict__ P,
+__global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict__ P,
                                                       const uint16_t* __restrict__ hiv,
                                                       const uint16_t* __restrict__ lov,
                                                       int64_t kpad, int64_t n, int64_t sb,
@@ -411,16 +412,17 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
     const int64_t i0 = bi * T, j0 = bj * T;
     if (!tile_in_range(i0, j0, n, sb, se)) return;
 
-    __shared__ __attribute__((aligned(16))) uint16_t As[T * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bh[T * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bl[T * LD];
+    // two stages of A (presence rows i), Bh and Bl (length-masked presence rows j)
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bh[2][T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bl[2][T * LD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wi = wave & 1, wj = wave >> 1;
-    floatx16 c[2][2];
+    const int wi = wave & 1, wj = wave >> 1;     // wave tile: rows wi*128 + [0,128), cols wj*64 + [0,64)
+    floatx16 c[4][2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -429,64 +431,80 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
     const int lrow = tid >> 1;          // staging: row of the tile
     const int lseg = (tid & 1) * 16;    // staging: first of 16 K columns
     const int64_t gi = i0 + lrow, gj = j0 + lrow;
+    const bool gi_ok = gi < n, gj_ok = gj < n;
 
-    for (int64_t k0 = 0; k0 < kpad; k0 += KT) {
-        uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
-        if (gi < n) {
+    uint4 a0, a1, b0, b1, h0, h1, l0, l1;
+    auto fetch = [&](int64_t k0) {
+        a0 = a1 = b0 = b1 = make_uint4(0, 0, 0, 0);
+        if (gi_ok) {
             const uint4* src = reinterpret_cast<const uint4*>(P + gi * kpad + k0 + lseg);
             a0 = src[0];
             a1 = src[1];
         }
-        if (gj < n) {
+        if (gj_ok) {
             const uint4* src = reinterpret_cast<const uint4*>(P + gj * kpad + k0 + lseg);
             b0 = src[0];
             b1 = src[1];
         }
         const uint4* hsrc = reinterpret_cast<const uint4*>(hiv + k0 + lseg);
         const uint4* lsrc = reinterpret_cast<const uint4*>(lov + k0 + lseg);
-        const uint4 h0 = hsrc[0], h1 = hsrc[1], l0 = lsrc[0], l1 = lsrc[1];
-        // B = P (0 or 0x3F80 per BF16) masked onto the lengths
-        auto mask = [](unsigned p) -> unsigned {
-            const unsigned lo = (p & 0x0000FFFFu) ? 0x0000FFFFu : 0u;
-            const unsigned hi = (p & 0xFFFF0000u) ? 0xFFFF0000u : 0u;
-            return lo | hi;
-        };
+        h0 = hsrc[0];
+        h1 = hsrc[1];
+        l0 = lsrc[0];
+        l1 = lsrc[1];
+    };
+    // B = P (0 or 0x3F80 per BF16) masked onto the lengths
+    auto mask = [](unsigned p) -> unsigned {
+        const unsigned lo = (p & 0x0000FFFFu) ? 0x0000FFFFu : 0u;
+        const unsigned hi = (p & 0xFFFF0000u) ? 0xFFFF0000u : 0u;
+        return lo | hi;
+    };
+    auto stash = [&](int buf) {
         const uint4 m0 = make_uint4(mask(b0.x), mask(b0.y), mask(b0.z), mask(b0.w));
         const uint4 m1 = make_uint4(mask(b1.x), mask(b1.y), mask(b1.z), mask(b1.w));
-        __syncthreads();
-        uint4* ad = reinterpret_cast<uint4*>(As + lrow * LD + lseg);
-        uint4* hd = reinterpret_cast<uint4*>(Bh + lrow * LD + lseg);
-        uint4* ld = reinterpret_cast<uint4*>(Bl + lrow * LD + lseg);
+        uint4* ad = reinterpret_cast<uint4*>(As[buf] + lrow * LD + lseg);
+        uint4* hd = reinterpret_cast<uint4*>(Bh[buf] + lrow * LD + lseg);
+        uint4* ld = reinterpret_cast<uint4*>(Bl[buf] + lrow * LD + lseg);
         ad[0] = a0;
         ad[1] = a1;
         hd[0] = make_uint4(h0.x & m0.x, h0.y & m0.y, h0.z & m0.z, h0.w & m0.w);
         hd[1] = make_uint4(h1.x & m1.x, h1.y & m1.y, h1.z & m1.z, h1.w & m1.w);
         ld[0] = make_uint4(l0.x & m0.x, l0.y & m0.y, l0.z & m0.z, l0.w & m0.w);
         ld[1] = make_uint4(l1.x & m1.x, l1.y & m1.y, l1.z & m1.z, l1.w & m1.w);
+    };
+
+    // one barrier per K step: the stage written in step t was last read in step
+    // t-2, which every wave finished before passing the barrier of step t-1
+    fetch(0);
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < kpad; k0 += KT) {
+        stash(buf);
         __syncthreads();
+        if (k0 + KT < kpad) fetch(k0 + KT);    // next stage in flight during the MFMAs
 #pragma unroll
         for (int kk = 0; kk < KT; kk += 16) {
             const int kq = kk + 8 * (lane >> 5);
-            bf16x8 fa[2], fh[2], fl[2];
+            bf16x8 fa[4], fh[2], fl[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                const int row = wi * 64 + x * 32 + (lane & 31);
-                fa[x] = *reinterpret_cast<const bf16x8*>(As + row * LD + kq);
+            for (int x = 0; x < 4; ++x) {
+                const int row = wi * 128 + x * 32 + (lane & 31);
+                fa[x] = *reinterpret_cast<const bf16x8*>(As[buf] + row * LD + kq);
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 const int col = wj * 64 + y * 32 + (lane & 31);
-                fh[y] = *reinterpret_cast<const bf16x8*>(Bh + col * LD + kq);
-                fl[y] = *reinterpret_cast<const bf16x8*>(Bl + col * LD + kq);
+                fh[y] = *reinterpret_cast<const bf16x8*>(Bh[buf] + col * LD + kq);
+                fl[y] = *reinterpret_cast<const bf16x8*>(Bl[buf] + col * LD + kq);
             }
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
                     c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fh[y], c[x][y], 0, 0, 0);
                     c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fl[y], c[x][y], 0, 0, 0);
                 }
         }
+        buf ^= 1;
     }
 
     // epilogue: D[i][j] for 32x32 block: lane holds column lane%32 and rows
@@ -494,12 +512,12 @@ __global__ __launch_bounds__(256, 2) void k_gram_mfma(const uint16_t* __restrict
     const int64_t S = n / 2;
     const bool even = (n & 1) == 0;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wi * 64 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t i = i0 + wi * 128 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int64_t j = j0 + wj * 64 + y * 32 + (lane & 31);
                 if (!(i < j && j < n)) continue;
                 const int64_t d = j - i;
@@ -811,7 +829,7 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
     const int64_t blocks = (n_super + 7) / 8 * 8 * kGramGroup * kGramGroup;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid{unsigned(blocks), 1u, 1u};
-    hipLaunchKernelGGL(k_gram_mfma, grid, dim3(256), 0, st, P, hi, lo, kpad, n, sb, se, first,
+    hipLaunchKernelGGL(k_gram_mfma, grid, dim3(512), 0, st, P, hi, lo, kpad, n, sb, se, first,
                        acc);
     return hipGetLastError();
 }
