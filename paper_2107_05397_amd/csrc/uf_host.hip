@@ -282,7 +282,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->n_dense = int64_t(dense.size());
     sc->n_lists = int64_t(roff.size()) - 1;
     sc->n_entries = roff.back();
-    sc->n_dense_pad = (sc->n_dense + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    sc->n_dense_pad = (sc->n_dense + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
     if (weighted) {
         // packed members hold the sample in kSampleBits bits and the value in the
         // other 40: choose the fixed-point step so that l * u <= max l stays below 2^40
@@ -424,11 +424,11 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
         kc = static_cast<int64_t>(budget / (double(std::max<int64_t>(n, 1)) * double(elem)));
     }
     kc = std::max<int64_t>(kc, 32);
-    if (mfma) kc = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    if (mfma) kc = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
     kc = std::min<int64_t>(kc, std::max<int64_t>(nb, 1));
     p->kc = kc;
     p->nchunks = nb > 0 ? (nb + kc - 1) / kc : 0;
-    p->kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+    p->kpad = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
     p->n_parts = std::max<int64_t>(1, (p->sr + 255) / 256);
     Carver c;
     const size_t acc_elem = (prec == UF_FP64) ? 8 : 4;
@@ -521,7 +521,7 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
         } else {
             const bool ms = prec == UF_MFMA_SPLIT;
             uint16_t* P = static_cast<uint16_t*>(chunk);
-            const int64_t kpad = (kc + ufk::kGramK - 1) / ufk::kGramK * ufk::kGramK;
+            const int64_t kpad = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
             {
                 ProfScope ps("embed_pres", s);
                 UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s,
@@ -829,7 +829,7 @@ uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embe
         const int64_t m = t->n_nodes;
         const int64_t nb = m - 1;
         const int64_t nnz = int64_t(tb->rank.size());
-        const int64_t nb_pad = (nb + 2 * ufk::kGramK + 63) / 64 * 64;  // room for the last K step
+        const int64_t nb_pad = (nb + ufk::kGramKPad + 63) / 64 * 64;  // room for the last K step
         // host-side arrays
         std::vector<int64_t> cum(size_t(nnz + n), 0);
         for (int64_t r = 0; r < n; ++r) {

@@ -128,6 +128,7 @@ constexpr int kBandI = 128;       // samples per band tile
 constexpr int kBandS = 128;       // stripes per band tile
 constexpr int kGramT = 256;       // square tile of the MFMA Gram kernel
 constexpr int kGramK = 32;        // K step of the MFMA Gram kernel
+constexpr int kGramKPad = 64;     // K of its presence matrix is padded to this (steps go in pairs)
 
 // Per-sample scalars from the postorder leaf intervals (one wave per sample).
 hipError_t sample_scalars(const uf_embedding& e, const int32_t* parent_pos,

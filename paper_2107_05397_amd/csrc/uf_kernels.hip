@@ -352,8 +352,8 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
 // (exact in BF16) and l = l_hi + l_lo, both BF16; two MFMAs per K step share
 // the A fragment.  v_mfma_f32_32x32x16_bf16 accumulates in FP32.
 // Block = 8 waves in 2x4, tile 256x256 (wave 128x64 = 4x2 MFMA blocks of 32x32),
-// K step 32 staged in two LDS stages (rows padded by 8 BF16 against bank
-// conflicts); the next step's global loads are in flight during the MFMAs.
+// K step 32 staged through registers into two LDS stages (rows padded by 8 BF16
+// against bank conflicts); global loads run two K steps ahead of the MFMAs.
 // Only upper-triangle tiles (bi <= bj) that hold a pair of the stripe range
 // run; each pair i<j of the range is written to its stripe-major slot.
 // ----------------------------------------------------------------------------
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
     const int64_t i0 = bi * T, j0 = bj * T;
     if (!tile_in_range(i0, j0, n, sb, se)) return;
 
-    // two stages of A (presence rows i), Bh and Bl (length-masked presence rows j)
+    // two LDS stages of A (presence rows i), Bh and Bl (length-masked presence rows j)
     __shared__ __attribute__((aligned(16))) uint16_t As[2][T * LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bh[2][T * LD];
     __shared__ __attribute__((aligned(16))) uint16_t Bl[2][T * LD];
@@ -430,28 +430,32 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
 
     const int lrow = tid >> 1;          // staging: row of the tile
     const int lseg = (tid & 1) * 16;    // staging: first of 16 K columns
-    const int64_t gi = i0 + lrow, gj = j0 + lrow;
-    const bool gi_ok = gi < n, gj_ok = gj < n;
+    // rows past n read row n-1: their products land in rows/columns >= n, which
+    // the epilogue drops
+    const int64_t ci = i0 + lrow < n ? i0 + lrow : n - 1;
+    const int64_t cj = j0 + lrow < n ? j0 + lrow : n - 1;
 
-    uint4 a0, a1, b0, b1, h0, h1, l0, l1;
-    auto fetch = [&](int64_t k0) {
-        a0 = a1 = b0 = b1 = make_uint4(0, 0, 0, 0);
-        if (gi_ok) {
-            const uint4* src = reinterpret_cast<const uint4*>(P + gi * kpad + k0 + lseg);
-            a0 = src[0];
-            a1 = src[1];
-        }
-        if (gj_ok) {
-            const uint4* src = reinterpret_cast<const uint4*>(P + gj * kpad + k0 + lseg);
-            b0 = src[0];
-            b1 = src[1];
-        }
+    // one K step in registers: 16 BF16 of rows ci and cj, and of l_hi, l_lo
+    struct Regs {
+        uint4 a0, a1, b0, b1, h0, h1, l0, l1;
+    };
+    // (Regs move by value: a reference would leave them in memory, which the
+    // compiler may place in LDS and wait on at once)
+    auto fetch = [&](int64_t k0) -> Regs {
+        Regs R;
+        const uint4* asrc = reinterpret_cast<const uint4*>(P + ci * kpad + k0 + lseg);
+        const uint4* bsrc = reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
         const uint4* hsrc = reinterpret_cast<const uint4*>(hiv + k0 + lseg);
         const uint4* lsrc = reinterpret_cast<const uint4*>(lov + k0 + lseg);
-        h0 = hsrc[0];
-        h1 = hsrc[1];
-        l0 = lsrc[0];
-        l1 = lsrc[1];
+        R.a0 = asrc[0];
+        R.a1 = asrc[1];
+        R.b0 = bsrc[0];
+        R.b1 = bsrc[1];
+        R.h0 = hsrc[0];
+        R.h1 = hsrc[1];
+        R.l0 = lsrc[0];
+        R.l1 = lsrc[1];
+        return R;
     };
     // B = P (0 or 0x3F80 per BF16) masked onto the lengths
     auto mask = [](unsigned p) -> unsigned {
@@ -459,28 +463,20 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
         const unsigned hi = (p & 0xFFFF0000u) ? 0xFFFF0000u : 0u;
         return lo | hi;
     };
-    auto stash = [&](int buf) {
-        const uint4 m0 = make_uint4(mask(b0.x), mask(b0.y), mask(b0.z), mask(b0.w));
-        const uint4 m1 = make_uint4(mask(b1.x), mask(b1.y), mask(b1.z), mask(b1.w));
+    auto stash = [&](const Regs R, int buf) {
+        const uint4 m0 = make_uint4(mask(R.b0.x), mask(R.b0.y), mask(R.b0.z), mask(R.b0.w));
+        const uint4 m1 = make_uint4(mask(R.b1.x), mask(R.b1.y), mask(R.b1.z), mask(R.b1.w));
         uint4* ad = reinterpret_cast<uint4*>(As[buf] + lrow * LD + lseg);
         uint4* hd = reinterpret_cast<uint4*>(Bh[buf] + lrow * LD + lseg);
         uint4* ld = reinterpret_cast<uint4*>(Bl[buf] + lrow * LD + lseg);
-        ad[0] = a0;
-        ad[1] = a1;
-        hd[0] = make_uint4(h0.x & m0.x, h0.y & m0.y, h0.z & m0.z, h0.w & m0.w);
-        hd[1] = make_uint4(h1.x & m1.x, h1.y & m1.y, h1.z & m1.z, h1.w & m1.w);
-        ld[0] = make_uint4(l0.x & m0.x, l0.y & m0.y, l0.z & m0.z, l0.w & m0.w);
-        ld[1] = make_uint4(l1.x & m1.x, l1.y & m1.y, l1.z & m1.z, l1.w & m1.w);
+        ad[0] = R.a0;
+        ad[1] = R.a1;
+        hd[0] = make_uint4(R.h0.x & m0.x, R.h0.y & m0.y, R.h0.z & m0.z, R.h0.w & m0.w);
+        hd[1] = make_uint4(R.h1.x & m1.x, R.h1.y & m1.y, R.h1.z & m1.z, R.h1.w & m1.w);
+        ld[0] = make_uint4(R.l0.x & m0.x, R.l0.y & m0.y, R.l0.z & m0.z, R.l0.w & m0.w);
+        ld[1] = make_uint4(R.l1.x & m1.x, R.l1.y & m1.y, R.l1.z & m1.z, R.l1.w & m1.w);
     };
-
-    // one barrier per K step: the stage written in step t was last read in step
-    // t-2, which every wave finished before passing the barrier of step t-1
-    fetch(0);
-    int buf = 0;
-    for (int64_t k0 = 0; k0 < kpad; k0 += KT) {
-        stash(buf);
-        __syncthreads();
-        if (k0 + KT < kpad) fetch(k0 + KT);    // next stage in flight during the MFMAs
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < KT; kk += 16) {
             const int kq = kk + 8 * (lane >> 5);
@@ -504,7 +500,29 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
                     c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fl[y], c[x][y], 0, 0, 0);
                 }
         }
-        buf ^= 1;
+    };
+
+    // K step t: registers of step t (fetched two steps earlier) go to LDS stage
+    // t mod 2, the same registers are refilled with step t+2, then the MFMAs of
+    // step t run.  The stage written at step t was last read by the MFMAs of step
+    // t-2, which every wave finished before the barrier of step t-1.  kpad is a
+    // multiple of two steps, so both halves of the loop body always run; the
+    // fetches past the end re-read the last step (kept unconditional so that the
+    // compiler's wait counts stay exact) and are never stored.
+    const int64_t nk = kpad / KT;
+    const int64_t klast = kpad - KT;
+    Regs R0 = fetch(0);
+    __builtin_amdgcn_sched_barrier(0);  // issue step 0 before step 1 (in-order wait counts)
+    Regs R1 = fetch(KT);
+    for (int64_t t = 0; t < nk; t += 2) {
+        stash(R0, 0);
+        R0 = fetch(min((t + 2) * KT, klast));
+        __syncthreads();
+        compute(0);
+        stash(R1, 1);
+        R1 = fetch(min((t + 3) * KT, klast));
+        __syncthreads();
+        compute(1);
     }
 
     // epilogue: D[i][j] for 32x32 block: lane holds column lane%32 and rows
@@ -823,7 +841,7 @@ hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, 
                      int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
     const int64_t nblk = (n + kGramT - 1) / kGramT;
-    if (nblk > 65535 || (kpad % kGramK) != 0) return hipErrorInvalidValue;
+    if (nblk > 65535 || kpad <= 0 || (kpad % kGramKPad) != 0) return hipErrorInvalidValue;
     const int64_t ns = (nblk + kGramGroup - 1) / kGramGroup;
     const int64_t n_super = ns * (ns + 1) / 2;
     const int64_t blocks = (n_super + 7) / 8 * 8 * kGramGroup * kGramGroup;
