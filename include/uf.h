@@ -144,7 +144,9 @@ void uf_set_chunk_nodes(int64_t nodes);
  * fixed-point atomics than one pass of the variant's dense kernel over all
  * N x floor(N/2) stripe slots (rates measured on MI355X).  Process-wide; the
  * split of an embedding is built on first use and rebuilt when its variant's
- * threshold changes.  UF_ERR_ARG for fraction > 1 or NaN. */
+ * threshold changes.  The split takes at most 2^24 samples and fewer than
+ * 2^40 (sample, shared branch) memberships; beyond that the split
+ * precisions return UF_ERR_UNSUPPORTED.  UF_ERR_ARG for fraction > 1 or NaN. */
 uf_status uf_set_split_threshold(int weighted, double fraction);
 /* Size of the split of `emb` for one variant at its current threshold: dense
  * branches, shared non-dense branches, and sample pairs enumerated over them
@@ -159,8 +161,9 @@ uf_status uf_split_stats(const uf_embedding* emb, int weighted, int64_t* n_dense
  * PCoA centring terms defined above; either may be NULL.
  * ws/ws_bytes: device workspace of at least uf_workspace_size(..., 0,
  * floor(N/2), row_means || grand_mean) bytes.
- * Precisions: weighted {UF_FP64, UF_FP32}; unweighted {UF_FP64, UF_FP32,
- * UF_MFMA_BF16X2}.  Errors: UF_ERR_ARG, UF_ERR_UNSUPPORTED,
+ * Precisions: weighted {UF_FP64, UF_FP32, UF_FP32_SPLIT}; unweighted
+ * {UF_FP64, UF_FP32, UF_MFMA_BF16X2, UF_MFMA_SPLIT}.  Errors: UF_ERR_ARG,
+ * UF_ERR_UNSUPPORTED,
  * UF_ERR_WORKSPACE, UF_ERR_DEVICE. */
 uf_status uf_dm_unweighted(const uf_embedding* emb, uf_precision precision,
                            uf_out_dtype out_dtype, void* out_condensed,

@@ -283,11 +283,15 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->n_lists = int64_t(roff.size()) - 1;
     sc->n_entries = roff.back();
     sc->n_dense_pad = (sc->n_dense + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
+    // list entries carry a kBaseBits-bit start and a window length of up to N/2 in
+    // the other 24 bits; weighted members hold the sample in kSampleBits bits
+    if (n > (int64_t(1) << ufs::kSampleBits))
+        return fail(UF_ERR_UNSUPPORTED, "the sparse split takes at most 2^24 samples");
+    if (sc->n_entries >= (int64_t(1) << ufs::kBaseBits))
+        return fail(UF_ERR_UNSUPPORTED, "the sparse split takes fewer than 2^40 list entries");
     if (weighted) {
-        // packed members hold the sample in kSampleBits bits and the value in the
-        // other 40: choose the fixed-point step so that l * u <= max l stays below 2^40
-        if (n > (int64_t(1) << ufs::kSampleBits))
-            return fail(UF_ERR_UNSUPPORTED, "the weighted sparse split takes at most 2^24 samples");
+        // weighted members hold the value in the 40 bits above the sample: choose
+        // the fixed-point step so that l * u <= max l stays below 2^40
         std::vector<double> len(size_t(std::max<int64_t>(nb, 1)), 0.0);
         if (nb) UF_HIP(hipMemcpy(len.data(), e->len, size_t(nb) * 8, hipMemcpyDeviceToHost));
         double lmax = 0.0;
@@ -367,7 +371,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
         return fail_free(fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree"));
     if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
     if (rc == hipSuccess)
-        rc = ufs::sort_lists(sc->roff, sc->n_lists, rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur,
+        rc = ufs::sort_lists(sc->roff, sc->n_lists, n, rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur,
                              sc->entries, s);
     if (rc == hipSuccess)
         rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,

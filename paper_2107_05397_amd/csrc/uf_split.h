@@ -13,12 +13,16 @@ constexpr int32_t kClassDense = -1;    // branch in the dense set
 constexpr int32_t kClassAlone = -2;    // touched by at most one sample: no pairs
 constexpr int kSampleBits = 24;         // packed weighted list member: value << 24 | sample
 
+constexpr int kBaseBits = 40;           // SlotEntry::bw: list start in the low 40 bits
+
 // One list membership of a sample, as the slot kernel reads it: the list's first
-// entry and length, the sample's position in it, and its value (weighted: the
-// sample's own l*u in the split's fixed-point step; unweighted: the branch length
-// l_hi + l_lo in 2^-40).
+// entry (low kBaseBits bits of bw) and the window length w (high 24 bits: the
+// members at cyclic distance 1..floor(N/2) after the sample, which follow it in
+// the sorted list), the list length, the sample's position in it, and its value
+// (weighted: the sample's own l*u in the split's fixed-point step; unweighted:
+// the branch length l_hi + l_lo in 2^-40).
 struct SlotEntry {
-    int64_t base;
+    int64_t bw;
     int32_t m;
     int32_t p;
     unsigned long long v;
@@ -34,7 +38,8 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
 // rw_out as packed words rq << kSampleBits | sample; per-sample index rows
 // [soff[s], soff[s+1]) of SlotEntry filled through the cursors scur (zeroed by the
 // caller); v holds the sample's value (weighted) or the list id (unweighted).
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
+hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, const int32_t* rs_in,
+                      const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st);
 // Unweighted: replace each entry's list id (left in v by sort_lists) by rl[list].

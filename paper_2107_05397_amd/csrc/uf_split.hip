@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
 constexpr int kSortLds = 4096;
 
 __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
-                                             int32_t r, const int64_t* __restrict__ rq_in,
+                                             int32_t r, int32_t w, const int64_t* __restrict__ rq_in,
                                              int32_t* __restrict__ rs_out,
                                              unsigned long long* __restrict__ rw_out,
                                              const int64_t* __restrict__ soff,
@@ -97,14 +97,26 @@ __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k,
         rs_out[base + r] = smp;
     const int32_t slot = atomicAdd(&scur[smp], 1);
     SlotEntry ent;
-    ent.base = base;
+    ent.bw = int64_t((unsigned long long)base | ((unsigned long long)w << kBaseBits));
     ent.m = m;
     ent.p = r;
     ent.v = rw_out ? q : (unsigned long long)L;
     se[soff[smp] + slot] = ent;
 }
 
-__global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff,
+// Rank of sample smp in its list (members are distinct) and the size of its
+// window: members at cyclic distance 1..floor(N/2) after it.
+struct RankWin {
+    int32_t r = 0, w = 0;
+    __device__ __forceinline__ void add(int32_t other, int32_t smp, int64_t n) {
+        r += other < smp;
+        int64_t d = int64_t(other) - smp;
+        if (d < 0) d += n;
+        w += d >= 1 && d <= n / 2;
+    }
+};
+
+__global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff, int64_t n,
                                                     const int32_t* __restrict__ rs_in,
                                                     const int64_t* __restrict__ rq_in,
                                                     int32_t* __restrict__ rs_out,
@@ -121,16 +133,18 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
         __syncthreads();
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = ks[k];
-            int32_t r = 0;
-            for (int64_t t = 0; t < m; ++t) r += ks[t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, int32_t(m), se);
+            RankWin rw;
+            for (int64_t t = 0; t < m; ++t) rw.add(ks[t], smp, n);
+            place_member(L, base, k, smp, rw.r, rw.w, rq_in, rs_out, rw_out, soff, scur,
+                         int32_t(m), se);
         }
     } else {
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = rs_in[base + k];
-            int32_t r = 0;
-            for (int64_t t = 0; t < m; ++t) r += rs_in[base + t] < smp;
-            place_member(L, base, k, smp, r, rq_in, rs_out, rw_out, soff, scur, int32_t(m), se);
+            RankWin rw;
+            for (int64_t t = 0; t < m; ++t) rw.add(rs_in[base + t], smp, n);
+            place_member(L, base, k, smp, rw.r, rw.w, rq_in, rs_out, rw_out, soff, scur,
+                         int32_t(m), se);
         }
     }
 }
@@ -236,14 +250,20 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     // run below floor(N/2), so the window is d in [g0 + 1, min(g1, N/2)]
     const int64_t dlo = g0 + 1;
     const int64_t dhi = min(g1, n / 2);
-    for (int64_t k = soff[i] + wave; k < soff[i + 1]; k += kSlotWaves) {
-        const SlotEntry ent = entries[k];
-        const int64_t base = ent.base;
+    const int64_t k_end = soff[i + 1];
+    int64_t k = soff[i] + wave;
+    SlotEntry nxt{};
+    if (k < k_end) nxt = entries[k];
+    for (; k < k_end; k += kSlotWaves) {
+        const SlotEntry ent = nxt;
+        if (k + kSlotWaves < k_end) nxt = entries[k + kSlotWaves];  // in flight meanwhile
+        const int64_t base = ent.bw & ((int64_t(1) << kBaseBits) - 1);
+        const int64_t w = int64_t((unsigned long long)ent.bw >> kBaseBits);
         const int64_t m = ent.m;
         const int64_t p = ent.p;
         const unsigned long long vi = ent.v;
-        // the c-th member after i (c in [0, m-1)), cyclically, sits at position
-        // (p + 1 + c) mod m; its distance from i grows with c
+        // the c-th member after i, cyclically, sits at position (p + 1 + c) mod m;
+        // its distance from i grows with c, and members c < w lie within N/2
         auto pos_of = [&](int64_t c) {
             const int64_t q = p + 1 + c;
             return q >= m ? q - m : q;
@@ -256,14 +276,13 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
             const int64_t d = sample_at(q) - i;
             return d <= 0 ? d + n : d;
         };
-        // first c whose distance reaches dlo: 64-way search, one probe per lane
-        // (answer in [lo, hi]; hi = m - 1 stands for "none")
-        int64_t lo = 0, hi = m - 1;
-        if (dlo > 1) {
+        // first c in [lo, hi) whose distance reaches dt, else hi: 64-way search,
+        // one probe per lane
+        auto first_reaching = [&](int64_t dt, int64_t lo, int64_t hi) {
             while (lo < hi) {
                 const int64_t step = (hi - lo + 63) / 64;
                 const int64_t c = lo + int64_t(lane) * step;
-                const bool pred = c < hi && dist_of(pos_of(c)) >= dlo;
+                const bool pred = c < hi && dist_of(pos_of(c)) >= dt;
                 const unsigned long long ball = __ballot(pred);
                 if (ball) {
                     const int64_t f = __ffsll((long long)ball) - 1;
@@ -277,23 +296,37 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
                     lo = lo + ((hi - 1 - lo) / step) * step + 1;
                 }
             }
-        }
-        for (int64_t c = lo + lane; c < m - 1; c += 64) {
-            const int64_t q = pos_of(c);
-            unsigned long long v = vi;
-            int64_t j;
-            if constexpr (W) {
-                const unsigned long long word = rw[base + q];
-                j = int64_t(word & kMask);
-                const unsigned long long vj = word >> kSampleBits;
-                v = vj < vi ? vj : vi;
-            } else {
-                j = rs[base + q];
+            return hi;
+        };
+        const int64_t c_lo = dlo > 1 ? first_reaching(dlo, 0, w) : 0;
+        const int64_t c_hi = dhi < n / 2 ? first_reaching(dhi + 1, c_lo, w) : w;
+        // members c in [c_lo, c_hi) all fall in this segment: four loads in
+        // flight per lane, then their LDS adds
+        constexpr int U = 4;
+        for (int64_t c0 = c_lo + lane; c0 < c_hi; c0 += 64 * U) {
+            unsigned long long word[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t c = c0 + 64 * u;
+                word[u] = 0;
+                if (c < c_hi) {
+                    if constexpr (W) word[u] = rw[base + pos_of(c)];
+                    else word[u] = (unsigned long long)(unsigned)rs[base + pos_of(c)];
+                }
             }
-            int64_t d = j - i;
-            if (d <= 0) d += n;
-            if (d > dhi) break;
-            atomicAdd(&acc[d - 1 - g0], v);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (c0 + 64 * u >= c_hi) continue;
+                const int64_t j = int64_t(word[u] & kMask);
+                unsigned long long v = vi;
+                if constexpr (W) {
+                    const unsigned long long vj = word[u] >> kSampleBits;
+                    v = vj < vi ? vj : vi;
+                }
+                int64_t d = j - i;
+                if (d <= 0) d += n;
+                atomicAdd(&acc[d - 1 - g0], v);
+            }
         }
     }
     __syncthreads();
@@ -317,12 +350,13 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
     return hipGetLastError();
 }
 
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, const int32_t* rs_in, const int64_t* rq_in,
+hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, const int32_t* rs_in,
+                      const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st) {
     if (n_lists <= 0) return hipSuccess;
     if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, rs_in, rq_in,
+    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, n, rs_in, rq_in,
                        rs_out, rw_out, soff, scur, se);
     return hipGetLastError();
 }
