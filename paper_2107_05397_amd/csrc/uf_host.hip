@@ -31,10 +31,13 @@ std::atomic<double> g_split_threshold[2] = {{-1.0}, {-1.0}};
 // Measured MI355X rates of the split's two halves (pair updates per second,
 // chunk embedding included, C2-sized inputs): the weighted dense stripe pass
 // (32-bit fixed point; FP32 is within 10%), the BF16x2 MFMA Gram, and the
-// marginal rate of the slot kernel over the pairs that share a non-dense branch.
+// marginal rates of the slot kernel over the pairs that share a non-dense branch
+// (fitted to the optimum of a threshold sweep: near the threshold the lists are
+// long and the walk keeps its lanes full).
 constexpr double kRateBandDense = 2.9e13;
-constexpr double kRateGramMfma = 1.55e14;
-constexpr double kRatePairs = 3.5e11;
+constexpr double kRateGramMfma = 2.2e14;
+constexpr double kRatePairsWeighted = 7.9e11;
+constexpr double kRatePairsUnweighted = 9.0e11;
 
 uf_status fail(uf_status st, const std::string& msg) {
     g_last_error = msg;
@@ -226,7 +229,7 @@ double fixed_point_scale(const std::vector<double>& sw, const std::vector<unsign
 // A branch touched by c samples costs c(c-1)/2 pair atomics when left out of the
 // dense set, and one pass over all N*floor(N/2) stripe slots of the dense kernel
 // when put in it.  With a fixed threshold f it is dense when c > f*N; with the
-// automatic one when c(c-1)/2 / kRatePairs > N*floor(N/2) / rate of the
+// automatic one when c(c-1)/2 / (slot rate) > N*floor(N/2) / rate of the
 // variant's dense kernel, i.e. when it is cheaper in the dense kernel.
 uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     uf_embedding* e = const_cast<uf_embedding*>(ce);   // the cache is internal state
@@ -265,8 +268,9 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     std::vector<int32_t> cls(size_t(std::max<int64_t>(nb, 1)), ufs::kClassAlone), dense;
     std::vector<int64_t> roff(1, 0);
     const double lim = thr * double(n);
-    const double pair_lim = 2.0 * double(n) * double(n / 2) * kRatePairs /
-                            (weighted ? kRateBandDense : kRateGramMfma);
+    const double pair_lim = 2.0 * double(n) * double(n / 2) *
+                            (weighted ? kRatePairsWeighted / kRateBandDense
+                                      : kRatePairsUnweighted / kRateGramMfma);
     for (int64_t v = 0; v < nb; ++v) {
         const int64_t c = cnt[size_t(v)];
         const bool is_dense = thr >= 0.0 ? double(c) > lim : double(c) * double(c - 1) > pair_lim;
