@@ -319,6 +319,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     const size_t o_rl = c.take(nl * 8);
     const size_t o_soff = c.take(size_t(n + 1) * 8);
     const size_t o_ent = c.take(ne * sizeof(ufs::SlotEntry));
+    const size_t o_lord = weighted ? c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4) : 0;
     if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
     char* b = static_cast<char*>(sc->arena);
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
@@ -332,6 +333,7 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->rl = reinterpret_cast<int64_t*>(b + o_rl);
     sc->soff = reinterpret_cast<int64_t*>(b + o_soff);
     sc->entries = reinterpret_cast<ufs::SlotEntry*>(b + o_ent);
+    sc->lo_ord = weighted ? reinterpret_cast<int32_t*>(b + o_lord) : nullptr;
     auto fail_free = [&](uf_status code) {
         (void)hipFree(sc->arena);
         sc->arena = nullptr;
@@ -347,6 +349,18 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
         return fail_free(fail(UF_ERR_NOMEM, "split temporaries"));
     hipError_t rc = hipSuccess;
     if (sc->n_dense) rc = hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice);
+    if (rc == hipSuccess && weighted && sc->n_dense) {
+        // the dense list in ascending lo, for the merge embedding of the dense chunks
+        std::vector<int32_t> lo(size_t(nb + 1));
+        rc = hipMemcpy(lo.data(), e->lo, size_t(nb + 1) * 4, hipMemcpyDeviceToHost);
+        std::vector<int32_t> ord(size_t(sc->n_dense));
+        for (int64_t k = 0; k < sc->n_dense; ++k) ord[size_t(k)] = int32_t(k);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+            return lo[size_t(dense[size_t(x)])] < lo[size_t(dense[size_t(y)])];
+        });
+        if (rc == hipSuccess)
+            rc = hipMemcpy(sc->lo_ord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice);
+    }
     if (rc == hipSuccess && nb) rc = hipMemcpy(sc->cls, cls.data(), size_t(nb) * 4, hipMemcpyHostToDevice);
     if (rc == hipSuccess) rc = hipMemcpy(sc->roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice);
     if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, nl * 4, s);
@@ -513,7 +527,9 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
             uint32_t* E = static_cast<uint32_t*>(chunk);
             {
                 ProfScope ps("embed_nm", s);
-                UF_HIP(ufs::embed_list_u32(emb_view(*e), sp->dense, k0, kc, sp->q_scale, E, s));
+                UF_HIP(ufs::embed_list_u32(emb_view(*e), sp->dense, sp->lo_ord, sp->n_dense,
+                                           e->max_total < (int64_t(1) << 32), k0, kc,
+                                           sp->q_scale, E, s));
             }
             ProfScope ps("band_wn_u32", s);
             UF_HIP(ufk::band_u32(E, kc, p.n, p.sb, p.se, first, static_cast<uint32_t*>(acc), s));
@@ -521,7 +537,8 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
             float* E = static_cast<float*>(chunk);
             {
                 ProfScope ps("embed_nm", s);
-                UF_HIP(ufs::embed_list_f32(emb_view(*e), sp->dense, k0, kc, E, s));
+                UF_HIP(ufs::embed_list_f32(emb_view(*e), sp->dense, sp->lo_ord, sp->n_dense,
+                                           e->max_total < (int64_t(1) << 32), k0, kc, E, s));
             }
             ProfScope ps("band_wn_f32", s);
             UF_HIP(ufk::band_f32(E, nullptr, kc, p.n, p.sb, p.se, 1, first,
@@ -897,6 +914,7 @@ uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embe
         e->n = n;
         e->nb = nb;
         e->nnz = nnz;
+        for (int64_t r = 0; r < n; ++r) e->max_total = std::max<int64_t>(e->max_total, tb->total[r]);
         char* b = static_cast<char*>(arena);
         e->row_ptr = reinterpret_cast<int64_t*>(b + o_rowptr);
         e->rank = reinterpret_cast<int32_t*>(b + o_rank);

@@ -68,6 +68,7 @@ struct SplitCache {
     int64_t* soff = nullptr;      // [n+1] per-sample rows of `entries`
     ufs::SlotEntry* entries = nullptr;   // [n_entries] the sample's list memberships
     double q_scale = 0.0;         // weighted: 32-bit fixed-point scale of the dense pass (0: FP32)
+    int32_t* lo_ord = nullptr;    // weighted: [n_dense] indices into dense, by ascending lo
 };
 
 // Device-resident inputs of the distance calls.  All arrays are on `device`.
@@ -76,6 +77,7 @@ struct uf_embedding {
     int64_t n = 0;          // samples
     int64_t nb = 0;         // branches (non-root nodes) = positions [0, nb)
     int64_t nnz = 0;
+    int64_t max_total = 0;  // largest sample total T_s (host copy)
     // table
     int64_t* row_ptr = nullptr;   // [n+1]
     int32_t* rank = nullptr;      // [nnz]

@@ -3,7 +3,7 @@
 //
 //   k_sample_scalars   per-sample FP64 scalars from the postorder leaf intervals
 //   k_embed_nm<T>      node-major chunk of the embedding (weighted or 0/1)
-//   k_embed_pres_bf16  sample-major BF16 0/1 presence for the MFMA Gram path
+//   k_embed_pres_bf16  sample-major BF16 0/1 presence for the MFMA Gram path (merge)
 //   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled);
 //                      T = uint32_t: weighted, 32-bit fixed point, one v_sad_u32
 //                      (|a - b| + acc) per update
@@ -149,20 +149,70 @@ __global__ __launch_bounds__(256) void k_embed_nm(
 }
 
 // Sample-major BF16 presence: out[s][k], k in [0, kpad); 0x3F80 = 1.0, zero past kc.
+// Sample-major BF16 presence by a forward merge.  Postorder positions have
+// non-decreasing hi, so along a list of ascending positions a cursor over the
+// sample's tips (sorted by rank) only moves forward: it stops at the first tip
+// with rank >= hi, and the branch is touched iff the last tip before it has rank
+// >= lo.  Thread = sample; block = 256 samples x 64 list entries, transposed
+// through LDS into 128-byte row writes.  Entries in [kc, kpad) are zero.
+constexpr int kPresSamples = 256, kPresQ = 64;
 __global__ __launch_bounds__(256) void k_embed_pres_bf16(
     int64_t n, int64_t k0, int64_t kc, int64_t kpad, const int64_t* __restrict__ row_ptr,
-    const int32_t* __restrict__ rank, const int64_t* __restrict__ cum,
-    const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ rank, const int32_t* __restrict__ lo,
+    const int32_t* __restrict__ hi, const int32_t* __restrict__ list,
     uint16_t* __restrict__ out) {
-    const int64_t s = blockIdx.y;
-    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (k >= kpad) return;
-    uint16_t v = 0;
-    if (k < kc) {
-        const int64_t pos = list ? int64_t(list[k0 + k]) : k0 + k;
-        v = embedded_count(row_ptr, rank, cum, s, lo[pos], hi[pos]) > 0 ? uint16_t(0x3F80) : 0;
+    // rows of 64 + 8 BF16 (144 bytes: 16-byte aligned, rows spread over banks)
+    __shared__ __attribute__((aligned(16))) uint16_t tile[kPresSamples][kPresQ + 8];
+    __shared__ int32_t qlo[kPresQ], qhi[kPresQ];
+    const int tid = threadIdx.x;
+    const int64_t sb = int64_t(blockIdx.x) * kPresSamples;
+    const int64_t s = sb + tid;
+    const int64_t nseg = kpad / kPresQ;
+    for (int64_t g = blockIdx.y; g < nseg; g += gridDim.y) {
+        const int64_t q0 = g * kPresQ;
+        const int nq = kc - q0 <= 0 ? 0 : (kc - q0 < kPresQ ? int(kc - q0) : kPresQ);
+        if (tid < nq) {
+            const int64_t pos = list ? int64_t(list[k0 + q0 + tid]) : k0 + q0 + tid;
+            qlo[tid] = lo[pos];
+            qhi[tid] = hi[pos];
+        }
+        __syncthreads();
+        if (s < n) {
+            const int64_t a = row_ptr[s], b = row_ptr[s + 1];
+            int64_t cur = a;
+            int32_t last = -1;
+            if (nq > 0) {
+                cur = lower_bound_rank(rank, a, b, qhi[0]);
+                if (cur > a) last = rank[cur - 1];
+            }
+            for (int q8 = 0; q8 < kPresQ; q8 += 8) {
+                unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q8 + u;
+                    if (q < nq) {
+                        const int32_t h = qhi[q];
+                        while (cur < b) {
+                            const int32_t r = rank[cur];
+                            if (r >= h) break;
+                            last = r;
+                            ++cur;
+                        }
+                        if (last >= qlo[q]) w[u >> 1] |= 0x3F80u << (16 * (u & 1));
+                    }
+                }
+                *reinterpret_cast<uint4*>(&tile[tid][q8]) = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < kPresSamples * (kPresQ / 8); c += 256) {
+            const int row = c / (kPresQ / 8), part = c % (kPresQ / 8);
+            if (sb + row < n)
+                *reinterpret_cast<uint4*>(out + (sb + row) * kpad + q0 + part * 8) =
+                    *reinterpret_cast<const uint4*>(&tile[row][part * 8]);
+        }
+        __syncthreads();
     }
-    out[s * kpad + k] = v;
 }
 
 // ----------------------------------------------------------------------------
@@ -778,22 +828,12 @@ hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, i
 hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
                                uint16_t* out, hipStream_t st, const int32_t* list) {
     if (kpad <= 0 || e.n <= 0) return hipSuccess;
-    if (e.n > 65535) {
-        // one launch per 65535 samples keeps grid.y in range
-        for (int64_t s0 = 0; s0 < e.n; s0 += 65535) {
-            const int64_t ns = std::min<int64_t>(65535, e.n - s0);
-            dim3 grid(unsigned((kpad + 255) / 256), unsigned(ns));
-            hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, ns, k0, kc, kpad,
-                               e.row_ptr + s0, e.rank, e.cum + s0, e.lo, e.hi, list,
-                               out + s0 * kpad);
-            hipError_t err = hipGetLastError();
-            if (err != hipSuccess) return err;
-        }
-        return hipSuccess;
-    }
-    dim3 grid(unsigned((kpad + 255) / 256), unsigned(e.n));
-    hipLaunchKernelGGL(k_embed_pres_bf16, grid, dim3(256), 0, st, e.n, k0, kc, kpad, e.row_ptr,
-                       e.rank, e.cum, e.lo, e.hi, list, out);
+    if (kpad % kPresQ != 0) return hipErrorInvalidValue;
+    const int64_t gx = (e.n + kPresSamples - 1) / kPresSamples;
+    const int64_t gy = std::min<int64_t>(kpad / kPresQ, 65535);
+    if (gx > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_embed_pres_bf16, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, st, e.n,
+                       k0, kc, kpad, e.row_ptr, e.rank, e.lo, e.hi, list, out);
     return hipGetLastError();
 }
 

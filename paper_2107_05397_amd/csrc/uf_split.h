@@ -45,10 +45,14 @@ hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, const int
 // Unweighted: replace each entry's list id (left in v by sort_lists) by rl[list].
 hipError_t entry_lengths(SlotEntry* se, int64_t n_entries, const int64_t* rl, hipStream_t st);
 // Node-major chunk E[k][s] over positions list[k0 .. k0+kc): x = l * c / T as FP32,
-// or as rint(x * q) in 32-bit fixed point.
-hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, float* out,
+// or as rint(x * q) in 32-bit fixed point.  merge (every T_s < 2^32) with lo_ord
+// (the n_list entries of list ordered by lo): two forward-merge passes; else one
+// binary search per element.  Same values either way.
+hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
+                          int64_t n_list, bool merge, int64_t k0, int64_t kc, float* out,
                           hipStream_t st);
-hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, double q,
+hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
+                          int64_t n_list, bool merge, int64_t k0, int64_t kc, double q,
                           uint32_t* out, hipStream_t st);
 // Per-list (hi+lo) branch length in fixed point, and the bf16 length parts of the
 // dense set gathered in order (zero beyond n_dense up to n_pad).

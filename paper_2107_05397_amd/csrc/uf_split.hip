@@ -188,6 +188,91 @@ __global__ __launch_bounds__(256) void k_embed_list(ufp::Emb e, const int32_t* _
     }
 }
 
+// The same chunk by a forward merge, in two passes over the list (thread =
+// sample; block = 256 samples x a run of kMergeQ list entries, whose positions
+// and bounds are staged in LDS first; k in [k0, k0+kc)).
+// Pass lo: visiting the entries in increasing lo (lo_ord: indices into list),
+// the cursor over the sample's tips only moves forward; out[k - k0][s] takes the
+// low 32 bits of the sample's count prefix below lo_k.  Pass hi: along the list
+// (ascending positions, so non-decreasing hi) the prefix below hi_k minus that
+// value is the count on branch k; it needs T_s < 2^32, so the 32-bit difference
+// is exact.  Both passes give the values of k_embed_list bit for bit.  The
+// prefix is re-read only in lanes whose cursor moved.
+constexpr int kMergeQ = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ lo_ord,
+                                                       int64_t n_list, int64_t k0, int64_t kc,
+                                                       T* __restrict__ out) {
+    __shared__ int32_t qk[kMergeQ], ql[kMergeQ];
+    const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    uint32_t* o = reinterpret_cast<uint32_t*>(out);
+    const int64_t nseg = (n_list + kMergeQ - 1) / kMergeQ;
+    for (int64_t g = blockIdx.y; g < nseg; g += gridDim.y) {
+        const int64_t t0 = g * kMergeQ;
+        const int nq = n_list - t0 < kMergeQ ? int(n_list - t0) : kMergeQ;
+        __syncthreads();
+        if (threadIdx.x < nq) {
+            const int32_t k = lo_ord[t0 + threadIdx.x];
+            qk[threadIdx.x] = k;
+            ql[threadIdx.x] = e.lo[list[k]];
+        }
+        __syncthreads();
+        if (s >= e.n) continue;
+        const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
+        int64_t cur = ufd::lower_bound_rank(e.rank, a, b, ql[0]);
+        uint32_t below = uint32_t(e.cum[cur + s]);
+        for (int t = 0; t < nq; ++t) {
+            const int32_t l = ql[t];
+            const int64_t from = cur;
+            while (cur < b && e.rank[cur] < l) ++cur;
+            if (cur != from) below = uint32_t(e.cum[cur + s]);
+            const int64_t k = qk[t];
+            if (k >= k0 && k < k0 + kc) o[(k - k0) * e.n + s] = below;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_embed_list_hi(ufp::Emb e, const int32_t* __restrict__ list,
+                                                       int64_t k0, int64_t kc, double q,
+                                                       T* __restrict__ out) {
+    __shared__ int32_t qh[kMergeQ];
+    __shared__ double qlen[kMergeQ];
+    const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t nseg = (kc + kMergeQ - 1) / kMergeQ;
+    const double tot = s < e.n ? e.total[s] : 1.0;
+    for (int64_t g = blockIdx.y; g < nseg; g += gridDim.y) {
+        const int64_t t0 = k0 + g * kMergeQ;
+        const int nq = k0 + kc - t0 < kMergeQ ? int(k0 + kc - t0) : kMergeQ;
+        __syncthreads();
+        if (threadIdx.x < nq) {
+            const int32_t pos = list[t0 + threadIdx.x];
+            qh[threadIdx.x] = e.hi[pos];
+            qlen[threadIdx.x] = e.len[pos];
+        }
+        __syncthreads();
+        if (s >= e.n) continue;
+        const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
+        int64_t cur = ufd::lower_bound_rank(e.rank, a, b, qh[0]);
+        uint32_t below = uint32_t(e.cum[cur + s]);
+        for (int t = 0; t < nq; ++t) {
+            const int32_t h = qh[t];
+            const int64_t from = cur;
+            while (cur < b && e.rank[cur] < h) ++cur;
+            if (cur != from) below = uint32_t(e.cum[cur + s]);
+            const size_t idx = size_t(t0 + t - k0) * size_t(e.n) + size_t(s);
+            const int64_t c = int64_t(below - reinterpret_cast<const uint32_t*>(out)[idx]);
+            const double x = qlen[t] * (double(c) / tot);
+            T v;
+            if constexpr (std::is_same<T, uint32_t>::value) v = uint32_t(llrint(x * q));
+            else v = T(x);
+            out[idx] = v;
+        }
+    }
+}
+
 __device__ __forceinline__ uint32_t bf16_to_bits32(uint16_t h) { return uint32_t(h) << 16; }
 
 __global__ __launch_bounds__(256) void k_split_lengths(const int32_t* __restrict__ cls, int64_t nb,
@@ -369,9 +454,23 @@ hipError_t entry_lengths(SlotEntry* se, int64_t n_entries, const int64_t* rl, hi
 }
 
 template <typename T>
-static hipError_t embed_list(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc,
-                             double q, T* out, hipStream_t st) {
+static hipError_t embed_list(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
+                             int64_t n_list, bool merge, int64_t k0, int64_t kc, double q, T* out,
+                             hipStream_t st) {
     if (kc <= 0 || e.n <= 0) return hipSuccess;
+    if (merge && lo_ord && n_list >= k0 + kc) {
+        const int64_t gx = (e.n + 255) / 256;
+        const int64_t gy_lo = std::min<int64_t>((n_list + kMergeQ - 1) / kMergeQ, 65535);
+        const int64_t gy_hi = std::min<int64_t>((kc + kMergeQ - 1) / kMergeQ, 65535);
+        if (gx > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_embed_list_lo<T>, dim3(unsigned(gx), unsigned(gy_lo)), dim3(256), 0, st,
+                           e, list, lo_ord, n_list, k0, kc, out);
+        hipError_t rc = hipGetLastError();
+        if (rc != hipSuccess) return rc;
+        hipLaunchKernelGGL(k_embed_list_hi<T>, dim3(unsigned(gx), unsigned(gy_hi)), dim3(256), 0, st,
+                           e, list, k0, kc, q, out);
+        return hipGetLastError();
+    }
     const int64_t gy = (e.n + 63) / 64;
     if (gy > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_embed_list<T>, dim3(unsigned((kc + 255) / 256), unsigned(gy)), dim3(256), 0,
@@ -379,14 +478,16 @@ static hipError_t embed_list(const ufp::Emb& e, const int32_t* list, int64_t k0,
     return hipGetLastError();
 }
 
-hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, float* out,
+hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
+                          int64_t n_list, bool merge, int64_t k0, int64_t kc, float* out,
                           hipStream_t st) {
-    return embed_list<float>(e, list, k0, kc, 1.0, out, st);
+    return embed_list<float>(e, list, lo_ord, n_list, merge, k0, kc, 1.0, out, st);
 }
 
-hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, int64_t k0, int64_t kc, double q,
+hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
+                          int64_t n_list, bool merge, int64_t k0, int64_t kc, double q,
                           uint32_t* out, hipStream_t st) {
-    return embed_list<uint32_t>(e, list, k0, kc, q, out, st);
+    return embed_list<uint32_t>(e, list, lo_ord, n_list, merge, k0, kc, q, out, st);
 }
 
 hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,

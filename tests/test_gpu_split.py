@@ -85,6 +85,49 @@ def test_split_stripes_merge_bitwise_and_repeat(variant, threshold):
         assert torch.max(torch.abs(full - buf)).item() < 1e-5
 
 
+def _fp32_forcing(tree, table):
+    """Sample 0 reduced to one tip whose root path has lengths 1e-12: the
+    fixed-point bound of the weighted dense pass fails, so it runs in FP32."""
+    t = int(table.tips[table.indptr[0]])
+    v = t
+    while tree.parent[v] >= 0:
+        tree.length[v] = 1e-12
+        v = int(tree.parent[v])
+    table.tips = np.concatenate([[t], table.tips[table.indptr[1]:]])
+    table.counts = np.concatenate([[5], table.counts[table.indptr[1]:]])
+    table.indptr = np.concatenate([[0], table.indptr[1:] - table.indptr[1] + 1])
+
+
+@pytest.mark.parametrize("dense_kind", ["band_wn_u32", "band_wn_f32"])
+def test_merge_and_search_embeddings_agree_bitwise(dense_kind, threshold):
+    """The dense chunk of the weighted split is embedded by a forward merge when
+    every sample total is below 2^32, else by one binary search per element.
+    Multiplying every count by 2^32 keeps each relative abundance c/T bit for bit,
+    so the two paths must give the same matrix bit for bit, for the fixed-point
+    and the FP32 dense pass, and the oracle's within the FP32 tolerance."""
+    import torch
+    import paper_2107_05397_amd as uf
+    threshold(0.2, "weighted_normalized")
+    tree = synth.gen_tree(500, 0.1, seed=31)
+    table = synth.gen_table_zipf(300, np.arange(500), 60, seed=32)
+    if dense_kind == "band_wn_f32":
+        _fp32_forcing(tree, table)
+    big = synth.Table(indptr=table.indptr.copy(), tips=table.tips.copy(),
+                      counts=table.counts.astype(np.int64) * (1 << 32))
+    got = []
+    for tb in (table, big):
+        emb = _emb(tree, tb)
+        assert uf.split_stats(emb, "weighted_normalized")[0] > 0
+        d, used = _dense_kernel_used(uf, emb)
+        torch.cuda.synchronize()
+        assert used == {dense_kind}
+        got.append(d.cpu().numpy())
+    assert np.array_equal(got[0], got[1])
+    err = np.abs(got[0] - core.dm(tree, table, "weighted_normalized")[0]).max()
+    print(f"[merge vs search embedding, {dense_kind}] max|err|={err:.3e}")
+    assert err <= 1e-4
+
+
 def test_mfma_split_exact_with_integer_lengths(threshold):
     """Integer lengths < 256 are exact in bf16 and their FP32 Gram sums stay below
     2^24, so the dense MFMA part is exact too: the split equals the oracle."""
@@ -189,15 +232,7 @@ def test_weighted_dense_pass_falls_back_to_fp32(threshold):
     threshold(0.1, "weighted_normalized")
     tree = synth.gen_tree(600, 0.1, seed=33)
     table = synth.gen_table_zipf(200, np.arange(600), 60, seed=34)
-    # sample 0: one tip whose root path has lengths 1e-12
-    t = int(table.tips[table.indptr[0]])
-    v = t
-    while tree.parent[v] >= 0:
-        tree.length[v] = 1e-12
-        v = int(tree.parent[v])
-    table.tips = np.concatenate([[t], table.tips[table.indptr[1]:]])
-    table.counts = np.concatenate([[5], table.counts[table.indptr[1]:]])
-    table.indptr = np.concatenate([[0], table.indptr[1:] - table.indptr[1] + 1])
+    _fp32_forcing(tree, table)
     emb = _emb(tree, table)
     d, used = _dense_kernel_used(uf, emb)
     torch.cuda.synchronize()
