@@ -609,6 +609,47 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
 // With the sparse-aware split (split_m != NULL) the weighted numerator adds the
 // exact fixed-point part sigma_i + sigma_j - 2 M_ij (2^-40 units) of the branches
 // outside the dense set.
+//
+// A block takes tiles of 64 stripes x 64 samples.  Distances are computed with
+// lanes along samples (coalesced accumulator reads and stripe-major writes);
+// for the condensed layout the tile goes through LDS and out in two sweeps:
+// pairs (i, i+s+1) with i+s+1 < n sit in condensed row i at column offset s, so
+// a run over s is contiguous; wrapped pairs (i+s+1-n, i) sit in row i+s+1-n, so
+// a run over i along an anti-diagonal (i+s fixed) is contiguous.  Lane l of
+// group g takes diagonal g or g+64 of the tile, so every lane has an element
+// and a 64-lane store covers at most two runs.
+constexpr int kFinT = 64;
+
+template <typename A>
+__device__ __forceinline__ double final_distance(int kind, const A* __restrict__ acc,
+                                                 double acc_scale, const double* __restrict__ scal,
+                                                 int64_t n, int64_t sb, int64_t s, int64_t i,
+                                                 int64_t j,
+                                                 const unsigned long long* __restrict__ split_m,
+                                                 const unsigned long long* __restrict__ sigma,
+                                                 double split_unit) {
+    double num = double(acc[(s - sb) * n + i]) * acc_scale;
+    if (split_m) {
+        if (kind == 0) {
+            const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
+            num += double(r) * split_unit;
+        } else {
+            num += double(split_m[(s - sb) * n + i]) * split_unit;
+        }
+    }
+    double d;
+    if (kind == 0) {
+        const double den = scal[i] + scal[j];
+        d = den > 0.0 ? num / den : 0.0;
+    } else {
+        const double sum = scal[i] + scal[j];
+        const double orr = sum - num;
+        const double xr = sum - 2.0 * num;
+        d = orr > 0.0 ? xr / orr : 0.0;
+    }
+    return fmin(fmax(d, 0.0), 1.0);
+}
+
 template <typename A>
 __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict__ acc,
                                                   double acc_scale,
@@ -618,42 +659,49 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
                                                   const unsigned long long* __restrict__ split_m,
                                                   const unsigned long long* __restrict__ sigma,
                                                   double split_unit) {
-    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n) return;
+    // row pitch 66 doubles: the run over s (step 66) has 4-way and the
+    // anti-diagonal run (step -65) no LDS bank conflicts
+    __shared__ double tile[kFinT][kFinT + 2];
+    const int tid = threadIdx.x;
+    const int64_t i0 = int64_t(blockIdx.x) * kFinT;
     const bool even = (n & 1) == 0;
-    for (int64_t s = sb + blockIdx.y; s < se; s += gridDim.y) {
-        const int64_t j = (i + s + 1) % n;
-        double num = double(acc[(s - sb) * n + i]) * acc_scale;
-        if (split_m) {
-            if (kind == 0) {
-                const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
-                num += double(r) * split_unit;
-            } else {
-                num += double(split_m[(s - sb) * n + i]) * split_unit;
-            }
-        }
-        double d;
-        if (kind == 0) {
-            const double den = scal[i] + scal[j];
-            d = den > 0.0 ? num / den : 0.0;
-        } else {
-            const double sum = scal[i] + scal[j];
-            const double orr = sum - num;
-            const double xr = sum - 2.0 * num;
-            d = orr > 0.0 ? xr / orr : 0.0;
-        }
-        d = fmin(fmax(d, 0.0), 1.0);
-        if (q) q[(s - sb) * n + i] = -0.5 * d * d;
-        int64_t idx;
-        if (layout == UF_STRIPES) {
-            idx = (s - sb) * n + i;
-        } else {
-            if (even && s == n / 2 - 1 && i >= n / 2) continue;
-            const int64_t a = i < j ? i : j, b = i < j ? j : i;
-            idx = a * n - a * (a + 1) / 2 + (b - a - 1);
-        }
+    const bool condensed = layout != UF_STRIPES;
+    const int64_t n_tiles = (se - sb + kFinT - 1) / kFinT;
+    auto put = [&](int64_t idx, double d) {
         if (out_f32) static_cast<float*>(out)[idx] = float(d);
         else static_cast<double*>(out)[idx] = d;
+    };
+    for (int64_t t = blockIdx.y; t < n_tiles; t += gridDim.y) {
+        const int64_t s0 = sb + t * kFinT;
+        for (int ls = tid >> 6; ls < kFinT; ls += 4) {
+            const int li = tid & 63;
+            const int64_t s = s0 + ls, i = i0 + li;
+            if (s >= se || i >= n) continue;
+            const int64_t j = (i + s + 1) % n;
+            const double d = final_distance(kind, acc, acc_scale, scal, n, sb, s, i, j, split_m,
+                                            sigma, split_unit);
+            if (q) q[(s - sb) * n + i] = -0.5 * d * d;
+            if (condensed) tile[ls][li] = d;
+            else put((s - sb) * n + i, d);
+        }
+        if (!condensed) continue;
+        __syncthreads();
+        for (int e = tid; e < kFinT * kFinT; e += 256) {
+            const int li = e / kFinT, ls = e % kFinT;
+            const int64_t s = s0 + ls, i = i0 + li;
+            if (s >= se || i >= n || i + s + 1 >= n) continue;
+            put(i * n - i * (i + 1) / 2 + s, tile[ls][li]);
+        }
+        for (int e = tid; e < kFinT * kFinT; e += 256) {
+            const int g = e / kFinT, li = e % kFinT;
+            const int ls = (g - li) & (kFinT - 1);
+            const int64_t s = s0 + ls, i = i0 + li;
+            if (s >= se || i >= n || i + s + 1 < n) continue;
+            if (even && s == n / 2 - 1 && i >= n / 2) continue;   // the pair's other copy
+            const int64_t jw = i + s + 1 - n;
+            put(jw * n - jw * (jw + 1) / 2 + (i - jw - 1), tile[ls][li]);
+        }
+        __syncthreads();
     }
 }
 
@@ -897,7 +945,9 @@ hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, c
                     hipStream_t st, const unsigned long long* split_m,
                     const unsigned long long* sigma, double split_unit) {
     if (se <= sb || n <= 0) return hipSuccess;
-    dim3 grid(unsigned((n + 255) / 256), grid_y(se - sb));
+    const int64_t gx = (n + kFinT - 1) / kFinT;
+    if (gx > 0x7fffffff) return hipErrorInvalidValue;
+    dim3 grid(unsigned(gx), grid_y((se - sb + kFinT - 1) / kFinT));
     if (acc_type == kAccF64)
         hipLaunchKernelGGL(k_finalize<double>, grid, dim3(256), 0, st, kind,
                            static_cast<const double*>(acc), acc_scale, scal, n, sb, se, layout,
