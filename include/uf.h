@@ -144,7 +144,7 @@ void uf_set_chunk_nodes(int64_t nodes);
  * fixed-point atomics than one pass of the variant's dense kernel over all
  * N x floor(N/2) stripe slots (rates measured on MI355X).  Process-wide; the
  * split of an embedding is built on first use and rebuilt when its variant's
- * threshold changes.  The split takes at most 2^24 samples and fewer than
+ * threshold changes.  The split takes fewer than 2^24 samples and fewer than
  * 2^40 (sample, shared branch) memberships; beyond that the split
  * precisions return UF_ERR_UNSUPPORTED.  UF_ERR_ARG for fraction > 1 or NaN. */
 uf_status uf_set_split_threshold(int weighted, double fraction);

@@ -288,9 +288,10 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->n_entries = roff.back();
     sc->n_dense_pad = (sc->n_dense + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
     // list entries carry a kBaseBits-bit start and a window length of up to N/2 in
-    // the other 24 bits; weighted members hold the sample in kSampleBits bits
-    if (n > (int64_t(1) << ufs::kSampleBits))
-        return fail(UF_ERR_UNSUPPORTED, "the sparse split takes at most 2^24 samples");
+    // the other 24 bits, and list lengths and positions in 24 bits; weighted
+    // members hold the sample in kSampleBits bits
+    if (n >= (int64_t(1) << ufs::kSampleBits))
+        return fail(UF_ERR_UNSUPPORTED, "the sparse split takes fewer than 2^24 samples");
     if (sc->n_entries >= (int64_t(1) << ufs::kBaseBits))
         return fail(UF_ERR_UNSUPPORTED, "the sparse split takes fewer than 2^40 list entries");
     if (weighted) {
@@ -389,7 +390,8 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
         return fail_free(fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree"));
     if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
     if (rc == hipSuccess)
-        rc = ufs::sort_lists(sc->roff, sc->n_lists, n, rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur,
+        rc = ufs::sort_lists(sc->roff, sc->n_lists, n, ufs::slot_segment_len(0, n / 2), rs_tmp,
+                             rq_tmp, sc->rs, sc->rw, sc->soff, scur,
                              sc->entries, s);
     if (rc == hipSuccess)
         rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,

@@ -15,16 +15,27 @@ constexpr int kSampleBits = 24;         // packed weighted list member: value <<
 
 constexpr int kBaseBits = 40;           // SlotEntry::bw: list start in the low 40 bits
 
-// One list membership of a sample, as the slot kernel reads it: the list's first
-// entry (low kBaseBits bits of bw) and the window length w (high 24 bits: the
-// members at cyclic distance 1..floor(N/2) after the sample, which follow it in
-// the sorted list), the list length, the sample's position in it, and its value
-// (weighted: the sample's own l*u in the split's fixed-point step; unweighted:
-// the branch length l_hi + l_lo in 2^-40).
+// Stripes per slot workgroup: its LDS row takes 8 bytes per stripe, up to the
+// 160 KiB of a gfx950 CU.
+constexpr int64_t kSegStripes = 20480;
+// Stripes per segment when the slot kernel covers stripes [sb, se).
+inline int64_t slot_segment_len(int64_t sb, int64_t se) {
+    const int64_t nseg = (se - sb + kSegStripes - 1) / kSegStripes;
+    return nseg > 0 ? (se - sb + nseg - 1) / nseg : 0;
+}
+
+// One list membership of a sample, as the slot kernel reads it:
+// * bw: the list's first entry (low kBaseBits bits) and the window length w (high
+//   24 bits): the members at cyclic distance 1..floor(N/2) after the sample, which
+//   follow it in the sorted list;
+// * mpw: the list length m (bits 0-23), the sample's position p in it (24-47), and
+//   w0 (48-63), the members of the window at distance <= slot_segment_len(0,
+//   floor(N/2)) (the first segment boundary of a full-range call);
+// * v: its value (weighted: the sample's own l*u in the split's fixed-point step;
+//   unweighted: the branch length l_hi + l_lo in 2^-40).
 struct SlotEntry {
     int64_t bw;
-    int32_t m;
-    int32_t p;
+    unsigned long long mpw;
     unsigned long long v;
 };
 
@@ -38,7 +49,7 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
 // rw_out as packed words rq << kSampleBits | sample; per-sample index rows
 // [soff[s], soff[s+1]) of SlotEntry filled through the cursors scur (zeroed by the
 // caller); v holds the sample's value (weighted) or the list id (unweighted).
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, const int32_t* rs_in,
+hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, int64_t seg0, const int32_t* rs_in,
                       const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st);

@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
 constexpr int kSortLds = 4096;
 
 __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
-                                             int32_t r, int32_t w, const int64_t* __restrict__ rq_in,
+                                             int32_t r, int32_t w, int32_t w0,
+                                             const int64_t* __restrict__ rq_in,
                                              int32_t* __restrict__ rs_out,
                                              unsigned long long* __restrict__ rw_out,
                                              const int64_t* __restrict__ soff,
@@ -98,25 +99,28 @@ __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k,
     const int32_t slot = atomicAdd(&scur[smp], 1);
     SlotEntry ent;
     ent.bw = int64_t((unsigned long long)base | ((unsigned long long)w << kBaseBits));
-    ent.m = m;
-    ent.p = r;
+    ent.mpw = (unsigned long long)unsigned(m) | ((unsigned long long)unsigned(r) << 24) |
+              ((unsigned long long)unsigned(w0) << 48);
     ent.v = rw_out ? q : (unsigned long long)L;
     se[soff[smp] + slot] = ent;
 }
 
-// Rank of sample smp in its list (members are distinct) and the size of its
-// window: members at cyclic distance 1..floor(N/2) after it.
+// Rank of sample smp in its list (members are distinct), the size of its window
+// (members at cyclic distance 1..floor(N/2) after it) and of the window's part
+// at distance <= seg0.
 struct RankWin {
-    int32_t r = 0, w = 0;
-    __device__ __forceinline__ void add(int32_t other, int32_t smp, int64_t n) {
+    int32_t r = 0, w = 0, w0 = 0;
+    __device__ __forceinline__ void add(int32_t other, int32_t smp, int64_t n, int64_t seg0) {
         r += other < smp;
         int64_t d = int64_t(other) - smp;
         if (d < 0) d += n;
         w += d >= 1 && d <= n / 2;
+        w0 += d >= 1 && d <= n / 2 && d <= seg0;
     }
 };
 
 __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff, int64_t n,
+                                                    int64_t seg0,
                                                     const int32_t* __restrict__ rs_in,
                                                     const int64_t* __restrict__ rq_in,
                                                     int32_t* __restrict__ rs_out,
@@ -134,16 +138,16 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = ks[k];
             RankWin rw;
-            for (int64_t t = 0; t < m; ++t) rw.add(ks[t], smp, n);
-            place_member(L, base, k, smp, rw.r, rw.w, rq_in, rs_out, rw_out, soff, scur,
+            for (int64_t t = 0; t < m; ++t) rw.add(ks[t], smp, n, seg0);
+            place_member(L, base, k, smp, rw.r, rw.w, rw.w0, rq_in, rs_out, rw_out, soff, scur,
                          int32_t(m), se);
         }
     } else {
         for (int64_t k = threadIdx.x; k < m; k += 256) {
             const int32_t smp = rs_in[base + k];
             RankWin rw;
-            for (int64_t t = 0; t < m; ++t) rw.add(rs_in[base + t], smp, n);
-            place_member(L, base, k, smp, rw.r, rw.w, rq_in, rs_out, rw_out, soff, scur,
+            for (int64_t t = 0; t < m; ++t) rw.add(rs_in[base + t], smp, n, seg0);
+            place_member(L, base, k, smp, rw.r, rw.w, rw.w0, rq_in, rs_out, rw_out, soff, scur,
                          int32_t(m), se);
         }
     }
@@ -312,15 +316,12 @@ __device__ __forceinline__ int64_t xcd_sample(int64_t b, int64_t n) {
 
 constexpr int kSlotThreads = 1024;
 constexpr int kSlotWaves = kSlotThreads / 64;
-// Stripes per workgroup segment: the LDS row takes 8 bytes per stripe, up to the
-// 160 KiB of a gfx950 CU.
-constexpr int64_t kSegStripes = 20480;
 
 template <bool W>
 __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
     const int32_t* __restrict__ rs, const unsigned long long* __restrict__ rw,
     const int64_t* __restrict__ soff, const SlotEntry* __restrict__ entries, int64_t n,
-    int64_t sb, int64_t se, int64_t seg_len, unsigned long long* __restrict__ M) {
+    int64_t sb, int64_t se, int64_t seg_len, int64_t seg0, unsigned long long* __restrict__ M) {
     extern __shared__ unsigned long long acc[];   // [seg_len]
     const int64_t i = xcd_sample(blockIdx.x, n);
     const int64_t g0 = sb + int64_t(blockIdx.y) * seg_len;
@@ -344,8 +345,9 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         if (k + kSlotWaves < k_end) nxt = entries[k + kSlotWaves];  // in flight meanwhile
         const int64_t base = ent.bw & ((int64_t(1) << kBaseBits) - 1);
         const int64_t w = int64_t((unsigned long long)ent.bw >> kBaseBits);
-        const int64_t m = ent.m;
-        const int64_t p = ent.p;
+        const int64_t m = int64_t(ent.mpw & 0xFFFFFFull);
+        const int64_t p = int64_t((ent.mpw >> 24) & 0xFFFFFFull);
+        const int64_t w0 = int64_t(ent.mpw >> 48);
         const unsigned long long vi = ent.v;
         // the c-th member after i, cyclically, sits at position (p + 1 + c) mod m;
         // its distance from i grows with c, and members c < w lie within N/2
@@ -383,8 +385,9 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
             }
             return hi;
         };
-        const int64_t c_lo = dlo > 1 ? first_reaching(dlo, 0, w) : 0;
-        const int64_t c_hi = dhi < n / 2 ? first_reaching(dhi + 1, c_lo, w) : w;
+        // segment edges at distance 0, floor(N/2) or seg0 need no search
+        const int64_t c_lo = dlo == 1 ? 0 : (dlo == seg0 + 1 ? w0 : first_reaching(dlo, 0, w));
+        const int64_t c_hi = dhi >= n / 2 ? w : (dhi == seg0 ? w0 : first_reaching(dhi + 1, c_lo, w));
         // members c in [c_lo, c_hi) all fall in this segment: four loads in
         // flight per lane, then their LDS adds
         constexpr int U = 4;
@@ -435,13 +438,13 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
     return hipGetLastError();
 }
 
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, const int32_t* rs_in,
+hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, int64_t seg0, const int32_t* rs_in,
                       const int64_t* rq_in,
                       int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st) {
     if (n_lists <= 0) return hipSuccess;
     if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, n, rs_in, rq_in,
+    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, n, seg0, rs_in, rq_in,
                        rs_out, rw_out, soff, scur, se);
     return hipGetLastError();
 }
@@ -505,8 +508,9 @@ hipError_t rare_slots(const int32_t* rs, const unsigned long long* rw, const int
                       unsigned long long* M, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
     if (n > 0x7fffffff || (rw && n > (int64_t(1) << kSampleBits))) return hipErrorInvalidValue;
-    const int64_t nseg = (se - sb + kSegStripes - 1) / kSegStripes;
-    const int64_t seg_len = (se - sb + nseg - 1) / nseg;
+    const int64_t seg_len = slot_segment_len(sb, se);
+    const int64_t nseg = (se - sb + seg_len - 1) / seg_len;
+    const int64_t seg0 = slot_segment_len(0, n / 2);   // boundary the entries count w0 for
     if (nseg > 65535) return hipErrorInvalidValue;
     const dim3 grid{unsigned(n), unsigned(nseg)};
     const size_t lds = size_t(seg_len) * 8;
@@ -520,10 +524,10 @@ hipError_t rare_slots(const int32_t* rs, const unsigned long long* rw, const int
     if (!attr_ok) return hipErrorInvalidValue;
     if (rw)
         hipLaunchKernelGGL(k_rare_slots<true>, grid, dim3(kSlotThreads), lds, st, rs, rw, soff,
-                           entries, n, sb, se, seg_len, M);
+                           entries, n, sb, se, seg_len, seg0, M);
     else
         hipLaunchKernelGGL(k_rare_slots<false>, grid, dim3(kSlotThreads), lds, st, rs, rw, soff,
-                           entries, n, sb, se, seg_len, M);
+                           entries, n, sb, se, seg_len, seg0, M);
     return hipGetLastError();
 }
 

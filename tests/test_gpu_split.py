@@ -128,6 +128,46 @@ def test_merge_and_search_embeddings_agree_bitwise(dense_kind, threshold):
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("variant", sorted(SPLIT))
+def test_two_segment_slots_exact_and_mergeable(variant, threshold):
+    """N = 41,000: floor(N/2) = 20,500 stripes exceed one slot workgroup's LDS row,
+    so each sample's lists are walked in two segments.  A full-range call takes
+    the segment boundary from the counts the list entries carry; stripe-range
+    calls find their edges by search.  With no dense branch (threshold 1) both
+    give the same integers, so the pieces merge bit for bit, and sampled pairs
+    match the oracle within the 2^-40 quantisation (the unweighted lengths are
+    l_hi + l_lo, as in the split)."""
+    import torch
+    import paper_2107_05397_amd as uf
+    n = 41000
+    threshold(1.0, variant)
+    tree = synth.gen_tree(3000, 0.1, seed=41)
+    table = synth.gen_table_zipf(n, np.arange(3000), 12, seed=42)
+    emb = _emb(tree, table)
+    assert uf.split_stats(emb, variant)[0] == 0
+    full, _, _ = uf.dm(emb, variant, SPLIT[variant])
+    S = uf.n_stripes(n)
+    buf = torch.full_like(full, -1.0)
+    for a, b in ((0, 7), (7, 12000), (12000, S)):
+        uf.dm_stripes(emb, variant, SPLIT[variant], a, b, layout="condensed", out=buf)
+    torch.cuda.synchronize()
+    assert torch.equal(full, buf)
+    del buf
+    rng = np.random.default_rng(43)
+    pairs = rng.integers(0, n, size=(3000, 2))
+    pairs = pairs[pairs[:, 0] != pairs[:, 1]]
+    idx = torch.tensor([uf.condensed_index(n, int(i), int(j)) for i, j in pairs], device="cuda")
+    got = full[idx].cpu().numpy()
+    ref_tree = tree
+    if variant == "unweighted":
+        hi, lo = oracle.gram_split_bf16(tree.length)
+        ref_tree = synth.Tree(tree.parent.copy(), hi + lo, tree.n_tips)
+    want = oracle.dm_pairs(ref_tree, table, pairs, variant)
+    err = np.abs(got - want).max()
+    print(f"[two-segment slots {variant}] max|err|={err:.3e}")
+    assert err <= 1e-10
+
+
 def test_mfma_split_exact_with_integer_lengths(threshold):
     """Integer lengths < 256 are exact in bf16 and their FP32 Gram sums stay below
     2^24, so the dense MFMA part is exact too: the split equals the oracle."""
