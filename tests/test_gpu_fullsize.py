@@ -5,12 +5,17 @@ oracle computes one by one, plus properties that hold at any size.
 Pairs sampled: random pairs, the first and last samples, and pairs at the
 stripe boundary (partner N/2 away, the duplicated last stripe of even N).
 Tolerances as in test_gpu_parity.py.
+
+The 50,000-sample workload (same tree laws) is checked on all pairs among its
+first 300 samples, taken from the full GPU matrix: there floor(N/2) exceeds one
+slot workgroup's LDS row, so the sparse part runs in two segments per sample.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from oracle import core
 from tests.conftest import gpu_available
 
 pytestmark = [pytest.mark.gpu,
@@ -76,3 +81,35 @@ def test_c2_sampled_pairs_and_row_means(c2, variant, precision, tol):
         r = -0.5 * np.sum(dd[k] ** 2) / n
         assert abs(rmh[i] - r) <= 1e-12 * max(1.0, abs(r))
     assert abs(float(gm.cpu()[0]) - rmh.mean()) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import paper_2107_05397_amd as uf
+    tree, table = synth.config("C3")
+    t = uf.Tree(tree.parent, tree.length)
+    tb = uf.Table(t, table.indptr, table.tips, table.counts)
+    emb = uf.Embedding(t, tb)
+    m = 300
+    sub = synth.subset_rows(table, np.arange(m))
+    want = {v: core.dm(tree, sub, v)[0] for v in ("weighted_normalized", "unweighted")}
+    return table.n_samples, emb, m, want
+
+
+@pytest.mark.parametrize("variant,precision", [
+    ("weighted_normalized", "fp32_split"),
+    ("unweighted", "mfma_split"),
+    ("unweighted", "mfma"),
+])
+def test_c3_leading_samples_all_pairs(c3, variant, precision):
+    import torch
+    import paper_2107_05397_amd as uf
+    n, emb, m, want = c3
+    d, _, _ = uf.dm(emb, variant, precision)
+    ii, jj = np.triu_indices(m, 1)
+    idx = torch.from_numpy(n * ii - ii * (ii + 1) // 2 + (jj - ii - 1)).to("cuda")
+    got = d[idx].cpu().numpy()
+    err = np.abs(got - want[variant])
+    print(f"[C3 {variant} {precision}] first {m} samples max|err|={err.max():.3e}", flush=True)
+    assert err.max() <= 1e-4
+    assert float(d.min()) >= 0.0 and float(d.max()) <= 1.0
