@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
 
 // Sort each list by sample: a member's new position is the number of members
 // with a smaller sample id (ids in a list are distinct).  Also records, in the
-// sample's row of the per-sample index, the list and the member's position.
+// sample's row of the per-sample index, the list, the member's position and the
+// sizes of its window (RankWin).
 constexpr int kSortLds = 4096;
 
 __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
