@@ -620,29 +620,52 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
 // and a 64-lane store covers at most two runs.
 constexpr int kFinT = 64;
 
+// Inputs of one (stripe, sample) element, loaded ahead of the arithmetic.
 template <typename A>
-__device__ __forceinline__ double final_distance(int kind, const A* __restrict__ acc,
-                                                 double acc_scale, const double* __restrict__ scal,
-                                                 int64_t n, int64_t sb, int64_t s, int64_t i,
-                                                 int64_t j,
+struct FinIn {
+    A acc;                         // dense accumulator (unscaled)
+    unsigned long long m;          // split: exact pair sum in the split's unit
+    unsigned long long sg_i, sg_j; // weighted split: sigma of both samples
+    double sc_i, sc_j;             // per-sample scalars
+};
+
+// Loads only (no arithmetic on the loaded values, so that the loads of several
+// elements stay in flight together).  Indices must be in range.
+template <typename A>
+__device__ __forceinline__ FinIn<A> final_inputs(const A* __restrict__ acc,
+                                                 const double* __restrict__ scal, int64_t n,
+                                                 int64_t sb, int64_t s, int64_t i, int64_t j,
                                                  const unsigned long long* __restrict__ split_m,
-                                                 const unsigned long long* __restrict__ sigma,
-                                                 double split_unit) {
-    double num = double(acc[(s - sb) * n + i]) * acc_scale;
-    if (split_m) {
+                                                 const unsigned long long* __restrict__ sigma) {
+    FinIn<A> f;
+    const int64_t e = (s - sb) * n + i;
+    f.acc = acc[e];
+    f.m = split_m ? split_m[e] : 0ull;
+    f.sg_i = sigma ? sigma[i] : 0ull;
+    f.sg_j = sigma ? sigma[j] : 0ull;
+    f.sc_i = scal[i];
+    f.sc_j = scal[j];
+    return f;
+}
+
+template <typename A>
+__device__ __forceinline__ double final_distance(int kind, const FinIn<A>& f, double acc_scale,
+                                                 bool split, double split_unit) {
+    double num = double(f.acc) * acc_scale;
+    if (split) {
         if (kind == 0) {
-            const long long r = (long long)(sigma[i] + sigma[j] - 2ull * split_m[(s - sb) * n + i]);
+            const long long r = (long long)(f.sg_i + f.sg_j - 2ull * f.m);
             num += double(r) * split_unit;
         } else {
-            num += double(split_m[(s - sb) * n + i]) * split_unit;
+            num += double(f.m) * split_unit;
         }
     }
     double d;
     if (kind == 0) {
-        const double den = scal[i] + scal[j];
+        const double den = f.sc_i + f.sc_j;
         d = den > 0.0 ? num / den : 0.0;
     } else {
-        const double sum = scal[i] + scal[j];
+        const double sum = f.sc_i + f.sc_j;
         const double orr = sum - num;
         const double xr = sum - 2.0 * num;
         d = orr > 0.0 ? xr / orr : 0.0;
@@ -673,16 +696,32 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
     };
     for (int64_t t = blockIdx.y; t < n_tiles; t += gridDim.y) {
         const int64_t s0 = sb + t * kFinT;
-        for (int ls = tid >> 6; ls < kFinT; ls += 4) {
-            const int li = tid & 63;
-            const int64_t s = s0 + ls, i = i0 + li;
-            if (s >= se || i >= n) continue;
-            const int64_t j = (i + s + 1) % n;
-            const double d = final_distance(kind, acc, acc_scale, scal, n, sb, s, i, j, split_m,
-                                            sigma, split_unit);
-            if (q) q[(s - sb) * n + i] = -0.5 * d * d;
-            if (condensed) tile[ls][li] = d;
-            else put((s - sb) * n + i, d);
+        const int li = tid & 63;
+        const int64_t i = i0 + li;
+        // the thread's 16 elements in two batches of 8, all loads of a batch in
+        // flight before its arithmetic
+        // (elements outside the range load from a clamped in-range element and are
+        // not stored)
+        const int64_t ic = i < n ? i : n - 1;
+        for (int half = 0; half < 2; ++half) {
+            FinIn<A> in[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ls = (tid >> 6) + 4 * (8 * half + u);
+                const int64_t sc = s0 + ls < se ? s0 + ls : se - 1;
+                in[u] = final_inputs(acc, scal, n, sb, sc, ic, (ic + sc + 1) % n, split_m, sigma);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ls = (tid >> 6) + 4 * (8 * half + u);
+                const int64_t s = s0 + ls;
+                if (s >= se || i >= n) continue;
+                const double d = final_distance(kind, in[u], acc_scale, split_m != nullptr,
+                                                split_unit);
+                if (q) q[(s - sb) * n + i] = -0.5 * d * d;
+                if (condensed) tile[ls][li] = d;
+                else put((s - sb) * n + i, d);
+            }
         }
         if (!condensed) continue;
         __syncthreads();

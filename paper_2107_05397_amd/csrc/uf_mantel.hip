@@ -145,7 +145,20 @@ __global__ __launch_bounds__(kRowThreads) void k_perm_rows(const double* __restr
                 for (int64_t lo = 0; lo < n; lo += part_len) {
                     const int len = int(min(part_len, n - lo));
                     __syncthreads();
-                    for (int k = tid; k < len; k += kRowThreads) row[k] = S[pi * n + lo + k];
+                    // eight loads in flight per thread before their LDS stores
+                    for (int k0 = tid; k0 < len; k0 += kRowThreads * 8) {
+                        double v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int k = k0 + u * kRowThreads;
+                            v[u] = k < len ? S[pi * n + lo + k] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int k = k0 + u * kRowThreads;
+                            if (k < len) row[k] = v[u];
+                        }
+                    }
                     __syncthreads();
                     const int lo32 = int(lo);
 #pragma unroll

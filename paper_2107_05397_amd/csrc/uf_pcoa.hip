@@ -38,10 +38,13 @@ __device__ __forceinline__ int64_t cidx(int64_t n, int64_t a, int64_t b) {   // 
 
 // P[seg][i][c] = sum over j in the segment's column blocks, j != i, of
 // (-d_ij^2 / 2) X[j][c].  Block (ib, seg); 256 threads; tile 64 x 64 of A in
-// LDS transposed (At[j][r]) so the inner loop reads consecutive rows.
+// LDS transposed (At[j][r]) so the inner loop reads consecutive rows.  The next
+// tile is loaded into registers while the current one is multiplied.
 __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64_t n,
                                             const double* __restrict__ X, int cols,
                                             int64_t nblk, double* __restrict__ P) {
+    constexpr int kPer = kRB * kRB / 256;                  // tile elements per thread
+    constexpr int kXPer = (kRB * kMaxCols + 255) / 256;    // X elements per thread, at most
     __shared__ double At[kRB][kRB + 1];
     __shared__ double Xs[kRB][kMaxCols];
     const int tid = threadIdx.x;
@@ -52,32 +55,48 @@ __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64
     double acc[kMaxCols / 4];
 #pragma unroll
     for (int k = 0; k < kMaxCols / 4; ++k) acc[k] = 0.0;
-    for (int64_t jb = jb0; jb < jb1; ++jb) {
+    // One tile's distances and X rows, all loads in flight at once: element u of
+    // this thread is e = tid + 256 u, taken along the contiguous side of the
+    // condensed rows (row i fixed and j consecutive above the diagonal, row j
+    // fixed and i consecutive below it).  Zero outside the matrix and on it.
+    double va[kPer], vx[kXPer];
+    auto load = [&](int64_t jb) {
         const int64_t j0 = jb * kRB;
-        __syncthreads();
-        // tile of A: coalesced along the contiguous side of the condensed rows
-        for (int e = tid; e < kRB * kRB; e += 256) {
-            int rr, cc;
-            if (jb >= ib) {
-                rr = e / kRB;   // row i fixed, j consecutive
-                cc = e % kRB;
-            } else {
-                cc = e / kRB;   // row j fixed (j < i), i consecutive
-                rr = e % kRB;
-            }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = jb >= ib ? e / kRB : e % kRB;
+            const int cc = jb >= ib ? e % kRB : e / kRB;
             const int64_t i = i0 + rr, j = j0 + cc;
-            double a = 0.0;
-            if (i < n && j < n && i != j) {
-                const double d = i < j ? dm[cidx(n, i, j)] : dm[cidx(n, j, i)];
-                a = -0.5 * d * d;
-            }
-            At[cc][rr] = a;
+            va[u] = 0.0;
+            if (i < n && j < n && i != j) va[u] = i < j ? dm[cidx(n, i, j)] : dm[cidx(n, j, i)];
         }
-        for (int e = tid; e < kRB * cols; e += 256) {
-            const int jj = e / cols, c = e % cols;
-            const int64_t j = j0 + jj;
-            Xs[jj][c] = j < n ? X[j * cols + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kXPer; ++u) {
+            const int e = tid + 256 * u;
+            const int64_t j = j0 + e / (cols > 0 ? cols : 1);
+            vx[u] = (e < kRB * cols && j < n) ? X[j0 * cols + e] : 0.0;
         }
+    };
+    auto store = [&](int64_t jb) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = tid + 256 * u;
+            const int rr = jb >= ib ? e / kRB : e % kRB;
+            const int cc = jb >= ib ? e % kRB : e / kRB;
+            At[cc][rr] = 0.0 - 0.5 * va[u] * va[u];   // +0 where the distance is absent
+        }
+#pragma unroll
+        for (int u = 0; u < kXPer; ++u) {
+            const int e = tid + 256 * u;
+            if (e < kRB * cols) Xs[e / cols][e % cols] = vx[u];
+        }
+    };
+    if (jb0 < jb1) load(jb0);
+    for (int64_t jb = jb0; jb < jb1; ++jb) {
+        __syncthreads();
+        store(jb);
+        if (jb + 1 < jb1) load(jb + 1);          // next tile in flight during the FMAs
         __syncthreads();
         for (int jj = 0; jj < kRB; ++jj) {
             const double a = At[jj][r];
