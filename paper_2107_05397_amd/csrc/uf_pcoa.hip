@@ -29,7 +29,7 @@ namespace ufq {
 namespace {
 
 constexpr int kRB = 64;          // rows per block of the A X kernel
-constexpr int kMaxCols = 48;     // columns of the test matrix (LDS: 33 KiB + 24 KiB)
+constexpr int kMaxCols = 48;     // columns of the test matrix (LDS: 33 KiB + up to 24 KiB)
 constexpr int kSegs = 8;         // column-block segments of the A X kernel
 
 __device__ __forceinline__ int64_t cidx(int64_t n, int64_t a, int64_t b) {   // a < b
@@ -40,21 +40,23 @@ __device__ __forceinline__ int64_t cidx(int64_t n, int64_t a, int64_t b) {   // 
 // (-d_ij^2 / 2) X[j][c].  Block (ib, seg); 256 threads; tile 64 x 64 of A in
 // LDS transposed (At[j][r]) so the inner loop reads consecutive rows.  The next
 // tile is loaded into registers while the current one is multiplied.
+template <int CPT>
 __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64_t n,
                                             const double* __restrict__ X, int cols,
                                             int64_t nblk, double* __restrict__ P) {
-    constexpr int kPer = kRB * kRB / 256;                  // tile elements per thread
-    constexpr int kXPer = (kRB * kMaxCols + 255) / 256;    // X elements per thread, at most
+    constexpr int kPer = kRB * kRB / 256;                 // tile elements per thread
+    constexpr int kW = 4 * CPT;                           // X columns, zero-padded
+    constexpr int kXPer = (kRB * kW + 255) / 256;         // X elements per thread
     __shared__ double At[kRB][kRB + 1];
-    __shared__ double Xs[kRB][kMaxCols];
+    __shared__ double Xs[kRB][kW];
     const int tid = threadIdx.x;
     const int64_t ib = blockIdx.x, seg = blockIdx.y;
     const int64_t i0 = ib * kRB;
     const int64_t jb0 = nblk * seg / kSegs, jb1 = nblk * (seg + 1) / kSegs;
-    const int r = tid & 63, cg = tid >> 6;      // output row, column group
-    double acc[kMaxCols / 4];
+    const int r = tid & 63, cg = tid >> 6;      // output row; columns cg*CPT ..
+    double acc[CPT];
 #pragma unroll
-    for (int k = 0; k < kMaxCols / 4; ++k) acc[k] = 0.0;
+    for (int k = 0; k < CPT; ++k) acc[k] = 0.0;
     // One tile's distances and X rows, all loads in flight at once: element u of
     // this thread is e = tid + 256 u, taken along the contiguous side of the
     // condensed rows (row i fixed and j consecutive above the diagonal, row j
@@ -74,8 +76,9 @@ __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64
 #pragma unroll
         for (int u = 0; u < kXPer; ++u) {
             const int e = tid + 256 * u;
-            const int64_t j = j0 + e / (cols > 0 ? cols : 1);
-            vx[u] = (e < kRB * cols && j < n) ? X[j0 * cols + e] : 0.0;
+            const int c = e % kW;
+            const int64_t j = j0 + e / kW;
+            vx[u] = (e < kRB * kW && c < cols && j < n) ? X[j * cols + c] : 0.0;
         }
     };
     auto store = [&](int64_t jb) {
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64
 #pragma unroll
         for (int u = 0; u < kXPer; ++u) {
             const int e = tid + 256 * u;
-            if (e < kRB * cols) Xs[e / cols][e % cols] = vx[u];
+            if (e < kRB * kW) Xs[e / kW][e % kW] = vx[u];
         }
     };
     if (jb0 < jb1) load(jb0);
@@ -101,19 +104,43 @@ __global__ __launch_bounds__(256) void k_ax(const double* __restrict__ dm, int64
         for (int jj = 0; jj < kRB; ++jj) {
             const double a = At[jj][r];
 #pragma unroll
-            for (int k = 0; k < kMaxCols / 4; ++k) {
-                const int c = cg + 4 * k;
-                if (c < cols) acc[k] = fma(a, Xs[jj][c], acc[k]);
-            }
+            for (int k = 0; k < CPT; ++k) acc[k] = fma(a, Xs[jj][cg * CPT + k], acc[k]);
         }
     }
     const int64_t i = i0 + r;
     if (i < n) {
 #pragma unroll
-        for (int k = 0; k < kMaxCols / 4; ++k) {
-            const int c = cg + 4 * k;
+        for (int k = 0; k < CPT; ++k) {
+            const int c = cg * CPT + k;
             if (c < cols) P[(seg * n + i) * cols + c] = acc[k];
         }
+    }
+}
+
+// k_ax for `cols` test columns: CPT = ceil(cols / 4) columns per thread.
+template <int CPT>
+hipError_t launch_ax_cpt(dim3 g, hipStream_t s, const double* dm, int64_t n, const double* X,
+                         int cols, int64_t nblk, double* P) {
+    hipLaunchKernelGGL(k_ax<CPT>, g, dim3(256), 0, s, dm, n, X, cols, nblk, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_ax(dim3 g, hipStream_t s, const double* dm, int64_t n, const double* X, int cols,
+                     int64_t nblk, double* P) {
+    switch ((cols + 3) / 4) {
+        case 1: return launch_ax_cpt<1>(g, s, dm, n, X, cols, nblk, P);
+        case 2: return launch_ax_cpt<2>(g, s, dm, n, X, cols, nblk, P);
+        case 3: return launch_ax_cpt<3>(g, s, dm, n, X, cols, nblk, P);
+        case 4: return launch_ax_cpt<4>(g, s, dm, n, X, cols, nblk, P);
+        case 5: return launch_ax_cpt<5>(g, s, dm, n, X, cols, nblk, P);
+        case 6: return launch_ax_cpt<6>(g, s, dm, n, X, cols, nblk, P);
+        case 7: return launch_ax_cpt<7>(g, s, dm, n, X, cols, nblk, P);
+        case 8: return launch_ax_cpt<8>(g, s, dm, n, X, cols, nblk, P);
+        case 9: return launch_ax_cpt<9>(g, s, dm, n, X, cols, nblk, P);
+        case 10: return launch_ax_cpt<10>(g, s, dm, n, X, cols, nblk, P);
+        case 11: return launch_ax_cpt<11>(g, s, dm, n, X, cols, nblk, P);
+        case 12: return launch_ax_cpt<12>(g, s, dm, n, X, cols, nblk, P);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -369,8 +396,7 @@ uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const do
         double* one = reinterpret_cast<double*>(base + p.off_one);
         std::vector<double> h1(static_cast<size_t>(n), 1.0);
         UFQ_HIP(hipMemcpyAsync(one, h1.data(), size_t(n) * 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_ax, gax, dim3(256), 0, s, dm, n, one, 1, p.nblk, P);
-        UFQ_HIP(hipGetLastError());
+        UFQ_HIP(launch_ax(gax, s, dm, n, one, 1, p.nblk, P));
         // r = (sum_seg P) / n via k_centre with zero means: reuse Y as scratch
         UFQ_HIP(hipMemsetAsync(sums, 0, size_t(2 * cols) * 8, s));
         UFQ_HIP(hipMemsetAsync(g, 0, 8, s));
@@ -396,8 +422,7 @@ uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const do
 
     // X (n x c) -> B X into out
     auto bx = [&](const double* X, int c, double* out) -> uf_status {
-        hipLaunchKernelGGL(k_ax, gax, dim3(256), 0, s, dm, n, X, c, p.nblk, P);
-        UFQ_HIP(hipGetLastError());
+        UFQ_HIP(launch_ax(gax, s, dm, n, X, c, p.nblk, P));
         hipLaunchKernelGGL(k_colsums, dim3(unsigned(c)), dim3(256), 0, s, X, c, n, rm, sums);
         UFQ_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_centre, dim3(unsigned((n * c + 255) / 256)), dim3(256), 0, s, P, n, c, rm,
