@@ -14,10 +14,11 @@
 // comparisons behind the p-value see identical arithmetic.  Every reduction runs
 // in a fixed order.
 //
-// Ranks (Spearman): a stable LSD sort of the order-preserving 64-bit images of
-// the values, one bit per pass (a pass is an exclusive scan of the zero bits and
-// a scatter; passes whose bit is constant are skipped), then runs of equal keys
-// get the mean of the positions they span, plus one.
+// Ranks (Spearman): a stable LSD radix sort of the order-preserving 64-bit
+// images of the values, 8 bits per pass (per-block digit histograms, their
+// exclusive scan, a stable scatter; bytes in which no two keys differ are
+// skipped), then runs of equal keys get the mean of the positions they span,
+// plus one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -209,10 +210,103 @@ __global__ __launch_bounds__(256) void k_keys(const double* __restrict__ v, int6
 }
 
 // z[k] = 1 if bit `bit` of key[k] is 0
-__global__ __launch_bounds__(256) void k_zero_bits(const unsigned long long* __restrict__ key,
-                                                   int64_t m, int bit, uint32_t* __restrict__ z) {
-    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (k < m) z[k] = ((key[k] >> bit) & 1ull) ? 0u : 1u;
+// ---- stable LSD radix sort of the order keys, 8 bits per pass ----
+constexpr int kRadixItems = 16;                      // elements per thread per block
+constexpr int64_t kRadixBlock = 256 * kRadixItems;   // elements per block
+
+// vary |= OR over all keys of (key ^ key[0]): the bits in which keys differ
+__global__ __launch_bounds__(256) void k_key_vary(const unsigned long long* __restrict__ key,
+                                                  int64_t m, unsigned long long* __restrict__ vary) {
+    const unsigned long long k0 = key[0];
+    unsigned long long acc = 0;
+    for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < m; k += int64_t(gridDim.x) * 256)
+        acc |= key[k] ^ k0;
+    for (int off = 32; off > 0; off >>= 1) acc |= __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicOr(vary, acc);
+}
+
+// H[d * nblk + b]: elements of block b whose digit (key >> sh) & 255 is d
+__global__ __launch_bounds__(256) void k_digit_hist(const unsigned long long* __restrict__ key,
+                                                    int64_t m, int sh, int64_t nblk,
+                                                    uint32_t* __restrict__ H) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x, base = b * kRadixBlock;
+    h[tid] = 0;
+    unsigned long long kk[kRadixItems];
+#pragma unroll
+    for (int u = 0; u < kRadixItems; ++u) {
+        const int64_t k = base + u * 256 + tid;
+        kk[u] = k < m ? key[k] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRadixItems; ++u)
+        if (base + u * 256 + tid < m) atomicAdd(&h[(kk[u] >> sh) & 255ull], 1u);
+    __syncthreads();
+    H[int64_t(tid) * nblk + b] = h[tid];
+}
+
+// Stable scatter by digit: Hs is the exclusive scan of H (digit-major), so
+// Hs[d * nblk + b] is where block b's first element of digit d goes.  Within
+// the block the elements are taken in order, 256 per round: a lane's rank
+// among the same digit in its wave comes from eight ballots on the digit bits;
+// the waves of a round and the earlier rounds add their counts (LDS).
+__global__ __launch_bounds__(256) void k_digit_scatter(const unsigned long long* __restrict__ key,
+                                                       const uint32_t* __restrict__ idx, int64_t m,
+                                                       int sh, int64_t nblk,
+                                                       const uint32_t* __restrict__ Hs,
+                                                       unsigned long long* __restrict__ key_out,
+                                                       uint32_t* __restrict__ idx_out) {
+    __shared__ uint32_t cnt[4][256];   // per wave of the round: count, then its offset
+    __shared__ uint32_t run[256];      // elements of each digit in earlier rounds
+    __shared__ uint32_t start[256];    // global position of the block's first element of d
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t b = blockIdx.x, base = b * kRadixBlock;
+    start[tid] = Hs[int64_t(tid) * nblk + b];
+    run[tid] = 0;
+    unsigned long long kk[kRadixItems];
+    uint32_t ii[kRadixItems];
+#pragma unroll
+    for (int u = 0; u < kRadixItems; ++u) {
+        const int64_t k = base + u * 256 + tid;
+        kk[u] = k < m ? key[k] : 0ull;
+        ii[u] = k < m ? idx[k] : 0u;
+    }
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int u = 0; u < kRadixItems; ++u) {
+        const bool valid = base + u * 256 + tid < m;
+        const uint32_t d = uint32_t((kk[u] >> sh) & 255ull);
+        for (int w = 0; w < 4; ++w) cnt[w][tid] = 0;
+        __syncthreads();
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool set = (d >> bit) & 1u;
+            const unsigned long long bb = __ballot(set);
+            same &= set ? bb : ~bb;
+        }
+        const uint32_t r = uint32_t(__popcll(same & below));
+        if (valid && r == 0) cnt[wave][d] = uint32_t(__popcll(same));
+        __syncthreads();
+        {
+            const uint32_t c0 = cnt[0][tid], c1 = cnt[1][tid], c2 = cnt[2][tid], c3 = cnt[3][tid];
+            const uint32_t r0 = run[tid];
+            cnt[0][tid] = r0;
+            cnt[1][tid] = r0 + c0;
+            cnt[2][tid] = r0 + c0 + c1;
+            cnt[3][tid] = r0 + c0 + c1 + c2;
+            run[tid] = r0 + c0 + c1 + c2 + c3;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dest = start[d] + cnt[wave][d] + r;
+            key_out[dest] = kk[u];
+            idx_out[dest] = ii[u];
+        }
+        __syncthreads();
+    }
 }
 
 // Block-level exclusive scan of kScanBlock elements; block totals to agg.
@@ -249,21 +343,6 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t* __restrict__ out, in
                                                   const uint32_t* __restrict__ off) {
     const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (k < m) out[k] += off[k / kScanBlock];
-}
-
-// stable split by the scanned zero flags
-__global__ __launch_bounds__(256) void k_split_scatter(const unsigned long long* __restrict__ key,
-                                                       const uint32_t* __restrict__ idx,
-                                                       const uint32_t* __restrict__ z,
-                                                       const uint32_t* __restrict__ zpos,
-                                                       int64_t m, uint32_t zeros,
-                                                       unsigned long long* __restrict__ key2,
-                                                       uint32_t* __restrict__ idx2) {
-    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (k >= m) return;
-    const int64_t pos = z[k] ? int64_t(zpos[k]) : int64_t(zeros) + (k - int64_t(zpos[k]));
-    key2[pos] = key[k];
-    idx2[pos] = idx[k];
 }
 
 // run starts (flag) over sorted keys
@@ -326,8 +405,8 @@ struct MantelPlan {
     int64_t n = 0, m = 0, n_pairs = 0, n_perm = 0;
     size_t off_sq = 0, off_y = 0, off_part = 0, off_tot = 0, off_cs = 0, off_rx = 0, off_ry = 0,
            off_ka = 0, off_kb = 0, off_ia = 0, off_ib = 0, off_z = 0, off_zp = 0, off_agg = 0,
-           off_first = 0, off_last = 0, total = 0;
-    int64_t agg_len = 0;
+           off_first = 0, off_last = 0, off_h = 0, off_hs = 0, off_vary = 0, total = 0;
+    int64_t agg_len = 0, nblk = 0;
 };
 
 size_t take(size_t& off, size_t bytes) {
@@ -357,17 +436,26 @@ MantelPlan mantel_plan(int64_t n, int method, int64_t n_perm) {
         p.off_ib = take(off, size_t(p.m) * 4);
         p.off_z = take(off, size_t(p.m) * 4);
         p.off_zp = take(off, size_t(p.m) * 4);
-        // scan_u32 at a level of m values uses nb aggregates, and when nb > 1 their
-        // scan (nb) plus one spare slot, then the next level's space
-        int64_t len = 0, lv = p.m;
-        for (;;) {
-            const int64_t nb = (lv + ufm::kScanBlock - 1) / ufm::kScanBlock;
-            len += nb;
-            if (nb <= 1) break;
-            len += nb + 1;
-            lv = nb;
-        }
-        p.agg_len = len + 1;
+        // radix passes: per-block digit histograms and their scan
+        p.nblk = (p.m + ufm::kRadixBlock - 1) / ufm::kRadixBlock;
+        p.off_h = take(off, size_t(256 * p.nblk) * 4);
+        p.off_hs = take(off, size_t(256 * p.nblk) * 4);
+        p.off_vary = take(off, 8);
+        // scan_u32 at a level of v values uses nb aggregates, and when nb > 1 their
+        // scan (nb) plus one spare slot, then the next level's space; it scans m
+        // run flags and 256 * nblk histogram entries
+        auto agg_for = [](int64_t lv) {
+            int64_t len = 0;
+            for (;;) {
+                const int64_t nb = (lv + ufm::kScanBlock - 1) / ufm::kScanBlock;
+                len += nb;
+                if (nb <= 1) break;
+                len += nb + 1;
+                lv = nb;
+            }
+            return len + 1;
+        };
+        p.agg_len = std::max(agg_for(p.m), agg_for(256 * p.nblk));
         p.off_agg = take(off, size_t(p.agg_len) * 4);
         p.off_first = take(off, size_t(p.m) * 4);
         p.off_last = take(off, size_t(p.m) * 4);
@@ -419,20 +507,27 @@ uf_status ranks(const MantelPlan& p, char* base, const double* v, double* rank, 
     auto* agg = reinterpret_cast<uint32_t*>(base + p.off_agg);
     auto* first = reinterpret_cast<uint32_t*>(base + p.off_first);
     auto* last = reinterpret_cast<uint32_t*>(base + p.off_last);
+    auto* H = reinterpret_cast<uint32_t*>(base + p.off_h);
+    auto* Hs = reinterpret_cast<uint32_t*>(base + p.off_hs);
+    auto* vary = reinterpret_cast<unsigned long long*>(base + p.off_vary);
     hipLaunchKernelGGL(k_keys, dim3(grid_of(m)), dim3(256), 0, s, v, m, ka, ia);
     UFM_HIP(hipGetLastError());
-    for (int bit = 0; bit < 64; ++bit) {
-        hipLaunchKernelGGL(k_zero_bits, dim3(grid_of(m)), dim3(256), 0, s, ka, m, bit, z);
+    // bytes in which the keys differ; the passes over the others change nothing
+    UFM_HIP(hipMemsetAsync(vary, 0, 8, s));
+    hipLaunchKernelGGL(k_key_vary, dim3(std::min<unsigned>(grid_of(m), 4096u)), dim3(256), 0, s, ka,
+                       m, vary);
+    UFM_HIP(hipGetLastError());
+    unsigned long long hvary = 0;
+    UFM_HIP(hipMemcpyAsync(&hvary, vary, 8, hipMemcpyDeviceToHost, s));
+    UFM_HIP(hipStreamSynchronize(s));
+    for (int sh = 0; sh < 64; sh += 8) {
+        if (((hvary >> sh) & 255ull) == 0) continue;
+        hipLaunchKernelGGL(k_digit_hist, dim3(unsigned(p.nblk)), dim3(256), 0, s, ka, m, sh, p.nblk,
+                           H);
         UFM_HIP(hipGetLastError());
-        UFM_HIP(scan_u32(z, zp, m, agg, s));
-        uint32_t last_pos = 0, last_z = 0;
-        UFM_HIP(hipMemcpyAsync(&last_pos, zp + (m - 1), 4, hipMemcpyDeviceToHost, s));
-        UFM_HIP(hipMemcpyAsync(&last_z, z + (m - 1), 4, hipMemcpyDeviceToHost, s));
-        UFM_HIP(hipStreamSynchronize(s));
-        const uint64_t zeros = uint64_t(last_pos) + last_z;
-        if (zeros == 0 || zeros == uint64_t(m)) continue;   // bit constant: order unchanged
-        hipLaunchKernelGGL(k_split_scatter, dim3(grid_of(m)), dim3(256), 0, s, ka, ia, z, zp, m,
-                           uint32_t(zeros), kb, ib);
+        UFM_HIP(scan_u32(H, Hs, 256 * p.nblk, agg, s));
+        hipLaunchKernelGGL(k_digit_scatter, dim3(unsigned(p.nblk)), dim3(256), 0, s, ka, ia, m, sh,
+                           p.nblk, Hs, kb, ib);
         UFM_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(ia, ib);
