@@ -185,6 +185,9 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
                 cur = lower_bound_rank(rank, a, b, qhi[0]);
                 if (cur > a) last = rank[cur - 1];
             }
+            // rank of the tip at the cursor (past the row: larger than any bound), so
+            // that a query which does not move the cursor loads nothing
+            int32_t nxt = cur < b ? rank[cur] : 0x7fffffff;
             for (int q8 = 0; q8 < kPresQ; q8 += 8) {
                 unsigned w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -192,11 +195,10 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
                     const int q = q8 + u;
                     if (q < nq) {
                         const int32_t h = qhi[q];
-                        while (cur < b) {
-                            const int32_t r = rank[cur];
-                            if (r >= h) break;
-                            last = r;
+                        while (nxt < h) {
+                            last = nxt;
                             ++cur;
+                            nxt = cur < b ? rank[cur] : 0x7fffffff;
                         }
                         if (last >= qlo[q]) w[u >> 1] |= 0x3F80u << (16 * (u & 1));
                     }

@@ -228,10 +228,14 @@ __global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t
         const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
         int64_t cur = ufd::lower_bound_rank(e.rank, a, b, ql[0]);
         uint32_t below = uint32_t(e.cum[cur + s]);
+        int32_t nxt = cur < b ? e.rank[cur] : 0x7fffffff;   // rank at the cursor
         for (int t = 0; t < nq; ++t) {
             const int32_t l = ql[t];
             const int64_t from = cur;
-            while (cur < b && e.rank[cur] < l) ++cur;
+            while (nxt < l) {
+                ++cur;
+                nxt = cur < b ? e.rank[cur] : 0x7fffffff;
+            }
             if (cur != from) below = uint32_t(e.cum[cur + s]);
             const int64_t k = qk[t];
             if (k >= k0 && k < k0 + kc) o[(k - k0) * e.n + s] = below;
@@ -262,10 +266,14 @@ __global__ __launch_bounds__(256) void k_embed_list_hi(ufp::Emb e, const int32_t
         const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
         int64_t cur = ufd::lower_bound_rank(e.rank, a, b, qh[0]);
         uint32_t below = uint32_t(e.cum[cur + s]);
+        int32_t nxt = cur < b ? e.rank[cur] : 0x7fffffff;   // rank at the cursor
         for (int t = 0; t < nq; ++t) {
             const int32_t h = qh[t];
             const int64_t from = cur;
-            while (cur < b && e.rank[cur] < h) ++cur;
+            while (nxt < h) {
+                ++cur;
+                nxt = cur < b ? e.rank[cur] : 0x7fffffff;
+            }
             if (cur != from) below = uint32_t(e.cum[cur + s]);
             const size_t idx = size_t(t0 + t - k0) * size_t(e.n) + size_t(s);
             const int64_t c = int64_t(below - reinterpret_cast<const uint32_t*>(out)[idx]);
