@@ -34,10 +34,10 @@ std::atomic<double> g_split_threshold[2] = {{-1.0}, {-1.0}};
 // marginal rates of the slot kernel over the pairs that share a non-dense branch
 // (fitted to the optimum of a threshold sweep: near the threshold the lists are
 // long and the walk keeps its lanes full).
-constexpr double kRateBandDense = 2.9e13;
-constexpr double kRateGramMfma = 2.2e14;
-constexpr double kRatePairsWeighted = 7.9e11;
-constexpr double kRatePairsUnweighted = 9.0e11;
+constexpr double kRateBandDense = 3.05e13;
+constexpr double kRateGramMfma = 2.87e14;
+constexpr double kRatePairsWeighted = 6.4e11;
+constexpr double kRatePairsUnweighted = 9.3e11;
 
 uf_status fail(uf_status st, const std::string& msg) {
     g_last_error = msg;
