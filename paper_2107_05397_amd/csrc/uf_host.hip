@@ -441,7 +441,7 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
     const bool mfma = prec == UF_MFMA_BF16X2 || prec == UF_MFMA_SPLIT;
     const int64_t nb = split ? e->split[weighted ? 1 : 0]->n_dense : e->nb;
-    const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 2 : 4);
+    const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 1 : 4);
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
         const double budget = 8.0 * 1024 * 1024 * 1024;
@@ -459,7 +459,7 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     p->off_acc = c.take(size_t(p->sr) * size_t(n) * acc_elem);
     p->off_q = rowstats ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
     if (mfma)
-        p->off_chunk = c.take(size_t(n) * size_t(p->kpad) * 2);
+        p->off_chunk = c.take(size_t(n) * size_t(p->kpad));   // FP8 presence
     else
         p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
     p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
@@ -547,11 +547,11 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
                                  static_cast<float*>(acc), s));
         } else {
             const bool ms = prec == UF_MFMA_SPLIT;
-            uint16_t* P = static_cast<uint16_t*>(chunk);
+            uint8_t* P = static_cast<uint8_t*>(chunk);
             const int64_t kpad = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
             {
                 ProfScope ps("embed_pres", s);
-                UF_HIP(ufk::embed_presence_bf16(*e, k0, kc, kpad, P, s,
+                UF_HIP(ufk::embed_presence_fp8(*e, k0, kc, kpad, P, s,
                                                 ms ? sp->dense : nullptr));
             }
             ProfScope ps("gram_mfma", s);

@@ -143,10 +143,11 @@ hipError_t embed_node_major_f64(const uf_embedding& e, int64_t k0, int64_t kc, i
                                 double* out, hipStream_t st);
 hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
                                 float* out, hipStream_t st);
-// Sample-major BF16 0/1 presence P[s][k], k < kpad (zero beyond kc), for positions
-// [k0, k0+kc), or for positions list[k0 .. k0+kc) when list is non-null.
-hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
-                               uint16_t* out, hipStream_t st, const int32_t* list = nullptr);
+// Sample-major FP8 (e4m3) 0/1 presence P[s][k] (0x38 or 0), k < kpad (zero beyond
+// kc), for positions [k0, k0+kc), or for positions list[k0 .. k0+kc) when list is
+// non-null.  kpad is a multiple of kGramKPad.
+hipError_t embed_presence_fp8(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
+                              uint8_t* out, hipStream_t st, const int32_t* list = nullptr);
 
 // Band accumulation over one node chunk for stripes [sb, se):
 // weighted: acc += sum_k |E[k][i] - E[k][j]|;  unweighted: acc += sum_k l_k E[k][i] E[k][j].
@@ -159,10 +160,10 @@ hipError_t band_f32(const float* E, const float* lenk, int64_t kc, int64_t n, in
 hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_t se, int first,
                     uint32_t* acc, hipStream_t st);
 
-// MFMA Gram over one chunk: for every upper-triangle 128x128 tile (bi <= bj) that holds
+// MFMA Gram over one chunk: for every upper-triangle 256x256 tile (bi <= bj) that holds
 // a pair of stripes [sb, se), G_ij (+)= sum_k P_ik P_jk (hi_k + lo_k), scattered into the
-// FP32 stripe-major accumulator (first: overwrite, else add).
-hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
+// FP32 stripe-major accumulator (first: overwrite, else add).  P: FP8 presence as above.
+hipError_t gram_mfma(const uint8_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
                      int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st);
 
 // Distances from the accumulators.  kind 0: weighted (num / (s_i + s_j));

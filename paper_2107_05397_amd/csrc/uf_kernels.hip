@@ -3,7 +3,7 @@
 //
 //   k_sample_scalars   per-sample FP64 scalars from the postorder leaf intervals
 //   k_embed_nm<T>      node-major chunk of the embedding (weighted or 0/1)
-//   k_embed_pres_bf16  sample-major BF16 0/1 presence for the MFMA Gram path (merge)
+//   k_embed_pres_bf16  sample-major FP8 (e4m3) 0/1 presence for the MFMA Gram path (merge)
 //   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled);
 //                      T = uint32_t: weighted, 32-bit fixed point, one v_sad_u32
 //                      (|a - b| + acc) per update
@@ -148,21 +148,22 @@ __global__ __launch_bounds__(256) void k_embed_nm(
     }
 }
 
-// Sample-major BF16 presence: out[s][k], k in [0, kpad); 0x3F80 = 1.0, zero past kc.
-// Sample-major BF16 presence by a forward merge.  Postorder positions have
+// Sample-major FP8 (e4m3) presence out[s][k], k in [0, kpad): 0x38 (1.0) or 0,
+// zero past kc; the Gram kernel widens it to BF16 on the way into LDS.  Built by
+// a forward merge.  Postorder positions have
 // non-decreasing hi, so along a list of ascending positions a cursor over the
 // sample's tips (sorted by rank) only moves forward: it stops at the first tip
 // with rank >= hi, and the branch is touched iff the last tip before it has rank
 // >= lo.  Thread = sample; block = 256 samples x 64 list entries, transposed
-// through LDS into 128-byte row writes.  Entries in [kc, kpad) are zero.
+// through LDS into 64-byte row writes.  Entries in [kc, kpad) are zero.
 constexpr int kPresSamples = 256, kPresQ = 64;
 __global__ __launch_bounds__(256) void k_embed_pres_bf16(
     int64_t n, int64_t k0, int64_t kc, int64_t kpad, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ lo,
     const int32_t* __restrict__ hi, const int32_t* __restrict__ list,
-    uint16_t* __restrict__ out) {
-    // rows of 64 + 8 BF16 (144 bytes: 16-byte aligned, rows spread over banks)
-    __shared__ __attribute__((aligned(16))) uint16_t tile[kPresSamples][kPresQ + 8];
+    uint8_t* __restrict__ out) {
+    // rows of 64 + 16 bytes (80 bytes: 16-byte aligned, rows spread over banks)
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kPresSamples][kPresQ + 16];
     __shared__ int32_t qlo[kPresQ], qhi[kPresQ];
     const int tid = threadIdx.x;
     const int64_t sb = int64_t(blockIdx.x) * kPresSamples;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
             // that a query which does not move the cursor loads nothing
             int32_t nxt = cur < b ? rank[cur] : 0x7fffffff;
             for (int q8 = 0; q8 < kPresQ; q8 += 8) {
-                unsigned w[4] = {0u, 0u, 0u, 0u};
+                unsigned w[2] = {0u, 0u};
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int q = q8 + u;
@@ -200,18 +201,18 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
                             ++cur;
                             nxt = cur < b ? rank[cur] : 0x7fffffff;
                         }
-                        if (last >= qlo[q]) w[u >> 1] |= 0x3F80u << (16 * (u & 1));
+                        if (last >= qlo[q]) w[u >> 2] |= 0x38u << (8 * (u & 3));
                     }
                 }
-                *reinterpret_cast<uint4*>(&tile[tid][q8]) = make_uint4(w[0], w[1], w[2], w[3]);
+                *reinterpret_cast<uint2*>(&tile[tid][q8]) = make_uint2(w[0], w[1]);
             }
         }
         __syncthreads();
-        for (int c = tid; c < kPresSamples * (kPresQ / 8); c += 256) {
-            const int row = c / (kPresQ / 8), part = c % (kPresQ / 8);
+        for (int c = tid; c < kPresSamples * (kPresQ / 16); c += 256) {
+            const int row = c / (kPresQ / 16), part = c % (kPresQ / 16);
             if (sb + row < n)
-                *reinterpret_cast<uint4*>(out + (sb + row) * kpad + q0 + part * 8) =
-                    *reinterpret_cast<const uint4*>(&tile[row][part * 8]);
+                *reinterpret_cast<uint4*>(out + (sb + row) * kpad + q0 + part * 16) =
+                    *reinterpret_cast<const uint4*>(&tile[row][part * 16]);
         }
         __syncthreads();
     }
@@ -401,8 +402,9 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
 
 // ----------------------------------------------------------------------------
 // Unweighted Gram product on MFMA: G = P diag(l) P^T with P the 0/1 presence
-// (exact in BF16) and l = l_hi + l_lo, both BF16; two MFMAs per K step share
-// the A fragment.  v_mfma_f32_32x32x16_bf16 accumulates in FP32.
+// (FP8 e4m3 in HBM, widened to BF16, exact either way) and l = l_hi + l_lo, both
+// BF16; two MFMAs per K step share the A fragment.  v_mfma_f32_32x32x16_bf16
+// accumulates in FP32.
 // Block = 8 waves in 2x4, tile 256x256 (wave 128x64 = 4x2 MFMA blocks of 32x32),
 // K step 32 staged through registers into two LDS stages (rows padded by 8 BF16
 // against bank conflicts); global loads run two K steps ahead of the MFMAs.
@@ -452,7 +454,7 @@ __device__ __forceinline__ bool gram_tile_of(int64_t b, int64_t nblk, int64_t& b
     return bi < nblk && bj < nblk && bj >= bi;
 }
 
-__global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict__ P,
+__global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict__ P,
                                                       const uint16_t* __restrict__ hiv,
                                                       const uint16_t* __restrict__ lov,
                                                       int64_t kpad, int64_t n, int64_t sb,
@@ -487,46 +489,49 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
     const int64_t ci = i0 + lrow < n ? i0 + lrow : n - 1;
     const int64_t cj = j0 + lrow < n ? j0 + lrow : n - 1;
 
-    // one K step in registers: 16 BF16 of rows ci and cj, and of l_hi, l_lo
+    // one K step in registers: 16 FP8 presence bytes of rows ci and cj, and 16
+    // BF16 of l_hi and of l_lo
     struct Regs {
-        uint4 a0, a1, b0, b1, h0, h1, l0, l1;
+        uint4 a, b, h0, h1, l0, l1;
     };
     // (Regs move by value: a reference would leave them in memory, which the
     // compiler may place in LDS and wait on at once)
     auto fetch = [&](int64_t k0) -> Regs {
         Regs R;
-        const uint4* asrc = reinterpret_cast<const uint4*>(P + ci * kpad + k0 + lseg);
-        const uint4* bsrc = reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
         const uint4* hsrc = reinterpret_cast<const uint4*>(hiv + k0 + lseg);
         const uint4* lsrc = reinterpret_cast<const uint4*>(lov + k0 + lseg);
-        R.a0 = asrc[0];
-        R.a1 = asrc[1];
-        R.b0 = bsrc[0];
-        R.b1 = bsrc[1];
+        R.a = *reinterpret_cast<const uint4*>(P + ci * kpad + k0 + lseg);
+        R.b = *reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
         R.h0 = hsrc[0];
         R.h1 = hsrc[1];
         R.l0 = lsrc[0];
         R.l1 = lsrc[1];
         return R;
     };
-    // B = P (0 or 0x3F80 per BF16) masked onto the lengths
-    auto mask = [](unsigned p) -> unsigned {
-        const unsigned lo = (p & 0x0000FFFFu) ? 0x0000FFFFu : 0u;
-        const unsigned hi = (p & 0xFFFF0000u) ? 0xFFFF0000u : 0u;
-        return lo | hi;
+    // two presence bytes (low half of x if half == 0) widened to two BF16 lanes
+    // of one dword: `one` per nonzero byte (0x3F80 for 1.0, 0xFFFF for a mask)
+    auto widen = [](unsigned x, int half, unsigned one) -> unsigned {
+        const unsigned b = x >> (16 * half);
+        return ((b & 0xFFu) ? one : 0u) | ((b & 0xFF00u) ? (one << 16) : 0u);
     };
     auto stash = [&](const Regs R, int buf) {
-        const uint4 m0 = make_uint4(mask(R.b0.x), mask(R.b0.y), mask(R.b0.z), mask(R.b0.w));
-        const uint4 m1 = make_uint4(mask(R.b1.x), mask(R.b1.y), mask(R.b1.z), mask(R.b1.w));
+        const unsigned ax[4] = {R.a.x, R.a.y, R.a.z, R.a.w};
+        const unsigned bx[4] = {R.b.x, R.b.y, R.b.z, R.b.w};
+        unsigned av[8], m[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            av[q] = widen(ax[q >> 1], q & 1, 0x3F80u);
+            m[q] = widen(bx[q >> 1], q & 1, 0xFFFFu);
+        }
         uint4* ad = reinterpret_cast<uint4*>(As[buf] + lrow * LD + lseg);
         uint4* hd = reinterpret_cast<uint4*>(Bh[buf] + lrow * LD + lseg);
         uint4* ld = reinterpret_cast<uint4*>(Bl[buf] + lrow * LD + lseg);
-        ad[0] = R.a0;
-        ad[1] = R.a1;
-        hd[0] = make_uint4(R.h0.x & m0.x, R.h0.y & m0.y, R.h0.z & m0.z, R.h0.w & m0.w);
-        hd[1] = make_uint4(R.h1.x & m1.x, R.h1.y & m1.y, R.h1.z & m1.z, R.h1.w & m1.w);
-        ld[0] = make_uint4(R.l0.x & m0.x, R.l0.y & m0.y, R.l0.z & m0.z, R.l0.w & m0.w);
-        ld[1] = make_uint4(R.l1.x & m1.x, R.l1.y & m1.y, R.l1.z & m1.z, R.l1.w & m1.w);
+        ad[0] = make_uint4(av[0], av[1], av[2], av[3]);
+        ad[1] = make_uint4(av[4], av[5], av[6], av[7]);
+        hd[0] = make_uint4(R.h0.x & m[0], R.h0.y & m[1], R.h0.z & m[2], R.h0.w & m[3]);
+        hd[1] = make_uint4(R.h1.x & m[4], R.h1.y & m[5], R.h1.z & m[6], R.h1.w & m[7]);
+        ld[0] = make_uint4(R.l0.x & m[0], R.l0.y & m[1], R.l0.z & m[2], R.l0.w & m[3]);
+        ld[1] = make_uint4(R.l1.x & m[4], R.l1.y & m[5], R.l1.z & m[6], R.l1.w & m[7]);
     };
     auto compute = [&](int buf) {
 #pragma unroll
@@ -564,7 +569,6 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint16_t* __restrict
     const int64_t nk = kpad / KT;
     const int64_t klast = kpad - KT;
     Regs R0 = fetch(0);
-    __builtin_amdgcn_sched_barrier(0);  // issue step 0 before step 1 (in-order wait counts)
     Regs R1 = fetch(KT);
     for (int64_t t = 0; t < nk; t += 2) {
         stash(R0, 0);
@@ -914,8 +918,8 @@ hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, i
     return embed_nm<float>(e, k0, kc, weighted, out, st);
 }
 
-hipError_t embed_presence_bf16(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
-                               uint16_t* out, hipStream_t st, const int32_t* list) {
+hipError_t embed_presence_fp8(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
+                              uint8_t* out, hipStream_t st, const int32_t* list) {
     if (kpad <= 0 || e.n <= 0) return hipSuccess;
     if (kpad % kPresQ != 0) return hipErrorInvalidValue;
     const int64_t gx = (e.n + kPresSamples - 1) / kPresSamples;
@@ -966,7 +970,7 @@ hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_
     return hipGetLastError();
 }
 
-hipError_t gram_mfma(const uint16_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
+hipError_t gram_mfma(const uint8_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
                      int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st) {
     if (se <= sb || n <= 0) return hipSuccess;
     const int64_t nblk = (n + kGramT - 1) / kGramT;
