@@ -1081,6 +1081,7 @@ struct uf_batch {
     int2* d_items = nullptr;
     int64_t* d_qbeg = nullptr;
     int64_t* d_qend = nullptr;
+    int32_t* d_lo_chunks = nullptr;           // positions of each chunk ordered by lo
     size_t off_E = 0, off_acc = 0, off_cnt = 0, ws_total = 0;
     hipStream_t cap = nullptr;                // capture stream (default priority)
     hipGraph_t graph = nullptr;
@@ -1169,6 +1170,16 @@ bool write_tune_cache(const char* path, const std::map<int64_t, TuneEntry>& m) {
 
 const char* tune_path(const char* p) { return p ? p : std::getenv("UF_TUNE_CACHE"); }
 
+// node-major FP32 embedding of chunk [k0, k0+kc) of every table: forward merge
+// when every sample total is below 2^32, else binary searches (same values)
+hipError_t batch_embed(const uf_batch* b, int64_t k0, int64_t kc, float* E, hipStream_t s) {
+    const uf_embedding& e = *b->emb;
+    if (b->d_lo_chunks && e.max_total < (int64_t(1) << 32))
+        return ufs::embed_batch_merge_f32(emb_view(e), b->d_tabs, b->d_tab_of, b->d_lo_chunks + k0,
+                                          k0, kc, E, s);
+    return ufk::embed_batch_f32(e, b->d_tabs, b->d_tab_of, k0, kc, E, s);
+}
+
 // enqueue the whole batch on stream s (also used under graph capture)
 uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t s) {
     float* E = reinterpret_cast<float*>(base + b->off_E);
@@ -1180,7 +1191,7 @@ uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t
     for (int64_t c = 0; c < b->n_chunks; ++c) {
         const int64_t k0 = c * b->kc;
         const int64_t kc = std::min<int64_t>(b->kc, e.nb - k0);
-        UF_HIP(ufk::embed_batch_f32(e, b->d_tabs, b->d_tab_of, k0, kc, E, s));
+        UF_HIP(batch_embed(b, k0, kc, E, s));
         if (b->n_items > 0)
             UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend,
                                             cnt + c * 8, kc, c == 0, acc, b->stage_branches, nblk, s));
@@ -1368,6 +1379,8 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         const size_t o_items = c.take(sizeof(int2) * size_t(std::max<int64_t>(b->n_items, 1)));
         const size_t o_qb = c.take(8 * 8);
         const size_t o_qe = c.take(8 * 8);
+        const int64_t nb = b->emb->nb;
+        const size_t o_lord = c.take(size_t(std::max<int64_t>(nb, 1)) * 4);
         if (hipMalloc(&b->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "batch descriptors");
         char* base = static_cast<char*>(b->arena);
         b->d_tabs = reinterpret_cast<BatchTable*>(base + o_tabs);
@@ -1375,6 +1388,19 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         b->d_items = reinterpret_cast<int2*>(base + o_items);
         b->d_qbeg = reinterpret_cast<int64_t*>(base + o_qb);
         b->d_qend = reinterpret_cast<int64_t*>(base + o_qe);
+        b->d_lo_chunks = reinterpret_cast<int32_t*>(base + o_lord);
+        {
+            // positions of each chunk [c kc, (c+1) kc) in ascending lo (stable)
+            std::vector<int32_t> ord(size_t(std::max<int64_t>(nb, 1)));
+            for (int64_t k = 0; k < nb; ++k) ord[size_t(k)] = int32_t(k);
+            for (int64_t k0 = 0; k0 < nb; k0 += kc) {
+                const auto first = ord.begin() + k0, last = ord.begin() + std::min<int64_t>(nb, k0 + kc);
+                std::stable_sort(first, last, [&](int32_t x, int32_t y) {
+                    return tree->lo[size_t(x)] < tree->lo[size_t(y)];
+                });
+            }
+            if (nb) UF_HIP(hipMemcpy(b->d_lo_chunks, ord.data(), size_t(nb) * 4, hipMemcpyHostToDevice));
+        }
         UF_HIP(hipMemcpy(b->d_tabs, b->tabs.data(), sizeof(BatchTable) * size_t(n_tables), hipMemcpyHostToDevice));
         UF_HIP(hipMemcpy(b->d_tab_of, tab_of.data(), size_t(n_all) * 4, hipMemcpyHostToDevice));
         if (b->n_items) UF_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * size_t(b->n_items), hipMemcpyHostToDevice));
@@ -1554,7 +1580,7 @@ uf_status uf_autotune(uf_batch* b, void* ws, size_t ws_bytes, const char* tune_c
         const uf_embedding& e = *b->emb;
         if (b->n_chunks == 0 || b->n_items == 0) return UF_OK;
         const int64_t kc = std::min<int64_t>(b->kc, e.nb);
-        UF_HIP(ufk::embed_batch_f32(e, b->d_tabs, b->d_tab_of, 0, kc, E, s));
+        UF_HIP(batch_embed(b, 0, kc, E, s));
         hipEvent_t e0, e1;
         UF_HIP(hipEventCreate(&e0));
         UF_HIP(hipEventCreate(&e1));

@@ -7,6 +7,8 @@
 
 #include "uf_place.h"
 
+struct BatchTable;
+
 namespace ufs {
 
 constexpr int32_t kClassDense = -1;    // branch in the dense set
@@ -65,6 +67,12 @@ hipError_t embed_list_f32(const ufp::Emb& e, const int32_t* list, const int32_t*
 hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, const int32_t* lo_ord,
                           int64_t n_list, bool merge, int64_t k0, int64_t kc, double q,
                           uint32_t* out, hipStream_t st);
+// The same two merge passes for a batch: every position of [k0, k0+kc) (FP32),
+// each sample's values into its table's block [kc][n_t] at e_off.  lo_ord_chunk:
+// the chunk's kc positions ordered by lo.  Every T_s must be below 2^32.
+hipError_t embed_batch_merge_f32(const ufp::Emb& e, const BatchTable* tabs, const int32_t* tab_of,
+                                 const int32_t* lo_ord_chunk, int64_t k0, int64_t kc, float* out,
+                                 hipStream_t st);
 // Per-list (hi+lo) branch length in fixed point, and the bf16 length parts of the
 // dense set gathered in order (zero beyond n_dense up to n_pad).
 hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,

@@ -205,10 +205,29 @@ __global__ __launch_bounds__(256) void k_embed_list(ufp::Emb e, const int32_t* _
 // prefix is re-read only in lanes whose cursor moved.
 constexpr int kMergeQ = 64;
 
+// Where element (k - k0, s) of the chunk goes: row-major [kc][n] (tabs null), or
+// the block [kc][n_t] of the sample's table in a batch.
+struct ChunkSlot {
+    int64_t base, stride;
+    __device__ ChunkSlot(int64_t s, int64_t n, const BatchTable* tabs, const int32_t* tab_of) {
+        if (tabs) {
+            const BatchTable t = tabs[tab_of[s]];
+            base = t.e_off + (s - t.off);
+            stride = t.n;
+        } else {
+            base = s;
+            stride = n;
+        }
+    }
+    __device__ size_t at(int64_t kk) const { return size_t(base + kk * stride); }
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t* __restrict__ list,
                                                        const int32_t* __restrict__ lo_ord,
                                                        int64_t n_list, int64_t k0, int64_t kc,
+                                                       const BatchTable* __restrict__ tabs,
+                                                       const int32_t* __restrict__ tab_of,
                                                        T* __restrict__ out) {
     __shared__ int32_t qk[kMergeQ], ql[kMergeQ];
     const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -221,10 +240,11 @@ __global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t
         if (threadIdx.x < nq) {
             const int32_t k = lo_ord[t0 + threadIdx.x];
             qk[threadIdx.x] = k;
-            ql[threadIdx.x] = e.lo[list[k]];
+            ql[threadIdx.x] = e.lo[list ? list[k] : k];
         }
         __syncthreads();
         if (s >= e.n) continue;
+        const ChunkSlot slot(s, e.n, tabs, tab_of);
         const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
         int64_t cur = ufd::lower_bound_rank(e.rank, a, b, ql[0]);
         uint32_t below = uint32_t(e.cum[cur + s]);
@@ -238,7 +258,7 @@ __global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t
             }
             if (cur != from) below = uint32_t(e.cum[cur + s]);
             const int64_t k = qk[t];
-            if (k >= k0 && k < k0 + kc) o[(k - k0) * e.n + s] = below;
+            if (k >= k0 && k < k0 + kc) o[slot.at(k - k0)] = below;
         }
     }
 }
@@ -246,6 +266,8 @@ __global__ __launch_bounds__(256) void k_embed_list_lo(ufp::Emb e, const int32_t
 template <typename T>
 __global__ __launch_bounds__(256) void k_embed_list_hi(ufp::Emb e, const int32_t* __restrict__ list,
                                                        int64_t k0, int64_t kc, double q,
+                                                       const BatchTable* __restrict__ tabs,
+                                                       const int32_t* __restrict__ tab_of,
                                                        T* __restrict__ out) {
     __shared__ int32_t qh[kMergeQ];
     __shared__ double qlen[kMergeQ];
@@ -257,12 +279,13 @@ __global__ __launch_bounds__(256) void k_embed_list_hi(ufp::Emb e, const int32_t
         const int nq = k0 + kc - t0 < kMergeQ ? int(k0 + kc - t0) : kMergeQ;
         __syncthreads();
         if (threadIdx.x < nq) {
-            const int32_t pos = list[t0 + threadIdx.x];
+            const int64_t pos = list ? int64_t(list[t0 + threadIdx.x]) : t0 + threadIdx.x;
             qh[threadIdx.x] = e.hi[pos];
             qlen[threadIdx.x] = e.len[pos];
         }
         __syncthreads();
         if (s >= e.n) continue;
+        const ChunkSlot slot(s, e.n, tabs, tab_of);
         const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
         int64_t cur = ufd::lower_bound_rank(e.rank, a, b, qh[0]);
         uint32_t below = uint32_t(e.cum[cur + s]);
@@ -275,7 +298,7 @@ __global__ __launch_bounds__(256) void k_embed_list_hi(ufp::Emb e, const int32_t
                 nxt = cur < b ? e.rank[cur] : 0x7fffffff;
             }
             if (cur != from) below = uint32_t(e.cum[cur + s]);
-            const size_t idx = size_t(t0 + t - k0) * size_t(e.n) + size_t(s);
+            const size_t idx = slot.at(t0 + t - k0);
             const int64_t c = int64_t(below - reinterpret_cast<const uint32_t*>(out)[idx]);
             const double x = qlen[t] * (double(c) / tot);
             T v;
@@ -476,11 +499,13 @@ static hipError_t embed_list(const ufp::Emb& e, const int32_t* list, const int32
         const int64_t gy_hi = std::min<int64_t>((kc + kMergeQ - 1) / kMergeQ, 65535);
         if (gx > 0x7fffffff) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_embed_list_lo<T>, dim3(unsigned(gx), unsigned(gy_lo)), dim3(256), 0, st,
-                           e, list, lo_ord, n_list, k0, kc, out);
+                           e, list, lo_ord, n_list, k0, kc, static_cast<const BatchTable*>(nullptr),
+                           static_cast<const int32_t*>(nullptr), out);
         hipError_t rc = hipGetLastError();
         if (rc != hipSuccess) return rc;
         hipLaunchKernelGGL(k_embed_list_hi<T>, dim3(unsigned(gx), unsigned(gy_hi)), dim3(256), 0, st,
-                           e, list, k0, kc, q, out);
+                           e, list, k0, kc, q, static_cast<const BatchTable*>(nullptr),
+                           static_cast<const int32_t*>(nullptr), out);
         return hipGetLastError();
     }
     const int64_t gy = (e.n + 63) / 64;
@@ -500,6 +525,23 @@ hipError_t embed_list_u32(const ufp::Emb& e, const int32_t* list, const int32_t*
                           int64_t n_list, bool merge, int64_t k0, int64_t kc, double q,
                           uint32_t* out, hipStream_t st) {
     return embed_list<uint32_t>(e, list, lo_ord, n_list, merge, k0, kc, q, out, st);
+}
+
+hipError_t embed_batch_merge_f32(const ufp::Emb& e, const BatchTable* tabs, const int32_t* tab_of,
+                                 const int32_t* lo_ord_chunk, int64_t k0, int64_t kc, float* out,
+                                 hipStream_t st) {
+    if (kc <= 0 || e.n <= 0) return hipSuccess;
+    const int64_t gx = (e.n + 255) / 256;
+    const int64_t gy = std::min<int64_t>((kc + kMergeQ - 1) / kMergeQ, 65535);
+    if (gx > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_embed_list_lo<float>, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, st, e,
+                       static_cast<const int32_t*>(nullptr), lo_ord_chunk, kc, k0, kc, tabs, tab_of,
+                       out);
+    hipError_t rc = hipGetLastError();
+    if (rc != hipSuccess) return rc;
+    hipLaunchKernelGGL(k_embed_list_hi<float>, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, st, e,
+                       static_cast<const int32_t*>(nullptr), k0, kc, 1.0, tabs, tab_of, out);
+    return hipGetLastError();
 }
 
 hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,
