@@ -129,8 +129,8 @@ namespace ufk {
 constexpr int kBandI = 128;       // samples per band tile
 constexpr int kBandS = 128;       // stripes per band tile
 constexpr int kGramT = 256;       // square tile of the MFMA Gram kernel
-constexpr int kGramK = 32;        // K step of the MFMA Gram kernel
-constexpr int kGramKPad = 64;     // K of its presence matrix is padded to this (steps go in pairs)
+constexpr int kGramK = 64;        // K step of the MFMA Gram kernel
+constexpr int kGramKPad = 128;    // K of its presence matrix is padded to this (steps go in pairs)
 
 // Per-sample scalars from the postorder leaf intervals (one wave per sample).
 hipError_t sample_scalars(const uf_embedding& e, const int32_t* parent_pos,
@@ -143,7 +143,7 @@ hipError_t embed_node_major_f64(const uf_embedding& e, int64_t k0, int64_t kc, i
                                 double* out, hipStream_t st);
 hipError_t embed_node_major_f32(const uf_embedding& e, int64_t k0, int64_t kc, int weighted,
                                 float* out, hipStream_t st);
-// Sample-major FP8 (e4m3) 0/1 presence P[s][k] (0x38 or 0), k < kpad (zero beyond
+// Sample-major presence P[s][k]: FP8 e4m3 -2.0 (0xC0) where present, else 0, k < kpad (zero beyond
 // kc), for positions [k0, k0+kc), or for positions list[k0 .. k0+kc) when list is
 // non-null.  kpad is a multiple of kGramKPad.
 hipError_t embed_presence_fp8(const uf_embedding& e, int64_t k0, int64_t kc, int64_t kpad,
@@ -161,8 +161,9 @@ hipError_t band_u32(const uint32_t* E, int64_t kc, int64_t n, int64_t sb, int64_
                     uint32_t* acc, hipStream_t st);
 
 // MFMA Gram over one chunk: for every upper-triangle 256x256 tile (bi <= bj) that holds
-// a pair of stripes [sb, se), G_ij (+)= sum_k P_ik P_jk (hi_k + lo_k), scattered into the
-// FP32 stripe-major accumulator (first: overwrite, else add).  P: FP8 presence as above.
+// a pair of stripes [sb, se), G_ij (+)= sum_k [P_ik != 0][P_jk != 0] (hi_k + lo_k), scattered
+// into the FP32 stripe-major accumulator (first: overwrite, else add).  P: presence bytes as
+// above; hi and lo hold kpad values from the chunk's first position (zero past its end).
 hipError_t gram_mfma(const uint8_t* P, const uint16_t* hi, const uint16_t* lo, int64_t kpad,
                      int64_t n, int64_t sb, int64_t se, int first, float* acc, hipStream_t st);
 

@@ -3,7 +3,7 @@
 //
 //   k_sample_scalars   per-sample FP64 scalars from the postorder leaf intervals
 //   k_embed_nm<T>      node-major chunk of the embedding (weighted or 0/1)
-//   k_embed_pres_bf16  sample-major FP8 (e4m3) 0/1 presence for the MFMA Gram path (merge)
+//   k_embed_pres_fp8  sample-major FP8 (e4m3) 0/1 presence for the MFMA Gram path (merge)
 //   k_band<T, W>       stripe-band accumulation on the vector ALUs (LDS-tiled);
 //                      T = uint32_t: weighted, 32-bit fixed point, one v_sad_u32
 //                      (|a - b| + acc) per update
@@ -148,8 +148,9 @@ __global__ __launch_bounds__(256) void k_embed_nm(
     }
 }
 
-// Sample-major FP8 (e4m3) presence out[s][k], k in [0, kpad): 0x38 (1.0) or 0,
-// zero past kc; the Gram kernel widens it to BF16 on the way into LDS.  Built by
+// Sample-major presence out[s][k], k in [0, kpad): FP8 e4m3 -2.0 (0xC0) or 0,
+// zero past kc.  The Gram kernel turns a byte into a BF16 operand (the byte as
+// high byte: -2.0) or into a length mask (from its sign bit).  Built by
 // a forward merge.  Postorder positions have
 // non-decreasing hi, so along a list of ascending positions a cursor over the
 // sample's tips (sorted by rank) only moves forward: it stops at the first tip
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_embed_nm(
 // >= lo.  Thread = sample; block = 256 samples x 64 list entries, transposed
 // through LDS into 64-byte row writes.  Entries in [kc, kpad) are zero.
 constexpr int kPresSamples = 256, kPresQ = 64;
-__global__ __launch_bounds__(256) void k_embed_pres_bf16(
+__global__ __launch_bounds__(256) void k_embed_pres_fp8(
     int64_t n, int64_t k0, int64_t kc, int64_t kpad, const int64_t* __restrict__ row_ptr,
     const int32_t* __restrict__ rank, const int32_t* __restrict__ lo,
     const int32_t* __restrict__ hi, const int32_t* __restrict__ list,
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_embed_pres_bf16(
                             ++cur;
                             nxt = cur < b ? rank[cur] : 0x7fffffff;
                         }
-                        if (last >= qlo[q]) w[u >> 2] |= 0x38u << (8 * (u & 3));
+                        if (last >= qlo[q]) w[u >> 2] |= 0xC0u << (8 * (u & 3));
                     }
                 }
                 *reinterpret_cast<uint2*>(&tile[tid][q8]) = make_uint2(w[0], w[1]);
@@ -402,12 +403,19 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
 
 // ----------------------------------------------------------------------------
 // Unweighted Gram product on MFMA: G = P diag(l) P^T with P the 0/1 presence
-// (FP8 e4m3 in HBM, widened to BF16, exact either way) and l = l_hi + l_lo, both
-// BF16; two MFMAs per K step share the A fragment.  v_mfma_f32_32x32x16_bf16
-// accumulates in FP32.
+// and l = l_hi + l_lo, both BF16; v_mfma_f32_32x32x16_bf16 accumulates in FP32.
 // Block = 8 waves in 2x4, tile 256x256 (wave 128x64 = 4x2 MFMA blocks of 32x32),
-// K step 32 staged through registers into two LDS stages (rows padded by 8 BF16
-// against bank conflicts); global loads run two K steps ahead of the MFMAs.
+// K step 64.  Presence bytes go through LDS as they are (rows of 64 + 16 bytes)
+// and become MFMA operands in registers:
+// * A (rows i): the byte as the high byte of a BF16 lane, -2.0 where present;
+// * B (rows j): the byte's sign bit spread over a BF16 lane, as a mask of the
+//   K step's l_hi and l_lo (staged in LDS, read as broadcasts).
+// So the MFMAs sum -2 l over the shared branches (exactly twice the negated
+// sum in FP32) and the epilogue scales by -1/2.  The contraction is free to
+// order K within a step: the MFMA of sub-step s takes, from lane group g
+// (lanes 32g..32g+31), the positions 32g + 8s + [0, 8), so that one 16-byte LDS
+// read serves two sub-steps.  Global loads run two K steps ahead of the
+// MFMAs, through registers into two LDS stages.
 // Only upper-triangle tiles (bi <= bj) that hold a pair of the stripe range
 // run; each pair i<j of the range is written to its stripe-major slot.
 // ----------------------------------------------------------------------------
@@ -460,20 +468,23 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
                                                       int64_t kpad, int64_t n, int64_t sb,
                                                       int64_t se, int first,
                                                       float* __restrict__ acc) {
-    constexpr int T = kGramT, KT = kGramK, LD = KT + 8;
+    constexpr int T = kGramT, KT = kGramK, LD = KT + 16;
+    static_assert(KT == 64, "the fragment layout below assumes a K step of 64");
     int64_t bi, bj;
     if (!gram_tile_of(blockIdx.x, (n + T - 1) / T, bi, bj)) return;
     const int64_t i0 = bi * T, j0 = bj * T;
     if (!tile_in_range(i0, j0, n, sb, se)) return;
 
-    // two LDS stages of A (presence rows i), Bh and Bl (length-masked presence rows j)
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][T * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bh[2][T * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bl[2][T * LD];
+    // two LDS stages of the presence bytes of rows i (A) and j (B), and of the
+    // step's lengths (l_hi in [0, KT), l_lo in [KT, 2 KT))
+    __shared__ __attribute__((aligned(16))) uint8_t As[2][T * LD];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T * LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Ls[2][2 * KT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wi = wave & 1, wj = wave >> 1;     // wave tile: rows wi*128 + [0,128), cols wj*64 + [0,64)
+    const int lg = lane >> 5;                    // lane group: K positions 32*lg + [0, 32) of a step
     floatx16 c[4][2];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -482,80 +493,113 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
 
-    const int lrow = tid >> 1;          // staging: row of the tile
-    const int lseg = (tid & 1) * 16;    // staging: first of 16 K columns
+    // staging: row (tid mod 256) of the tile, bytes 32 * (tid / 256) + [0, 32) of
+    // the step (eight consecutive rows fill all LDS banks: the row pitch is an odd
+    // multiple of 16 bytes); and 16 bytes of the step's lengths (every thread loads
+    // them, the first 16 threads store them)
+    const int lrow = tid & (T - 1);
+    const int lseg = (tid >> 8) * 32;
+    const int lq = tid & 15;
+    const uint16_t* lsrc = (lq < 8 ? hiv : lov) + 8 * (lq & 7);
     // rows past n read row n-1: their products land in rows/columns >= n, which
     // the epilogue drops
     const int64_t ci = i0 + lrow < n ? i0 + lrow : n - 1;
     const int64_t cj = j0 + lrow < n ? j0 + lrow : n - 1;
 
-    // one K step in registers: 16 FP8 presence bytes of rows ci and cj, and 16
-    // BF16 of l_hi and of l_lo
     struct Regs {
-        uint4 a, b, h0, h1, l0, l1;
+        uint4 a0, a1, b0, b1, l;
     };
     // (Regs move by value: a reference would leave them in memory, which the
     // compiler may place in LDS and wait on at once)
     auto fetch = [&](int64_t k0) -> Regs {
         Regs R;
-        const uint4* hsrc = reinterpret_cast<const uint4*>(hiv + k0 + lseg);
-        const uint4* lsrc = reinterpret_cast<const uint4*>(lov + k0 + lseg);
-        R.a = *reinterpret_cast<const uint4*>(P + ci * kpad + k0 + lseg);
-        R.b = *reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
-        R.h0 = hsrc[0];
-        R.h1 = hsrc[1];
-        R.l0 = lsrc[0];
-        R.l1 = lsrc[1];
+        const uint4* pa = reinterpret_cast<const uint4*>(P + ci * kpad + k0 + lseg);
+        const uint4* pb = reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
+        R.a0 = pa[0];
+        R.a1 = pa[1];
+        R.b0 = pb[0];
+        R.b1 = pb[1];
+        R.l = *reinterpret_cast<const uint4*>(lsrc + k0);
         return R;
     };
-    // two presence bytes (low half of x if half == 0) widened to two BF16 lanes
-    // of one dword: `one` per nonzero byte (0x3F80 for 1.0, 0xFFFF for a mask)
-    auto widen = [](unsigned x, int half, unsigned one) -> unsigned {
-        const unsigned b = x >> (16 * half);
-        return ((b & 0xFFu) ? one : 0u) | ((b & 0xFF00u) ? (one << 16) : 0u);
-    };
     auto stash = [&](const Regs R, int buf) {
-        const unsigned ax[4] = {R.a.x, R.a.y, R.a.z, R.a.w};
-        const unsigned bx[4] = {R.b.x, R.b.y, R.b.z, R.b.w};
-        unsigned av[8], m[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            av[q] = widen(ax[q >> 1], q & 1, 0x3F80u);
-            m[q] = widen(bx[q >> 1], q & 1, 0xFFFFu);
-        }
         uint4* ad = reinterpret_cast<uint4*>(As[buf] + lrow * LD + lseg);
-        uint4* hd = reinterpret_cast<uint4*>(Bh[buf] + lrow * LD + lseg);
-        uint4* ld = reinterpret_cast<uint4*>(Bl[buf] + lrow * LD + lseg);
-        ad[0] = make_uint4(av[0], av[1], av[2], av[3]);
-        ad[1] = make_uint4(av[4], av[5], av[6], av[7]);
-        hd[0] = make_uint4(R.h0.x & m[0], R.h0.y & m[1], R.h0.z & m[2], R.h0.w & m[3]);
-        hd[1] = make_uint4(R.h1.x & m[4], R.h1.y & m[5], R.h1.z & m[6], R.h1.w & m[7]);
-        ld[0] = make_uint4(R.l0.x & m[0], R.l0.y & m[1], R.l0.z & m[2], R.l0.w & m[3]);
-        ld[1] = make_uint4(R.l1.x & m[4], R.l1.y & m[5], R.l1.z & m[6], R.l1.w & m[7]);
+        uint4* bd = reinterpret_cast<uint4*>(Bs[buf] + lrow * LD + lseg);
+        ad[0] = R.a0;
+        ad[1] = R.a1;
+        bd[0] = R.b0;
+        bd[1] = R.b1;
+        if (tid < 16) reinterpret_cast<uint4*>(Ls[buf])[lq] = R.l;
     };
+    // v_perm_b32 selectors over {S0, S1} (S1 = bytes 0-3, S0 = bytes 4-7):
+    // 12 -> 0x00; 8, 9, 10, 11 -> sign bit of byte 1, 3, 5, 7 spread over a byte
+    constexpr unsigned kSelA0 = 0x010C000Cu;   // bytes 0, 1 -> high bytes of two BF16 lanes
+    constexpr unsigned kSelA1 = 0x030C020Cu;   // bytes 2, 3
+    constexpr unsigned kSelM0 = 0x08080A0Au;   // S0 = x << 8: masks of bytes 0, 1
+    constexpr unsigned kSelM1 = 0x09090B0Bu;   // masks of bytes 2, 3
     auto compute = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < KT; kk += 16) {
-            const int kq = kk + 8 * (lane >> 5);
-            bf16x8 fa[4], fh[2], fl[2];
+        for (int h = 0; h < 2; ++h) {
+            // 16 bytes per fragment row: positions 32*lg + 16*h + [0, 16), i.e.
+            // sub-steps 2h and 2h+1
+            uint4 ra[4], rb[2];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int row = wi * 128 + x * 32 + (lane & 31);
-                fa[x] = *reinterpret_cast<const bf16x8*>(As[buf] + row * LD + kq);
+                ra[x] = *reinterpret_cast<const uint4*>(As[buf] + row * LD + 32 * lg + 16 * h);
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 const int col = wj * 64 + y * 32 + (lane & 31);
-                fh[y] = *reinterpret_cast<const bf16x8*>(Bh[buf] + col * LD + kq);
-                fl[y] = *reinterpret_cast<const bf16x8*>(Bl[buf] + col * LD + kq);
+                rb[y] = *reinterpret_cast<const uint4*>(Bs[buf] + col * LD + 32 * lg + 16 * h);
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int q = 0; q < 2; ++q) {
+                const int kq = 32 * lg + 16 * h + 8 * q;
+                const uint4 lh = *reinterpret_cast<const uint4*>(Ls[buf] + kq);
+                const uint4 ll = *reinterpret_cast<const uint4*>(Ls[buf] + KT + kq);
+                const unsigned lhw[4] = {lh.x, lh.y, lh.z, lh.w};
+                const unsigned llw[4] = {ll.x, ll.y, ll.z, ll.w};
+                bf16x8 fa[4], fh[2], fl[2];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const unsigned u0 = q ? ra[x].z : ra[x].x, u1 = q ? ra[x].w : ra[x].y;
+                    unsigned w[4];
+                    w[0] = __builtin_amdgcn_perm(0u, u0, kSelA0);
+                    w[1] = __builtin_amdgcn_perm(0u, u0, kSelA1);
+                    w[2] = __builtin_amdgcn_perm(0u, u1, kSelA0);
+                    w[3] = __builtin_amdgcn_perm(0u, u1, kSelA1);
+                    __builtin_memcpy(&fa[x], w, sizeof(w));
+                }
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
-                    c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fh[y], c[x][y], 0, 0, 0);
-                    c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fl[y], c[x][y], 0, 0, 0);
+                    const unsigned u0 = q ? rb[y].z : rb[y].x, u1 = q ? rb[y].w : rb[y].y;
+                    unsigned m[4], wh[4], wl[4];
+                    m[0] = __builtin_amdgcn_perm(u0 << 8, u0, kSelM0);
+                    m[1] = __builtin_amdgcn_perm(u0 << 8, u0, kSelM1);
+                    m[2] = __builtin_amdgcn_perm(u1 << 8, u1, kSelM0);
+                    m[3] = __builtin_amdgcn_perm(u1 << 8, u1, kSelM1);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        wh[e] = m[e] & lhw[e];
+                        wl[e] = m[e] & llw[e];
+                    }
+                    __builtin_memcpy(&fh[y], wh, sizeof(wh));
+                    __builtin_memcpy(&fl[y], wl, sizeof(wl));
                 }
+                // the hi products of all eight blocks, then the lo products, so that
+                // no MFMA waits on the one before it
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fh[y], c[x][y], 0, 0, 0);
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fl[y], c[x][y], 0, 0, 0);
+            }
         }
     };
 
@@ -595,7 +639,7 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
                 const int64_t j = j0 + wj * 64 + y * 32 + (lane & 31);
                 if (!(i < j && j < n)) continue;
                 const int64_t d = j - i;
-                const float g = c[x][y][r];
+                const float g = -0.5f * c[x][y][r];
                 int64_t s, slot;
                 if (d <= S) { s = d - 1; slot = i; }
                 else { s = n - d - 1; slot = j; }
@@ -925,7 +969,7 @@ hipError_t embed_presence_fp8(const uf_embedding& e, int64_t k0, int64_t kc, int
     const int64_t gx = (e.n + kPresSamples - 1) / kPresSamples;
     const int64_t gy = std::min<int64_t>(kpad / kPresQ, 65535);
     if (gx > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_embed_pres_bf16, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, st, e.n,
+    hipLaunchKernelGGL(k_embed_pres_fp8, dim3(unsigned(gx), unsigned(gy)), dim3(256), 0, st, e.n,
                        k0, kc, kpad, e.row_ptr, e.rank, e.lo, e.hi, list, out);
     return hipGetLastError();
 }
