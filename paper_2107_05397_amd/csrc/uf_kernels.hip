@@ -436,30 +436,49 @@ __device__ __forceinline__ bool tile_in_range(int64_t i0, int64_t j0, int64_t n,
     return a1 <= b1 || a2 <= b2;
 }
 
-// Block -> tile of the Gram kernel.  Tiles are grouped in G x G super-tiles over
-// the upper triangle (super-row <= super-column); super-tile u runs on XCD u mod 8
-// (blocks are dealt to the 8 XCDs round-robin), so the ~2 blocks per CU of one XCD
-// cover one super-tile at a time and read each of its G row and G column panels
-// once into that XCD's L2 instead of once per tile.  Returns false for slots
-// outside the matrix or below the diagonal.
+// Block -> tile of the Gram kernel.  The upper-triangle tiles (bi <= bj) are
+// numbered super-tile by super-tile: G x G super-tiles, super-row-major, the
+// diagonal super-tile first in its super-row, tiles row-major inside.  Blocks are
+// dealt to the 8 XCDs round-robin, and XCD x takes the x-th eighth of that order:
+// its CUs walk neighbouring super-tiles together, reading each row and column
+// panel into the XCD's L2 about once per super-tile, and every XCD gets the same
+// number of tiles.  Returns false for slots past the last tile.
 constexpr int kGramGroup = 8;
 
 __device__ __forceinline__ bool gram_tile_of(int64_t b, int64_t nblk, int64_t& bi, int64_t& bj) {
-    constexpr int64_t G = kGramGroup, GG = G * G;
-    const int64_t ns = (nblk + G - 1) / G;
-    const int64_t x = b & 7, k = b >> 3;
-    int64_t u = (k / GG) * 8 + x;          // super-tile, upper triangle row-major
-    const int64_t w = k % GG;
-    int64_t si = 0;
-    while (si < ns && u >= ns - si) {
-        u -= ns - si;
-        ++si;
+    constexpr int64_t G = kGramGroup;
+    const int64_t L = nblk * (nblk + 1) / 2;
+    const int64_t per = (L + 7) / 8;
+    const int64_t k = b >> 3;
+    int64_t v = (b & 7) * per + k;
+    if (k >= per || v >= L) return false;
+    int64_t r0 = 0;                              // first row of the super-row
+    for (;;) {
+        const int64_t r = min(G, nblk - r0);     // rows of the super-row
+        const int64_t cnt = r * (r + 1) / 2 + r * (nblk - r0 - r);
+        if (v < cnt) {
+            const int64_t diag = r * (r + 1) / 2;
+            if (v < diag) {                      // diagonal super-tile: row a holds r - a tiles
+                int64_t a = 0;
+                while (v >= r - a) {
+                    v -= r - a;
+                    ++a;
+                }
+                bi = r0 + a;
+                bj = r0 + a + v;
+            } else {                             // off-diagonal super-tiles of r x G tiles (the last may be narrower)
+                v -= diag;
+                const int64_t c0 = r0 + r + (v / (r * G)) * G;   // first column of the super-tile
+                const int64_t c = min(G, nblk - c0);
+                const int64_t w = v % (r * G);
+                bi = r0 + w / c;
+                bj = c0 + w % c;
+            }
+            return true;
+        }
+        v -= cnt;
+        r0 += r;
     }
-    if (si >= ns) return false;
-    const int64_t sj = si + u;
-    bi = si * G + w / G;
-    bj = sj * G + w % G;
-    return bi < nblk && bj < nblk && bj >= bi;
 }
 
 __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict__ P,
@@ -1019,9 +1038,7 @@ hipError_t gram_mfma(const uint8_t* P, const uint16_t* hi, const uint16_t* lo, i
     if (se <= sb || n <= 0) return hipSuccess;
     const int64_t nblk = (n + kGramT - 1) / kGramT;
     if (nblk > 65535 || kpad <= 0 || (kpad % kGramKPad) != 0) return hipErrorInvalidValue;
-    const int64_t ns = (nblk + kGramGroup - 1) / kGramGroup;
-    const int64_t n_super = ns * (ns + 1) / 2;
-    const int64_t blocks = (n_super + 7) / 8 * 8 * kGramGroup * kGramGroup;
+    const int64_t blocks = 8 * ((nblk * (nblk + 1) / 2 + 7) / 8);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid{unsigned(blocks), 1u, 1u};
     hipLaunchKernelGGL(k_gram_mfma, grid, dim3(512), 0, st, P, hi, lo, kpad, n, sb, se, first,
