@@ -35,7 +35,7 @@ std::atomic<double> g_split_threshold[2] = {{-1.0}, {-1.0}};
 // (fitted to the optimum of a threshold sweep: near the threshold the lists are
 // long and the walk keeps its lanes full).
 constexpr double kRateBandDense = 3.05e13;
-constexpr double kRateGramMfma = 2.87e14;
+constexpr double kRateGramMfma = 3.78e14;
 constexpr double kRatePairsWeighted = 6.4e11;
 constexpr double kRatePairsUnweighted = 9.3e11;
 

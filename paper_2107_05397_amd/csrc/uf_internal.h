@@ -129,8 +129,8 @@ namespace ufk {
 constexpr int kBandI = 128;       // samples per band tile
 constexpr int kBandS = 128;       // stripes per band tile
 constexpr int kGramT = 256;       // square tile of the MFMA Gram kernel
-constexpr int kGramK = 64;        // K step of the MFMA Gram kernel
-constexpr int kGramKPad = 128;    // K of its presence matrix is padded to this (steps go in pairs)
+constexpr int kGramK = 128;        // K step of the MFMA Gram kernel
+constexpr int kGramKPad = 256;    // K of its presence matrix is padded to this (steps go in pairs)
 
 // Per-sample scalars from the postorder leaf intervals (one wave per sample).
 hipError_t sample_scalars(const uf_embedding& e, const int32_t* parent_pos,

@@ -405,17 +405,17 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
 // Unweighted Gram product on MFMA: G = P diag(l) P^T with P the 0/1 presence
 // and l = l_hi + l_lo, both BF16; v_mfma_f32_32x32x16_bf16 accumulates in FP32.
 // Block = 8 waves in 2x4, tile 256x256 (wave 128x64 = 4x2 MFMA blocks of 32x32),
-// K step 64.  Presence bytes go through LDS as they are (rows of 64 + 16 bytes)
+// K step 128.  Presence bytes go through LDS as they are (rows of 128 + 16 bytes)
 // and become MFMA operands in registers:
 // * A (rows i): the byte as the high byte of a BF16 lane, -2.0 where present;
 // * B (rows j): the byte's sign bit spread over a BF16 lane, as a mask of the
 //   K step's l_hi and l_lo (staged in LDS, read as broadcasts).
 // So the MFMAs sum -2 l over the shared branches (exactly twice the negated
 // sum in FP32) and the epilogue scales by -1/2.  The contraction is free to
-// order K within a step: the MFMA of sub-step s takes, from lane group g
-// (lanes 32g..32g+31), the positions 32g + 8s + [0, 8), so that one 16-byte LDS
-// read serves two sub-steps.  Global loads run two K steps ahead of the
-// MFMAs, through registers into two LDS stages.
+// order K within a step: the MFMA of sub-step s (0..7) takes, from lane group
+// g (lanes 32g..32g+31), the positions 64g + 8s + [0, 8), so that one 16-byte
+// LDS read serves two sub-steps.  Global loads run one K step ahead of the
+// MFMAs, through registers into two LDS stages (one barrier per K step).
 // Only upper-triangle tiles (bi <= bj) that hold a pair of the stripe range
 // run; each pair i<j of the range is written to its stripe-major slot.
 // ----------------------------------------------------------------------------
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
                                                       int64_t se, int first,
                                                       float* __restrict__ acc) {
     constexpr int T = kGramT, KT = kGramK, LD = KT + 16;
-    static_assert(KT == 64, "the fragment layout below assumes a K step of 64");
+    static_assert(KT % 32 == 0, "the fragment layout below assumes a K step of 32m");
     int64_t bi, bj;
     if (!gram_tile_of(blockIdx.x, (n + T - 1) / T, bi, bj)) return;
     const int64_t i0 = bi * T, j0 = bj * T;
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wi = wave & 1, wj = wave >> 1;     // wave tile: rows wi*128 + [0,128), cols wj*64 + [0,64)
-    const int lg = lane >> 5;                    // lane group: K positions 32*lg + [0, 32) of a step
+    const int lg = lane >> 5;                    // lane group: K positions (KT/2)*lg + [0, KT/2) of a step
     floatx16 c[4][2];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
@@ -512,21 +512,24 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
 #pragma unroll
             for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
 
-    // staging: row (tid mod 256) of the tile, bytes 32 * (tid / 256) + [0, 32) of
-    // the step (eight consecutive rows fill all LDS banks: the row pitch is an odd
-    // multiple of 16 bytes); and 16 bytes of the step's lengths (every thread loads
-    // them, the first 16 threads store them)
+    // staging: row (tid mod 256) of the tile, bytes (KT/2) * (tid / 256) + [0, KT/2)
+    // of the step (eight consecutive rows fill all LDS banks: the row pitch is an
+    // odd multiple of 16 bytes); and 16 bytes of the step's lengths (every thread
+    // loads them, the first KT/4 threads store them)
     const int lrow = tid & (T - 1);
-    const int lseg = (tid >> 8) * 32;
-    const int lq = tid & 15;
-    const uint16_t* lsrc = (lq < 8 ? hiv : lov) + 8 * (lq & 7);
+    const int lseg = (tid >> 8) * (KT / 2);
+    constexpr int NL = KT / 4;                  // 16-byte pieces of the step's lengths
+    const int lq = tid & (NL - 1);
+    const uint16_t* lsrc = (lq < NL / 2 ? hiv : lov) + 8 * (lq & (NL / 2 - 1));
     // rows past n read row n-1: their products land in rows/columns >= n, which
     // the epilogue drops
     const int64_t ci = i0 + lrow < n ? i0 + lrow : n - 1;
     const int64_t cj = j0 + lrow < n ? j0 + lrow : n - 1;
 
+    constexpr int NV = KT / 32;                 // 16-byte pieces per staged row half
+    static_assert(NV == 4, "named staging registers below");
     struct Regs {
-        uint4 a0, a1, b0, b1, l;
+        uint4 a0, a1, a2, a3, b0, b1, b2, b3, l;
     };
     // (Regs move by value: a reference would leave them in memory, which the
     // compiler may place in LDS and wait on at once)
@@ -536,8 +539,12 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
         const uint4* pb = reinterpret_cast<const uint4*>(P + cj * kpad + k0 + lseg);
         R.a0 = pa[0];
         R.a1 = pa[1];
+        R.a2 = pa[2];
+        R.a3 = pa[3];
         R.b0 = pb[0];
         R.b1 = pb[1];
+        R.b2 = pb[2];
+        R.b3 = pb[3];
         R.l = *reinterpret_cast<const uint4*>(lsrc + k0);
         return R;
     };
@@ -546,9 +553,13 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
         uint4* bd = reinterpret_cast<uint4*>(Bs[buf] + lrow * LD + lseg);
         ad[0] = R.a0;
         ad[1] = R.a1;
+        ad[2] = R.a2;
+        ad[3] = R.a3;
         bd[0] = R.b0;
         bd[1] = R.b1;
-        if (tid < 16) reinterpret_cast<uint4*>(Ls[buf])[lq] = R.l;
+        bd[2] = R.b2;
+        bd[3] = R.b3;
+        if (tid < NL) reinterpret_cast<uint4*>(Ls[buf])[lq] = R.l;
     };
     // v_perm_b32 selectors over {S0, S1} (S1 = bytes 0-3, S0 = bytes 4-7):
     // 12 -> 0x00; 8, 9, 10, 11 -> sign bit of byte 1, 3, 5, 7 spread over a byte
@@ -558,23 +569,23 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
     constexpr unsigned kSelM1 = 0x09090B0Bu;   // masks of bytes 2, 3
     auto compute = [&](int buf) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            // 16 bytes per fragment row: positions 32*lg + 16*h + [0, 16), i.e.
+        for (int h = 0; h < KT / 32; ++h) {
+            // 16 bytes per fragment row: positions (KT/2)*lg + 16*h + [0, 16), i.e.
             // sub-steps 2h and 2h+1
             uint4 ra[4], rb[2];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 const int row = wi * 128 + x * 32 + (lane & 31);
-                ra[x] = *reinterpret_cast<const uint4*>(As[buf] + row * LD + 32 * lg + 16 * h);
+                ra[x] = *reinterpret_cast<const uint4*>(As[buf] + row * LD + (KT / 2) * lg + 16 * h);
             }
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 const int col = wj * 64 + y * 32 + (lane & 31);
-                rb[y] = *reinterpret_cast<const uint4*>(Bs[buf] + col * LD + 32 * lg + 16 * h);
+                rb[y] = *reinterpret_cast<const uint4*>(Bs[buf] + col * LD + (KT / 2) * lg + 16 * h);
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const int kq = 32 * lg + 16 * h + 8 * q;
+                const int kq = (KT / 2) * lg + 16 * h + 8 * q;
                 const uint4 lh = *reinterpret_cast<const uint4*>(Ls[buf] + kq);
                 const uint4 ll = *reinterpret_cast<const uint4*>(Ls[buf] + KT + kq);
                 const unsigned lhw[4] = {lh.x, lh.y, lh.z, lh.w};
@@ -622,24 +633,23 @@ __global__ __launch_bounds__(512, 1) void k_gram_mfma(const uint8_t* __restrict_
         }
     };
 
-    // K step t: registers of step t (fetched two steps earlier) go to LDS stage
-    // t mod 2, the same registers are refilled with step t+2, then the MFMAs of
-    // step t run.  The stage written at step t was last read by the MFMAs of step
-    // t-2, which every wave finished before the barrier of step t-1.  kpad is a
+    // K step t: registers of step t (fetched during step t-1) go to LDS stage
+    // t mod 2, the registers are refilled with step t+1, then the MFMAs of step t
+    // run.  The stage written at step t was last read by the MFMAs of step t-2,
+    // which every wave finished before the barrier of step t-1.  kpad is a
     // multiple of two steps, so both halves of the loop body always run; the
-    // fetches past the end re-read the last step (kept unconditional so that the
-    // compiler's wait counts stay exact) and are never stored.
+    // fetch past the end re-reads the last step (kept unconditional so that the
+    // compiler's wait counts stay exact) and is never stored.
     const int64_t nk = kpad / KT;
     const int64_t klast = kpad - KT;
-    Regs R0 = fetch(0);
-    Regs R1 = fetch(KT);
+    Regs R = fetch(0);
     for (int64_t t = 0; t < nk; t += 2) {
-        stash(R0, 0);
-        R0 = fetch(min((t + 2) * KT, klast));
+        stash(R, 0);
+        R = fetch(min((t + 1) * KT, klast));
         __syncthreads();
         compute(0);
-        stash(R1, 1);
-        R1 = fetch(min((t + 3) * KT, klast));
+        stash(R, 1);
+        R = fetch(min((t + 2) * KT, klast));
         __syncthreads();
         compute(1);
     }
