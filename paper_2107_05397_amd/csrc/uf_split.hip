@@ -420,14 +420,44 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         // segment edges at distance 0, floor(N/2) or seg0 need no search
         const int64_t c_lo = dlo == 1 ? 0 : (dlo == seg0 + 1 ? w0 : first_reaching(dlo, 0, w));
         const int64_t c_hi = dhi >= n / 2 ? w : (dhi == seg0 ? w0 : first_reaching(dhi + 1, c_lo, w));
-        // members c in [c_lo, c_hi) all fall in this segment: four loads in
-        // flight per lane, then their LDS adds
+        // members c in [c_lo, c_hi) all fall in this segment: rounds of four loads
+        // in flight per lane, then their LDS adds.  Full rounds run unchecked, with
+        // per-lane positions and distances in 32 bits (samples, N, list lengths
+        // and stripes are below 2^24); the last round loads and adds only below
+        // c_hi.
         constexpr int U = 4;
-        for (int64_t c0 = c_lo + lane; c0 < c_hi; c0 += 64 * U) {
+        int64_t c0 = c_lo;
+        {
+            const int32_t m32 = int32_t(m), i32 = int32_t(i), n32 = int32_t(n), a0 = int32_t(g0) + 1;
+            const int32_t q_first = int32_t(p + 1);
+            for (; c0 + 64 * U <= c_hi; c0 += 64 * U) {
+                unsigned long long word[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int32_t q = q_first + int32_t(c0) + lane + 64 * u;
+                    q -= q >= m32 ? m32 : 0;
+                    if constexpr (W) word[u] = rw[base + uint32_t(q)];
+                    else word[u] = (unsigned long long)(unsigned)rs[base + uint32_t(q)];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t j = int32_t(word[u] & kMask);
+                    unsigned long long v = vi;
+                    if constexpr (W) {
+                        const unsigned long long vj = word[u] >> kSampleBits;
+                        v = vj < vi ? vj : vi;
+                    }
+                    int32_t d = j - i32;
+                    d += d <= 0 ? n32 : 0;
+                    atomicAdd(&acc[d - a0], v);
+                }
+            }
+        }
+        if (c0 < c_hi) {
             unsigned long long word[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t c = c0 + 64 * u;
+                const int64_t c = c0 + lane + 64 * u;
                 word[u] = 0;
                 if (c < c_hi) {
                     if constexpr (W) word[u] = rw[base + pos_of(c)];
@@ -436,7 +466,7 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (c0 + 64 * u >= c_hi) continue;
+                if (c0 + lane + 64 * u >= c_hi) continue;
                 const int64_t j = int64_t(word[u] & kMask);
                 unsigned long long v = vi;
                 if constexpr (W) {
