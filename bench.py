@@ -44,11 +44,13 @@ PEAK_BF16_MFMA = 2.5e15                         # dense BF16 MFMA FLOP/s
 PEAK_HBM = 8.0e12
 
 
-KERNEL_SOURCES = ("uf_kernels.hip", "uf_split.hip", "uf_device.h", "uf_internal.h")
+# the distance kernels, and the host code whose split cost model fixes how much
+# work each of their launches does
+KERNEL_SOURCES = ("uf_kernels.hip", "uf_split.hip", "uf_device.h", "uf_internal.h", "uf_host.hip")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the distance-kernel sources the committed counter summaries were taken with."""
+    """Hash of the sources the committed counter summaries were taken with."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:

@@ -36,8 +36,8 @@ std::atomic<double> g_split_threshold[2] = {{-1.0}, {-1.0}};
 // long and the walk keeps its lanes full).
 constexpr double kRateBandDense = 3.05e13;
 constexpr double kRateGramMfma = 3.78e14;
-constexpr double kRatePairsWeighted = 6.4e11;
-constexpr double kRatePairsUnweighted = 9.3e11;
+constexpr double kRatePairsWeighted = 7.3e11;
+constexpr double kRatePairsUnweighted = 1.0e12;
 
 uf_status fail(uf_status st, const std::string& msg) {
     g_last_error = msg;
