@@ -420,12 +420,12 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         // segment edges at distance 0, floor(N/2) or seg0 need no search
         const int64_t c_lo = dlo == 1 ? 0 : (dlo == seg0 + 1 ? w0 : first_reaching(dlo, 0, w));
         const int64_t c_hi = dhi >= n / 2 ? w : (dhi == seg0 ? w0 : first_reaching(dhi + 1, c_lo, w));
-        // members c in [c_lo, c_hi) all fall in this segment: rounds of four loads
+        // members c in [c_lo, c_hi) all fall in this segment: rounds of eight loads
         // in flight per lane, then their LDS adds.  Full rounds run unchecked, with
         // per-lane positions and distances in 32 bits (samples, N, list lengths
         // and stripes are below 2^24); the last round loads and adds only below
         // c_hi.
-        constexpr int U = 4;
+        constexpr int U = 8;
         int64_t c0 = c_lo;
         {
             const int32_t m32 = int32_t(m), i32 = int32_t(i), n32 = int32_t(n), a0 = int32_t(g0) + 1;
