@@ -171,9 +171,9 @@ hipError_t gram_mfma(const uint8_t* P, const uint16_t* hi, const uint16_t* lo, i
 // kind 1: unweighted Gram form ((w_i + w_j - 2G) / (w_i + w_j - G)), clamped to [0, 1].
 // acc_type (kAcc*) selects the accumulator type; its values are multiplied by
 // acc_scale.  q (nullable) receives -d^2/2 in FP64, stripe-major.  layout/out dtype
-// as in uf.h.  split_m (nullable, fixed point with step split_unit, stripe-major
-// like acc) carries the non-dense branches: kind 0 adds sigma_i + sigma_j - 2 M to
-// the numerator, kind 1 adds M to the Gram value.
+// as in uf.h.  split_m (nullable, fixed point with step split_unit, sample-major:
+// M[i*(se-sb) + s-sb]) carries the non-dense branches: kind 0 adds sigma_i + sigma_j -
+// 2 M to the numerator, kind 1 adds M to the Gram value.
 constexpr int kAccF32 = 0, kAccF64 = 1, kAccU32 = 2;
 hipError_t finalize(int kind, const void* acc, int acc_type, double acc_scale, const double* scal,
                     int64_t n, int64_t sb, int64_t se, int layout, int out_f32, void* out, double* q,

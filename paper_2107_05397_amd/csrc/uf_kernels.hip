@@ -713,13 +713,13 @@ struct FinIn {
 template <typename A>
 __device__ __forceinline__ FinIn<A> final_inputs(const A* __restrict__ acc,
                                                  const double* __restrict__ scal, int64_t n,
-                                                 int64_t sb, int64_t s, int64_t i, int64_t j,
+                                                 int64_t sb, int64_t sr, int64_t s, int64_t i,
+                                                 int64_t j,
                                                  const unsigned long long* __restrict__ split_m,
                                                  const unsigned long long* __restrict__ sigma) {
     FinIn<A> f;
-    const int64_t e = (s - sb) * n + i;
-    f.acc = acc[e];
-    f.m = split_m ? split_m[e] : 0ull;
+    f.acc = acc[(s - sb) * n + i];
+    f.m = split_m ? split_m[i * sr + (s - sb)] : 0ull;   // the split's sums are sample-major
     f.sg_i = sigma ? sigma[i] : 0ull;
     f.sg_j = sigma ? sigma[j] : 0ull;
     f.sc_i = scal[i];
@@ -788,7 +788,8 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
             for (int u = 0; u < 8; ++u) {
                 const int ls = (tid >> 6) + 4 * (8 * half + u);
                 const int64_t sc = s0 + ls < se ? s0 + ls : se - 1;
-                in[u] = final_inputs(acc, scal, n, sb, sc, ic, (ic + sc + 1) % n, split_m, sigma);
+                in[u] = final_inputs(acc, scal, n, sb, se - sb, sc, ic, (ic + sc + 1) % n, split_m,
+                                     sigma);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {

@@ -78,9 +78,9 @@ hipError_t embed_batch_merge_f32(const ufp::Emb& e, const BatchTable* tabs, cons
 hipError_t split_lengths(const int32_t* cls, int64_t nb, const int32_t* dense, int64_t n_dense,
                          int64_t n_pad, const uint16_t* len_hi, const uint16_t* len_lo,
                          uint16_t* dlen_hi, uint16_t* dlen_lo, int64_t* rl, hipStream_t st);
-// M[(s-sb)*n + i] = sum over the pairs (i, (i+s+1) mod n), s in [sb, se), that share a
-// non-dense branch: rw non-null: weighted, min of the two values; else unweighted
-// (sample ids rs), the branch length.  Writes every element of the range.
+// M[i*(se-sb) + (s-sb)] (sample-major) = sum over the pairs (i, (i+s+1) mod n), s in
+// [sb, se), that share a non-dense branch: rw non-null: weighted, min of the two values;
+// else unweighted (sample ids rs), the branch length.  Writes every element of the range.
 hipError_t rare_slots(const int32_t* rs, const unsigned long long* rw, const int64_t* soff,
                       const SlotEntry* entries, int64_t n, int64_t sb, int64_t se,
                       unsigned long long* M, hipStream_t st);

@@ -480,7 +480,9 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
         }
     }
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < width; k += kSlotThreads) M[(g0 + k - sb) * n + i] = acc[k];
+    // sample-major: this sample's row of M is written contiguously
+    const int64_t sr = se - sb;
+    for (int64_t k = threadIdx.x; k < width; k += kSlotThreads) M[i * sr + (g0 + k - sb)] = acc[k];
 }
 
 }  // namespace
