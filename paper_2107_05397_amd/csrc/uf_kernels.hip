@@ -713,13 +713,11 @@ struct FinIn {
 template <typename A>
 __device__ __forceinline__ FinIn<A> final_inputs(const A* __restrict__ acc,
                                                  const double* __restrict__ scal, int64_t n,
-                                                 int64_t sb, int64_t sr, int64_t s, int64_t i,
-                                                 int64_t j,
-                                                 const unsigned long long* __restrict__ split_m,
+                                                 int64_t sb, int64_t s, int64_t i, int64_t j,
                                                  const unsigned long long* __restrict__ sigma) {
     FinIn<A> f;
     f.acc = acc[(s - sb) * n + i];
-    f.m = split_m ? split_m[i * sr + (s - sb)] : 0ull;   // the split's sums are sample-major
+    f.m = 0ull;   // the split's sum comes from the LDS stage
     f.sg_i = sigma ? sigma[i] : 0ull;
     f.sg_j = sigma ? sigma[j] : 0ull;
     f.sc_i = scal[i];
@@ -782,14 +780,29 @@ __global__ __launch_bounds__(256) void k_finalize(int kind, const A* __restrict_
         // (elements outside the range load from a clamped in-range element and are
         // not stored)
         const int64_t ic = i < n ? i : n - 1;
+        if (split_m) {
+            // the split's sums are sample-major: stage the tile's 64 rows of 64
+            // stripes through LDS with coalesced row reads (each element lands in
+            // the cell its distance later takes, read back by the same thread)
+            __syncthreads();
+            const int64_t sr = se - sb;
+            const int cs = tid & 63;
+            const int64_t scs = s0 + cs < se ? s0 + cs : se - 1;
+#pragma unroll 4
+            for (int r = tid >> 6; r < kFinT; r += 4) {
+                const int64_t ir = i0 + r < n ? i0 + r : n - 1;
+                tile[cs][r] = __longlong_as_double((long long)split_m[ir * sr + (scs - sb)]);
+            }
+            __syncthreads();
+        }
         for (int half = 0; half < 2; ++half) {
             FinIn<A> in[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int ls = (tid >> 6) + 4 * (8 * half + u);
                 const int64_t sc = s0 + ls < se ? s0 + ls : se - 1;
-                in[u] = final_inputs(acc, scal, n, sb, se - sb, sc, ic, (ic + sc + 1) % n, split_m,
-                                     sigma);
+                in[u] = final_inputs(acc, scal, n, sb, sc, ic, (ic + sc + 1) % n, sigma);
+                if (split_m) in[u].m = (unsigned long long)__double_as_longlong(tile[ls][li]);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
