@@ -310,7 +310,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(stripe-range sharding across GPUs is a design note, not code). "
               "Run with --gpus 1.", file=sys.stderr)
         return 2

@@ -12,7 +12,7 @@ weighted-normalized UniFrac:
 Placement of a query: its k' nearest references in z-space are candidates;
 the exact distance (uf_dm_rerank_weighted_normalized) re-ranks them and the
 best k are returned.  The exact method is both the fallback (k' = all) and
-the judge of the encoder's error.
+the reference for the encoder's error.
 
 This module only orchestrates library calls (argument marshalling, pair
 sampling on the host, the epoch loop); every numerical step runs in the HIP

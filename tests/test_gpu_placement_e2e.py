@@ -3,7 +3,7 @@ table, place new samples, and compare with the method without the network
 (the raw 1024-d projection, same exact re-rank budget).
 
 Encoder quality has no value printed in the paper to pin against ("parity
-unpinned" as a number); it is judged against exact UniFrac.  What the trained
+unpinned" as a number); it is measured against exact UniFrac.  What the trained
 network gains over the projection alone, asserted here:
 * its Euclidean distances estimate UniFrac itself: lower mean error on random
   query/reference pairs than the projection under its best single scale;
