@@ -338,8 +338,9 @@ __global__ __launch_bounds__(256) void k_entry_lengths(SlotEntry* __restrict__ s
     if (k < n_entries) se[k].v = (unsigned long long)rl[se[k].v];
 }
 
-// Workgroup -> sample: consecutive samples on one XCD (blocks are dealt to the
-// 8 XCDs round-robin), so the column writes of neighbours share L2 lines.
+// Workgroup -> sample: each XCD takes a contiguous range of samples (blocks are
+// dealt to the 8 XCDs round-robin), so neighbouring workgroups of an XCD write
+// adjacent rows of the sample-major sums.
 __device__ __forceinline__ int64_t xcd_sample(int64_t b, int64_t n) {
     const int64_t per = n / 8, rem = n % 8;
     const int64_t x = b % 8, k = b / 8;
