@@ -81,6 +81,7 @@ int orc_dm(int64_t m, const int64_t* parent, const double* length,
     if (!order) return ORC_ERR_NOMEM;
     if (postorder(m, parent, root, order) != m) { free(order); return ORC_ERR_TREE; }
     char* is_tip = (char*)calloc((size_t)m, 1);
+    if (!is_tip) { free(order); return ORC_ERR_NOMEM; }
     for (int64_t v = 0; v < m; ++v) is_tip[v] = 1;
     for (int64_t v = 0; v < m; ++v) if (parent[v] >= 0) is_tip[parent[v]] = 0;
 

@@ -404,3 +404,74 @@ def test_duplicate_feature_raises():
     tab = synth.Table(indptr=np.array([0, 2, 3]), tips=np.array([0, 0, 1]), counts=np.array([1, 1, 1]))
     with pytest.raises(oracle.TableError):
         oracle.dm(t, tab, "weighted_normalized")
+
+
+# ---------------------------------------------------------------- BF16 rounding (split lengths)
+# The split-precision lengths of the MFMA Gram path (l = hi + lo, each rounded
+# to bfloat16 with ties to even) are part of the oracle the unweighted split and
+# the Gram tests compare with.  bfloat16 keeps 8 significant bits (7 stored),
+# the FP32 exponent range, and a subnormal grid of spacing 2^-133 below 2^-126.
+@pytest.mark.parametrize("x, want", [
+    (1.0, 1.0),
+    (1.0 + 2.0 ** -8, 1.0),                      # exact tie: to the even neighbour 1.0
+    (1.0 + 3 * 2.0 ** -9, 1.0 + 2.0 ** -7),      # 0.75 of a unit: up
+    (1.0 + 2.0 ** -9, 1.0),                      # 0.25 of a unit: down
+    (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),      # tie between odd 1+2^-7 and even 1+2^-6
+    (1.0 + 5 * 2.0 ** -8, 1.0 + 2.0 ** -6),      # tie between even 1+2^-6 and odd 1+3*2^-7
+    (-(1.0 + 3 * 2.0 ** -9), -(1.0 + 2.0 ** -7)),  # sign kept, magnitude rounded
+    (255.0, 255.0), (257.0, 256.0), (259.0, 260.0),  # 8 significant bits: spacing 2 in [256, 512)
+    (0.1, 0.10009765625),                        # 0x3DCD
+    (2.0 ** -126, 2.0 ** -126),                  # smallest normal
+    (2.0 ** -126 - 2.0 ** -140, 2.0 ** -126),    # just below: the subnormal grid (2^-133) rounds up
+    (2.0 ** -134, 0.0),                          # half the smallest subnormal: tie to even 0
+    (3 * 2.0 ** -134, 2.0 ** -132),              # 1.5 subnormal units: tie to even 2 units
+    (5 * 2.0 ** -135, 2.0 ** -133),              # 1.25 units: down to 1 unit
+    (0.0, 0.0),
+])
+def test_bf16_rounding_hand_computed(x, want):
+    from oracle.unifrac import _round_bf16_f64
+    assert _round_bf16_f64(np.array([x]))[0] == want
+
+
+def test_bf16_rounding_matches_torch_on_float32_inputs():
+    # torch converts float32 -> bfloat16 with round-to-nearest-even on the bit
+    # pattern; on FP32-exact inputs (normal and subnormal) the oracle must agree.
+    # The oracle's domain stops below 2^127 (branch lengths are many orders of
+    # magnitude smaller; it does not model rounding up to infinity).
+    import torch
+    from oracle.unifrac import _round_bf16_f64
+    rng = np.random.default_rng(0)
+    bits = rng.integers(0, 0x7F000000, size=200_000, dtype=np.uint64).astype(np.uint32)
+    bits[:1000] = rng.integers(0, 2 ** 23, size=1000).astype(np.uint32)          # subnormals
+    # exact ties: the 16 dropped bits are 0x8000
+    bits[1000:2000] = ((rng.integers(0, 0x7F00, size=1000) << 16) | 0x8000).astype(np.uint32)
+    f32 = bits.view(np.float32)
+    f32 = np.concatenate([f32, -f32])
+    want = torch.from_numpy(f32.copy()).to(torch.bfloat16).to(torch.float64).numpy()
+    got = _round_bf16_f64(f32.astype(np.float64))
+    assert np.array_equal(got, want)
+
+
+def test_gram_split_lengths_residual_and_nearest():
+    # hi is the nearest bfloat16 to l (checked against both bfloat16 neighbours),
+    # lo the nearest to l - hi, and |l - hi - lo| <= 2^-16 l (8 significant bits
+    # per part, half a unit of each)
+    import torch
+    rng = np.random.default_rng(3)
+    length = np.concatenate([rng.exponential(0.05, size=20_000), [0.0, 1e-30, 7.0, 0.1]])
+    hi, lo = oracle.gram_split_bf16(length)
+    for part in (hi, lo):
+        rt = torch.from_numpy(part.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(rt, part)                    # exactly representable
+    assert np.all(np.abs(length - hi - lo) <= 2.0 ** -16 * length)
+
+    def neighbours(v):
+        b = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).view(torch.int16)
+        up = (b + 1).view(torch.bfloat16).to(torch.float64).numpy()
+        dn = (b - 1).view(torch.bfloat16).to(torch.float64).numpy()
+        return up, dn
+
+    pos = length > 1e-30
+    up, dn = neighbours(hi[pos])
+    err = np.abs(length[pos] - hi[pos])
+    assert np.all(err <= np.abs(length[pos] - up)) and np.all(err <= np.abs(length[pos] - dn))

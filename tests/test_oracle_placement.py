@@ -135,3 +135,144 @@ def test_recall_helper():
     exact = np.array([[0.1, 0.2, 0.3, 0.4], [0.5, 0.1, 0.1, 0.9]])
     assert op.recall_at_k(np.array([[0, 1], [1, 2]]), exact, 2) == 1.0
     assert op.recall_at_k(np.array([[0, 3], [1, 0]]), exact, 2) == 0.5
+
+
+# ---------------------------------------------------------------- loss options, skip path, AdamW
+def _fd_check(loss_fn, params, grads, skip=None, dskip=None, n_probe=5, seed=11):
+    """Central differences of loss_fn(params, skip) against the analytic gradients."""
+    h = 1e-6
+    rng = np.random.default_rng(seed)
+    for l, (w, b) in enumerate(params):
+        for _ in range(n_probe):
+            i, j = rng.integers(w.shape[0]), rng.integers(w.shape[1])
+            wp = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wm = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wp[l][0][i, j] += h
+            wm[l][0][i, j] -= h
+            fd = (loss_fn(wp, skip) - loss_fn(wm, skip)) / (2 * h)
+            assert grads[l][0][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+        i = rng.integers(b.shape[0])
+        bp = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bm = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bp[l][1][i] += h
+        bm[l][1][i] -= h
+        fd = (loss_fn(bp, skip) - loss_fn(bm, skip)) / (2 * h)
+        assert grads[l][1][i] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+    if skip is not None:
+        for _ in range(2 * n_probe):
+            i, j = rng.integers(skip.shape[0]), rng.integers(skip.shape[1])
+            sp_, sm_ = skip.copy(), skip.copy()
+            sp_[i, j] += h
+            sm_[i, j] -= h
+            fd = (loss_fn(params, sp_) - loss_fn(params, sm_)) / (2 * h)
+            assert dskip[i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+@pytest.mark.parametrize("rel_floor", [0.0, 0.3])
+@pytest.mark.parametrize("with_skip", [False, True])
+def test_loss_options_match_finite_differences(rel_floor, with_skip):
+    # targets straddle the floor so both branches of max(d, floor) are exercised
+    x, params, pa, pb, t = _problem(seed=21)
+    t = np.linspace(0.05, 0.9, t.shape[0])
+    rng = np.random.default_rng(4)
+    skip = rng.normal(size=(params[-1][0].shape[0], x.shape[1])) * 0.2 if with_skip else None
+    loss, grads = op.loss_and_grads(x, params, pa, pb, t, rel_floor=rel_floor, skip=skip)
+    assert len(grads) == len(params) + (1 if with_skip else 0)
+    lf = lambda ps, sk: op.loss_and_grads(x, ps, pa, pb, t, rel_floor=rel_floor, skip=sk)[0]  # noqa: E731
+    _fd_check(lf, params, grads, skip, grads[-1][0] if with_skip else None)
+
+
+@pytest.mark.parametrize("rel_floor", [0.0, 0.3])
+@pytest.mark.parametrize("with_skip", [False, True])
+def test_loss_options_match_torch_autograd(rel_floor, with_skip):
+    x, params, pa, pb, t = _problem(seed=23)
+    t = np.linspace(0.05, 0.9, t.shape[0])
+    rng = np.random.default_rng(6)
+    skip = rng.normal(size=(params[-1][0].shape[0], x.shape[1])) * 0.2 if with_skip else None
+    loss, grads = op.loss_and_grads(x, params, pa, pb, t, rel_floor=rel_floor, skip=skip)
+    tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for w, b in params]
+    ts = torch.tensor(skip, requires_grad=True) if with_skip else None
+    rows = np.concatenate([pa, pb])
+    x0 = torch.tensor(x)[rows]
+    h = x0
+    for l, (w, b) in enumerate(tp):
+        h = h @ w.T + b
+        if l < len(tp) - 1:
+            h = torch.relu(h)
+    if ts is not None:
+        h = h + x0 @ ts.T
+    p = len(pa)
+    dist = torch.sqrt(((h[:p] - h[p:]) ** 2).sum(1))
+    tt = torch.tensor(t)
+    wgt = 1.0 / torch.clamp(tt, min=rel_floor) if rel_floor > 0 else torch.ones_like(tt)
+    tl = (((dist - tt) * wgt) ** 2).mean()
+    tl.backward()
+    assert float(tl) == pytest.approx(loss, rel=1e-12)
+    for (w, b), (gw, gb) in zip(tp, grads):
+        assert np.allclose(w.grad.numpy(), gw, rtol=1e-10, atol=1e-12)
+        assert np.allclose(b.grad.numpy(), gb, rtol=1e-10, atol=1e-12)
+    if ts is not None:
+        assert grads[-1][1] is None
+        assert np.allclose(ts.grad.numpy(), grads[-1][0], rtol=1e-10, atol=1e-12)
+
+
+def test_adamw_matches_torch():
+    # decoupled weight decay (Loshchilov and Hutter): torch.optim.AdamW is an
+    # independent implementation of the same update
+    rng = np.random.default_rng(8)
+    p0 = rng.normal(size=30)
+    grads = [rng.normal(size=30) for _ in range(4)]
+    tp = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.AdamW([tp], lr=3e-3, betas=(0.9, 0.99), eps=1e-8, weight_decay=0.05)
+    p, m, v = p0.copy(), np.zeros(30), np.zeros(30)
+    for step, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = op.adam(p, g, m, v, 3e-3, 0.9, 0.99, 1e-8, step, weight_decay=0.05)
+        st = opt.state[tp]
+        assert np.allclose(tp.detach().numpy(), p, rtol=1e-12, atol=1e-14)
+        assert np.allclose(st["exp_avg"].numpy(), m, rtol=1e-12, atol=1e-15)
+        assert np.allclose(st["exp_avg_sq"].numpy(), v, rtol=1e-12, atol=1e-15)
+
+
+def test_bf16_storage_matches_an_independent_cast_chain():
+    # the kernel's precision model: inputs, hidden activations, dZ and the hidden
+    # gradients are stored in bfloat16, everything else in FP64.  Rebuilt here with
+    # torch's own bfloat16 casts at those points.
+    x, params, pa, pb, t = _problem(seed=31, dims=(32, 24, 16, 8), n=12, p=9)
+    rng = np.random.default_rng(9)
+    skip = rng.normal(size=(8, 32)) * 0.1
+    for sk in (None, skip):
+        loss, grads = op.loss_and_grads(x, params, pa, pb, t, bf16_storage=True, rel_floor=0.2,
+                                        skip=sk)
+        rb = lambda a: a.to(torch.bfloat16).to(torch.float64)  # noqa: E731
+        rows = np.concatenate([pa, pb])
+        h0 = rb(torch.tensor(x)[rows])
+        hs, h = [h0], h0
+        for l, (w, b) in enumerate(params):
+            a = h @ torch.tensor(w).T + torch.tensor(b)
+            if l < len(params) - 1:
+                h = rb(torch.relu(a))
+                hs.append(h)
+            else:
+                z = a
+        if sk is not None:
+            z = z + h0 @ torch.tensor(sk).T
+        p = len(pa)
+        diff = z[:p] - z[p:]
+        dist = torch.sqrt((diff ** 2).sum(1))
+        tt = torch.tensor(t)
+        wgt = 1.0 / torch.clamp(tt, min=0.2)
+        r = (dist - tt) * wgt
+        assert float((r ** 2).mean()) == pytest.approx(loss, rel=1e-12)
+        coef = 2.0 * r * wgt / dist / p
+        dz = rb(torch.cat([coef[:, None] * diff, -coef[:, None] * diff]))
+        g = dz
+        for l in range(len(params) - 1, -1, -1):
+            assert np.allclose((g.T @ hs[l]).numpy(), grads[l][0], rtol=1e-10, atol=1e-13)
+            assert np.allclose(g.sum(0).numpy(), grads[l][1], rtol=1e-10, atol=1e-13)
+            if l > 0:
+                g = rb((g @ torch.tensor(params[l][0])) * (hs[l] > 0))
+        if sk is not None:
+            assert np.allclose((dz.T @ h0).numpy(), grads[-1][0], rtol=1e-10, atol=1e-13)
