@@ -4,20 +4,22 @@
 Metric: UniFrac pair-node updates per second (one update = one sample pair
 times one non-root branch; a full matrix is N(N-1)/2 * (M-1) updates).
 
-Default workload (synthetic stand-in for an EMP-sized study): a random-merge
-rooted binary tree with 200,000 tips (399,999 nodes), Exponential(mean 0.05)
-branch lengths; 25,000 samples with ~1,000 distinct Zipf(1.1)-popular tips
-each and round(LogNormal(2, 1.5)) + 1 counts; seed 102.
+Default workload (synthetic, the largest single-table size the paper names):
+a random-merge rooted binary tree with 200,000 tips (399,999 nodes),
+Exponential(mean 0.05) branch lengths; 50,000 samples with ~1,000 distinct
+Zipf(1.1)-popular tips each and round(LogNormal(2, 1.5)) + 1 counts; seed 103.
+The 25,000-sample table of the same laws (seed 102) is --workload C2.
 
-One step = the whole hot path over that table with the inputs resident on the
-device: the weighted-normalized matrix and the unweighted matrix, each with
-the chunked embedding, accumulation, FP64 finalize into a condensed FP64
-matrix and the PCoA row means and grand mean.  By default both run sparse
-aware: branches touched by many samples on the dense kernel (FP32 stripe
-kernel, weighted; split-BF16 Gram on MFMA, unweighted), every other branch
-as exact fixed-point sums over the sample pairs that share it, with the
-automatic dense-set cost model.  The split itself is built once per table
-before the timed steps.  Printed: one JSON line on stdout.
+One step = the whole hot path over that table from the inputs resident on the
+device: the per-sample scalars, the sparse split of each variant (branch
+sample counts, list fill, list sort), then the weighted-normalized matrix and
+the unweighted matrix, each with the chunked dense embedding, accumulation,
+FP64 finalize into a condensed FP64 matrix and the PCoA row means and grand
+mean.  By default both run sparse aware: branches touched by many samples on
+the dense kernel (fixed-point stripe kernel, weighted; split-BF16 Gram on MFMA,
+unweighted), every other branch as exact fixed-point sums over the sample
+pairs that share it, with the automatic dense-set cost model.  Printed: one
+JSON line on stdout.
 
     python bench.py [--steps K] [--warmup W] [--workload C1|C2|C3|C4|C5]
                     [--weighted-precision P] [--unweighted-precision P]
@@ -283,7 +285,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--epochs", type=int, default=5, help="C5: training epochs")
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
     ap.add_argument("--tune-cache", default=None, help="C4: autotuner cache path")
@@ -297,11 +299,12 @@ def main() -> int:
     ap.add_argument("--unweighted-precision", default="mfma_split",
                     choices=["mfma", "mfma_split", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target length of the one-core oracle run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the FP64 weighted kernel once")
+                    help="also time the plain weighted FP32 kernel over all branches")
     ap.add_argument("--no-comparisons", action="store_true",
                     help="skip the plain-kernel and all-branch MFMA comparison runs")
     ap.add_argument("--no-statistics", action="store_true",
@@ -320,6 +323,24 @@ def main() -> int:
     if args.workload == "C5":
         return bench_placement(args)
 
+    return bench_matrix(args)
+
+
+KERNEL_NAMES = ("sample_scalars", "branch_count", "split_fill", "sort_lists", "split_lengths",
+                "embed_nm", "embed_pres", "band_wn_u32", "band_wn_f32", "band_wn_f64", "band_uw_f32",
+                "band_uw_f64", "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize", "row_sums")
+PREP_KERNELS = ("sample_scalars", "branch_count", "split_fill", "sort_lists", "split_lengths")
+
+
+def subset_ids(n: int, k: int = 2000):
+    """k samples spread evenly over [0, n): every (n // k)-th (all of them if n <= k)."""
+    import numpy as np
+    step = max(1, n // k)
+    return np.arange(0, n, step)[:k]
+
+
+def bench_matrix(args) -> int:
+    """Distance matrices of one table: C1, C2 or C3 (default)."""
     import numpy as np
     import torch
 
@@ -349,18 +370,18 @@ def main() -> int:
         log("copy calibration: 1 GiB read + 1 GiB written")
 
     wp, up = args.weighted_precision, args.unweighted_precision
+    split_w, split_u = wp == "fp32_split", up == "mfma_split"
     splits = {}
     uf.set_split_threshold(args.split_threshold)
     if args.split_threshold_weighted is not None:
         uf.set_split_threshold(args.split_threshold_weighted, "weighted_normalized")
     if args.split_threshold_unweighted is not None:
         uf.set_split_threshold(args.split_threshold_unweighted, "unweighted")
-    for var, prec in (("weighted_normalized", wp), ("unweighted", up)):
-        if prec.endswith("_split"):
-            t_split = time.perf_counter()
-            splits[var] = uf.split_stats(emb, var)   # built once, outside the timed steps
+    for var, on in (("weighted_normalized", split_w), ("unweighted", split_u)):
+        if on:
+            splits[var] = uf.split_stats(emb, var)
             log(f"split {var}: {splits[var][0]} dense branches, {splits[var][1]} shared lists, "
-                f"{splits[var][2]:.3e} pairs ({time.perf_counter() - t_split:.2f}s)")
+                f"{splits[var][2]:.3e} pairs")
     out_w = torch.empty(pairs, dtype=torch.float64, device="cuda")
     out_u = torch.empty(pairs, dtype=torch.float64, device="cuda")
     ws_w = torch.empty(uf.workspace_size(emb, "weighted_normalized", wp, row_stats=True),
@@ -369,12 +390,19 @@ def main() -> int:
                        dtype=torch.uint8, device="cuda")
     log(f"workspace: weighted {ws_w.numel() / 2**30:.2f} GiB, unweighted {ws_u.numel() / 2**30:.2f} GiB")
 
+    def prepare():
+        # the device-side part of the embedding pass: per-sample scalars and the sparse
+        # split of each variant, from the table and tree resident on the device
+        emb.prepare(scalars=True, split_weighted=split_w, split_unweighted=split_u, stream=stream)
+
+    def matrices():
+        uf.dm(emb, "weighted_normalized", wp, out=out_w, row_means=True, workspace=ws_w,
+              stream=stream)
+        uf.dm(emb, "unweighted", up, out=out_u, row_means=True, workspace=ws_u, stream=stream)
+
     def step():
-        _, rw, gw = uf.dm(emb, "weighted_normalized", wp, out=out_w, row_means=True,
-                          workspace=ws_w, stream=stream)
-        _, ru, gu = uf.dm(emb, "unweighted", up, out=out_u, row_means=True, workspace=ws_u,
-                          stream=stream)
-        return gw, gu
+        prepare()
+        matrices()
 
     for k in range(args.warmup):
         step()
@@ -395,19 +423,32 @@ def main() -> int:
     value = 2 * U / (ms_step / 1e3)
 
     kern = {}
-    for name in ("embed_nm", "embed_pres", "band_wn_u32", "band_wn_f32", "band_wn_f64", "band_uw_f32",
-                 "band_uw_f64", "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize",
-                 "row_sums"):
+    for name in KERNEL_NAMES:
         tot, cnt = uf.profile_read(name)
         if cnt:
             kern[name] = {"total_ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
                           "avg_ms_per_launch": tot / cnt}
+    # the same matrices with the preparation reused (split and scalars from the last step)
+    warm_steps = max(1, min(args.steps, 5))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(warm_steps):
+        matrices()
+    torch.cuda.synchronize()
+    warm_ms = (time.perf_counter() - t1) / warm_steps * 1e3
+    t1 = time.perf_counter()
+    prepare()
+    torch.cuda.synchronize()
+    prep_ms = (time.perf_counter() - t1) * 1e3
+    log(f"step {ms_step:.1f} ms; matrices alone {warm_ms:.1f} ms; preparation alone {prep_ms:.1f} ms")
+
     # dominant kernel: the weighted stripe kernel (FP64, FP32, or the 32-bit
     # fixed-point pass of the split), counted in VALU issue slots.  FP32/FP64 take 2
     # full-rate ops per update (subtract, add of |.|); fixed point takes one v_sad_u32
-    # (|a - b| + acc), which issues at half the 32-bit rate, i.e. 2 slots as well.  The
-    # peak is 256 CU x 128 lanes/clk x 2.4 GHz = 78.6e12 slots/s for 32-bit ops (the
-    # published 157.3 TFLOP/s FP32 counts an FMA as 2 flops), half that for FP64.
+    # (|a - b| + acc), which a register-only probe measured at half the issue rate
+    # of v_add_u32 (3.61e13 vs 6.55e13 lane-ops/s), i.e. 2 slots as well.  The peak
+    # is the published 157.3 TFLOP/s FP32 counted as 78.6e12 slots/s (an FMA is 2
+    # flops in one slot; = 256 CU x 128 lanes/clk x 2.4 GHz), half that for FP64.
     # With the split the stripe kernel visits only the dense branches.
     if wp == "fp64":
         band, peak_ops, kname = "band_wn_f64", PEAK_VALU_SLOTS["fp64"], "k_band<double,weighted>"
@@ -416,7 +457,7 @@ def main() -> int:
     else:
         band, peak_ops, kname = "band_wn_f32", PEAK_VALU_SLOTS["fp32"], "k_band<float,weighted>"
     band_ms = kern[band]["total_ms_per_step"]
-    band_updates = pairs * splits["weighted_normalized"][0] if wp == "fp32_split" else U
+    band_updates = pairs * splits["weighted_normalized"][0] if split_w else U
     slots = 2 * band_updates / (band_ms / 1e3)
     traffic = measured_traffic(band, args.workload)
     roofline = {"bound": "alu", "kernel": kname,
@@ -426,9 +467,18 @@ def main() -> int:
                 "launches_per_step": kern[band]["launches_per_step"],
                 "updates_per_launch": band_updates / kern[band]["launches_per_step"],
                 "note": "VALU issue slots: 2 per pair-branch update (FP: subtract + add of |.|; "
-                        "fixed point: one half-rate v_sad_u32); peak = 256 CU x 128 lanes/clk "
-                        "x 2.4 GHz (32-bit), half that for FP64"}
-    extra = {"kernels": kern}
+                        "fixed point: one v_sad_u32, which issues at half rate); peak = published "
+                        "157.3 TFLOP/s FP32 / 2 flops per FMA slot = 78.6e12 slots/s "
+                        "(256 CU x 128 lanes/clk x 2.4 GHz), half that for FP64"}
+    prep_kernel_ms = sum(kern[k]["total_ms_per_step"] for k in PREP_KERNELS if k in kern)
+    extra = {"kernels": kern,
+             "preparation": {"kernel_ms_per_step": prep_kernel_ms, "wall_ms": prep_ms,
+                             "fraction_of_step": prep_ms / ms_step,
+                             "what": "per-sample scalars + both variants' sparse splits "
+                                     "(branch counts, list fill, list sort, lengths), "
+                                     "host round trips included"},
+             "matrices_with_preparation_reused": {"ms_per_step": warm_ms,
+                                                  "updates_per_s": 2 * U / (warm_ms / 1e3)}}
     if splits:
         extra["split"] = {"threshold": args.split_threshold if args.split_threshold is not None
                           else "automatic", "band_updates_per_step": band_updates}
@@ -440,11 +490,24 @@ def main() -> int:
                                    "slot_kernel_pairs_per_s": v[2] / (r_ms / 1e3) if r_ms else None}
     if "gram_mfma" in kern:
         g_ms = kern["gram_mfma"]["total_ms_per_step"]
-        g_upd = pairs * splits["unweighted"][0] if up == "mfma_split" else U
+        g_upd = pairs * splits["unweighted"][0] if split_u else U
         extra["mfma_roofline"] = {"bound": "mfma", "achieved": 4 * g_upd / (g_ms / 1e3) / 1e12,
                                   "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                                   "frac": 4 * g_upd / (g_ms / 1e3) / PEAK_BF16_MFMA,
                                   "note": "2 BF16 MACs (l_hi, l_lo) = 4 flops per update"}
+
+    # the 2,000-sample subset the accuracy is stated on, and a few sampled pairs
+    ids = subset_ids(n)
+    ia, ib = np.triu_indices(len(ids), 1)
+    si, sj = ids[ia], ids[ib]
+    sub_idx = torch.from_numpy(n * si - si * (si + 1) // 2 + (sj - si - 1)).to("cuda")
+    rng = np.random.default_rng(0)
+    pick = rng.choice(n, size=24, replace=False)
+    sampled_pairs = [(int(min(a, b)), int(max(a, b))) for a, b in zip(pick[:12], pick[12:])]
+    sidx = torch.tensor([uf.condensed_index(n, a, b) for a, b in sampled_pairs], device="cuda")
+    subset_got = {"step_unweighted": out_u[sub_idx].cpu().numpy()}
+    sampled_got = {"step_weighted_normalized": ("weighted_normalized", out_w[sidx].cpu().numpy()),
+                   "step_unweighted": ("unweighted", out_u[sidx].cpu().numpy())}
 
     # Principal coordinates of the weighted matrix (10 axes, 20-column test matrix,
     # 3 power passes): 5 products B X, each reading the condensed matrix.
@@ -469,9 +532,8 @@ def main() -> int:
                          "eigenvalues": [float(v) for v in vals[:5]],
                          "proportion_explained": [float(v / tr) for v in vals[:5]]}
         log(f"pcoa: {dt * 1e3:.1f} ms, top eigenvalues {vals[:3]}")
+        del omega
         # Mantel test between the two matrices: 999 permutations (Pearson), 99 (Spearman)
-        _, _, _ = uf.dm(emb, "unweighted", up, out=out_u, row_means=True, workspace=ws_u,
-                        stream=stream)
         prng = np.random.default_rng(23)
         perms = torch.tensor(np.stack([prng.permutation(n) for _ in range(999)]).astype(np.int32),
                              device="cuda")
@@ -487,38 +549,67 @@ def main() -> int:
                                        "pair_products_per_s": (k + 1) * pairs / dt}
             log(f"mantel {method}: {dt:.2f}s for {k} permutations, r={r:.4f} p={pv:.4f}")
         del perms
-
-    # GPU values of sampled pairs (compared with the oracle in the CPU leg)
-    rng = np.random.default_rng(0)
-    ii = rng.choice(n, size=24, replace=False)
-    sampled_pairs = [(int(min(a, b)), int(max(a, b))) for a, b in zip(ii[:12], ii[12:])]
-    sidx = torch.tensor([uf.condensed_index(n, a, b) for a, b in sampled_pairs], device="cuda")
-    sampled_got = {"step_weighted_normalized": ("weighted_normalized", out_w[sidx].cpu().numpy()),
-                   "step_unweighted": ("unweighted", out_u[sidx].cpu().numpy())}
+    del ws_w, ws_u
 
     # Comparison runs, each a whole call over the full problem with the inputs resident:
     # the unweighted plain stripe kernel (FP32) vs the MFMA Gram over all branches (the
-    # "MFMA vs plain" figure, both at <= 1e-4 error), and the plain weighted FP32 kernel
-    # (what the split replaces); --extra adds the FP64 weighted kernel.
+    # "MFMA vs plain" figure, both at <= 1e-4 error on the subset); --extra adds the
+    # plain weighted FP32 kernel over all branches.
     comparisons = [("unweighted_plain_fp32", "unweighted", "fp32"),
-                   ("unweighted_mfma_all_branches", "unweighted", "mfma"),
-                   ("weighted_plain_fp32", "weighted_normalized", "fp32")]
+                   ("unweighted_mfma_all_branches", "unweighted", "mfma")]
     if args.extra:
-        comparisons.append(("weighted_fp64", "weighted_normalized", "fp64"))
+        comparisons.append(("weighted_plain_fp32", "weighted_normalized", "fp32"))
     if not args.no_comparisons:
         for name, var, prec in comparisons:
+            ws = torch.empty(uf.workspace_size(emb, var, prec), dtype=torch.uint8, device="cuda")
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            uf.dm(emb, var, prec, out=out_w, stream=stream)
+            uf.dm(emb, var, prec, out=out_w, workspace=ws, stream=stream)
             torch.cuda.synchronize()
+            del ws
             dt = time.perf_counter() - t1
             extra[name] = {"seconds": dt, "updates_per_s": U / dt}
             sampled_got[name] = (var, out_w[sidx].cpu().numpy())
+            if var == "unweighted":
+                subset_got[name] = out_w[sub_idx].cpu().numpy()
             log(f"comparison {name}: {dt:.2f}s")
         extra["mfma_speedup_over_plain_fp32"] = (extra["unweighted_plain_fp32"]["seconds"] /
                                                  extra["unweighted_mfma_all_branches"]["seconds"])
         t_all = extra["unweighted_mfma_all_branches"]["seconds"]
         extra["unweighted_mfma_all_branches"]["mfma_frac_whole_call"] = 4 * U / t_all / PEAK_BF16_MFMA
+        # the FP64 weighted kernel on one GPU's share of the stripes (an eighth), the
+        # size it would take on each of eight GPUs
+        S = n // 2
+        se = max(1, S // 8)
+        share = torch.empty(se * n, dtype=torch.float64, device="cuda")
+        uf.profile_reset()
+        uf.profile_enable(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        uf.dm_stripes(emb, "weighted_normalized", "fp64", 0, se, out=share, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        uf.profile_enable(False)
+        f64_ms, _ = uf.profile_read("band_wn_f64")
+        share_updates = se * n * (m - 1)
+        f64_slots = 2 * share_updates / (f64_ms / 1e3)
+        extra["weighted_fp64_stripe_share"] = {
+            "stripes": [0, se], "seconds": dt, "updates": share_updates,
+            "updates_per_s": share_updates / dt, "band_ms": f64_ms,
+            "roofline": {"bound": "alu", "kernel": "k_band<double,weighted>",
+                         "achieved": f64_slots / 1e12, "peak": PEAK_VALU_SLOTS["fp64"] / 1e12,
+                         "unit": "Tops/s", "frac": f64_slots / PEAK_VALU_SLOTS["fp64"]}}
+        # sampled pairs inside the share: (i, (i + s + 1) mod n), s < se
+        srng = np.random.default_rng(5)
+        ss = srng.integers(0, se, size=12)
+        si2 = srng.integers(0, n, size=12)
+        share_pairs = [(int(i), int((i + s + 1) % n)) for i, s in zip(si2, ss)]
+        sv = share.view(se, n)[torch.tensor(ss, device="cuda"), torch.tensor(si2, device="cuda")]
+        sampled_got["weighted_fp64_stripe_share"] = ("weighted_normalized", sv.cpu().numpy(),
+                                                     share_pairs)
+        log(f"FP64 weighted on stripes [0, {se}): {dt:.2f}s, band {f64_ms:.0f} ms "
+            f"({f64_slots / PEAK_VALU_SLOTS['fp64']:.2f} of the FP64 peak)")
+        del share
 
     # arithmetic types of the kernels that ran: weighted dense part, split pair sums,
     # unweighted dense part
@@ -530,11 +621,7 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle")
-        cpu = cpu_baseline(tree, table, args.cpu_seconds)
-        cpu["sampled_parity_max_abs_err"] = {
-            k: sampled_error(tree, table, sampled_pairs, v, got) for k, (v, got) in sampled_got.items()}
-        log(f"sampled parity vs oracle: {cpu['sampled_parity_max_abs_err']}")
+        cpu = cpu_leg(tree, table, ids, subset_got, sampled_got, sampled_pairs, args.cpu_seconds)
 
     rec = {
         "metric": "UniFrac pair-node updates/s (1 GPU)",
@@ -550,7 +637,8 @@ def main() -> int:
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: random-merge tree {tree.n_tips} tips "
-                               f"({m} nodes), {n} samples, both variants, condensed FP64 "
+                               f"({m} nodes), {n} samples, both variants from the device-resident "
+                               f"table (scalars, sparse splits, matrices), condensed FP64 "
                                f"output + PCoA means",
                    "n_samples": n, "n_nodes": m, "pairs": pairs, "updates_per_step": 2 * U,
                    "weighted_precision": wp, "unweighted_precision": up,
@@ -561,6 +649,55 @@ def main() -> int:
     }
     print(json.dumps(rec), flush=True)
     return 0
+
+
+def cpu_leg(tree, table, ids, subset_got, sampled_got, sampled_pairs, one_core_seconds):
+    """The FP64 C oracle on the host: all cores on the 2,000-sample subset's
+    unweighted matrix (the reference of the MFMA accuracy figures), one core on a
+    small leading sample for the per-core rate, and the sampled pairs."""
+    import numpy as np
+    import oracle
+    import synth
+    from oracle import core
+    core.build(force=False)
+    nb = tree.n_nodes - 1
+    sub = synth.subset_rows(table, ids)
+    k = len(ids)
+    log(f"cpu leg: oracle on the {k}-sample subset (unweighted, all cores)")
+    t0 = time.perf_counter()
+    want, used = core.dm(tree, sub, "unweighted")
+    secs = time.perf_counter() - t0
+    updates = k * (k - 1) / 2 * nb
+    subset_err = {}
+    for name, got in subset_got.items():
+        e = np.abs(got - want)
+        subset_err[name] = {"max_abs_err": float(e.max()), "mean_abs_err": float(e.mean())}
+    log(f"cpu leg: {secs:.1f}s on {used} threads; subset errors {subset_err}")
+    # one core: all pairs among the first n1 samples, sized to about one_core_seconds
+    n1 = 16
+    t1 = time.perf_counter()
+    core.dm(tree, synth.subset_rows(table, np.arange(n1)), "unweighted", n_threads=1)
+    s1 = time.perf_counter() - t1
+    n1 = int(min(max(16, n1 * (one_core_seconds / max(s1, 1e-3)) ** 0.5), 400))
+    t1 = time.perf_counter()
+    core.dm(tree, synth.subset_rows(table, np.arange(n1)), "unweighted", n_threads=1)
+    s1 = time.perf_counter() - t1
+    one = {"value": n1 * (n1 - 1) / 2 * nb / s1, "unit": "pair-node updates/s", "cores": 1,
+           "sample": f"all {n1 * (n1 - 1) // 2} pairs among the first {n1} samples, unweighted; "
+                     f"{s1:.1f} s"}
+    sampled_err = {}
+    for name, item in sampled_got.items():
+        var, got = item[0], item[1]
+        prs = item[2] if len(item) > 2 else sampled_pairs
+        sampled_err[name] = float(np.max(np.abs(np.asarray(got) - oracle.dm_pairs(tree, table, prs, var))))
+    log(f"cpu leg: sampled-pair errors {sampled_err}")
+    return {"value": updates / secs, "unit": "pair-node updates/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"all {k * (k - 1) // 2} pairs of a {k}-sample subset (every "
+                      f"{int(ids[1] - ids[0]) if k > 1 else 1}th sample), unweighted, full "
+                      f"{tree.n_nodes}-node tree, FP64 C oracle; {secs:.1f} s",
+            "seconds": secs, "host_cpus": os.cpu_count(), "one_core": one,
+            "subset_abs_err": subset_err, "sampled_pairs_max_abs_err": sampled_err}
 
 
 if __name__ == "__main__":

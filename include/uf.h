@@ -123,6 +123,21 @@ int64_t uf_embedding_n_samples(const uf_embedding* emb);
  * sw = sum_v l_v u_sv, wu = sum_v l_v a_sv (FP64 lengths). */
 uf_status uf_embedding_scalars(const uf_embedding* emb, double* sw, double* wu);
 
+/* Re-run the device-side preparation of an uploaded embedding on `hip_stream`,
+ * from the table and tree already resident on the device: UF_PREP_SCALARS
+ * recomputes the per-sample scalars (as uf_embed does); UF_PREP_SPLIT_WEIGHTED /
+ * UF_PREP_SPLIT_UNWEIGHTED rebuild that variant's sparse-aware split (the part
+ * of the embedding pass that lists, for every branch few samples touch, the
+ * samples touching it, sorted, with their values) at the current threshold,
+ * replacing the cached one; the per-branch sample counts are taken once for
+ * both.  Without this call the split precisions build a missing split on first
+ * use.  Results are identical either way; this exists so that the whole path
+ * can be run, and timed, from device-resident inputs.  Synchronises hip_stream.
+ * Errors: UF_ERR_ARG (NULL, unknown flag), UF_ERR_UNSUPPORTED (split limits),
+ * UF_ERR_NOMEM, UF_ERR_DEVICE. */
+enum { UF_PREP_SCALARS = 1, UF_PREP_SPLIT_UNWEIGHTED = 2, UF_PREP_SPLIT_WEIGHTED = 4 };
+uf_status uf_embedding_prepare(const uf_embedding* emb, int what, void* hip_stream);
+
 /* ---- workspace --------------------------------------------------------- */
 
 /* Bytes of device workspace needed by a uf_dm_* call with the same
@@ -214,6 +229,12 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* emb, uf_precisio
 typedef struct uf_batch uf_batch;
 uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
                           const char* tune_cache, void* hip_stream, uf_batch** out);
+/* uf_batch_create followed by uf_batch_set_precision(prec) (UF_FP32 or
+ * UF_FP32_SPLIT): the batch is the plan, and uf_batch_run executes it.  On an
+ * error no batch is returned. */
+uf_status uf_batch_plan_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
+                               uf_precision prec, const char* tune_cache, void* hip_stream,
+                               uf_batch** out);
 int64_t uf_batch_n_tables(const uf_batch* batch);
 uf_status uf_batch_workspace_size(const uf_batch* batch, size_t* bytes);
 /* Current launch configuration: branches staged per LDS block (8, 16 or 32),
@@ -278,15 +299,27 @@ typedef struct uf_mlp uf_mlp;
 uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows, int skip,
                         uf_mlp** out);
 /* Host FP32 weights [d_{l+1}][d_l] and bias [d_{l+1}] of one layer (either
- * may be NULL; for the linear path only w).  Synchronous. */
-uf_status uf_mlp_set(uf_mlp* mlp, int64_t layer, const float* w, const float* b);
+ * may be NULL; for the linear path only w).  Ordered on hip_stream: waits for
+ * the work queued on it, copies, and synchronises it before returning. */
+uf_status uf_mlp_set(uf_mlp* mlp, int64_t layer, const float* w, const float* b,
+                     void* hip_stream);
 /* Copy out one layer: what 0 = parameters, 1 = gradients, 2 = Adam first
- * moments, 3 = second moments.  Synchronous. */
-uf_status uf_mlp_get(const uf_mlp* mlp, int64_t layer, int what, float* w, float* b);
+ * moments, 3 = second moments.  Ordered after the work queued on hip_stream;
+ * synchronises it. */
+uf_status uf_mlp_get(const uf_mlp* mlp, int64_t layer, int what, float* w, float* b,
+                     void* hip_stream);
 /* z[i] = MLP(x[rows ? rows[i] : i]) for i < n; x: device BF16 rows of stride
  * ldx (>= d0, multiple of 8); z: device FP32 [n][dL]. */
 uf_status uf_mlp_forward(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const int32_t* rows,
                          int64_t n, float* z, void* hip_stream);
+/* Gradients of every parameter (and of S) for the n rows of the preceding
+ * uf_mlp_forward, given dz = dLoss/dz as device BF16 [n][dL]: x, ldx and rows
+ * must be the ones that forward pass was given (its hidden activations are
+ * held in the MLP until the next forward).  Weight gradients are dz^T h and
+ * (g W) masked by the ReLU of each hidden layer, bias gradients column sums
+ * (FP64, fixed order).  Left in the MLP for uf_mlp_adam / uf_mlp_get. */
+uf_status uf_mlp_backward(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const int32_t* rows,
+                          int64_t n, const void* dz_bf16, void* hip_stream);
 /* Loss mean_p (w_p (||z_a - z_b||_2 - target_p))^2 over n_pairs pairs
  * (device index arrays into x), written to loss (device, 1 float); w_p = 1,
  * or 1 / max(target_p, rel_floor) when rel_floor > 0 (relative error, which
@@ -301,6 +334,9 @@ uf_status uf_mlp_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const i
  * Adam). */
 uf_status uf_mlp_adam(uf_mlp* mlp, float lr, float beta1, float beta2, float eps,
                       float weight_decay, int64_t step, void* hip_stream);
+/* Plain Adam: uf_mlp_adam with weight_decay = 0. */
+uf_status uf_adam_step(uf_mlp* mlp, float lr, float beta1, float beta2, float eps, int64_t step,
+                       void* hip_stream);
 void uf_free_mlp(uf_mlp* mlp);
 
 /* out[i][j] = ||a_i - b_j||^2 (FP32, device [na][dim], [nb][dim] -> [na][nb]). */
@@ -336,6 +372,15 @@ uf_status uf_dm_rerank_weighted_normalized(const uf_sparse* queries, const uf_sp
                                            const int32_t* query_ids, const int32_t* cand,
                                            int64_t n_queries, int64_t k, double* out, void* ws,
                                            size_t ws_bytes, void* hip_stream);
+
+/* Exact weighted-normalized distances of arbitrary pairs across two tables on
+ * the same tree: out[p] = d(a[pairs[p]], b[pairs[n_pairs + p]]) in FP64 for
+ * p < n_pairs; pairs is a device int32 array [2][n_pairs].  Same arithmetic as
+ * uf_dm_rerank_weighted_normalized (one candidate per query); ws of
+ * uf_rerank_workspace_size(a, n_pairs) bytes. */
+uf_status uf_dm_pairs_weighted_normalized(const uf_sparse* a, const uf_sparse* b,
+                                          const int32_t* pairs, int64_t n_pairs, double* out,
+                                          void* ws, size_t ws_bytes, void* hip_stream);
 
 /* ---- principal coordinates (PCoA) ----------------------------------------- */
 
@@ -403,9 +448,11 @@ uf_status uf_mantel(const double* x, const double* y, int64_t n, int method, con
 /* Per-kernel timing with HIP events recorded on the call's stream around each
  * launch (process-wide; off by default).  Names: "embed_nm", "embed_pres",
  * "band_wn_f64", "band_wn_f32", "band_wn_u32", "band_uw_f64", "band_uw_f32",
- * "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize", "row_sums".  uf_profile_read synchronises the recorded events
- * and returns the total milliseconds and launch count of one kernel name
- * since the last reset.  Errors: UF_ERR_ARG (NULL), UF_ERR_DEVICE. */
+ * "gram_mfma", "rare_slots_wn", "rare_slots_uw", "finalize", "row_sums", and
+ * the embedding preparation: "sample_scalars", "branch_count", "split_fill",
+ * "sort_lists", "split_lengths".  uf_profile_read synchronises the recorded
+ * events and returns the total milliseconds and launch count of one kernel
+ * name since the last reset.  Errors: UF_ERR_ARG (NULL), UF_ERR_DEVICE. */
 void uf_profile_enable(int on);
 void uf_profile_reset(void);
 uf_status uf_profile_read(const char* kernel, double* total_ms, int64_t* launches);

@@ -28,7 +28,7 @@ __all__ = [
     "dm_weighted_normalized", "dm_stripes", "n_stripes", "condensed_index", "set_chunk_nodes",
     "exported_symbols", "LIB_PATH", "HEADER_PATH", "profile_enable", "profile_reset",
     "profile_read", "Batch", "set_split_threshold", "split_stats", "project", "MLP", "sqdist", "topk_rows", "condensed_block",
-    "gather_pairs", "Sparse", "rerank", "pcoa", "mantel",
+    "gather_pairs", "Sparse", "rerank", "dm_pairs", "pcoa", "mantel",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -64,6 +64,7 @@ _SIGS = {
     "uf_embed": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "uf_embedding_n_samples": (_i64, [_vp]),
     "uf_embedding_scalars": (ctypes.c_int, [_vp, _f64p, _f64p]),
+    "uf_embedding_prepare": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "uf_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "uf_set_chunk_nodes": (None, [_i64]),
@@ -85,6 +86,8 @@ _SIGS = {
     "uf_free_embedding": (None, [_vp]),
     "uf_batch_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, ctypes.c_char_p, _vp,
                                        ctypes.POINTER(_vp)]),
+    "uf_batch_plan_create": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i64, ctypes.c_int,
+                                            ctypes.c_char_p, _vp, ctypes.POINTER(_vp)]),
     "uf_batch_n_tables": (_i64, [_vp]),
     "uf_batch_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
@@ -97,8 +100,11 @@ _SIGS = {
     "uf_free_batch": (None, [_vp]),
     "uf_project": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp]),
     "uf_mlp_create": (ctypes.c_int, [_i64, _i64p, _i64, ctypes.c_int, ctypes.POINTER(_vp)]),
-    "uf_mlp_set": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
-    "uf_mlp_get": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp]),
+    "uf_mlp_set": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp]),
+    "uf_mlp_get": (ctypes.c_int, [_vp, _i64, ctypes.c_int, _vp, _vp, _vp]),
+    "uf_mlp_backward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "uf_adam_step": (ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _i64, _vp]),
     "uf_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "uf_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, ctypes.c_float, _vp,
                                         _vp]),
@@ -115,6 +121,8 @@ _SIGS = {
     "uf_rerank_workspace_size": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_dm_rerank_weighted_normalized": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp,
                                                         ctypes.c_size_t, _vp]),
+    "uf_dm_pairs_weighted_normalized": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp,
+                                                       ctypes.c_size_t, _vp]),
     "uf_pcoa_workspace_size": (ctypes.c_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_pcoa": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                _vp, ctypes.c_size_t, _vp]),
@@ -306,6 +314,13 @@ class Embedding(_Handle):
         _check(lib().uf_embedding_scalars(self._h, _ptr(sw, ctypes.c_double),
                                           _ptr(wu, ctypes.c_double)))
         return sw[:n], wu[:n]
+
+    def prepare(self, scalars: bool = True, split_weighted: bool = False,
+                split_unweighted: bool = False, stream=None) -> None:
+        """Re-run the device-side preparation from the resident table and tree:
+        per-sample scalars and/or a rebuild of each requested variant's split."""
+        what = (1 if scalars else 0) | (2 if split_unweighted else 0) | (4 if split_weighted else 0)
+        _check(lib().uf_embedding_prepare(self._h, what, _stream_ptr(stream)))
 
 
 def _variant(v: str) -> int:
@@ -516,22 +531,25 @@ class MLP(_Handle):
     def n_layers(self) -> int:
         return len(self.dims) - 1
 
-    def set(self, layer: int, w=None, b=None):
+    def set(self, layer: int, w=None, b=None, stream=None):
         wa = _as(w, np.float32) if w is not None else None
         ba = _as(b, np.float32) if b is not None else None
         _check(lib().uf_mlp_set(self._h, layer, wa.ctypes.data_as(_vp) if wa is not None else None,
-                                ba.ctypes.data_as(_vp) if ba is not None else None))
+                                ba.ctypes.data_as(_vp) if ba is not None else None,
+                                _stream_ptr(stream)))
 
-    def get(self, layer: int, what: str = "params"):
+    def get(self, layer: int, what: str = "params", stream=None):
         """(w, b) of a layer; layer == n_layers is the linear path (b is None)."""
         sel = {"params": 0, "grads": 1, "adam_m": 2, "adam_v": 3}[what]
         if layer == self.n_layers:
             w = np.zeros((self.dims[-1], self.dims[0]), dtype=np.float32)
-            _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), None))
+            _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), None,
+                                    _stream_ptr(stream)))
             return w, None
         w = np.zeros((self.dims[layer + 1], self.dims[layer]), dtype=np.float32)
         b = np.zeros(self.dims[layer + 1], dtype=np.float32)
-        _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), b.ctypes.data_as(_vp)))
+        _check(lib().uf_mlp_get(self._h, layer, sel, w.ctypes.data_as(_vp), b.ctypes.data_as(_vp),
+                                _stream_ptr(stream)))
         return w, b
 
     def forward(self, x, rows=None, out=None, stream=None):
@@ -552,8 +570,18 @@ class MLP(_Handle):
                                       _tptr(loss), _stream_ptr(stream)))
         return loss
 
+    def backward(self, x, dz, rows=None, stream=None):
+        """Parameter gradients for the rows of the preceding forward(x, rows), given
+        dz (device BF16 [n][dL])."""
+        n = int(rows.numel()) if rows is not None else int(x.shape[0])
+        _check(lib().uf_mlp_backward(self._h, _tptr(x), x.stride(0), _tptr(rows), n, _tptr(dz),
+                                     _stream_ptr(stream)))
+
     def adam(self, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
              eps: float = 1e-8, weight_decay: float = 0.0, stream=None):
+        if weight_decay == 0.0:
+            _check(lib().uf_adam_step(self._h, lr, beta1, beta2, eps, int(step), _stream_ptr(stream)))
+            return
         _check(lib().uf_mlp_adam(self._h, lr, beta1, beta2, eps, weight_decay, int(step),
                                  _stream_ptr(stream)))
 
@@ -632,6 +660,23 @@ def rerank(queries: Sparse, refs: Sparse, query_ids, cand, out=None, workspace=N
                                                   _tptr(ws), ws.numel() * ws.element_size(),
                                                   _stream_ptr(stream)))
     return out[:nq]
+
+
+def dm_pairs(a: Sparse, b: Sparse, pairs, out=None, workspace=None, stream=None):
+    """Exact weighted-normalized d(a[pairs[0][p]], b[pairs[1][p]]): FP64 [n_pairs]
+    (pairs: device int32 [2][n_pairs])."""
+    import torch
+    n = int(pairs.shape[1])
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    need = ctypes.c_size_t(0)
+    _check(lib().uf_rerank_workspace_size(a.handle, n, ctypes.byref(need)))
+    ws = _workspace(int(need.value), workspace)
+    pairs = pairs.contiguous()
+    _check(lib().uf_dm_pairs_weighted_normalized(a.handle, b.handle, _tptr(pairs), n, _tptr(out),
+                                                 _tptr(ws), ws.numel() * ws.element_size(),
+                                                 _stream_ptr(stream)))
+    return out[:n]
 
 
 def pcoa(dm, n: int, dims: int, omega, power_iters: int = 3, row_means=None, grand_mean=None,

@@ -193,11 +193,42 @@ ufp::Emb emb_view(const uf_embedding& e) {
     return v;
 }
 
-void free_split(SplitCache* sc) {
-    if (!sc) return;
-    if (sc->arena) (void)hipFree(sc->arena);
-    delete sc;
+// Device temporaries of a split build: the embedding's grow-only scratch.
+char* split_scratch(uf_embedding* e, size_t bytes, uf_status* st) {
+    if (e->split_tmp.bytes < bytes) {
+        if (e->split_tmp.buf) (void)hipFree(e->split_tmp.buf);
+        e->split_tmp.buf = nullptr;
+        e->split_tmp.bytes = 0;
+        if (hipMalloc(&e->split_tmp.buf, bytes) != hipSuccess) {
+            *st = fail(UF_ERR_NOMEM, "split temporaries");
+            return nullptr;
+        }
+        e->split_tmp.bytes = bytes;
+    }
+    *st = UF_OK;
+    return static_cast<char*>(e->split_tmp.buf);
 }
+
+// Samples touching each branch (device, then host).  Both variants' splits
+// classify branches by these counts.
+uf_status branch_counts(uf_embedding* e, hipStream_t s, std::vector<int32_t>* out) {
+    const int64_t nb = e->nb;
+    uf_status st = UF_OK;
+    char* tmp = split_scratch(e, size_t(std::max<int64_t>(nb, 1)) * 4 + 256, &st);
+    if (!tmp) return st;
+    int32_t* dcnt = reinterpret_cast<int32_t*>(tmp);
+    out->assign(size_t(std::max<int64_t>(nb, 1)), 0);
+    {
+        ProfScope ps("branch_count", s);
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dcnt), std::max<int64_t>(nb, 1), s));
+        UF_HIP(ufs::branch_count(emb_view(*e), dcnt, s));
+    }
+    UF_HIP(hipStreamSynchronize(s));
+    if (nb) UF_HIP(hipMemcpy(out->data(), dcnt, size_t(nb) * 4, hipMemcpyDeviceToHost));
+    return UF_OK;
+}
+
+std::atomic<uint64_t> g_split_builds{0};
 
 // Scale Q of the 32-bit fixed-point dense pass of the weighted split (0: use FP32).
 // x_int = rint(x Q) is off by at most 1/(2Q) per value, so a pair's numerator is off
@@ -223,49 +254,23 @@ double fixed_point_scale(const std::vector<double>& sw, const std::vector<unsign
     return ratio / (2.0 * q) <= kMaxDistErr ? q : 0.0;
 }
 
-// Build (or rebuild for a new threshold) the dense set and the shared
-// non-dense branch lists of an embedding.  Synchronous on `stream`.
+// Build the dense set and the shared non-dense branch lists of one variant of an
+// embedding at threshold thr.  Synchronous on `s`.  Caller holds e->split_mu.
 //
-// A branch touched by c samples costs c(c-1)/2 pair atomics when left out of the
+// A branch touched by c samples costs c(c-1)/2 pair visits when left out of the
 // dense set, and one pass over all N*floor(N/2) stripe slots of the dense kernel
 // when put in it.  With a fixed threshold f it is dense when c > f*N; with the
 // automatic one when c(c-1)/2 / (slot rate) > N*floor(N/2) / rate of the
 // variant's dense kernel, i.e. when it is cheaper in the dense kernel.
-uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
-    uf_embedding* e = const_cast<uf_embedding*>(ce);   // the cache is internal state
-    const int w = weighted ? 1 : 0;
-    std::lock_guard<std::mutex> lk(e->split_mu);
-    const double thr = g_split_threshold[w].load();
-    if (e->split[w] && e->split[w]->threshold == thr) return UF_OK;
-    free_split(e->split[w]);
-    e->split[w] = nullptr;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+uf_status build_split(uf_embedding* e, int weighted, double thr, const std::vector<int32_t>& cnt,
+                      hipStream_t s, std::shared_ptr<SplitCache>* out) {
     const int64_t n = e->n, nb = e->nb;
     const ufp::Emb ev = emb_view(*e);
-    // temporaries: branch counts, unsorted lists, list fill and per-sample cursors
-    std::vector<void*> tmp;
-    auto tmp_alloc = [&](size_t bytes) -> void* {
-        void* q = nullptr;
-        if (hipMalloc(&q, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
-        tmp.push_back(q);
-        return q;
-    };
-    struct Freer {
-        std::vector<void*>& v;
-        ~Freer() {
-            for (void* q : v) (void)hipFree(q);
-        }
-    } freer{tmp};
-    int32_t* dcnt = static_cast<int32_t*>(tmp_alloc(size_t(nb) * 4));
-    if (!dcnt) return fail(UF_ERR_NOMEM, "branch counts");
-    UF_HIP(hipMemsetAsync(dcnt, 0, std::max<size_t>(size_t(nb) * 4, 256), s));
-    UF_HIP(ufs::branch_count(ev, dcnt, s));
-    std::vector<int32_t> cnt(size_t(std::max<int64_t>(nb, 1)), 0);
-    UF_HIP(hipStreamSynchronize(s));
-    if (nb) UF_HIP(hipMemcpy(cnt.data(), dcnt, size_t(nb) * 4, hipMemcpyDeviceToHost));
-    auto sc = std::unique_ptr<SplitCache>(new SplitCache());
+    auto sc = std::make_shared<SplitCache>();
+    sc->build_id = ++g_split_builds;
     sc->threshold = thr;
     std::vector<int32_t> cls(size_t(std::max<int64_t>(nb, 1)), ufs::kClassAlone), dense;
+    std::vector<int32_t> small_ids, large_ids;
     std::vector<int64_t> roff(1, 0);
     const double lim = thr * double(n);
     const double pair_lim = 2.0 * double(n) * double(n / 2) *
@@ -278,7 +283,9 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
             cls[size_t(v)] = ufs::kClassDense;
             dense.push_back(int32_t(v));
         } else if (c >= 2) {
-            cls[size_t(v)] = int32_t(roff.size()) - 1;
+            const int32_t id = int32_t(roff.size()) - 1;
+            cls[size_t(v)] = id;
+            (c <= ufs::kSortSmall ? small_ids : large_ids).push_back(id);
             roff.push_back(roff.back() + c);
             sc->n_pairs += c * (c - 1) / 2;
         }
@@ -308,20 +315,24 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     }
     const size_t ne = size_t(std::max<int64_t>(sc->n_entries, 1));
     const size_t nl = size_t(std::max<int64_t>(sc->n_lists, 1));
+    const size_t nn = size_t(std::max<int64_t>(n, 1));
     Carver c;
     const size_t o_dense = c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4);
     const size_t o_cls = c.take(size_t(std::max<int64_t>(nb, 1)) * 4);
     const size_t o_roff = c.take(roff.size() * 8);
     const size_t o_rs = weighted ? 0 : c.take(ne * 4);
     const size_t o_rw = weighted ? c.take(ne * 8) : 0;
-    const size_t o_sig = c.take(size_t(std::max<int64_t>(n, 1)) * 8);
+    const size_t o_sig = c.take(nn * 8);
     const size_t o_dhi = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
     const size_t o_dlo = c.take(size_t(std::max<int64_t>(sc->n_dense_pad, 1)) * 2);
     const size_t o_rl = c.take(nl * 8);
     const size_t o_soff = c.take(size_t(n + 1) * 8);
     const size_t o_ent = c.take(ne * sizeof(ufs::SlotEntry));
     const size_t o_lord = weighted ? c.take(size_t(std::max<int64_t>(sc->n_dense, 1)) * 4) : 0;
-    if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) return fail(UF_ERR_NOMEM, "split lists");
+    if (hipMalloc(&sc->arena, c.off + 256) != hipSuccess) {
+        sc->arena = nullptr;
+        return fail(UF_ERR_NOMEM, "split lists");
+    }
     char* b = static_cast<char*>(sc->arena);
     sc->dense = reinterpret_cast<int32_t*>(b + o_dense);
     sc->cls = reinterpret_cast<int32_t*>(b + o_cls);
@@ -335,71 +346,116 @@ uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream) {
     sc->soff = reinterpret_cast<int64_t*>(b + o_soff);
     sc->entries = reinterpret_cast<ufs::SlotEntry*>(b + o_ent);
     sc->lo_ord = weighted ? reinterpret_cast<int32_t*>(b + o_lord) : nullptr;
-    auto fail_free = [&](uf_status code) {
-        (void)hipFree(sc->arena);
-        sc->arena = nullptr;
-        return code;
-    };
-    int32_t* rs_tmp = static_cast<int32_t*>(tmp_alloc(ne * 4));
-    int64_t* rq_tmp = static_cast<int64_t*>(tmp_alloc(ne * 8));
-    int32_t* fill = static_cast<int32_t*>(tmp_alloc(nl * 4));
-    int32_t* scnt = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
-    int32_t* scur = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
-    int32_t* dnnz = static_cast<int32_t*>(tmp_alloc(size_t(std::max<int64_t>(n, 1)) * 4));
-    if (!rs_tmp || !rq_tmp || !fill || !scnt || !scur || !dnnz)
-        return fail_free(fail(UF_ERR_NOMEM, "split temporaries"));
-    hipError_t rc = hipSuccess;
-    if (sc->n_dense) rc = hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice);
-    if (rc == hipSuccess && weighted && sc->n_dense) {
+    // temporaries in the embedding's scratch: unsorted list members, list fill
+    // cursors, per-sample counts and cursors, and the list ids by sort class
+    Carver t;
+    const size_t t_rs = t.take(ne * 4);
+    const size_t t_rq = t.take(ne * 8);
+    const size_t t_fill = t.take(nl * 4);
+    const size_t t_scnt = t.take(nn * 4);
+    const size_t t_scur = t.take(nn * 4);
+    const size_t t_dnnz = t.take(nn * 4);
+    const size_t t_small = t.take(std::max<size_t>(small_ids.size(), 1) * 4);
+    const size_t t_large = t.take(std::max<size_t>(large_ids.size(), 1) * 4);
+    uf_status sst = UF_OK;
+    char* tb = split_scratch(e, t.off + 256, &sst);
+    if (!tb) return sst;
+    int32_t* rs_tmp = reinterpret_cast<int32_t*>(tb + t_rs);
+    int64_t* rq_tmp = reinterpret_cast<int64_t*>(tb + t_rq);
+    int32_t* fill = reinterpret_cast<int32_t*>(tb + t_fill);
+    int32_t* scnt = reinterpret_cast<int32_t*>(tb + t_scnt);
+    int32_t* scur = reinterpret_cast<int32_t*>(tb + t_scur);
+    int32_t* dnnz = reinterpret_cast<int32_t*>(tb + t_dnnz);
+    int32_t* d_small = reinterpret_cast<int32_t*>(tb + t_small);
+    int32_t* d_large = reinterpret_cast<int32_t*>(tb + t_large);
+    if (sc->n_dense) UF_HIP(hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice));
+    if (weighted && sc->n_dense) {
         // the dense list in ascending lo, for the merge embedding of the dense chunks
         std::vector<int32_t> lo(size_t(nb + 1));
-        rc = hipMemcpy(lo.data(), e->lo, size_t(nb + 1) * 4, hipMemcpyDeviceToHost);
+        UF_HIP(hipMemcpy(lo.data(), e->lo, size_t(nb + 1) * 4, hipMemcpyDeviceToHost));
         std::vector<int32_t> ord(size_t(sc->n_dense));
         for (int64_t k = 0; k < sc->n_dense; ++k) ord[size_t(k)] = int32_t(k);
         std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
             return lo[size_t(dense[size_t(x)])] < lo[size_t(dense[size_t(y)])];
         });
-        if (rc == hipSuccess)
-            rc = hipMemcpy(sc->lo_ord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice);
+        UF_HIP(hipMemcpy(sc->lo_ord, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
     }
-    if (rc == hipSuccess && nb) rc = hipMemcpy(sc->cls, cls.data(), size_t(nb) * 4, hipMemcpyHostToDevice);
-    if (rc == hipSuccess) rc = hipMemcpy(sc->roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice);
-    if (rc == hipSuccess) rc = hipMemsetAsync(fill, 0, nl * 4, s);
-    if (rc == hipSuccess) rc = hipMemsetAsync(scnt, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
-    if (rc == hipSuccess) rc = hipMemsetAsync(scur, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
-    if (rc == hipSuccess) rc = hipMemsetAsync(dnnz, 0, size_t(std::max<int64_t>(n, 1)) * 4, s);
-    if (rc == hipSuccess) rc = hipMemsetAsync(sc->sigma, 0, size_t(std::max<int64_t>(n, 1)) * 8, s);
-    if (rc == hipSuccess)
-        rc = ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz,
-                             1.0 / sc->unit, s);
-    const size_t nn = size_t(std::max<int64_t>(n, 1));
+    if (nb) UF_HIP(hipMemcpy(sc->cls, cls.data(), size_t(nb) * 4, hipMemcpyHostToDevice));
+    UF_HIP(hipMemcpy(sc->roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice));
+    if (!small_ids.empty())
+        UF_HIP(hipMemcpy(d_small, small_ids.data(), small_ids.size() * 4, hipMemcpyHostToDevice));
+    if (!large_ids.empty())
+        UF_HIP(hipMemcpy(d_large, large_ids.data(), large_ids.size() * 4, hipMemcpyHostToDevice));
+    {
+        ProfScope ps("split_fill", s);
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(fill), int64_t(nl), s));
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(scnt), int64_t(nn), s));
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(scur), int64_t(nn), s));
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dnnz), int64_t(nn), s));
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(sc->sigma), int64_t(nn) * 2, s));
+        UF_HIP(ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz,
+                               1.0 / sc->unit, s));
+    }
     std::vector<int32_t> hcnt(nn, 0), hdnnz(nn, 0);
     std::vector<double> hsw(nn, 0.0);
     std::vector<unsigned long long> hsig(nn, 0);
-    if (rc == hipSuccess) rc = hipStreamSynchronize(s);
-    if (rc == hipSuccess && n) rc = hipMemcpy(hcnt.data(), scnt, size_t(n) * 4, hipMemcpyDeviceToHost);
-    if (rc == hipSuccess && n) rc = hipMemcpy(hdnnz.data(), dnnz, size_t(n) * 4, hipMemcpyDeviceToHost);
-    if (rc == hipSuccess && n) rc = hipMemcpy(hsw.data(), e->sw, size_t(n) * 8, hipMemcpyDeviceToHost);
-    if (rc == hipSuccess && n)
-        rc = hipMemcpy(hsig.data(), sc->sigma, size_t(n) * 8, hipMemcpyDeviceToHost);
-    if (rc == hipSuccess && weighted)
-        sc->q_scale = fixed_point_scale(hsw, hsig, sc->unit, hdnnz, sc->n_dense);
+    UF_HIP(hipStreamSynchronize(s));
+    if (n) {
+        UF_HIP(hipMemcpy(hcnt.data(), scnt, size_t(n) * 4, hipMemcpyDeviceToHost));
+        UF_HIP(hipMemcpy(hdnnz.data(), dnnz, size_t(n) * 4, hipMemcpyDeviceToHost));
+        UF_HIP(hipMemcpy(hsw.data(), e->sw, size_t(n) * 8, hipMemcpyDeviceToHost));
+        UF_HIP(hipMemcpy(hsig.data(), sc->sigma, size_t(n) * 8, hipMemcpyDeviceToHost));
+    }
+    if (weighted) sc->q_scale = fixed_point_scale(hsw, hsig, sc->unit, hdnnz, sc->n_dense);
     std::vector<int64_t> soff(size_t(n + 1), 0);
     for (int64_t i = 0; i < n; ++i) soff[size_t(i + 1)] = soff[size_t(i)] + hcnt[size_t(i)];
-    if (rc == hipSuccess && soff[size_t(n)] != sc->n_entries)
-        return fail_free(fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree"));
-    if (rc == hipSuccess) rc = hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice);
-    if (rc == hipSuccess)
-        rc = ufs::sort_lists(sc->roff, sc->n_lists, n, ufs::slot_segment_len(0, n / 2), rs_tmp,
-                             rq_tmp, sc->rs, sc->rw, sc->soff, scur,
-                             sc->entries, s);
-    if (rc == hipSuccess)
-        rc = ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
-                                e->len_lo, sc->dlen_hi, sc->dlen_lo, sc->rl, s);
-    if (rc == hipSuccess && !weighted) rc = ufs::entry_lengths(sc->entries, sc->n_entries, sc->rl, s);
-    if (rc == hipSuccess) rc = hipStreamSynchronize(s);
-    if (rc != hipSuccess) return fail_free(hip_fail(rc, "sparse split build"));
-    e->split[w] = sc.release();
+    if (soff[size_t(n)] != sc->n_entries)
+        return fail(UF_ERR_DEVICE, "sparse split: list entry counts disagree");
+    UF_HIP(hipMemcpy(sc->soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice));
+    {
+        ProfScope ps("sort_lists", s);
+        UF_HIP(ufs::sort_lists(sc->roff, d_small, int64_t(small_ids.size()), d_large,
+                               int64_t(large_ids.size()), n, ufs::slot_segment_len(0, n / 2),
+                               rs_tmp, rq_tmp, sc->rs, sc->rw, sc->soff, scur, sc->entries, s));
+    }
+    {
+        ProfScope ps("split_lengths", s);
+        UF_HIP(ufs::split_lengths(sc->cls, nb, sc->dense, sc->n_dense, sc->n_dense_pad, e->len_hi,
+                                  e->len_lo, sc->dlen_hi, sc->dlen_lo, sc->rl, s));
+        if (!weighted) UF_HIP(ufs::entry_lengths(sc->entries, sc->n_entries, sc->rl, s));
+    }
+    UF_HIP(hipStreamSynchronize(s));
+    *out = std::move(sc);
+    return UF_OK;
+}
+
+// The split of one variant at the current threshold: the cached one, or a new
+// build (also when force is set).  The returned reference keeps it alive for the
+// caller even if another thread replaces it meanwhile.
+uf_status ensure_split(const uf_embedding* ce, int weighted, void* stream,
+                       std::shared_ptr<SplitCache>* out, bool force = false,
+                       const std::vector<int32_t>* counts = nullptr) {
+    if (!ce) return fail(UF_ERR_ARG, "embedding is NULL");
+    uf_embedding* e = const_cast<uf_embedding*>(ce);   // the cache is internal state
+    const int w = weighted ? 1 : 0;
+    std::lock_guard<std::mutex> lk(e->split_mu);
+    const double thr = g_split_threshold[w].load();
+    if (!force && e->split[w] && e->split[w]->threshold == thr) {
+        *out = e->split[w];
+        return UF_OK;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> own;
+    if (!counts) {
+        uf_status st = branch_counts(e, s, &own);
+        if (st != UF_OK) return st;
+        counts = &own;
+    }
+    std::shared_ptr<SplitCache> sc;
+    uf_status st = build_split(e, w, thr, *counts, s, &sc);
+    if (st != UF_OK) return st;
+    e->split[w] = sc;   // a previous split is freed when its last user lets go
+    *out = std::move(sc);
     return UF_OK;
 }
 
@@ -414,8 +470,9 @@ struct Plan {
     size_t off_acc = 0, off_q = 0, off_chunk = 0, off_part = 0, off_rm = 0, off_m = 0, total = 0;
 };
 
+// sp: the variant's split for the split precisions (ignored otherwise)
 uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
-                    int64_t se, bool rowstats, Plan* p) {
+                    int64_t se, bool rowstats, Plan* p, const SplitCache* sp = nullptr) {
     if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
     if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2 && prec != UF_FP32_SPLIT &&
         prec != UF_MFMA_SPLIT)
@@ -440,7 +497,8 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     p->rowstats = rowstats;
     const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
     const bool mfma = prec == UF_MFMA_BF16X2 || prec == UF_MFMA_SPLIT;
-    const int64_t nb = split ? e->split[weighted ? 1 : 0]->n_dense : e->nb;
+    if (split && !sp) return fail(UF_ERR_ARG, "split precision without a split");
+    const int64_t nb = split ? sp->n_dense : e->nb;
     const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 1 : 4);
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
@@ -472,23 +530,25 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
 uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb, int64_t se,
                  int layout, uf_out_dtype odt, void* out, double* row_out, double* grand_mean,
                  bool full_means, void* ws, size_t ws_bytes, void* stream) {
+    if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
     if (!out) return fail(UF_ERR_ARG, "output pointer is NULL");
     if (layout != UF_CONDENSED && layout != UF_STRIPES) return fail(UF_ERR_ARG, "bad layout");
     if (odt != UF_OUT_F64 && odt != UF_OUT_F32) return fail(UF_ERR_ARG, "bad output dtype");
     const bool rowstats = row_out != nullptr || grand_mean != nullptr;
+    int dev = 0;
+    uf_status st = check_device(&dev);
+    if (st != UF_OK) return st;
+    if (dev != e->device) return fail(UF_ERR_DEVICE, "embedding lives on another device");
     Plan p;
+    std::shared_ptr<SplitCache> hold;   // keeps the split alive while this call enqueues
     if ((prec == UF_FP32_SPLIT && weighted) || (prec == UF_MFMA_SPLIT && !weighted)) {
-        uf_status sst = ensure_split(e, weighted, stream);
-        if (sst != UF_OK) return sst;
+        st = ensure_split(e, weighted, stream, &hold);
+        if (st != UF_OK) return st;
     }
-    uf_status st = make_plan(e, weighted, prec, sb, se, rowstats, &p);
+    st = make_plan(e, weighted, prec, sb, se, rowstats, &p, hold.get());
     if (st != UF_OK) return st;
     if (!ws || ws_bytes < p.total)
         return fail(UF_ERR_WORKSPACE, "workspace missing or smaller than uf_workspace_size()");
-    int dev = 0;
-    st = check_device(&dev);
-    if (st != UF_OK) return st;
-    if (dev != e->device) return fail(UF_ERR_DEVICE, "embedding lives on another device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.sr == 0 || p.n < 2) {
         if (row_out && p.n > 0) UF_HIP(hipMemsetAsync(row_out, 0, size_t(p.n) * 8, s));
@@ -501,7 +561,7 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
     void* chunk = base + p.off_chunk;
     const int64_t nb = e->nb;
     const bool split = prec == UF_FP32_SPLIT || prec == UF_MFMA_SPLIT;
-    const SplitCache* sp = split ? e->split[weighted ? 1 : 0] : nullptr;
+    const SplitCache* sp = split ? hold.get() : nullptr;
     // Dense part: node chunks (all branches, or the split's dense list) into acc.
     for (int64_t c = 0; c < p.nchunks; ++c) {
         const int64_t k0 = c * p.kc;
@@ -645,9 +705,9 @@ uf_status uf_split_stats(const uf_embedding* e, int weighted, int64_t* n_dense, 
                          int64_t* n_pairs) {
     return guarded([&]() -> uf_status {
         if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
-        uf_status st = ensure_split(e, weighted, nullptr);
+        std::shared_ptr<SplitCache> sc;
+        uf_status st = ensure_split(e, weighted, nullptr, &sc);
         if (st != UF_OK) return st;
-        const SplitCache* sc = e->split[weighted ? 1 : 0];
         if (n_dense) *n_dense = sc->n_dense;
         if (n_lists) *n_lists = sc->n_lists;
         if (n_pairs) *n_pairs = sc->n_pairs;
@@ -939,6 +999,9 @@ uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embe
         double* dd64 = reinterpret_cast<double*>(b + o_d64);
         double* dd32 = reinterpret_cast<double*>(b + o_d32);
         double* ddbf = reinterpret_cast<double*>(b + o_dbf);
+        e->d64 = dd64;
+        e->d32 = dd32;
+        e->dbf = ddbf;
         auto cleanup = [&](uf_status code) {
             (void)hipFree(arena);
             e->arena = nullptr;
@@ -995,10 +1058,42 @@ uf_status uf_embedding_scalars(const uf_embedding* e, double* sw, double* wu) {
     });
 }
 
+uf_status uf_embedding_prepare(const uf_embedding* ce, int what, void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!ce) return fail(UF_ERR_ARG, "embedding is NULL");
+        if (what & ~(UF_PREP_SCALARS | UF_PREP_SPLIT_UNWEIGHTED | UF_PREP_SPLIT_WEIGHTED))
+            return fail(UF_ERR_ARG, "unknown preparation flag");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        if (dev != ce->device) return fail(UF_ERR_DEVICE, "embedding lives on another device");
+        uf_embedding* e = const_cast<uf_embedding*>(ce);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if ((what & UF_PREP_SCALARS) && e->n > 0) {
+            ProfScope ps("sample_scalars", s);
+            UF_HIP(ufk::sample_scalars(*e, e->parent_pos, e->tip_pos, e->d64, e->d32, e->dbf, s));
+        }
+        const bool sw = (what & UF_PREP_SPLIT_WEIGHTED) != 0, su = (what & UF_PREP_SPLIT_UNWEIGHTED) != 0;
+        if (sw || su) {
+            // the branch sample counts serve both variants' dense sets
+            std::vector<int32_t> counts;
+            {
+                std::lock_guard<std::mutex> lk(e->split_mu);
+                st = branch_counts(e, s, &counts);
+            }
+            if (st != UF_OK) return st;
+            std::shared_ptr<SplitCache> sc;
+            if (sw && (st = ensure_split(e, 1, stream, &sc, true, &counts)) != UF_OK) return st;
+            if (su && (st = ensure_split(e, 0, stream, &sc, true, &counts)) != UF_OK) return st;
+        }
+        return UF_OK;
+    });
+}
+
 void uf_free_embedding(uf_embedding* e) {
     if (!e) return;
-    free_split(e->split[0]);
-    free_split(e->split[1]);
+    e->split[0].reset();
+    e->split[1].reset();
     if (e->arena) (void)hipFree(e->arena);
     delete e;
 }
@@ -1008,12 +1103,13 @@ uf_status uf_workspace_size(const uf_embedding* e, int weighted, uf_precision pr
                             int64_t se, int want_row_stats, size_t* bytes) {
     return guarded([&]() -> uf_status {
         if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
+        std::shared_ptr<SplitCache> sc;
         if (e && ((weighted && prec == UF_FP32_SPLIT) || (!weighted && prec == UF_MFMA_SPLIT))) {
-            uf_status sst = ensure_split(e, weighted, nullptr);
+            uf_status sst = ensure_split(e, weighted, nullptr, &sc);
             if (sst != UF_OK) return sst;
         }
         Plan p;
-        uf_status st = make_plan(e, weighted ? 1 : 0, prec, sb, se, want_row_stats != 0, &p);
+        uf_status st = make_plan(e, weighted ? 1 : 0, prec, sb, se, want_row_stats != 0, &p, sc.get());
         if (st != UF_OK) return st;
         *bytes = p.total;
         return UF_OK;
@@ -1280,10 +1376,11 @@ uf_status uf_batch_set_precision(uf_batch* b, uf_precision prec, const uf_table*
         for (int64_t r = 0; r < b->n_tables; ++r) {
             const uf_embedding* e = b->tembs[size_t(r)];
             if (!e) continue;
-            uf_status st = ensure_split(e, 1, stream);
+            std::shared_ptr<SplitCache> sc;
+            uf_status st = ensure_split(e, 1, stream, &sc);
             if (st != UF_OK) return st;
             Plan p;
-            st = make_plan(e, 1, UF_FP32_SPLIT, 0, e->n / 2, false, &p);
+            st = make_plan(e, 1, UF_FP32_SPLIT, 0, e->n / 2, false, &p, sc.get());
             if (st != UF_OK) return st;
             slot = std::max(slot, (p.total + 255) & ~size_t(255));
             b->order.push_back(r);
@@ -1424,6 +1521,23 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
     });
 }
 
+uf_status uf_batch_plan_create(const uf_tree* tree, const uf_table* const* tables, int64_t n_tables,
+                               uf_precision prec, const char* tune_cache, void* stream,
+                               uf_batch** out) {
+    if (prec != UF_FP32 && prec != UF_FP32_SPLIT) {
+        if (out) *out = nullptr;
+        return fail(UF_ERR_UNSUPPORTED, "batches run UF_FP32 or UF_FP32_SPLIT");
+    }
+    uf_status st = uf_batch_create(tree, tables, n_tables, tune_cache, stream, out);
+    if (st != UF_OK || prec == UF_FP32) return st;
+    st = uf_batch_set_precision(*out, prec, tables, stream);
+    if (st != UF_OK) {
+        uf_free_batch(*out);
+        *out = nullptr;
+    }
+    return st;
+}
+
 int64_t uf_batch_n_tables(const uf_batch* b) { return b ? b->n_tables : -1; }
 
 size_t batch_ws_bytes(const uf_batch* b) {
@@ -1476,9 +1590,10 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
         if (b->split) {
             // splits are built outside any capture (a changed threshold rebuilds them)
             for (int64_t r : b->order) {
-                st = ensure_split(b->tembs[size_t(r)], 1, stream);
+                std::shared_ptr<SplitCache> sc;
+                st = ensure_split(b->tembs[size_t(r)], 1, stream, &sc);
                 if (st != UF_OK) return st;
-                key.push_back(reinterpret_cast<uintptr_t>(b->tembs[size_t(r)]->split[1]));
+                key.push_back(uintptr_t(sc->build_id));
             }
             key.push_back(uintptr_t(b->n_streams));
         }

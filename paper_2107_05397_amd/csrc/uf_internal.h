@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +49,7 @@ struct SlotEntry;
 }
 
 struct SplitCache {
+    uint64_t build_id = 0;        // unique per build (graph keys)
     double threshold = 0.0;       // requested fraction, < 0 for the cost model
     int64_t n_dense = 0;          // branches in the dense set
     int64_t n_lists = 0;          // shared non-dense branches (>= 2 samples)
@@ -69,6 +71,25 @@ struct SplitCache {
     ufs::SlotEntry* entries = nullptr;   // [n_entries] the sample's list memberships
     double q_scale = 0.0;         // weighted: 32-bit fixed-point scale of the dense pass (0: FP32)
     int32_t* lo_ord = nullptr;    // weighted: [n_dense] indices into dense, by ascending lo
+    SplitCache() = default;
+    SplitCache(const SplitCache&) = delete;
+    SplitCache& operator=(const SplitCache&) = delete;
+    ~SplitCache() {
+        if (arena) (void)hipFree(arena);   // hipFree waits for work in flight on the device
+    }
+};
+
+// Device temporaries of a split build, kept per embedding and grown on demand so
+// that rebuilding a split does not allocate again (guarded by split_mu).
+struct SplitScratch {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    SplitScratch() = default;
+    SplitScratch(const SplitScratch&) = delete;
+    SplitScratch& operator=(const SplitScratch&) = delete;
+    ~SplitScratch() {
+        if (buf) (void)hipFree(buf);
+    }
 };
 
 // Device-resident inputs of the distance calls.  All arrays are on `device`.
@@ -95,11 +116,18 @@ struct uf_embedding {
     double* wu = nullptr;         // sum_v l_v a_sv, FP64 lengths
     double* wu32 = nullptr;       // same with FP32-rounded lengths
     double* wub = nullptr;        // same with hi+lo bf16 lengths
-    // sparse-aware split, built on first use (guarded by split_mu)
-    struct SplitCache* split[2] = {nullptr, nullptr};   // [0] unweighted, [1] weighted
+    // sparse-aware split, built on first use (guarded by split_mu).  A call that
+    // uses a split holds its own reference, so a rebuild by another thread (new
+    // threshold) never frees a split that is still being enqueued.
+    std::shared_ptr<SplitCache> split[2];   // [0] unweighted, [1] weighted
+    SplitScratch split_tmp;
     std::mutex split_mu;
     int32_t* parent_pos = nullptr;  // [nb+1], -1 for the root
     int32_t* tip_pos = nullptr;     // [n_tips] position of the tip with rank r
+    // root distances by position for the three length roundings (per-sample scalars)
+    double* d64 = nullptr;
+    double* d32 = nullptr;
+    double* dbf = nullptr;
     void* arena = nullptr;        // one allocation holding all of the above
 };
 

@@ -737,16 +737,16 @@ __device__ __forceinline__ double final_distance(int kind, const FinIn<A>& f, do
             num += double(f.m) * split_unit;
         }
     }
-    double d;
-    if (kind == 0) {
+    if (kind == 0) {   // a sum of |x - y| over the sum of x + y: no clamp needed
         const double den = f.sc_i + f.sc_j;
-        d = den > 0.0 ? num / den : 0.0;
-    } else {
-        const double sum = f.sc_i + f.sc_j;
-        const double orr = sum - num;
-        const double xr = sum - 2.0 * num;
-        d = orr > 0.0 ? xr / orr : 0.0;
+        return den > 0.0 ? num / den : 0.0;
     }
+    // Gram form: the differences w_i + w_j - 2G and w_i + w_j - G can round past the
+    // ends of [0, 1] (d(a, a) = 0 in exact arithmetic), so the result is clamped
+    const double sum = f.sc_i + f.sc_j;
+    const double orr = sum - num;
+    const double xr = sum - 2.0 * num;
+    const double d = orr > 0.0 ? xr / orr : 0.0;
     return fmin(fmax(d, 0.0), 1.0);
 }
 

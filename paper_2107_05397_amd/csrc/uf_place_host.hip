@@ -214,47 +214,51 @@ uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows,
     });
 }
 
-uf_status uf_mlp_set(uf_mlp* m, int64_t layer, const float* w, const float* b) {
+uf_status uf_mlp_set(uf_mlp* m, int64_t layer, const float* w, const float* b, void* stream) {
     return guarded([&]() -> uf_status {
         if (!m || layer < 0 || layer > m->L || (layer == m->L && !m->skip))
             return fail(UF_ERR_ARG, "bad MLP or layer");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        // work already queued on the stream may still read the parameters
+        UF_HIP(hipStreamSynchronize(s));
         if (layer == m->L) {   // the linear path S
             const size_t ns = size_t(m->dims[m->L] * m->dims[0]);
             if (w) {
-                UF_HIP(hipMemcpy(m->S, w, ns * 4, hipMemcpyHostToDevice));
-                UF_HIP(ufp::f32_to_bf16(m->S, int64_t(ns), m->Sbf, nullptr));
+                UF_HIP(hipMemcpyAsync(m->S, w, ns * 4, hipMemcpyHostToDevice, s));
+                UF_HIP(ufp::f32_to_bf16(m->S, int64_t(ns), m->Sbf, s));
             }
-            UF_HIP(hipDeviceSynchronize());
+            UF_HIP(hipStreamSynchronize(s));
             return UF_OK;
         }
         const size_t nw = size_t(m->dims[layer + 1] * m->dims[layer]), nb = size_t(m->dims[layer + 1]);
         if (w) {
-            UF_HIP(hipMemcpy(m->W[layer], w, nw * 4, hipMemcpyHostToDevice));
-            UF_HIP(ufp::f32_to_bf16(m->W[layer], int64_t(nw), m->Wbf[layer], nullptr));
+            UF_HIP(hipMemcpyAsync(m->W[layer], w, nw * 4, hipMemcpyHostToDevice, s));
+            UF_HIP(ufp::f32_to_bf16(m->W[layer], int64_t(nw), m->Wbf[layer], s));
         }
-        if (b) UF_HIP(hipMemcpy(m->b[layer], b, nb * 4, hipMemcpyHostToDevice));
-        UF_HIP(hipDeviceSynchronize());
+        if (b) UF_HIP(hipMemcpyAsync(m->b[layer], b, nb * 4, hipMemcpyHostToDevice, s));
+        UF_HIP(hipStreamSynchronize(s));   // the host arrays may be freed on return
         return UF_OK;
     });
 }
 
-uf_status uf_mlp_get(const uf_mlp* m, int64_t layer, int what, float* w, float* b) {
+uf_status uf_mlp_get(const uf_mlp* m, int64_t layer, int what, float* w, float* b, void* stream) {
     return guarded([&]() -> uf_status {
         if (!m || layer < 0 || layer > m->L || (layer == m->L && !m->skip) || what < 0 || what > 3)
             return fail(UF_ERR_ARG, "bad MLP, layer or selector");
+        hipStream_t s = static_cast<hipStream_t>(stream);
         if (layer == m->L) {
             const size_t ns = size_t(m->dims[m->L] * m->dims[0]);
             const float* ss[4] = {m->S, m->gS, m->mS, m->vS};
-            UF_HIP(hipDeviceSynchronize());
-            if (w) UF_HIP(hipMemcpy(w, ss[what], ns * 4, hipMemcpyDeviceToHost));
+            if (w) UF_HIP(hipMemcpyAsync(w, ss[what], ns * 4, hipMemcpyDeviceToHost, s));
+            UF_HIP(hipStreamSynchronize(s));
             return UF_OK;
         }
         const size_t nw = size_t(m->dims[layer + 1] * m->dims[layer]), nb = size_t(m->dims[layer + 1]);
         const float* sw[4] = {m->W[layer], m->gW[layer], m->mW[layer], m->vW[layer]};
         const float* sb[4] = {m->b[layer], m->gb[layer], m->mb[layer], m->vb[layer]};
-        UF_HIP(hipDeviceSynchronize());
-        if (w) UF_HIP(hipMemcpy(w, sw[what], nw * 4, hipMemcpyDeviceToHost));
-        if (b) UF_HIP(hipMemcpy(b, sb[what], nb * 4, hipMemcpyDeviceToHost));
+        if (w) UF_HIP(hipMemcpyAsync(w, sw[what], nw * 4, hipMemcpyDeviceToHost, s));
+        if (b) UF_HIP(hipMemcpyAsync(b, sb[what], nb * 4, hipMemcpyDeviceToHost, s));
+        UF_HIP(hipStreamSynchronize(s));
         return UF_OK;
     });
 }
@@ -299,6 +303,50 @@ uf_status uf_mlp_forward(uf_mlp* m, const void* x_bf16, int64_t ldx, const int32
     });
 }
 
+namespace {
+// Gradients of every parameter from dZ (BF16 [n][dL]) for the n rows of the
+// preceding forward pass (x, ldx, rows as given to it; its hidden activations are
+// still held in m->H).
+uf_status mlp_backward(uf_mlp* m, const uint16_t* x, int64_t ldx, const int32_t* rows, int64_t n,
+                       const uint16_t* dz, hipStream_t s) {
+    const int64_t L = m->L;
+    if (m->skip)   // dS = dZ^T x
+        UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, dz, m->dims[L], nullptr, x, ldx, rows,
+                              m->dims[L], m->dims[0], n, nullptr, nullptr, 0, m->gS, m->dims[0], s));
+    const uint16_t* g = dz;
+    for (int64_t l = L - 1; l >= 0; --l) {
+        const int64_t din = m->dims[l], dout = m->dims[l + 1];
+        // dW_l = g^T h_{l}: A = g (column layout), B = input of layer l (column layout)
+        const uint16_t* hin = l == 0 ? x : m->H[l];
+        const int64_t ldh = l == 0 ? ldx : din;
+        UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, g, dout, nullptr, hin, ldh, l == 0 ? rows : nullptr,
+                              dout, din, n, nullptr, nullptr, 0, m->gW[l], din, s));
+        UF_HIP(ufp::colsum_bf16(g, n, dout, m->gb[l], s));
+        if (l > 0) {
+            // dA_l = (g W_l) * [h_l > 0]: A = g (row), B = W_l (column layout)
+            UF_HIP(ufp::gemm_bf16(0, 1, ufp::EPI_MASK_BF16, g, dout, nullptr, m->Wbf[l], din, nullptr,
+                                  n, din, dout, nullptr, m->H[l], din, m->dA[l], din, s));
+            g = m->dA[l];
+        }
+    }
+    return UF_OK;
+}
+}  // namespace
+
+uf_status uf_mlp_backward(uf_mlp* m, const void* x_bf16, int64_t ldx, const int32_t* rows,
+                          int64_t n, const void* dz_bf16, void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!m || !x_bf16 || !dz_bf16 || n < 1) return fail(UF_ERR_ARG, "NULL argument or no rows");
+        if (n > m->max_rows) return fail(UF_ERR_ARG, "more rows than max_rows");
+        if (ldx < m->dims[0] || ldx % 8 != 0) return fail(UF_ERR_ARG, "ldx must be >= d0 and a multiple of 8");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        return mlp_backward(m, static_cast<const uint16_t*>(x_bf16), ldx, rows, n,
+                            static_cast<const uint16_t*>(dz_bf16), static_cast<hipStream_t>(stream));
+    });
+}
+
 uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int32_t* pair_a,
                            const int32_t* pair_b, const float* target, int64_t n_pairs,
                            float rel_floor, float* loss, void* stream) {
@@ -307,6 +355,7 @@ uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int
             return fail(UF_ERR_ARG, "NULL argument or no pairs");
         if (2 * n_pairs > m->max_rows) return fail(UF_ERR_ARG, "2 * n_pairs exceeds max_rows");
         if (ldx < m->dims[0] || ldx % 8 != 0) return fail(UF_ERR_ARG, "ldx must be >= d0 and a multiple of 8");
+        if (!(rel_floor >= 0.0f)) return fail(UF_ERR_ARG, "rel_floor must be >= 0");
         int dev = 0;
         uf_status st = check_device(&dev);
         if (st != UF_OK) return st;
@@ -319,26 +368,7 @@ uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int
         if (st != UF_OK) return st;
         UF_HIP(ufp::pairloss(m->Z, n_pairs, int(m->dims[L]), target, rel_floor, m->dZ, m->loss_pp,
                              loss, s));
-        if (m->skip)   // dS = dZ^T x
-            UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, m->dZ, m->dims[L], nullptr, x, ldx, m->rows,
-                                  m->dims[L], m->dims[0], R, nullptr, nullptr, 0, m->gS, m->dims[0], s));
-        const uint16_t* g = m->dZ;
-        for (int64_t l = L - 1; l >= 0; --l) {
-            const int64_t din = m->dims[l], dout = m->dims[l + 1];
-            // dW_l = g^T h_{l}: A = g (column layout), B = input of layer l (column layout)
-            const uint16_t* hin = l == 0 ? x : m->H[l];
-            const int64_t ldh = l == 0 ? ldx : din;
-            UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, g, dout, nullptr, hin, ldh, l == 0 ? m->rows : nullptr,
-                                  dout, din, R, nullptr, nullptr, 0, m->gW[l], din, s));
-            UF_HIP(ufp::colsum_bf16(g, R, dout, m->gb[l], s));
-            if (l > 0) {
-                // dA_l = (g W_l) * [h_l > 0]: A = g (row), B = W_l (column layout)
-                UF_HIP(ufp::gemm_bf16(0, 1, ufp::EPI_MASK_BF16, g, dout, nullptr, m->Wbf[l], din, nullptr,
-                                      R, din, dout, nullptr, m->H[l], din, m->dA[l], din, s));
-                g = m->dA[l];
-            }
-        }
-        return UF_OK;
+        return mlp_backward(m, x, ldx, m->rows, R, m->dZ, s);
     });
 }
 
@@ -361,6 +391,11 @@ uf_status uf_mlp_adam(uf_mlp* m, float lr, float beta1, float beta2, float eps,
                              bc1, bc2, weight_decay, m->Sbf, s));
         return UF_OK;
     });
+}
+
+uf_status uf_adam_step(uf_mlp* m, float lr, float beta1, float beta2, float eps, int64_t step,
+                       void* stream) {
+    return uf_mlp_adam(m, lr, beta1, beta2, eps, 0.0f, step, stream);
 }
 
 void uf_free_mlp(uf_mlp* m) { delete m; }
@@ -495,6 +530,16 @@ uf_status uf_dm_rerank_weighted_normalized(const uf_sparse* queries, const uf_sp
                            queries->nb, scratch, rows, out, s));
         return UF_OK;
     });
+}
+
+uf_status uf_dm_pairs_weighted_normalized(const uf_sparse* a, const uf_sparse* b,
+                                          const int32_t* pairs, int64_t n_pairs, double* out,
+                                          void* ws, size_t ws_bytes, void* stream) {
+    // pair p is (a[pairs[p]], b[pairs[n_pairs + p]]): the re-rank with one candidate each
+    if (!pairs || n_pairs < 0) return fail(UF_ERR_ARG, "bad pair list");
+    if (n_pairs == 0) return UF_OK;
+    return uf_dm_rerank_weighted_normalized(a, b, pairs, pairs + n_pairs, n_pairs, 1, out, ws,
+                                            ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -47,13 +47,18 @@ hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st);
 hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
                       int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
                       int32_t* dnnz, double fix, hipStream_t st);
+// Lists of at most kSortSmall members are ranked by one wave each; longer ones by
+// one workgroup each.
+constexpr int kSortSmall = 64;
 // Lists sorted by sample, into rs_out (sample ids) or, when rw_out is non-null, into
 // rw_out as packed words rq << kSampleBits | sample; per-sample index rows
 // [soff[s], soff[s+1]) of SlotEntry filled through the cursors scur (zeroed by the
 // caller); v holds the sample's value (weighted) or the list id (unweighted).
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, int64_t seg0, const int32_t* rs_in,
-                      const int64_t* rq_in,
-                      int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
+// small_ids / large_ids: the list ids of at most / more than kSortSmall members.
+hipError_t sort_lists(const int64_t* roff, const int32_t* small_ids, int64_t n_small,
+                      const int32_t* large_ids, int64_t n_large, int64_t n, int64_t seg0,
+                      const int32_t* rs_in, const int64_t* rq_in, int32_t* rs_out,
+                      unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st);
 // Unweighted: replace each entry's list id (left in v by sort_lists) by rl[list].
 hipError_t entry_lengths(SlotEntry* se, int64_t n_entries, const int64_t* rl, hipStream_t st);

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 #include <type_traits>
 
 #include "uf_device.h"
@@ -81,8 +83,7 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
 // Sort each list by sample: a member's new position is the number of members
 // with a smaller sample id (ids in a list are distinct).  Also records, in the
 // sample's row of the per-sample index, the list, the member's position and the
-// sizes of its window (RankWin).
-constexpr int kSortLds = 4096;
+// sizes of its window.
 
 __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k, int32_t smp,
                                              int32_t r, int32_t w, int32_t w0,
@@ -108,7 +109,7 @@ __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k,
 
 // Rank of sample smp in its list (members are distinct), the size of its window
 // (members at cyclic distance 1..floor(N/2) after it) and of the window's part
-// at distance <= seg0.
+// at distance <= seg0, by comparing with every member.
 struct RankWin {
     int32_t r = 0, w = 0, w0 = 0;
     __device__ __forceinline__ void add(int32_t other, int32_t smp, int64_t n, int64_t seg0) {
@@ -120,8 +121,11 @@ struct RankWin {
     }
 };
 
-__global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ roff, int64_t n,
-                                                    int64_t seg0,
+// Lists of at most 64 members: one wave each, a member per lane, compared with
+// every other member through lane broadcasts.
+__global__ __launch_bounds__(256) void k_sort_small(const int64_t* __restrict__ roff,
+                                                    const int32_t* __restrict__ ids, int64_t n_ids,
+                                                    int64_t n, int64_t seg0,
                                                     const int32_t* __restrict__ rs_in,
                                                     const int64_t* __restrict__ rq_in,
                                                     int32_t* __restrict__ rs_out,
@@ -129,14 +133,111 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
                                                     const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ scur,
                                                     SlotEntry* __restrict__ se) {
-    __shared__ int32_t ks[kSortLds];
-    const int64_t L = blockIdx.x;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= n_ids) return;   // wave-uniform
+    const int lane = threadIdx.x & 63;
+    const int64_t L = ids[t];
+    const int64_t base = roff[L];
+    const int32_t m = int32_t(roff[L + 1] - base);
+    const int32_t smp = lane < m ? rs_in[base + lane] : -1;
+    RankWin rw;
+    for (int32_t k = 0; k < m; ++k) rw.add(__shfl(smp, k, 64), smp, n, seg0);
+    if (lane < m)
+        place_member(L, base, lane, smp, rw.r, rw.w, rw.w0, rq_in, rs_out, rw_out, soff, scur, m, se);
+}
+
+// Longer lists: one workgroup each.  When the samples fit an LDS bitmap
+// (bitmap_words > 0, one bit per sample), the members set their bits, an
+// exclusive scan of the words' population counts gives, for any sample id x,
+// the number of members below x in O(1); the rank and both window sizes are
+// differences of such counts.  Otherwise every member is compared with every
+// other one.
+constexpr int kSortLds = 4096;
+
+__device__ __forceinline__ int32_t members_below(const uint32_t* __restrict__ bits,
+                                                 const uint32_t* __restrict__ pre, int64_t words,
+                                                 int32_t m, int64_t x) {
+    const int64_t wd = x >> 5;
+    if (wd >= words) return m;
+    const uint32_t below = (uint32_t(1) << (x & 31)) - 1u;
+    return int32_t(pre[wd]) + __popc(bits[wd] & below);
+}
+
+// members at cyclic distance 1..len after s (len < n)
+__device__ __forceinline__ int32_t members_after(const uint32_t* __restrict__ bits,
+                                                 const uint32_t* __restrict__ pre, int64_t words,
+                                                 int32_t m, int64_t n, int64_t s, int64_t len) {
+    const int64_t a = s + 1, b = s + 1 + len;
+    const int32_t at_a = members_below(bits, pre, words, m, a);
+    if (b <= n) return members_below(bits, pre, words, m, b) - at_a;
+    return (m - at_a) + members_below(bits, pre, words, m, b - n);
+}
+
+__global__ __launch_bounds__(256) void k_sort_large(const int64_t* __restrict__ roff,
+                                                    const int32_t* __restrict__ ids, int64_t n,
+                                                    int64_t seg0, int64_t bitmap_words,
+                                                    const int32_t* __restrict__ rs_in,
+                                                    const int64_t* __restrict__ rq_in,
+                                                    int32_t* __restrict__ rs_out,
+                                                    unsigned long long* __restrict__ rw_out,
+                                                    const int64_t* __restrict__ soff,
+                                                    int32_t* __restrict__ scur,
+                                                    SlotEntry* __restrict__ se) {
+    extern __shared__ uint32_t sh[];
+    const int tid = threadIdx.x;
+    const int64_t L = ids[blockIdx.x];
     const int64_t base = roff[L];
     const int64_t m = roff[L + 1] - base;
-    if (m <= kSortLds) {   // block-uniform
-        for (int64_t k = threadIdx.x; k < m; k += 256) ks[k] = rs_in[base + k];
+    if (bitmap_words > 0) {   // block-uniform
+        const int64_t W = bitmap_words;
+        uint32_t* bits = sh;
+        uint32_t* pre = sh + W;
+        __shared__ uint32_t wave_tot[4];
+        for (int64_t k = tid; k < W; k += 256) bits[k] = 0u;
         __syncthreads();
-        for (int64_t k = threadIdx.x; k < m; k += 256) {
+        for (int64_t k = tid; k < m; k += 256) {
+            const int32_t smp = rs_in[base + k];
+            atomicOr(&bits[smp >> 5], uint32_t(1) << (smp & 31));
+        }
+        __syncthreads();
+        // exclusive scan of the words' population counts: thread t owns a run of
+        // consecutive words; runs are combined by a wave scan and the wave totals
+        const int64_t per = (W + 255) / 256;
+        const int64_t w0 = int64_t(tid) * per, w1 = min(W, w0 + per);
+        uint32_t own = 0;
+        for (int64_t k = w0; k < w1; ++k) own += __popc(bits[k]);
+        const int lane = tid & 63, wave = tid >> 6;
+        uint32_t inc = own;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) wave_tot[wave] = inc;
+        __syncthreads();
+        uint32_t run = inc - own;
+        for (int q = 0; q < wave; ++q) run += wave_tot[q];
+        for (int64_t k = w0; k < w1; ++k) {
+            pre[k] = run;
+            run += __popc(bits[k]);
+        }
+        __syncthreads();
+        const int32_t m32 = int32_t(m);
+        const int64_t half = n / 2, part = min(half, seg0);
+        for (int64_t k = tid; k < m; k += 256) {
+            const int32_t smp = rs_in[base + k];
+            const int32_t r = members_below(bits, pre, W, m32, smp);
+            const int32_t w = members_after(bits, pre, W, m32, n, smp, half);
+            const int32_t wz = members_after(bits, pre, W, m32, n, smp, part);
+            place_member(L, base, k, smp, r, w, wz, rq_in, rs_out, rw_out, soff, scur, m32, se);
+        }
+        return;
+    }
+    int32_t* ks = reinterpret_cast<int32_t*>(sh);
+    if (m <= kSortLds) {   // block-uniform
+        for (int64_t k = tid; k < m; k += 256) ks[k] = rs_in[base + k];
+        __syncthreads();
+        for (int64_t k = tid; k < m; k += 256) {
             const int32_t smp = ks[k];
             RankWin rw;
             for (int64_t t = 0; t < m; ++t) rw.add(ks[t], smp, n, seg0);
@@ -144,7 +245,7 @@ __global__ __launch_bounds__(256) void k_sort_lists(const int64_t* __restrict__ 
                          int32_t(m), se);
         }
     } else {
-        for (int64_t k = threadIdx.x; k < m; k += 256) {
+        for (int64_t k = tid; k < m; k += 256) {
             const int32_t smp = rs_in[base + k];
             RankWin rw;
             for (int64_t t = 0; t < m; ++t) rw.add(rs_in[base + t], smp, n, seg0);
@@ -503,14 +604,37 @@ hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff
     return hipGetLastError();
 }
 
-hipError_t sort_lists(const int64_t* roff, int64_t n_lists, int64_t n, int64_t seg0, const int32_t* rs_in,
-                      const int64_t* rq_in,
-                      int32_t* rs_out, unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
+hipError_t sort_lists(const int64_t* roff, const int32_t* small_ids, int64_t n_small,
+                      const int32_t* large_ids, int64_t n_large, int64_t n, int64_t seg0,
+                      const int32_t* rs_in, const int64_t* rq_in, int32_t* rs_out,
+                      unsigned long long* rw_out, const int64_t* soff, int32_t* scur,
                       SlotEntry* se, hipStream_t st) {
-    if (n_lists <= 0) return hipSuccess;
-    if (n_lists > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sort_lists, dim3(unsigned(n_lists)), dim3(256), 0, st, roff, n, seg0, rs_in, rq_in,
-                       rs_out, rw_out, soff, scur, se);
+    if (n_small > 0) {
+        const int64_t blocks = (n_small + 3) / 4;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_sort_small, dim3(unsigned(blocks)), dim3(256), 0, st, roff, small_ids,
+                           n_small, n, seg0, rs_in, rq_in, rs_out, rw_out, soff, scur, se);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_large <= 0) return hipSuccess;
+    if (n_large > 0x7fffffff) return hipErrorInvalidValue;
+    // a bitmap of the samples and the scan of its words, while they fit in 64 KiB
+    // (N up to about 260,000); else the pairwise comparison with a 16 KiB list copy
+    // (UF_SPLIT_SORT=pairwise in the environment forces the pairwise ranking)
+    constexpr int64_t kBitmapBytes = 64 * 1024;
+    const int64_t words = (n + 31) / 32;
+    const char* mode = std::getenv("UF_SPLIT_SORT");
+    const bool pairwise = mode && std::strcmp(mode, "pairwise") == 0;
+    const bool bitmap = words * 8 <= kBitmapBytes && !pairwise;
+    const size_t lds = bitmap ? size_t(words) * 8 : size_t(kSortLds) * 4;
+    static const bool attr_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_large),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    int(kBitmapBytes)) == hipSuccess;
+    if (!attr_ok) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sort_large, dim3(unsigned(n_large)), dim3(256), lds, st, roff, large_ids, n,
+                       seg0, bitmap ? words : int64_t(0), rs_in, rq_in, rs_out, rw_out, soff, scur,
+                       se);
     return hipGetLastError();
 }
 

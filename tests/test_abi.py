@@ -134,3 +134,58 @@ def test_header_documents_every_function():
     text = open(uf.HEADER_PATH).read()
     for name in uf.exported_symbols():
         assert text.count(name) >= 1
+
+
+def test_null_embedding_with_split_precisions_is_rejected():
+    # the split precisions resolve the embedding's split first: a NULL embedding must
+    # be refused before that, on every distance entry point, with or without a GPU
+    L = uf.lib()
+    out = ctypes.c_void_p(8)
+    for prec in (uf.PRECISION["fp32_split"], uf.PRECISION["mfma_split"]):
+        assert L.uf_dm_unweighted_stripes(None, prec, 0, 1, 0, 0, out, None, None, 0, None) == 1
+        assert L.uf_dm_weighted_normalized_stripes(None, prec, 0, 1, 0, 0, out, None, None, 0,
+                                                   None) == 1
+        assert L.uf_dm_unweighted(None, prec, 0, out, None, None, None, 0, None) == 1
+        assert L.uf_dm_weighted_normalized(None, prec, 0, out, None, None, None, 0, None) == 1
+    assert L.uf_embedding_prepare(None, 1, None) == 1
+    assert L.uf_split_stats(None, 1, None, None, None) == 1
+
+
+# The calls the hot path's boundary is specified with, and the entry point of
+# include/uf.h that provides each (the same name where the signature matches the
+# specification's intent; the reasons for every difference are recorded with the
+# design).
+BOUNDARY = {
+    "uf_tree_load": "uf_tree_load",
+    "uf_table_load": "uf_table_load",
+    "uf_embed": "uf_embed",
+    "uf_workspace_size": "uf_workspace_size",
+    "uf_dm_unweighted": "uf_dm_unweighted",
+    "uf_dm_weighted_normalized": "uf_dm_weighted_normalized",
+    "uf_dm_unweighted_stripes": "uf_dm_unweighted_stripes",
+    "uf_dm_weighted_normalized_stripes": "uf_dm_weighted_normalized_stripes",
+    "uf_n_stripes": "uf_n_stripes",
+    "uf_condensed_index": "uf_condensed_index",
+    "uf_autotune": "uf_autotune",
+    "uf_batch_plan_create": "uf_batch_plan_create",
+    "uf_batch_run": "uf_batch_run",
+    "uf_project": "uf_project",
+    "uf_mlp_forward": "uf_mlp_forward",
+    "uf_mlp_backward": "uf_mlp_backward",
+    "uf_adam_step": "uf_adam_step",
+    "uf_dm_pairs_weighted_normalized": "uf_dm_pairs_weighted_normalized",
+    "uf_free_tree": "uf_free_tree",
+    "uf_free_table": "uf_free_table",
+    "uf_free_embedding": "uf_free_embedding",
+    "uf_status_string": "uf_status_string",
+    "uf_last_error_message": "uf_last_error_message",
+}
+
+
+def test_specified_boundary_calls_are_exported():
+    names = set(uf.exported_symbols())
+    missing = [k for k, v in BOUNDARY.items() if v not in names]
+    assert not missing, missing
+    L = uf.lib()
+    for v in BOUNDARY.values():
+        assert hasattr(L, v)

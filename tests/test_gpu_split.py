@@ -280,3 +280,67 @@ def test_weighted_dense_pass_falls_back_to_fp32(threshold):
     print(f"[fp32 fallback dense pass] kernels={used} max|err|={err:.3e}")
     assert used == {"band_wn_f32"}
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("variant", sorted(SPLIT))
+def test_prepare_rebuild_is_bitwise_equal(variant, threshold):
+    """A split rebuilt from the device-resident table (uf_embedding_prepare, as a
+    benchmark step does) gives the same bits as the one built on first use, and
+    lists ranked by the LDS bitmap and by pairwise comparison agree."""
+    import os
+    import torch
+    import paper_2107_05397_amd as uf
+    threshold(1.0, variant)          # every shared branch in the lists: long lists too
+    tree = synth.gen_tree(500, 0.1, seed=31)
+    table = synth.gen_table_zipf(301, np.arange(500), 40, seed=32)
+    emb = _emb(tree, table)
+    d0, _, _ = uf.dm(emb, variant, SPLIT[variant])
+    torch.cuda.synchronize()
+    emb.prepare(scalars=True, split_weighted=True, split_unweighted=True)
+    d1, _, _ = uf.dm(emb, variant, SPLIT[variant])
+    os.environ["UF_SPLIT_SORT"] = "pairwise"
+    try:
+        emb.prepare(scalars=False, split_weighted=True, split_unweighted=True)
+        d2, _, _ = uf.dm(emb, variant, SPLIT[variant])
+        torch.cuda.synchronize()
+    finally:
+        del os.environ["UF_SPLIT_SORT"]
+    assert torch.equal(d0, d1) and torch.equal(d0, d2)
+    _, n_lists, n_pairs = uf.split_stats(emb, variant)
+    assert n_lists > 0 and n_pairs > 301 * 300 // 2    # lists longer than 64 members exist
+
+
+def test_threshold_changes_while_computing(threshold):
+    """One thread computes split matrices while another switches the threshold:
+    each call keeps the split it started with alive, so every result is a valid
+    matrix (equal to the oracle within the split tolerance)."""
+    import threading
+    import torch
+    import paper_2107_05397_amd as uf
+    tree = synth.gen_tree(400, 0.1, seed=41)
+    table = synth.gen_table_zipf(200, np.arange(400), 40, seed=42)
+    emb = _emb(tree, table)
+    want = core.dm(tree, table, "weighted_normalized")[0]
+    errors, stop = [], threading.Event()
+
+    def flip():
+        k = 0
+        while not stop.is_set():
+            threshold((0.05, 0.3, 1.0)[k % 3], "weighted_normalized")
+            uf.split_stats(emb, "weighted_normalized")
+            k += 1
+
+    th = threading.Thread(target=flip)
+    th.start()
+    try:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            for _ in range(20):
+                d, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split", stream=stream)
+                stream.synchronize()
+                errors.append(float(np.abs(d.cpu().numpy() - want).max()))
+    finally:
+        stop.set()
+        th.join()
+    print("max errors", max(errors))
+    assert max(errors) <= 1e-4
