@@ -660,6 +660,15 @@ namespace ufh {
 uf_status fail(uf_status st, const std::string& msg) { return ::fail(st, msg); }
 uf_status hip_fail(hipError_t e, const char* what) { return ::hip_fail(e, what); }
 uf_status check_device(int* dev_out) { return ::check_device(dev_out); }
+struct ProfHandle {
+    ProfScope scope;
+    ProfHandle(const char* name, hipStream_t s) : scope(name, s) {}
+};
+ProfHandle* prof_begin(const char* name, hipStream_t s) {
+    if (!g_prof_on.load() || t_prof_suppress) return nullptr;
+    return new (std::nothrow) ProfHandle(name, s);
+}
+void prof_end(ProfHandle* h) { delete h; }
 }  // namespace ufh
 
 // =========================================================================

@@ -137,6 +137,21 @@ namespace ufh {
 uf_status fail(uf_status st, const std::string& msg);
 uf_status hip_fail(hipError_t e, const char* what);
 uf_status check_device(int* dev_out);
+// Timing of the launches enqueued on s during the guard's lifetime, under a
+// kernel name of uf_profile_read (events recorded only while profiling is on).
+struct ProfHandle;
+ProfHandle* prof_begin(const char* name, hipStream_t s);
+void prof_end(ProfHandle* h);
+class ProfGuard {
+  public:
+    ProfGuard(const char* name, hipStream_t s) : h_(prof_begin(name, s)) {}
+    ~ProfGuard() { prof_end(h_); }
+    ProfGuard(const ProfGuard&) = delete;
+    ProfGuard& operator=(const ProfGuard&) = delete;
+
+  private:
+    ProfHandle* h_;
+};
 }  // namespace ufh
 
 // One table of a batch, as the batched kernels see it.

@@ -101,142 +101,283 @@ __global__ __launch_bounds__(256) void k_project(Emb e, const int32_t* __restric
 
 // ----------------------------------------------------------------------------
 // BF16 GEMM on MFMA: C[m][n] = sum_k A(m, k) B(n, k), FP32 accumulation.
-// Layout 0 (row): element (m, k) at P[src(m) * ld + k]   (k contiguous)
-// Layout 1 (col): element (m, k) at P[src(k) * ld + m]   (m contiguous)
-// src() applies the optional row-index array (a gather of source rows).
-// Tile 128x128, 4 waves (2x2, 64x64 each = 2x2 v_mfma_f32_32x32x16_bf16), K step
-// 32 staged in LDS as [row][k] (padded), transposing layout-1 sources.
+// Layout 0 (row): element (r, k) at P[src(r) * ld + k]   (k contiguous)
+// Layout 1 (col): element (r, k) at P[src(k) * ld + r]   (r contiguous)
+// src() applies the optional row-index array (a gather of storage rows).
+//
+// A block computes a BM x 128 tile (BM = 128 or 256) with 4 waves in 2 x 2; a
+// wave owns (BM/2) x 64 as (BM/64) x 2 blocks of v_mfma_f32_32x32x16_bf16.  The
+// K loop steps by 64 through two LDS stages that hold the tile's rows as
+// [row][k] with a 144-byte pitch (an odd multiple of 16 bytes, so the 16-byte
+// fragment reads of consecutive rows fall on distinct banks).  Row-layout
+// operands are staged in 16-byte pieces; column-layout ones in pieces of 4 (k)
+// x 8 (rows), transposed in registers on the way into LDS.  The global loads of
+// step t+1 are in flight while the MFMAs of step t run, and there is one
+// barrier per step: the stage written at step t was last read at step t-2,
+// which every wave finished before the barrier of step t-1.
+//
+// blockIdx.z takes one range of K steps (split K).  With a single range the
+// epilogue is applied here; with several, each range writes its raw sums to
+// part[z][M][N] and k_gemm_reduce adds the ranges in order and applies the
+// epilogue, so the result never depends on the order blocks run in.
 // ----------------------------------------------------------------------------
-template <int LAY>
-__device__ __forceinline__ void stage_operand(uint16_t* __restrict__ S,
-                                              const uint16_t* __restrict__ P, int64_t ld,
-                                              const int32_t* __restrict__ rows, int64_t r0,
-                                              int64_t R, int64_t k0, int64_t K) {
-    constexpr int LD = 40;
-    const int tid = threadIdx.x;
-    if (LAY == 0) {
-        const int r = tid >> 1, seg = (tid & 1) * 16;
-        const int64_t gr = r0 + r;
-        uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
-        if (gr < R) {
-            const int64_t src = rows ? rows[gr] : gr;
-            const uint4* p = reinterpret_cast<const uint4*>(P + src * ld + k0 + seg);
-            v0 = p[0];
-            v1 = p[1];
-        }
-        uint4* d = reinterpret_cast<uint4*>(S + r * LD + seg);
-        d[0] = v0;
-        d[1] = v1;
+constexpr int kGemmBN = 128;             // tile columns
+constexpr int kGemmKS = 64;              // K per step
+constexpr int kGemmLD = kGemmKS + 8;     // LDS row pitch in bf16 (144 bytes)
+
+template <int EPI>
+__device__ __forceinline__ void gemm_store(float v, int64_t i, int64_t j,
+                                           const float* __restrict__ bias,
+                                           const uint16_t* __restrict__ mask, int64_t ldm,
+                                           void* __restrict__ C, int64_t ldc) {
+    if (EPI == EPI_F32) {
+        static_cast<float*>(C)[i * ldc + j] = v;
+    } else if (EPI == EPI_ACC_F32) {
+        static_cast<float*>(C)[i * ldc + j] += v;
+    } else if (EPI == EPI_BIAS_RELU_BF16) {
+        static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(fmaxf(v + bias[j], 0.0f));
+    } else if (EPI == EPI_BIAS_F32) {
+        static_cast<float*>(C)[i * ldc + j] = v + bias[j];
+    } else if (EPI == EPI_MASK_BF16) {
+        static_cast<uint16_t*>(C)[i * ldc + j] = mask[i * ldm + j] != 0 ? f2bf(v) : uint16_t(0);
     } else {
-        const int kk = tid >> 3, seg = (tid & 7) * 16;
-        const int64_t gk = k0 + kk;
-        uint16_t v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = 0;
-        if (gk < K) {
-            const int64_t src = rows ? rows[gk] : gk;
-            const uint16_t* p = P + src * ld + r0 + seg;
-            if (r0 + seg + 16 <= R) {
-                const uint4 a = reinterpret_cast<const uint4*>(p)[0];
-                const uint4 b = reinterpret_cast<const uint4*>(p)[1];
-                const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    v[2 * e] = uint16_t(w[e] & 0xFFFFu);
-                    v[2 * e + 1] = uint16_t(w[e] >> 16);
-                }
-            } else {
-                for (int e = 0; e < 16; ++e)
-                    if (r0 + seg + e < R) v[e] = p[e];
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) S[(seg + e) * LD + kk] = v[e];
+        static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(v);
     }
 }
 
-template <int LA, int LB, int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_bf16(
+// One operand's share of a K step in a thread's registers: TR rows of the tile,
+// TR/32 uint4 per thread in either layout (row: TR*8 pieces of 16 bytes; col:
+// TR*2 pieces of 4 x 16 bytes).
+template <int LAY, int TR>
+struct GemmOperand {
+    static constexpr int NV = TR / 32;
+    static constexpr int NP = LAY == 0 ? NV : TR / 128;   // pieces per thread
+    const uint16_t* P;
+    int64_t ld;
+    const int32_t* rows;
+    int64_t r0, R, K;
+    const uint16_t* rowp[LAY == 0 ? NV : 1];              // row layout: source row of each piece
+
+    __device__ __forceinline__ void init(const uint16_t* P_, int64_t ld_, const int32_t* rows_,
+                                         int64_t r0_, int64_t R_, int64_t K_, int tid) {
+        P = P_;
+        ld = ld_;
+        rows = rows_;
+        r0 = r0_;
+        R = R_;
+        K = K_;
+        if constexpr (LAY == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int64_t gr = r0 + ((tid + 256 * i) >> 3);
+                rowp[i] = gr < R ? P + (rows ? int64_t(rows[gr]) : gr) * ld : nullptr;
+            }
+        }
+    }
+
+    // (staged values travel by value: an array passed by reference is kept in
+    // memory, which the compiler may place in LDS)
+    struct Regs {
+        uint4 v[NV];
+    };
+
+    __device__ __forceinline__ Regs fetch(int64_t k0, int tid) const {
+        Regs out;
+        uint4* v = out.v;
+        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (LAY == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int64_t k = k0 + 8 * ((tid + 256 * i) & 7);
+                v[i] = (rowp[i] && k < K) ? *reinterpret_cast<const uint4*>(rowp[i] + k) : z;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int p = tid + 256 * i;
+                const int64_t rr = r0 + 8 * (p / 16);
+                const int64_t kb = k0 + 4 * (p % 16);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t k = kb + e;
+                    if (k < K && rr < R) {
+                        const int64_t src = rows ? int64_t(rows[k]) : k;
+                        v[4 * i + e] = *reinterpret_cast<const uint4*>(P + src * ld + rr);
+                    } else {
+                        v[4 * i + e] = z;
+                    }
+                }
+            }
+        }
+        return out;
+    }
+
+    static __device__ __forceinline__ uint32_t half_of(const uint4& u, int j) {
+        const uint32_t w = j < 2 ? u.x : (j < 4 ? u.y : (j < 6 ? u.z : u.w));
+        return (j & 1) ? (w >> 16) : (w & 0xFFFFu);
+    }
+
+    static __device__ __forceinline__ void stash(const Regs in, uint16_t* __restrict__ S, int tid) {
+        const uint4* v = in.v;
+        if constexpr (LAY == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int p = tid + 256 * i;
+                *reinterpret_cast<uint4*>(S + (p >> 3) * kGemmLD + 8 * (p & 7)) = v[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int p = tid + 256 * i;
+                const int rb = p / 16, kq = p % 16;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    uint2 w;
+                    w.x = half_of(v[4 * i + 0], j) | (half_of(v[4 * i + 1], j) << 16);
+                    w.y = half_of(v[4 * i + 2], j) | (half_of(v[4 * i + 3], j) << 16);
+                    *reinterpret_cast<uint2*>(S + (8 * rb + j) * kGemmLD + 4 * kq) = w;
+                }
+            }
+        }
+    }
+};
+
+template <int LA, int LB, int EPI, int BM>
+__global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void k_gemm_bf16(
     const uint16_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ arow,
     const uint16_t* __restrict__ B, int64_t ldb, const int32_t* __restrict__ brow, int64_t M,
     int64_t N, int64_t K, const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-    int64_t ldm, void* __restrict__ C, int64_t ldc) {
-    constexpr int T = 128, KT = 32, LD = 40;
-    __shared__ __attribute__((aligned(16))) uint16_t As[T * LD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[T * LD];
-    const int64_t m0 = int64_t(blockIdx.y) * T, n0 = int64_t(blockIdx.x) * T;
+    int64_t ldm, void* __restrict__ C, int64_t ldc, float* __restrict__ part) {
+    constexpr int XB = BM / 64;   // 32-row blocks per wave
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * kGemmLD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN * kGemmLD];
+    const int64_t m0 = int64_t(blockIdx.y) * BM, n0 = int64_t(blockIdx.x) * kGemmBN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave & 1, wj = wave >> 1;
-    floatx16 c[2][2];
+
+    // this block's range of K steps
+    const int64_t nk = (K + kGemmKS - 1) / kGemmKS;
+    const int64_t per = (nk + gridDim.z - 1) / gridDim.z;
+    const int64_t t0 = int64_t(blockIdx.z) * per;
+    const int64_t t1 = min(nk, t0 + per);
+
+    // A in 128-row halves, so that no staged array exceeds 16 registers (larger
+    // ones would be kept in memory)
+    GemmOperand<LA, 128> oa0, oa1;
+    GemmOperand<LB, kGemmBN> ob;
+    oa0.init(A, lda, arow, m0, M, K, tid);
+    if constexpr (BM == 256) oa1.init(A, lda, arow, m0 + 128, M, K, tid);
+    ob.init(B, ldb, brow, n0, N, K, tid);
+
+    floatx16 c[XB][2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
-    for (int64_t k0 = 0; k0 < K; k0 += KT) {
-        __syncthreads();
-        stage_operand<LA>(As, A, lda, arow, m0, M, k0, K);
-        stage_operand<LB>(Bs, B, ldb, brow, n0, N, k0, K);
-        __syncthreads();
+
+    auto compute = [&](int buf) {
 #pragma unroll
-        for (int kk = 0; kk < KT; kk += 16) {
-            const int kq = kk + 8 * (lane >> 5);
-            bf16x8 fa[2], fb[2];
+        for (int s = 0; s < kGemmKS / 16; ++s) {
+            const int kq = 16 * s + 8 * (lane >> 5);
+            bf16x8 fa[XB], fb[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
-                fa[x] = *reinterpret_cast<const bf16x8*>(As + (wi * 64 + x * 32 + (lane & 31)) * LD + kq);
+            for (int x = 0; x < XB; ++x)
+                fa[x] = *reinterpret_cast<const bf16x8*>(
+                    As[buf] + (wi * (BM / 2) + x * 32 + (lane & 31)) * kGemmLD + kq);
 #pragma unroll
             for (int y = 0; y < 2; ++y)
-                fb[y] = *reinterpret_cast<const bf16x8*>(Bs + (wj * 64 + y * 32 + (lane & 31)) * LD + kq);
+                fb[y] = *reinterpret_cast<const bf16x8*>(
+                    Bs[buf] + (wj * 64 + y * 32 + (lane & 31)) * kGemmLD + kq);
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < XB; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y)
                     c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[y], c[x][y], 0, 0, 0);
         }
+    };
+
+    if (t0 < t1) {
+        using OA = GemmOperand<LA, 128>;
+        using OB = GemmOperand<LB, kGemmBN>;
+        typename OA::Regs ra0 = oa0.fetch(t0 * kGemmKS, tid), ra1{};
+        if constexpr (BM == 256) ra1 = oa1.fetch(t0 * kGemmKS, tid);
+        typename OB::Regs rb = ob.fetch(t0 * kGemmKS, tid);
+        auto stash_all = [&](int buf) {
+            OA::stash(ra0, As[buf], tid);
+            if constexpr (BM == 256) OA::stash(ra1, As[buf] + 128 * kGemmLD, tid);
+            OB::stash(rb, Bs[buf], tid);
+        };
+        auto fetch_all = [&](int64_t k0) {
+            ra0 = oa0.fetch(k0, tid);
+            if constexpr (BM == 256) ra1 = oa1.fetch(k0, tid);
+            rb = ob.fetch(k0, tid);
+        };
+        for (int64_t t = t0; t < t1; t += 2) {
+            stash_all(0);
+            fetch_all(min(t + 1, t1 - 1) * kGemmKS);   // past the end: re-read, unused
+            __syncthreads();
+            compute(0);
+            if (t + 1 < t1) {   // block-uniform
+                stash_all(1);
+                fetch_all(min(t + 2, t1 - 1) * kGemmKS);
+                __syncthreads();
+                compute(1);
+            }
+        }
     }
+
+    // D of a 32x32 block: lane holds column lane%32, rows 8*(r/4) + 4*(lane/32) + r%4
+    const bool split = gridDim.z > 1;
+    float* pz = split ? part + int64_t(blockIdx.z) * M * N : nullptr;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t i = m0 + wi * 64 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t i = m0 + wi * (BM / 2) + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 const int64_t j = n0 + wj * 64 + y * 32 + (lane & 31);
                 if (i >= M || j >= N) continue;
-                const float v = c[x][y][r];
-                if (EPI == EPI_F32) {
-                    static_cast<float*>(C)[i * ldc + j] = v;
-                } else if (EPI == EPI_ACC_F32) {
-                    static_cast<float*>(C)[i * ldc + j] += v;
-                } else if (EPI == EPI_BIAS_RELU_BF16) {
-                    static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(fmaxf(v + bias[j], 0.0f));
-                } else if (EPI == EPI_BIAS_F32) {
-                    static_cast<float*>(C)[i * ldc + j] = v + bias[j];
-                } else if (EPI == EPI_MASK_BF16) {
-                    static_cast<uint16_t*>(C)[i * ldc + j] = mask[i * ldm + j] != 0 ? f2bf(v) : uint16_t(0);
-                } else {
-                    static_cast<uint16_t*>(C)[i * ldc + j] = f2bf(v);
-                }
+                if (split) pz[i * N + j] = c[x][y][r];
+                else gemm_store<EPI>(c[x][y][r], i, j, bias, mask, ldm, C, ldc);
             }
 }
 
-// column sums in FP64, rows in order (deterministic)
-__global__ __launch_bounds__(256) void k_colsum_f32(const float* __restrict__ X, int64_t rows,
-                                                    int64_t cols, float* __restrict__ out) {
-    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= cols) return;
-    double s = 0.0;
-    for (int64_t i = 0; i < rows; ++i) s += X[i * cols + j];
-    out[j] = float(s);
+// Split-K: the ranges' sums added in range order, then the epilogue.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_reduce(const float* __restrict__ part, int splits,
+                                                     int64_t M, int64_t N,
+                                                     const float* __restrict__ bias,
+                                                     const uint16_t* __restrict__ mask, int64_t ldm,
+                                                     void* __restrict__ C, int64_t ldc) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    float v = part[idx];
+    for (int z = 1; z < splits; ++z) v += part[int64_t(z) * M * N + idx];
+    gemm_store<EPI>(v, idx / N, idx % N, bias, mask, ldm, C, ldc);
 }
-__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t* __restrict__ X, int64_t rows,
-                                                     int64_t cols, float* __restrict__ out) {
+
+// Column sums of a BF16 matrix in FP64 in a fixed order: block (x, y) sums rows
+// [y*chunk, (y+1)*chunk) of 256 columns into part[y][cols]; k_colsum_final adds
+// the chunks in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const uint16_t* __restrict__ X, int64_t rows,
+                                                     int64_t cols, int64_t chunk,
+                                                     double* __restrict__ part) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= cols) return;
+    const int64_t r0 = int64_t(blockIdx.y) * chunk, r1 = min(rows, r0 + chunk);
+    double s = 0.0;
+    for (int64_t i = r0; i < r1; ++i) s += bf2f(X[i * cols + j]);
+    part[int64_t(blockIdx.y) * cols + j] = s;
+}
+__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int chunks,
+                                                      int64_t cols, float* __restrict__ out) {
     const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (j >= cols) return;
     double s = 0.0;
-    for (int64_t i = 0; i < rows; ++i) s += bf2f(X[i * cols + j]);
+    for (int y = 0; y < chunks; ++y) s += part[int64_t(y) * cols + j];
     out[j] = float(s);
 }
 
@@ -578,17 +719,42 @@ hipError_t project(const Emb& e, const int32_t* dims, const int8_t* signs, int p
     return hipGetLastError();
 }
 
+// Launch plan of one GEMM: 256-row tiles while they still give every CU a
+// block, else 128-row tiles (two blocks per CU); K is split in powers of two
+// while the blocks do not fill those slots, every range keeps at least four K
+// steps and the partial sums fit in part_elems floats.
 hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, const int32_t* arow,
                      const uint16_t* B, int64_t ldb, const int32_t* brow, int64_t M, int64_t N,
                      int64_t K, const float* bias, const uint16_t* mask, int64_t ldm, void* C,
-                     int64_t ldc, hipStream_t st) {
+                     int64_t ldc, float* part, int64_t part_elems, hipStream_t st) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const dim3 grid{unsigned((N + 127) / 128), unsigned((M + 127) / 128), 1u};
-#define UF_GEMM(LA_, LB_, EPI_)                                                                 \
-    if (la == LA_ && lb == LB_ && epi == EPI_) {                                                \
-        hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_>), grid, dim3(256), 0, st, A, lda, arow, \
-                           B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc);                     \
-        return hipGetLastError();                                                               \
+    if (K < 0) return hipErrorInvalidValue;
+    // the 16-byte loads: row layout reads 8 consecutive k, column layout 8
+    // consecutive rows, from 16-byte aligned storage rows
+    auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+    if (!aligned(A) || !aligned(B) || lda % 8 || ldb % 8) return hipErrorInvalidValue;
+    if ((la == 0 ? K : M) % 8 || (lb == 0 ? K : N) % 8) return hipErrorInvalidValue;
+    const int64_t tn = (N + kGemmBN - 1) / kGemmBN;
+    const int bm = (M + 255) / 256 * tn >= 256 ? 256 : 128;
+    const int64_t tm = (M + bm - 1) / bm;
+    const int64_t slots = bm == 128 ? 512 : 256;
+    const int64_t nk = (K + kGemmKS - 1) / kGemmKS;
+    int64_t splits = 1;
+    while (part && tm * tn * splits < slots && nk / (2 * splits) >= 4 &&
+           2 * splits * M * N <= part_elems)
+        splits *= 2;
+    if (tm > 65535 || tn > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(tn), unsigned(tm), unsigned(splits)};
+    bool launched = false;
+#define UF_GEMM(LA_, LB_, EPI_)                                                                  \
+    if (!launched && la == LA_ && lb == LB_ && epi == EPI_) {                                    \
+        if (bm == 256)                                                                           \
+            hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, 256>), grid, dim3(256), 0, st, A,    \
+                               lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part); \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, 128>), grid, dim3(256), 0, st, A,    \
+                               lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part); \
+        launched = true;                                                                         \
     }
     UF_GEMM(0, 0, EPI_BIAS_RELU_BF16)
     UF_GEMM(0, 0, EPI_BIAS_F32)
@@ -598,17 +764,49 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     UF_GEMM(0, 1, EPI_F32)
     UF_GEMM(1, 1, EPI_F32)
 #undef UF_GEMM
-    return hipErrorInvalidValue;
-}
-
-hipError_t colsum_f32(const float* X, int64_t rows, int64_t cols, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_colsum_f32, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, st, X, rows,
-                       cols, out);
+    if (!launched) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || splits == 1) return e;
+    const dim3 rg{unsigned((M * N + 255) / 256)};
+    switch (epi) {
+        case EPI_BIAS_RELU_BF16:
+            hipLaunchKernelGGL(k_gemm_reduce<EPI_BIAS_RELU_BF16>, rg, dim3(256), 0, st, part,
+                               int(splits), M, N, bias, mask, ldm, C, ldc);
+            break;
+        case EPI_BIAS_F32:
+            hipLaunchKernelGGL(k_gemm_reduce<EPI_BIAS_F32>, rg, dim3(256), 0, st, part, int(splits),
+                               M, N, bias, mask, ldm, C, ldc);
+            break;
+        case EPI_ACC_F32:
+            hipLaunchKernelGGL(k_gemm_reduce<EPI_ACC_F32>, rg, dim3(256), 0, st, part, int(splits),
+                               M, N, bias, mask, ldm, C, ldc);
+            break;
+        case EPI_MASK_BF16:
+            hipLaunchKernelGGL(k_gemm_reduce<EPI_MASK_BF16>, rg, dim3(256), 0, st, part,
+                               int(splits), M, N, bias, mask, ldm, C, ldc);
+            break;
+        default:
+            hipLaunchKernelGGL(k_gemm_reduce<EPI_F32>, rg, dim3(256), 0, st, part, int(splits), M, N,
+                               bias, mask, ldm, C, ldc);
+    }
     return hipGetLastError();
 }
-hipError_t colsum_bf16(const uint16_t* X, int64_t rows, int64_t cols, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_colsum_bf16, dim3(unsigned((cols + 255) / 256)), dim3(256), 0, st, X,
-                       rows, cols, out);
+
+hipError_t colsum_bf16(const uint16_t* X, int64_t rows, int64_t cols, double* part,
+                       int64_t part_elems, float* out, hipStream_t st) {
+    if (cols <= 0) return hipSuccess;
+    if (rows < 0 || !part || part_elems < cols) return hipErrorInvalidValue;
+    int64_t chunks = rows / 128 < 64 ? rows / 128 : 64;
+    if (chunks < 1) chunks = 1;
+    while (chunks > 1 && chunks * cols > part_elems) chunks /= 2;
+    const int64_t chunk = (rows + chunks - 1) / chunks;
+    if (chunk > 0) chunks = (rows + chunk - 1) / chunk;
+    const unsigned gx = unsigned((cols + 255) / 256);
+    hipLaunchKernelGGL(k_colsum_part, dim3(gx, unsigned(chunks)), dim3(256), 0, st, X, rows, cols,
+                       chunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum_final, dim3(gx), dim3(256), 0, st, part, int(chunks), cols, out);
     return hipGetLastError();
 }
 

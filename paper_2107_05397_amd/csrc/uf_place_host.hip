@@ -69,6 +69,8 @@ struct uf_mlp {
     uint16_t* dZ = nullptr;
     float* loss_pp = nullptr;
     int32_t* rows = nullptr;          // [max_rows]
+    float* part = nullptr;            // split-K partial sums / column-sum chunks
+    int64_t part_elems = 0;           // floats in part
     // optional linear path z += S x (S: [dims[L]][dims[0]])
     bool skip = false;
     float *S = nullptr, *gS = nullptr, *mS = nullptr, *vS = nullptr;
@@ -174,6 +176,8 @@ uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows,
         take(size_t(max_rows * dims[n_layers]) * 2);   // dZ
         take(size_t(max_rows) * 4);                    // loss per pair
         take(size_t(max_rows) * 4);                    // rows
+        const int64_t part_elems = int64_t(8) << 20;   // 32 MiB of GEMM / column-sum scratch
+        take(size_t(part_elems) * 4);                  // part
         m->skip = skip != 0;
         const size_t ns = m->skip ? size_t(dims[n_layers] * dims[0]) : 0;
         take(ns * 4); take(ns * 4); take(ns * 4); take(ns * 4); take(ns * 2);   // S gS mS vS Sbf
@@ -202,6 +206,8 @@ uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows,
         m->dZ = reinterpret_cast<uint16_t*>(base + offs[k++]);
         m->loss_pp = reinterpret_cast<float*>(base + offs[k++]);
         m->rows = reinterpret_cast<int32_t*>(base + offs[k++]);
+        m->part = reinterpret_cast<float*>(base + offs[k++]);
+        m->part_elems = part_elems;
         if (m->skip) {
             m->S = reinterpret_cast<float*>(base + offs[k]);
             m->gS = reinterpret_cast<float*>(base + offs[k + 1]);
@@ -264,6 +270,17 @@ uf_status uf_mlp_get(const uf_mlp* m, int64_t layer, int what, float* w, float* 
 }
 
 namespace {
+// One GEMM of the MLP with its split-K scratch, timed as "encoder_gemm" while
+// profiling is enabled.
+hipError_t mlp_gemm(const uf_mlp* m, int la, int lb, int epi, const uint16_t* A, int64_t lda,
+                    const int32_t* arow, const uint16_t* B, int64_t ldb, const int32_t* brow,
+                    int64_t M, int64_t N, int64_t K, const float* bias, const uint16_t* mask,
+                    int64_t ldm, void* C, int64_t ldc, hipStream_t s) {
+    ufh::ProfGuard pg("encoder_gemm", s);
+    return ufp::gemm_bf16(la, lb, epi, A, lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc,
+                          m->part, m->part_elems, s);
+}
+
 uf_status mlp_forward(uf_mlp* m, const uint16_t* x, int64_t ldx, const int32_t* rows, int64_t n,
                       float* z, hipStream_t s) {
     const uint16_t* in = x;
@@ -272,19 +289,19 @@ uf_status mlp_forward(uf_mlp* m, const uint16_t* x, int64_t ldx, const int32_t* 
     for (int64_t l = 0; l < m->L; ++l) {
         const int64_t din = m->dims[l], dout = m->dims[l + 1];
         if (l < m->L - 1) {
-            UF_HIP(ufp::gemm_bf16(0, 0, ufp::EPI_BIAS_RELU_BF16, in, ld, r, m->Wbf[l], din, nullptr, n,
-                                  dout, din, m->b[l], nullptr, 0, m->H[l + 1], dout, s));
+            UF_HIP(mlp_gemm(m, 0, 0, ufp::EPI_BIAS_RELU_BF16, in, ld, r, m->Wbf[l], din, nullptr, n,
+                            dout, din, m->b[l], nullptr, 0, m->H[l + 1], dout, s));
             in = m->H[l + 1];
             ld = dout;
             r = nullptr;
         } else {
-            UF_HIP(ufp::gemm_bf16(0, 0, ufp::EPI_BIAS_F32, in, ld, r, m->Wbf[l], din, nullptr, n, dout,
-                                  din, m->b[l], nullptr, 0, z, dout, s));
+            UF_HIP(mlp_gemm(m, 0, 0, ufp::EPI_BIAS_F32, in, ld, r, m->Wbf[l], din, nullptr, n, dout,
+                            din, m->b[l], nullptr, 0, z, dout, s));
         }
     }
     if (m->skip)   // z += x S^T
-        UF_HIP(ufp::gemm_bf16(0, 0, ufp::EPI_ACC_F32, x, ldx, rows, m->Sbf, m->dims[0], nullptr, n,
-                              m->dims[m->L], m->dims[0], nullptr, nullptr, 0, z, m->dims[m->L], s));
+        UF_HIP(mlp_gemm(m, 0, 0, ufp::EPI_ACC_F32, x, ldx, rows, m->Sbf, m->dims[0], nullptr, n,
+                        m->dims[m->L], m->dims[0], nullptr, nullptr, 0, z, m->dims[m->L], s));
     return UF_OK;
 }
 }  // namespace
@@ -311,21 +328,25 @@ uf_status mlp_backward(uf_mlp* m, const uint16_t* x, int64_t ldx, const int32_t*
                        const uint16_t* dz, hipStream_t s) {
     const int64_t L = m->L;
     if (m->skip)   // dS = dZ^T x
-        UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, dz, m->dims[L], nullptr, x, ldx, rows,
-                              m->dims[L], m->dims[0], n, nullptr, nullptr, 0, m->gS, m->dims[0], s));
+        UF_HIP(mlp_gemm(m, 1, 1, ufp::EPI_F32, dz, m->dims[L], nullptr, x, ldx, rows,
+                        m->dims[L], m->dims[0], n, nullptr, nullptr, 0, m->gS, m->dims[0], s));
     const uint16_t* g = dz;
     for (int64_t l = L - 1; l >= 0; --l) {
         const int64_t din = m->dims[l], dout = m->dims[l + 1];
         // dW_l = g^T h_{l}: A = g (column layout), B = input of layer l (column layout)
         const uint16_t* hin = l == 0 ? x : m->H[l];
         const int64_t ldh = l == 0 ? ldx : din;
-        UF_HIP(ufp::gemm_bf16(1, 1, ufp::EPI_F32, g, dout, nullptr, hin, ldh, l == 0 ? rows : nullptr,
-                              dout, din, n, nullptr, nullptr, 0, m->gW[l], din, s));
-        UF_HIP(ufp::colsum_bf16(g, n, dout, m->gb[l], s));
+        UF_HIP(mlp_gemm(m, 1, 1, ufp::EPI_F32, g, dout, nullptr, hin, ldh, l == 0 ? rows : nullptr,
+                        dout, din, n, nullptr, nullptr, 0, m->gW[l], din, s));
+        {
+            ufh::ProfGuard pc("encoder_colsum", s);
+            UF_HIP(ufp::colsum_bf16(g, n, dout, reinterpret_cast<double*>(m->part),
+                                    m->part_elems / 2, m->gb[l], s));
+        }
         if (l > 0) {
             // dA_l = (g W_l) * [h_l > 0]: A = g (row), B = W_l (column layout)
-            UF_HIP(ufp::gemm_bf16(0, 1, ufp::EPI_MASK_BF16, g, dout, nullptr, m->Wbf[l], din, nullptr,
-                                  n, din, dout, nullptr, m->H[l], din, m->dA[l], din, s));
+            UF_HIP(mlp_gemm(m, 0, 1, ufp::EPI_MASK_BF16, g, dout, nullptr, m->Wbf[l], din, nullptr,
+                            n, din, dout, nullptr, m->H[l], din, m->dA[l], din, s));
             g = m->dA[l];
         }
     }
@@ -366,8 +387,11 @@ uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int
         UF_HIP(hipMemcpyAsync(m->rows + n_pairs, pair_b, size_t(n_pairs) * 4, hipMemcpyDeviceToDevice, s));
         st = mlp_forward(m, x, ldx, m->rows, R, m->Z, s);
         if (st != UF_OK) return st;
-        UF_HIP(ufp::pairloss(m->Z, n_pairs, int(m->dims[L]), target, rel_floor, m->dZ, m->loss_pp,
-                             loss, s));
+        {
+            ufh::ProfGuard pl("encoder_loss", s);
+            UF_HIP(ufp::pairloss(m->Z, n_pairs, int(m->dims[L]), target, rel_floor, m->dZ,
+                                 m->loss_pp, loss, s));
+        }
         return mlp_backward(m, x, ldx, m->rows, R, m->dZ, s);
     });
 }
@@ -379,6 +403,7 @@ uf_status uf_mlp_adam(uf_mlp* m, float lr, float beta1, float beta2, float eps,
         hipStream_t s = static_cast<hipStream_t>(stream);
         const float bc1 = float(1.0 - std::pow(double(beta1), double(step)));
         const float bc2 = float(1.0 - std::pow(double(beta2), double(step)));
+        ufh::ProfGuard pa("encoder_adam", s);
         for (int64_t l = 0; l < m->L; ++l) {
             const int64_t nw = m->dims[l + 1] * m->dims[l], nb = m->dims[l + 1];
             UF_HIP(ufp::adam(m->W[l], m->gW[l], m->mW[l], m->vW[l], nw, lr, beta1, beta2, eps, bc1, bc2,

@@ -25,7 +25,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import MLP, Sparse, gather_pairs, rerank, sqdist, topk_rows
+from . import (MLP, Sparse, gather_pairs, profile_enable, profile_read, profile_reset, rerank,
+               sqdist, topk_rows)
 
 
 def train(x, pair_a: np.ndarray, pair_b: np.ndarray, target, dims: Sequence[int],
@@ -64,6 +65,19 @@ def train(x, pair_a: np.ndarray, pair_b: np.ndarray, target, dims: Sequence[int]
         if log:
             log(f"epoch {ep + 1}/{epochs}: mean loss {losses[-1]:.3e}")
     return mlp, losses
+
+
+def train_step_flops(dims: Sequence[int], rows: int, skip: bool) -> int:
+    """Multiply-add flops of one training step's GEMMs over `rows` rows: the
+    forward product of every layer, every weight gradient, and the data gradient
+    of every layer but the first (the input needs none); the linear path adds a
+    forward product and a weight gradient."""
+    mac = sum(dims[l] * dims[l + 1] for l in range(len(dims) - 1))
+    mac_data = sum(dims[l] * dims[l + 1] for l in range(1, len(dims) - 1))
+    total = 2 * mac + mac_data
+    if skip:
+        total += 2 * dims[0] * dims[-1]
+    return 2 * rows * total
 
 
 def place(z_ref, z_q, q_sparse: Sparse, r_sparse: Sparse, k_candidates: int, k: int = 10):
@@ -176,13 +190,28 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
         s_init = synth.gaussian_matrix(dims[-1], dims[0], seed=init_seed + 1) * np.float32(
             ratio / np.sqrt(dims[-1]))
         init[-1] = (np.zeros_like(init[-1][0]), np.zeros_like(init[-1][1]))
+    profile_reset()
+    profile_enable(True)
     mlp, losses = train(x_ref, pa, pb, tg, dims, init, epochs=epochs, batch_pairs=batch_pairs,
                         lr=lr, rel_floor=rel_floor, skip=s_init, weight_decay=weight_decay,
                         log=log)
     sync()
+    profile_enable(False)
     out["train_s"] = time.perf_counter() - t2
     out["train_losses"] = losses
     out["train_pairs"] = int(len(pa))
+    # the training GEMMs, timed with HIP events on the training stream
+    steps = epochs * (len(pa) // batch_pairs if len(pa) >= batch_pairs else 1)
+    flops = steps * train_step_flops(dims, 2 * batch_pairs, skip)
+    out["train_steps"] = steps
+    out["train_gemm_flops"] = flops
+    for name in ("encoder_gemm", "encoder_colsum", "encoder_loss", "encoder_adam"):
+        ms, cnt = profile_read(name)
+        out[f"{name}_ms"] = ms
+        out[f"{name}_launches"] = cnt
+    gemm_s = out["encoder_gemm_ms"] / 1e3
+    out["train_gemm_tflops"] = flops / gemm_s / 1e12 if gemm_s > 0 else None
+    out["train_step_tflops"] = flops / max(out["train_s"], 1e-9) / 1e12
 
     def encode(x):
         z = torch.empty((x.shape[0], dims[-1]), dtype=torch.float32, device="cuda")

@@ -97,6 +97,57 @@ def test_all_gemm_layouts_exact_on_integers():
     assert np.array_equal(gs, (dz.T @ xr).astype(np.float32))
 
 
+def test_gemm_paths_exact_at_encoder_shapes():
+    """The encoder's own shapes (4096 -> 1024 -> 1024 -> 128 with the linear path,
+    8,192 gathered rows, as one training batch of 4,096 pairs): these take the
+    256-row tiles and every split-K path (the narrow layers and the weight
+    gradients over 8,192 rows).  Integer operands chosen so that every FP32 sum
+    and every BF16-stored activation or gradient is exact: forward, backward-data
+    and weight gradients must equal a float64 numpy computation bit for bit."""
+    import torch
+    import paper_2107_05397_amd as uf
+    rng = np.random.default_rng(2107)
+    d0, d1, d2, d3, n_src, n = 4096, 1024, 1024, 128, 9000, 8192
+    x = rng.integers(-1, 2, size=(n_src, d0)).astype(np.float64)
+    w1 = np.zeros((d1, d0))                       # 32 entries +-1 per row: |h1| <= 35
+    for r in range(d1):
+        w1[r, rng.choice(d0, size=32, replace=False)] = rng.choice([-1.0, 1.0], size=32)
+    b1 = rng.integers(-3, 4, size=d1).astype(np.float64)
+    w2 = np.zeros((d2, d1))                       # 4 signed permutations: 4 per row and column
+    for _ in range(4):
+        w2[np.arange(d2), rng.permutation(d1)] += rng.choice([-1.0, 1.0], size=d2)
+    b2 = rng.integers(-3, 4, size=d2).astype(np.float64)
+    w3 = np.zeros((d3, d2))                       # 2 entries per column: |dz W3| <= 2
+    for c in range(d2):
+        w3[rng.choice(d3, size=2, replace=False), c] = rng.choice([-1.0, 1.0], size=2)
+    b3 = rng.integers(-3, 4, size=d3).astype(np.float64)
+    sk = rng.integers(-1, 2, size=(d3, d0)).astype(np.float64)
+    rows = rng.integers(0, n_src, size=n).astype(np.int32)
+    dz = rng.integers(-1, 2, size=(n, d3)).astype(np.float64)
+    mlp = uf.MLP([d0, d1, d2, d3], max_rows=n, params=[(w1, b1), (w2, b2), (w3, b3)], skip=sk)
+    xt = _t(x, torch.bfloat16)
+    rt = _t(rows, torch.int32)
+    z = mlp.forward(xt, rows=rt).cpu().numpy().astype(np.float64)
+    xr = x[rows]
+    h1 = np.maximum(xr @ w1.T + b1, 0)
+    h2 = np.maximum(h1 @ w2.T + b2, 0)
+    assert np.abs(h1).max() <= 256 and np.abs(h2).max() <= 256   # exact in bf16
+    want_z = h2 @ w3.T + b3 + xr @ sk.T
+    assert np.abs(want_z).max() < 2 ** 24
+    assert np.array_equal(z, want_z)
+    mlp.backward(xt, _t(dz, torch.bfloat16), rows=rt)
+    g2 = (dz @ w3) * (h2 > 0)
+    g1 = (g2 @ w2) * (h1 > 0)
+    assert np.abs(g2).max() <= 256 and np.abs(g1).max() <= 256
+    want = {0: (g1.T @ xr, g1.sum(0)), 1: (g2.T @ h1, g2.sum(0)), 2: (dz.T @ h2, dz.sum(0))}
+    for l in (0, 1, 2):
+        gw, gb = mlp.get(l, "grads")
+        assert np.array_equal(gw.astype(np.float64), want[l][0]), l
+        assert np.array_equal(gb.astype(np.float64), want[l][1]), l
+    gs, _ = mlp.get(3, "grads")
+    assert np.array_equal(gs.astype(np.float64), dz.T @ xr)
+
+
 def _mlp_problem(seed=0, dims=(64, 32, 32, 32), n=50, p=40):
     rng = np.random.default_rng(seed)
     x = _bf(rng, (n, dims[0]))
