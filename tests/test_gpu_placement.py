@@ -224,11 +224,15 @@ def test_adam_three_steps_vs_oracle(weight_decay):
             for k, (p, m, v) in enumerate(state[l]):
                 g = grads[l][k].astype(np.float64)
                 wd = weight_decay if k == 0 else 0.0
+                # m = b1 m' + (1 - b1) g can cancel: its FP32 error is relative to
+                # the magnitudes that enter it (products and sum each rounded once,
+                # m' already FP32-rounded), not to the result
+                m_scale = float(np.float32(b1)) * np.abs(m) + (1 - float(np.float32(b1))) * np.abs(g)
                 p, m, v = op.adam(p, g, m, v, *(float(np.float32(h)) for h in (lr, b1, b2, eps)),
                                   step, weight_decay=float(np.float32(wd)))
                 state[l][k] = (p, m, v)
                 gp, gm, gv = got[0][k], got[1][k], got[2][k]
-                assert np.allclose(gm, m, rtol=1e-5, atol=1e-12), (step, l, k)
+                assert np.all(np.abs(gm - m) <= 1e-6 * m_scale + 1e-30), (step, l, k)
                 assert np.allclose(gv, v, rtol=1e-5, atol=1e-16), (step, l, k)
                 assert np.all(np.abs(gp - p) <= 1e-6 * np.abs(p) + 1e-8), (step, l, k)
             # the moments are the ones after `step` updates, not a first step again

@@ -322,6 +322,14 @@ def test_threshold_changes_while_computing(threshold):
     emb = _emb(tree, table)
     want = core.dm(tree, table, "weighted_normalized")[0]
     errors, stop = [], threading.Event()
+    # the workspace size depends on the split's dense set, hence on the threshold
+    # another thread may change at any moment: the caller provides one large
+    # enough for every threshold it uses
+    need = 0
+    for f in (0.05, 0.3, 1.0):
+        threshold(f, "weighted_normalized")
+        need = max(need, uf.workspace_size(emb, "weighted_normalized", "fp32_split"))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
 
     def flip():
         k = 0
@@ -336,7 +344,8 @@ def test_threshold_changes_while_computing(threshold):
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             for _ in range(20):
-                d, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split", stream=stream)
+                d, _, _ = uf.dm(emb, "weighted_normalized", "fp32_split", stream=stream,
+                                workspace=ws)
                 stream.synchronize()
                 errors.append(float(np.abs(d.cpu().numpy() - want).max()))
     finally:
