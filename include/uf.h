@@ -209,6 +209,29 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* emb, uf_precisio
                                             void* out, double* row_sums, void* ws,
                                             size_t ws_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the full weighted-
+ * normalized matrix as uf_dm_weighted_normalized, with the workspace taken from
+ * a fixed device array of UF_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the caller still
+ * passes the output and the optional row_means / grand_mean.  The node chunk
+ * is sized to fit the array (at least 32 branches per chunk); larger matrices
+ * return UF_ERR_RANGE with nothing written.  The largest N that fits: FP64
+ * 2,877 with row means or grand mean requested, 4,064 without; FP32 3,328 and
+ * 5,761.  Precisions:
+ * UF_FP64, UF_FP32 (UF_ERR_UNSUPPORTED otherwise: the split precisions build
+ * device-side lists).  Per-pair values are bitwise equal to those of
+ * uf_dm_weighted_normalized with the same precision.  All calls on one device
+ * share its array and leave their contents in it: calls that overlap on one
+ * device (concurrent streams or threads) race.
+ * Errors: UF_ERR_ARG, UF_ERR_UNSUPPORTED, UF_ERR_RANGE, UF_ERR_DEVICE. */
+#define UF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+uf_status uf_dm_weighted_normalized_noalloc(const uf_embedding* emb, uf_precision precision,
+                                            uf_out_dtype out_dtype, void* out_condensed,
+                                            double* row_means, double* grand_mean,
+                                            void* hip_stream);
+
 /* ---- batches: many tables on one tree --------------------------------------- */
 
 /* Many tables of uneven size on one tree -- e.g. rarefied replicates of a study

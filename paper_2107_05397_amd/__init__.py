@@ -79,6 +79,8 @@ _SIGS = {
     "uf_dm_weighted_normalized_stripes": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64,
                                                          ctypes.c_int, ctypes.c_int, _vp, _vp, _vp,
                                                          ctypes.c_size_t, _vp]),
+    "uf_dm_weighted_normalized_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp,
+                                                         _vp, _vp, _vp]),
     "uf_n_stripes": (_i64, [_i64]),
     "uf_condensed_index": (_i64, [_i64, _i64, _i64]),
     "uf_free_tree": (None, [_vp]),
@@ -379,6 +381,27 @@ def dm(emb: Embedding, variant: str, precision: str = "fp64", out_dtype=None, ou
               _tptr(out), _tptr(rm), _tptr(gm), _tptr(ws), ws.numel() * ws.element_size(),
               _stream_ptr(stream)))
     return out[:npairs], (rm[:n] if rm is not None else None), gm
+
+
+def dm_weighted_normalized_noalloc(emb: Embedding, precision: str = "fp64", out=None,
+                                   row_means=None, grand_mean=None, stream=None):
+    """The weighted-normalized matrix into caller-provided tensors, with the
+    library's fixed device scratch as workspace: the C call allocates nothing.
+    out: contiguous float64/float32 CUDA tensor of >= N(N-1)/2 entries;
+    row_means (>= N float64) and grand_mean (>= 1 float64) are optional."""
+    import torch
+    n = emb.n_samples
+    npairs = n * (n - 1) // 2
+    if out is None or out.dtype not in (torch.float64, torch.float32) or \
+            out.numel() < npairs or not out.is_contiguous():
+        raise UFError(1, "out must be a contiguous float32/float64 CUDA tensor of N(N-1)/2 entries")
+    for t, k in ((row_means, n), (grand_mean, 1)):
+        if t is not None and (t.dtype != torch.float64 or t.numel() < k or not t.is_contiguous()):
+            raise UFError(1, "row_means / grand_mean must be contiguous float64 CUDA tensors")
+    _check(lib().uf_dm_weighted_normalized_noalloc(
+        emb.handle, PRECISION[precision], 1 if out.dtype == torch.float32 else 0, _tptr(out),
+        _tptr(row_means), _tptr(grand_mean), _stream_ptr(stream)))
+    return out
 
 
 def dm_unweighted(emb, precision="mfma", **kw):

@@ -470,9 +470,12 @@ struct Plan {
     size_t off_acc = 0, off_q = 0, off_chunk = 0, off_part = 0, off_rm = 0, off_m = 0, total = 0;
 };
 
-// sp: the variant's split for the split precisions (ignored otherwise)
+// sp: the variant's split for the split precisions (ignored otherwise).
+// fit > 0: the node chunk is sized so that the whole workspace fits in fit bytes
+// (at least 32 branches per chunk, or all of them when fewer), else UF_ERR_RANGE.
 uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb,
-                    int64_t se, bool rowstats, Plan* p, const SplitCache* sp = nullptr) {
+                    int64_t se, bool rowstats, Plan* p, const SplitCache* sp = nullptr,
+                    size_t fit = 0) {
     if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
     if (prec != UF_FP64 && prec != UF_FP32 && prec != UF_MFMA_BF16X2 && prec != UF_FP32_SPLIT &&
         prec != UF_MFMA_SPLIT)
@@ -500,36 +503,59 @@ uf_status make_plan(const uf_embedding* e, int weighted, uf_precision prec, int6
     if (split && !sp) return fail(UF_ERR_ARG, "split precision without a split");
     const int64_t nb = split ? sp->n_dense : e->nb;
     const size_t elem = prec == UF_FP64 ? 8 : (mfma ? 1 : 4);
+    p->n_parts = std::max<int64_t>(1, (p->sr + 255) / 256);
+    const size_t acc_elem = (prec == UF_FP64) ? 8 : 4;
+    // workspace layout for a chunk of kc branches
+    auto layout = [&](int64_t kc) {
+        p->kc = kc;
+        p->nchunks = nb > 0 && kc > 0 ? (nb + kc - 1) / kc : 0;
+        p->kpad = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
+        Carver c;
+        p->off_acc = c.take(size_t(p->sr) * size_t(n) * acc_elem);
+        p->off_q = rowstats ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
+        if (mfma)
+            p->off_chunk = c.take(size_t(n) * size_t(p->kpad));   // FP8 presence
+        else
+            p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
+        p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
+        p->off_rm = rowstats ? c.take(size_t(n) * 8) : 0;
+        p->off_m = split ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
+        p->total = c.off + 256;
+    };
+    auto shape = [&](int64_t kc) {
+        kc = std::max<int64_t>(kc, 32);
+        if (mfma) kc = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
+        return std::min<int64_t>(kc, std::max<int64_t>(nb, 1));
+    };
+    if (fit > 0) {
+        // the chunk takes what the rest leaves (each carved piece may lose up to
+        // 255 bytes to alignment)
+        layout(0);
+        const size_t rest = p->total + 6 * 256;
+        const size_t per = mfma ? size_t(n) : size_t(n) * elem;
+        const int64_t room = rest < fit ? int64_t((fit - rest) / std::max<size_t>(per, 1)) : 0;
+        const int64_t kc = std::min<int64_t>(room, std::max<int64_t>(nb, 1));
+        if (mfma || kc < std::min<int64_t>(32, std::max<int64_t>(nb, 1)))
+            return fail(UF_ERR_RANGE, "problem too large for the fixed scratch (" +
+                                          std::to_string(fit) + " bytes)");
+        layout(kc);
+        if (p->total > fit)
+            return fail(UF_ERR_RANGE, "problem too large for the fixed scratch (" +
+                                          std::to_string(fit) + " bytes)");
+        return UF_OK;
+    }
     int64_t kc = g_chunk_nodes.load();
     if (kc <= 0) {
         const double budget = 8.0 * 1024 * 1024 * 1024;
         kc = static_cast<int64_t>(budget / (double(std::max<int64_t>(n, 1)) * double(elem)));
     }
-    kc = std::max<int64_t>(kc, 32);
-    if (mfma) kc = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
-    kc = std::min<int64_t>(kc, std::max<int64_t>(nb, 1));
-    p->kc = kc;
-    p->nchunks = nb > 0 ? (nb + kc - 1) / kc : 0;
-    p->kpad = (kc + ufk::kGramKPad - 1) / ufk::kGramKPad * ufk::kGramKPad;
-    p->n_parts = std::max<int64_t>(1, (p->sr + 255) / 256);
-    Carver c;
-    const size_t acc_elem = (prec == UF_FP64) ? 8 : 4;
-    p->off_acc = c.take(size_t(p->sr) * size_t(n) * acc_elem);
-    p->off_q = rowstats ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
-    if (mfma)
-        p->off_chunk = c.take(size_t(n) * size_t(p->kpad));   // FP8 presence
-    else
-        p->off_chunk = c.take(size_t(kc) * size_t(n) * elem);
-    p->off_part = rowstats ? c.take(size_t(p->n_parts) * size_t(n) * 8) : 0;
-    p->off_rm = rowstats ? c.take(size_t(n) * 8) : 0;
-    p->off_m = split ? c.take(size_t(p->sr) * size_t(n) * 8) : 0;
-    p->total = c.off + 256;
+    layout(shape(kc));
     return UF_OK;
 }
 
 uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t sb, int64_t se,
                  int layout, uf_out_dtype odt, void* out, double* row_out, double* grand_mean,
-                 bool full_means, void* ws, size_t ws_bytes, void* stream) {
+                 bool full_means, void* ws, size_t ws_bytes, void* stream, bool fit_ws = false) {
     if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
     if (!out) return fail(UF_ERR_ARG, "output pointer is NULL");
     if (layout != UF_CONDENSED && layout != UF_STRIPES) return fail(UF_ERR_ARG, "bad layout");
@@ -545,14 +571,15 @@ uf_status run_dm(const uf_embedding* e, int weighted, uf_precision prec, int64_t
         st = ensure_split(e, weighted, stream, &hold);
         if (st != UF_OK) return st;
     }
-    st = make_plan(e, weighted, prec, sb, se, rowstats, &p, hold.get());
+    st = make_plan(e, weighted, prec, sb, se, rowstats, &p, hold.get(), fit_ws ? ws_bytes : 0);
     if (st != UF_OK) return st;
     if (!ws || ws_bytes < p.total)
         return fail(UF_ERR_WORKSPACE, "workspace missing or smaller than uf_workspace_size()");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p.sr == 0 || p.n < 2) {
-        if (row_out && p.n > 0) UF_HIP(hipMemsetAsync(row_out, 0, size_t(p.n) * 8, s));
-        if (grand_mean) UF_HIP(hipMemsetAsync(grand_mean, 0, 8, s));
+        // zeroed by a kernel, so that the call can be captured into a graph
+        if (row_out && p.n > 0) UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(row_out), 2 * p.n, s));
+        if (grand_mean) UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(grand_mean), 2, s));
         return UF_OK;
     }
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
@@ -1162,6 +1189,59 @@ uf_status uf_dm_weighted_normalized_stripes(const uf_embedding* e, uf_precision 
     return guarded([&]() -> uf_status {
         return run_dm(e, 1, prec, sb, se, layout, odt, out, row_sums, nullptr, false, ws,
                       ws_bytes, stream);
+    });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no allocation
+// Workspace of uf_dm_weighted_normalized_noalloc: a fixed device array.  Every
+// device the library runs on holds its own copy, at its own address, for the
+// life of the process.  In host code `scratch` names a host-side stand-in, so
+// kernels only ever receive the per-device address looked up below.
+static __device__ __align__(256) unsigned char scratch[UF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current): looked up
+// once per device.
+uf_status scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(UF_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (he != hipSuccess || !ptr) return hip_fail(he, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return UF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+uf_status uf_dm_weighted_normalized_noalloc(const uf_embedding* e, uf_precision prec,
+                                            uf_out_dtype odt, void* out, double* row_means,
+                                            double* grand_mean, void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!e) return fail(UF_ERR_ARG, "embedding is NULL");
+        if (prec != UF_FP64 && prec != UF_FP32)
+            return fail(UF_ERR_UNSUPPORTED,
+                        "the no-allocation call takes UF_FP64 or UF_FP32 (the split precisions "
+                        "build their split with device allocations)");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        if (dev != e->device) return fail(UF_ERR_DEVICE, "embedding lives on another device");
+        void* ws = nullptr;
+        st = scratch_address(dev, &ws);
+        if (st != UF_OK) return st;
+        return run_dm(e, 1, prec, 0, e->n / 2, UF_CONDENSED, odt, out, row_means, grand_mean,
+                      true, ws, size_t(UF_NOALLOC_SCRATCH_BYTES), stream, true);
     });
 }
 
