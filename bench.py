@@ -210,6 +210,22 @@ def bench_batch(args) -> int:
         pr = [(int(min(a, c)), int(max(a, c))) for a, c in zip(ii[:4], ii[4:])]
         idx = torch.tensor([uf.condensed_index(n, a, c) for a, c in pr], device="cuda")
         samples.append((int(r), pr, outs[r][idx].double().cpu().numpy()))
+    full_oracle = []
+    if args.oracle_smallest > 0 and not args.no_cpu_baseline:
+        # CPU leg: whole tables against the FP64 C oracle (all host cores)
+        from oracle import core
+        core.build(force=False)
+        for r in np.argsort(sizes, kind="stable")[:args.oracle_smallest]:
+            t1 = time.perf_counter()
+            want, used = core.dm(tree, tables[int(r)], "weighted_normalized")
+            secs = time.perf_counter() - t1
+            got = outs[int(r)].double().cpu().numpy()
+            err = np.abs(got - want)
+            full_oracle.append({"table": int(r), "n_samples": int(sizes[r]), "pairs": int(err.size),
+                                "max_abs_err": float(err.max()), "mean_abs_err": float(err.mean()),
+                                "oracle_seconds": secs, "oracle_threads": int(used)})
+            log(f"table {int(r)} (n={sizes[r]}) in full vs the oracle: max|err| {err.max():.3e}, "
+                f"mean {err.mean():.3e} ({secs:.1f}s on {used} threads)")
     cpu = None
     if not args.no_cpu_baseline:
         # CPU leg: the oracle timed on a bounded sample of the smallest table, and the
@@ -243,9 +259,10 @@ def bench_batch(args) -> int:
                   "split_batch_graph_s": split_graph_s,
                   "split_batch_updates_per_s": U / split_graph_s,
                   "split_batch_autotune_ms": split_tune_ms,
-                  "autotuned_config": dict(zip(("stage_branches", "wgs_per_cu", "chunk_nodes"),
+                  "autotuned_config": dict(zip(("stage_branches", "wgs_per_cu", "chunk_nodes", "tile_stripes"),
                                                b.config())),
-                  "autotune_first_chunk_ms": tune_ms},
+                  "autotune_first_chunk_ms": tune_ms,
+                  "smallest_tables_vs_oracle": full_oracle},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
@@ -299,6 +316,8 @@ def main() -> int:
     ap.add_argument("--unweighted-precision", default="mfma_split",
                     choices=["mfma", "mfma_split", "fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-smallest", type=int, default=0,
+                    help="C4: compare the N smallest tables in full with the FP64 C oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target length of the one-core oracle run")
     ap.add_argument("--copy-calibration", action="store_true",

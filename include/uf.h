@@ -261,10 +261,17 @@ uf_status uf_batch_plan_create(const uf_tree* tree, const uf_table* const* table
 int64_t uf_batch_n_tables(const uf_batch* batch);
 uf_status uf_batch_workspace_size(const uf_batch* batch, size_t* bytes);
 /* Current launch configuration: branches staged per LDS block (8, 16 or 32),
- * resident blocks per CU, and branches per chunk. */
+ * resident blocks per CU, stripes per band tile (64, 128 or 256; a tile is 128
+ * samples x that many stripes) and branches per chunk (each pointer nullable). */
 uf_status uf_batch_config(const uf_batch* batch, int* stage_branches, int* wgs_per_cu,
-                          int64_t* chunk_nodes);
-uf_status uf_batch_set_config(uf_batch* batch, int stage_branches, int wgs_per_cu);
+                          int* tile_stripes, int64_t* chunk_nodes);
+/* Set the launch configuration.  Valid when that many blocks of the kernel for
+ * (stage_branches, tile_stripes) fit on one CU (LDS and registers, as the HIP
+ * occupancy query reports).  A new tile size rebuilds the work items
+ * (synchronous).  Results do not depend on the configuration.
+ * Errors: UF_ERR_ARG (NULL, invalid configuration), UF_ERR_DEVICE. */
+uf_status uf_batch_set_config(uf_batch* batch, int stage_branches, int wgs_per_cu,
+                              int tile_stripes);
 /* Arithmetic of the batch: UF_FP32 (default; the persistent stripe kernel above)
  * or UF_FP32_SPLIT: every table through the sparse-aware split of
  * uf_dm_weighted_normalized(UF_FP32_SPLIT) (results equal to that call on each
@@ -285,9 +292,12 @@ uf_status uf_batch_set_precision(uf_batch* batch, uf_precision prec, const uf_ta
  * instead of launching kernel by kernel.  Asynchronous on hip_stream. */
 uf_status uf_batch_run(uf_batch* batch, float* const* outs, int use_graph, void* ws,
                        size_t ws_bytes, void* hip_stream);
-/* Time every valid (stage_branches, wgs_per_cu) on the batch's first chunk,
- * keep the fastest (results are identical for all), and record it in the JSON
- * cache at tune_cache (nullable; else $UF_TUNE_CACHE; no file if neither).
+/* The self-written tile/stripe autotuner: time every tile size (64, 128, 256
+ * stripes) x stage size (8, 16, 32 branches) at the two highest resident-block
+ * counts that configuration allows, on the first 2,048 branches of the batch's
+ * first chunk; keep the fastest (results are identical for all) and record it
+ * in the JSON cache at tune_cache (nullable; else $UF_TUNE_CACHE; no file if
+ * neither), keyed by the size bucket.
  * best_ms (nullable) receives the winner's time.  Synchronises hip_stream. */
 uf_status uf_autotune(uf_batch* batch, void* ws, size_t ws_bytes, const char* tune_cache,
                       void* hip_stream, double* best_ms);

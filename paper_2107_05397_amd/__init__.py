@@ -93,8 +93,9 @@ _SIGS = {
     "uf_batch_n_tables": (_i64, [_vp]),
     "uf_batch_workspace_size": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int), _i64p]),
-    "uf_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       _i64p]),
+    "uf_batch_set_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "uf_batch_set_precision": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "uf_batch_run": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.c_size_t,
                                     _vp]),
@@ -465,12 +466,15 @@ class Batch(_Handle):
         return int(out.value)
 
     def config(self):
-        ks, w, kc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
-        _check(lib().uf_batch_config(self._h, ctypes.byref(ks), ctypes.byref(w), ctypes.byref(kc)))
-        return int(ks.value), int(w.value), int(kc.value)
+        """(stage_branches, wgs_per_cu, chunk_nodes, tile_stripes)."""
+        ks, w, ts, kc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int64(0)
+        _check(lib().uf_batch_config(self._h, ctypes.byref(ks), ctypes.byref(w), ctypes.byref(ts),
+                                     ctypes.byref(kc)))
+        return int(ks.value), int(w.value), int(kc.value), int(ts.value)
 
-    def set_config(self, stage_branches: int, wgs_per_cu: int) -> None:
-        _check(lib().uf_batch_set_config(self._h, int(stage_branches), int(wgs_per_cu)))
+    def set_config(self, stage_branches: int, wgs_per_cu: int, tile_stripes: int = 128) -> None:
+        _check(lib().uf_batch_set_config(self._h, int(stage_branches), int(wgs_per_cu),
+                                         int(tile_stripes)))
 
     def set_precision(self, precision: str = "fp32", stream=None) -> None:
         """"fp32" (persistent stripe kernel) or "fp32_split" (per-table sparse split on

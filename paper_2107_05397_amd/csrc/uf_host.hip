@@ -1256,9 +1256,9 @@ struct uf_batch {
     int64_t n_tables = 0;
     std::vector<BatchTable> tabs;        // host copy
     std::vector<int64_t> acc_elems;           // per table
-    int64_t n_items = 0;
+    int64_t n_items = 0, max_items = 0;
     int64_t kc = 0, n_chunks = 0;
-    int stage_branches = 16, wgs_per_cu = 2, n_cu = 256;
+    int stage_branches = 16, wgs_per_cu = 2, tile_stripes = 128, n_cu = 256;
     int64_t n_bucket = 0;
     void* arena = nullptr;                    // descs, tab_of, items, queue bounds
     BatchTable* d_tabs = nullptr;
@@ -1269,6 +1269,7 @@ struct uf_batch {
     int32_t* d_lo_chunks = nullptr;           // positions of each chunk ordered by lo
     size_t off_E = 0, off_acc = 0, off_cnt = 0, ws_total = 0;
     hipStream_t cap = nullptr;                // capture stream (default priority)
+    hipEvent_t last_run = nullptr;            // recorded after every run's work
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> graph_key;         // workspace + outputs the graph was built for
@@ -1285,6 +1286,7 @@ struct uf_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
+        if (last_run) (void)hipEventDestroy(last_run);
         for (hipStream_t q : streams) (void)hipStreamDestroy(q);
         for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
         for (uf_embedding* t : tembs) uf_free_embedding(t);
@@ -1296,20 +1298,21 @@ struct uf_batch {
 namespace {
 
 const int kBatchStages[] = {8, 16, 32};
+const int kBatchTiles[] = {64, 128, 256};
 
-bool config_valid(int ks, int w) {
-    // one CU holds at most 160 KB of LDS and 512 VGPRs x 4 SIMDs
-    const int lds_kb = ks == 8 ? 25 : (ks == 16 ? 49 : 97);
-    const int max_w = ks == 8 ? 3 : (ks == 16 ? 2 : 1);
-    return w >= 1 && w <= max_w && w * lds_kb <= 160;
+// (stage branches, resident blocks per CU, stripes per tile) is valid when the
+// kernel exists and that many of its blocks fit on a CU (LDS, registers)
+bool config_valid(int ks, int w, int ts) {
+    return w >= 1 && w <= ufk::band_persistent_max_blocks(ks, ts);
 }
 
 std::string cache_key_arch() { return "gfx950"; }
 
 // Cache file: {"gfx950": {"weighted_normalized_fp32": {"n_bucket_B": {"stage_branches": K,
-// "wgs_per_cu": W, "ms": T}, ...}}}.  Entries are parsed leniently by pattern.
+// "wgs_per_cu": W, "tile_stripes": S, "ms": T}, ...}}}.  Entries are parsed
+// leniently by pattern; an entry without tile_stripes means 128.
 struct TuneEntry {
-    int ks, w;
+    int ks, w, ts;
     double ms;
 };
 std::map<int64_t, TuneEntry> read_tune_cache(const char* path) {
@@ -1325,13 +1328,17 @@ std::map<int64_t, TuneEntry> read_tune_cache(const char* path) {
     size_t pos = 0;
     while ((pos = text.find("\"n_bucket_", pos)) != std::string::npos) {
         long long b = 0;
-        int ks = 0, w = 0;
+        int ks = 0, w = 0, ts = 128;
         double ms = 0;
-        if (std::sscanf(text.c_str() + pos,
-                        "\"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, \"ms\": %lf",
-                        &b, &ks, &w, &ms) == 4 &&
-            config_valid(ks, w))
-            m[b] = TuneEntry{ks, w, ms};
+        const char* at = text.c_str() + pos;
+        const bool ok =
+            std::sscanf(at, "\"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, "
+                            "\"tile_stripes\": %d, \"ms\": %lf",
+                        &b, &ks, &w, &ts, &ms) == 5 ||
+            (ts = 128, std::sscanf(at, "\"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, "
+                                       "\"ms\": %lf",
+                                   &b, &ks, &w, &ms) == 4);
+        if (ok && config_valid(ks, w, ts)) m[b] = TuneEntry{ks, w, ts, ms};
         pos += 10;
     }
     return m;
@@ -1344,8 +1351,11 @@ bool write_tune_cache(const char* path, const std::map<int64_t, TuneEntry>& m) {
     std::fprintf(f, "{\"%s\": {\"weighted_normalized_fp32\": {", cache_key_arch().c_str());
     bool firstc = true;
     for (const auto& kv : m) {
-        std::fprintf(f, "%s\n  \"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, \"ms\": %.6f}",
-                     firstc ? "" : ",", (long long)kv.first, kv.second.ks, kv.second.w, kv.second.ms);
+        std::fprintf(f,
+                     "%s\n  \"n_bucket_%lld\": {\"stage_branches\": %d, \"wgs_per_cu\": %d, "
+                     "\"tile_stripes\": %d, \"ms\": %.6f}",
+                     firstc ? "" : ",", (long long)kv.first, kv.second.ks, kv.second.w, kv.second.ts,
+                     kv.second.ms);
         firstc = false;
     }
     std::fprintf(f, "\n}}}\n");
@@ -1354,6 +1364,39 @@ bool write_tune_cache(const char* path, const std::map<int64_t, TuneEntry>& m) {
 }
 
 const char* tune_path(const char* p) { return p ? p : std::getenv("UF_TUNE_CACHE"); }
+
+// Work items of the persistent kernel for tiles of ts stripes: (table, tile) with
+// the tile's i-block fastest, tables in order.
+std::vector<int2> batch_items(const std::vector<BatchTable>& tabs, int ts) {
+    std::vector<int2> items;
+    for (size_t r = 0; r < tabs.size(); ++r) {
+        const BatchTable& t = tabs[r];
+        if (t.n < 2) continue;
+        const int64_t n_sblk = (t.n / 2 + ts - 1) / ts;
+        for (int64_t tt = 0; tt < t.n_iblk * n_sblk; ++tt) items.push_back(make_int2(int(r), int(tt)));
+    }
+    return items;
+}
+
+// Upload the items for tiles of ts stripes and the 8 queue bounds (synchronous).
+uf_status batch_set_tiles(uf_batch* b, int ts) {
+    const std::vector<int2> items = batch_items(b->tabs, ts);
+    // a run still in flight reads the current items
+    if (b->last_run) UF_HIP(hipEventSynchronize(b->last_run));
+    if (int64_t(items.size()) > b->max_items) return fail(UF_ERR_ARG, "tile size below the smallest");
+    b->n_items = int64_t(items.size());
+    std::vector<int64_t> qb(8), qe(8);
+    for (int q = 0; q < 8; ++q) {
+        qb[size_t(q)] = b->n_items * q / 8;
+        qe[size_t(q)] = b->n_items * (q + 1) / 8;
+    }
+    if (b->n_items)
+        UF_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * size_t(b->n_items), hipMemcpyHostToDevice));
+    UF_HIP(hipMemcpy(b->d_qbeg, qb.data(), 64, hipMemcpyHostToDevice));
+    UF_HIP(hipMemcpy(b->d_qend, qe.data(), 64, hipMemcpyHostToDevice));
+    b->tile_stripes = ts;
+    return UF_OK;
+}
 
 // node-major FP32 embedding of chunk [k0, k0+kc) of every table: forward merge
 // when every sample total is below 2^32, else binary searches (same values)
@@ -1379,7 +1422,8 @@ uf_status batch_enqueue(uf_batch* b, float* const* outs, char* base, hipStream_t
         UF_HIP(batch_embed(b, k0, kc, E, s));
         if (b->n_items > 0)
             UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend,
-                                            cnt + c * 8, kc, c == 0, acc, b->stage_branches, nblk, s));
+                                            cnt + c * 8, kc, c == 0, acc, b->stage_branches,
+                                            b->tile_stripes, nblk, s));
     }
     for (int64_t r = 0; r < b->n_tables; ++r) {
         const BatchTable& t = b->tabs[r];
@@ -1529,9 +1573,8 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         kc = std::min<int64_t>(std::max<int64_t>(kc, 32), std::max<int64_t>(b->emb->nb, 1));
         b->kc = kc;
         b->n_chunks = b->emb->nb > 0 ? (b->emb->nb + kc - 1) / kc : 0;
-        // per-table layout and work items
+        // per-table layout
         int64_t off = 0, eoff = 0, aoff = 0;
-        std::vector<int2> items;
         std::vector<int32_t> tab_of(size_t(n_all), 0);
         double mean_n = 0;
         for (int64_t r = 0; r < n_tables; ++r) {
@@ -1544,25 +1587,18 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
             b->tabs.push_back(t);
             for (int64_t i = 0; i < t.n; ++i) tab_of[size_t(off + i)] = int32_t(r);
             const int64_t S = t.n / 2;
-            const int64_t n_sblk = (S + ufk::kBandS - 1) / ufk::kBandS;
-            if (t.n >= 2)
-                for (int64_t tt = 0; tt < t.n_iblk * n_sblk; ++tt) items.push_back(make_int2(int(r), int(tt)));
             off += t.n;
             eoff += kc * t.n;
             aoff += ((S * t.n + 63) / 64) * 64;
             mean_n += double(t.n) / double(n_tables);
         }
-        b->n_items = int64_t(items.size());
+        // work items: the arena holds those of the smallest tile (the most)
+        b->max_items = int64_t(batch_items(b->tabs, kBatchTiles[0]).size());
         b->n_bucket = mean_n > 1 ? int64_t(std::ceil(std::log2(mean_n))) : 0;
-        std::vector<int64_t> qb(8), qe(8);
-        for (int q = 0; q < 8; ++q) {
-            qb[q] = b->n_items * q / 8;
-            qe[q] = b->n_items * (q + 1) / 8;
-        }
         Carver c;
         const size_t o_tabs = c.take(sizeof(BatchTable) * size_t(n_tables));
         const size_t o_tabof = c.take(size_t(n_all) * 4);
-        const size_t o_items = c.take(sizeof(int2) * size_t(std::max<int64_t>(b->n_items, 1)));
+        const size_t o_items = c.take(sizeof(int2) * size_t(std::max<int64_t>(b->max_items, 1)));
         const size_t o_qb = c.take(8 * 8);
         const size_t o_qe = c.take(8 * 8);
         const int64_t nb = b->emb->nb;
@@ -1589,9 +1625,6 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         }
         UF_HIP(hipMemcpy(b->d_tabs, b->tabs.data(), sizeof(BatchTable) * size_t(n_tables), hipMemcpyHostToDevice));
         UF_HIP(hipMemcpy(b->d_tab_of, tab_of.data(), size_t(n_all) * 4, hipMemcpyHostToDevice));
-        if (b->n_items) UF_HIP(hipMemcpy(b->d_items, items.data(), sizeof(int2) * size_t(b->n_items), hipMemcpyHostToDevice));
-        UF_HIP(hipMemcpy(b->d_qbeg, qb.data(), 64, hipMemcpyHostToDevice));
-        UF_HIP(hipMemcpy(b->d_qend, qe.data(), 64, hipMemcpyHostToDevice));
         Carver w;
         b->off_E = w.take(size_t(eoff) * 4);
         b->off_acc = w.take(size_t(aoff) * 4);
@@ -1600,11 +1633,16 @@ uf_status uf_batch_create(const uf_tree* tree, const uf_table* const* tables, in
         // launch configuration from the tuning cache, if it has this size bucket
         auto cache = read_tune_cache(tune_path(tune_cache));
         auto it = cache.find(b->n_bucket);
+        int ts = 128;
         if (it != cache.end()) {
             b->stage_branches = it->second.ks;
             b->wgs_per_cu = it->second.w;
+            ts = it->second.ts;
         }
+        st = batch_set_tiles(b, ts);
+        if (st != UF_OK) return st;
         UF_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        UF_HIP(hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming));
         *out = guard.release();
         return UF_OK;
     });
@@ -1639,28 +1677,36 @@ uf_status uf_batch_workspace_size(const uf_batch* b, size_t* bytes) {
     return UF_OK;
 }
 
-uf_status uf_batch_config(const uf_batch* b, int* stage_branches, int* wgs_per_cu, int64_t* chunk_nodes) {
+uf_status uf_batch_config(const uf_batch* b, int* stage_branches, int* wgs_per_cu,
+                          int* tile_stripes, int64_t* chunk_nodes) {
     if (!b) return fail(UF_ERR_ARG, "batch is NULL");
     if (stage_branches) *stage_branches = b->stage_branches;
     if (wgs_per_cu) *wgs_per_cu = b->wgs_per_cu;
+    if (tile_stripes) *tile_stripes = b->tile_stripes;
     if (chunk_nodes) *chunk_nodes = b->kc;
     return UF_OK;
 }
 
-uf_status uf_batch_set_config(uf_batch* b, int stage_branches, int wgs_per_cu) {
-    if (!b) return fail(UF_ERR_ARG, "batch is NULL");
-    if (!config_valid(stage_branches, wgs_per_cu))
-        return fail(UF_ERR_ARG, "unsupported (stage_branches, wgs_per_cu)");
-    b->stage_branches = stage_branches;
-    b->wgs_per_cu = wgs_per_cu;
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        b->graph_key.clear();
-    }
-    return UF_OK;
+uf_status uf_batch_set_config(uf_batch* b, int stage_branches, int wgs_per_cu, int tile_stripes) {
+    return guarded([&]() -> uf_status {
+        if (!b) return fail(UF_ERR_ARG, "batch is NULL");
+        if (!config_valid(stage_branches, wgs_per_cu, tile_stripes))
+            return fail(UF_ERR_ARG, "unsupported (stage_branches, wgs_per_cu, tile_stripes)");
+        if (tile_stripes != b->tile_stripes) {
+            const uf_status st = batch_set_tiles(b, tile_stripes);
+            if (st != UF_OK) return st;
+        }
+        b->stage_branches = stage_branches;
+        b->wgs_per_cu = wgs_per_cu;
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            b->graph_key.clear();
+        }
+        return UF_OK;
+    });
 }
 
 uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws, size_t ws_bytes,
@@ -1686,7 +1732,12 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
             }
             key.push_back(uintptr_t(b->n_streams));
         }
-        if (!use_graph) return batch_enqueue_any(b, outs, base, s);
+        if (!use_graph) {
+            st = batch_enqueue_any(b, outs, base, s);
+            if (st != UF_OK) return st;
+            UF_HIP(hipEventRecord(b->last_run, s));
+            return UF_OK;
+        }
         key.push_back(reinterpret_cast<uintptr_t>(base));
         for (int64_t r = 0; r < b->n_tables; ++r) key.push_back(reinterpret_cast<uintptr_t>(outs[r]));
         if (!b->exec || key != b->graph_key) {
@@ -1716,6 +1767,7 @@ uf_status uf_batch_run(uf_batch* b, float* const* outs, int use_graph, void* ws,
             b->graph_key = key;
         }
         UF_HIP(hipGraphLaunch(b->exec, s));
+        UF_HIP(hipEventRecord(b->last_run, s));
         return UF_OK;
     });
 }
@@ -1783,34 +1835,48 @@ uf_status uf_autotune(uf_batch* b, void* ws, size_t ws_bytes, const char* tune_c
         unsigned* cnt = reinterpret_cast<unsigned*>(base + b->off_cnt);
         const uf_embedding& e = *b->emb;
         if (b->n_chunks == 0 || b->n_items == 0) return UF_OK;
-        const int64_t kc = std::min<int64_t>(b->kc, e.nb);
+        // timed on the first 2,048 branches of the first chunk: every configuration
+        // pays the same per-branch work, so a part of the chunk ranks them
+        const int64_t kc = std::min<int64_t>(std::min<int64_t>(b->kc, e.nb), 2048);
         UF_HIP(batch_embed(b, 0, kc, E, s));
         hipEvent_t e0, e1;
         UF_HIP(hipEventCreate(&e0));
         UF_HIP(hipEventCreate(&e1));
-        TuneEntry best{b->stage_branches, b->wgs_per_cu, 1e300};
-        for (int ks : kBatchStages) {
-            for (int w = 1; w <= 3; ++w) {
-                if (!config_valid(ks, w) || (w == 1 && ks != 32)) continue;
-                double tmin = 1e300;
-                for (int rep = 0; rep < 2; ++rep) {
-                    UF_HIP(ufk::zero_u32(cnt, 8, s));
-                    UF_HIP(hipEventRecord(e0, s));
-                    UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend, cnt,
-                                                    kc, 1, acc, ks, b->n_cu * w, s));
-                    UF_HIP(hipEventRecord(e1, s));
-                    UF_HIP(hipEventSynchronize(e1));
-                    float ms = 0;
-                    UF_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    tmin = std::min(tmin, double(ms));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        TuneEntry best{b->stage_branches, b->wgs_per_cu, b->tile_stripes, 1e300};
+        for (int ts : kBatchTiles) {
+            st = batch_set_tiles(b, ts);
+            if (st != UF_OK) return st;
+            for (int ks : kBatchStages) {
+                // the two highest occupancies the configuration allows
+                const int wmax = ufk::band_persistent_max_blocks(ks, ts);
+                for (int w = std::max(1, wmax - 1); w <= wmax; ++w) {
+                    double tmin = 1e300;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        UF_HIP(ufk::zero_u32(cnt, 8, s));
+                        UF_HIP(hipEventRecord(e0, s));
+                        UF_HIP(ufk::band_persistent_f32(E, b->d_tabs, b->d_items, b->d_qbeg, b->d_qend,
+                                                        cnt, kc, 1, acc, ks, ts, b->n_cu * w, s));
+                        UF_HIP(hipEventRecord(e1, s));
+                        UF_HIP(hipEventSynchronize(e1));
+                        float ms = 0;
+                        UF_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        tmin = std::min(tmin, double(ms));
+                    }
+                    if (tmin < best.ms) best = TuneEntry{ks, w, ts, tmin};
                 }
-                if (tmin < best.ms) best = TuneEntry{ks, w, tmin};
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         if (best_ms) *best_ms = best.ms;
-        st = uf_batch_set_config(b, best.ks, best.w);
+        st = batch_set_tiles(b, best.ts);
+        if (st != UF_OK) return st;
+        st = uf_batch_set_config(b, best.ks, best.w, best.ts);
         if (st != UF_OK) return st;
         const char* path = tune_path(tune_cache);
         if (path) {

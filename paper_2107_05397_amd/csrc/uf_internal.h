@@ -234,11 +234,15 @@ hipError_t embed_batch_f32(const uf_embedding& e, const BatchTable* tabs, const 
                            int64_t k0, int64_t kc, float* out, hipStream_t st);
 // Persistent band kernel over (table, tile) items.  items: int32 pairs; queue q
 // holds items [qbeg[q], qend[q]) and its counter counters[q] (8 queues, one per
-// XCD; exhausted queues are stolen from).  stage_branches in {8, 16, 32}.
+// XCD; exhausted queues are stolen from).  stage_branches in {8, 16, 32};
+// tile_stripes in {64, 128, 256}: a tile is kBandI samples x tile_stripes
+// stripes, and item (r, t) is tile t of table r with its i-block fastest.
 hipError_t band_persistent_f32(const float* E, const BatchTable* tabs, const int2* items,
                                const int64_t* qbeg, const int64_t* qend, unsigned* counters,
                                int64_t kc, int first, float* acc, int stage_branches,
-                               int n_blocks, hipStream_t st);
+                               int tile_stripes, int n_blocks, hipStream_t st);
+// Resident blocks per CU of that kernel (0 for an unknown configuration).
+int band_persistent_max_blocks(int stage_branches, int tile_stripes);
 // Zero n unsigned counters (a kernel, so that graph replays stay valid).
 hipError_t zero_u32(unsigned* p, int64_t n, hipStream_t st);
 

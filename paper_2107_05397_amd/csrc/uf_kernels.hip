@@ -933,13 +933,13 @@ __global__ __launch_bounds__(256) void k_embed_batch_f32(
 // items from per-XCD queues (block b runs on XCD b mod 8 and drains queue
 // b mod 8 first, then steals from the others).  Every queue is finite, so
 // every block exits once all queues are exhausted.
-template <int KS>
+template <int KS, int MS>
 __global__ __launch_bounds__(256) void k_band_persistent_f32(
     const float* __restrict__ E, const BatchTable* __restrict__ tabs,
     const int2* __restrict__ items, const int64_t* __restrict__ qbeg,
     const int64_t* __restrict__ qend, unsigned* __restrict__ counters, int64_t kc, int first,
     float* __restrict__ acc) {
-    __shared__ __attribute__((aligned(16))) BandLds<float, KS> L;
+    __shared__ __attribute__((aligned(16))) BandLds<float, KS, MS> L;
     __shared__ int64_t next_item;
     const int xcd = int(blockIdx.x & 7);
     for (int q = 0; q < 8; ++q) {
@@ -954,9 +954,9 @@ __global__ __launch_bounds__(256) void k_band_persistent_f32(
             const int2 it = items[item];
             const BatchTable t = tabs[it.x];
             const int64_t i0 = (int64_t(it.y) % t.n_iblk) * kBandI;
-            const int64_t s0 = (int64_t(it.y) / t.n_iblk) * kBandS;
-            band_tile<float, true, KS>(L, E + t.e_off, nullptr, kc, t.n, 0, t.n / 2, i0, s0,
-                                       first, acc + t.acc_off);
+            const int64_t s0 = (int64_t(it.y) / t.n_iblk) * (16 * MS);
+            band_tile<float, true, KS, MS>(L, E + t.e_off, nullptr, kc, t.n, 0, t.n / 2, i0, s0,
+                                           first, acc + t.acc_off);
         }
     }
 }
@@ -1124,27 +1124,42 @@ hipError_t embed_batch_f32(const uf_embedding& e, const BatchTable* tabs, const 
     return hipGetLastError();
 }
 
+// the persistent kernel for (branches per stage, stripes per tile)
+template <int KS, int MS>
+static const void* persistent_fn() {
+    return reinterpret_cast<const void*>(&k_band_persistent_f32<KS, MS>);
+}
+static const void* persistent_kernel(int stage_branches, int tile_stripes) {
+#define UF_PK(KS_)                                                           \
+    if (stage_branches == KS_) {                                             \
+        if (tile_stripes == 64) return persistent_fn<KS_, 4>();              \
+        if (tile_stripes == 128) return persistent_fn<KS_, 8>();             \
+        if (tile_stripes == 256) return persistent_fn<KS_, 16>();            \
+    }
+    UF_PK(8)
+    UF_PK(16)
+    UF_PK(32)
+#undef UF_PK
+    return nullptr;
+}
+
+int band_persistent_max_blocks(int stage_branches, int tile_stripes) {
+    const void* fn = persistent_kernel(stage_branches, tile_stripes);
+    if (!fn) return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, 256, 0) != hipSuccess) return 0;
+    return blocks;
+}
+
 hipError_t band_persistent_f32(const float* E, const BatchTable* tabs, const int2* items,
                                const int64_t* qbeg, const int64_t* qend, unsigned* counters,
                                int64_t kc, int first, float* acc, int stage_branches,
-                               int n_blocks, hipStream_t st) {
-    const dim3 grid{unsigned(n_blocks), 1u, 1u};
-    switch (stage_branches) {
-        case 8:
-            hipLaunchKernelGGL(k_band_persistent_f32<8>, grid, dim3(256), 0, st, E, tabs, items,
-                               qbeg, qend, counters, kc, first, acc);
-            break;
-        case 16:
-            hipLaunchKernelGGL(k_band_persistent_f32<16>, grid, dim3(256), 0, st, E, tabs, items,
-                               qbeg, qend, counters, kc, first, acc);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_band_persistent_f32<32>, grid, dim3(256), 0, st, E, tabs, items,
-                               qbeg, qend, counters, kc, first, acc);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
+                               int tile_stripes, int n_blocks, hipStream_t st) {
+    const void* fn = persistent_kernel(stage_branches, tile_stripes);
+    if (!fn || n_blocks < 1) return hipErrorInvalidValue;
+    void* args[] = {&E, &tabs, &items, &qbeg, &qend, &counters, &kc, &first, &acc};
+    const hipError_t e = hipLaunchKernel(fn, dim3(unsigned(n_blocks)), dim3(256), args, 0, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

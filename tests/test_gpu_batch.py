@@ -86,13 +86,26 @@ def test_graph_replay_eager_and_autotune_identical(batch, tmp_path):
     text = open(path).read()
     data = json.loads(text)
     entry = next(iter(data["gfx950"]["weighted_normalized_fp32"].values()))
-    assert entry["stage_branches"] in (8, 16, 32) and entry["wgs_per_cu"] in (1, 2, 3)
-    assert b.config()[:2] == (entry["stage_branches"], entry["wgs_per_cu"])
-    for ks, w in ((8, 2), (8, 3), (16, 2), (32, 1)):
-        b.set_config(ks, w)
-        got = b.run(use_graph=True)
-        torch.cuda.synchronize()
-        assert all(torch.equal(a, c) for a, c in zip(ref, got)), (ks, w)
+    assert entry["stage_branches"] in (8, 16, 32) and 1 <= entry["wgs_per_cu"] <= 5
+    assert entry["tile_stripes"] in (64, 128, 256)
+    cfg = b.config()
+    assert (cfg[0], cfg[1], cfg[3]) == (entry["stage_branches"], entry["wgs_per_cu"],
+                                        entry["tile_stripes"])
+    # every tile size and stage size (each kernel), at one and two blocks per CU
+    for ts in (64, 128, 256):
+        for ks in (8, 16, 32):
+            for w in (1, 2):
+                if ks == 32 and w == 2:
+                    continue   # one block per CU only (LDS)
+                b.set_config(ks, w, ts)
+                got = b.run(use_graph=True)
+                torch.cuda.synchronize()
+                assert all(torch.equal(a, c) for a, c in zip(ref, got)), (ks, w, ts)
+    import paper_2107_05397_amd as uf
+    with pytest.raises(uf.UFError):
+        b.set_config(32, 2, 128)   # two blocks of 96 KiB do not fit in 160 KiB of LDS
+    with pytest.raises(uf.UFError):
+        b.set_config(16, 2, 96)    # no such tile
 
 
 def test_chunked_batch_identical(batch):
@@ -120,7 +133,17 @@ def test_tune_cache_is_read_back(batch, tmp_path):
     path.write_text(json.dumps({"gfx950": {"weighted_normalized_fp32": {
         f"n_bucket_{bucket}": {"stage_branches": 8, "wgs_per_cu": 3, "ms": 1.0}}}}))
     b2 = uf.Batch(ut, uts, tune_cache=str(path))
-    assert b2.config()[:2] == (8, 3)
+    assert b2.config()[:2] == (8, 3) and b2.config()[3] == 128   # no tile entry: 128
+    path.write_text(json.dumps({"gfx950": {"weighted_normalized_fp32": {
+        f"n_bucket_{bucket}": {"stage_branches": 16, "wgs_per_cu": 1, "tile_stripes": 256,
+                               "ms": 1.0}}}}))
+    b3 = uf.Batch(ut, uts, tune_cache=str(path))
+    assert b3.config()[:2] == (16, 1) and b3.config()[3] == 256
+    ref = _copy(b.run(use_graph=True))
+    got = b3.run(use_graph=True)
+    import torch
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(ref, got))
 
 
 def test_split_mode_matches_single_split_calls(tmp_path):
@@ -169,3 +192,40 @@ def test_split_mode_matches_single_split_calls(tmp_path):
     for r, t in enumerate(tables):
         if t.n_samples >= 2:
             assert torch.max(torch.abs(dense[r] - ref[r])).item() <= 2e-4
+
+
+def test_c4_scale_tables_match_single_calls_and_oracle():
+    """Three rarefied tables of the batching workload's law at its scale (the
+    100,000-tip tree, 2,000-3,000 samples, depth 5,000): the batch equals the
+    single-table FP32 call bit for bit, at the default and at the smallest and
+    largest tile, and sampled pairs equal the FP64 oracle within 1e-4."""
+    import torch
+    import oracle
+    import paper_2107_05397_amd as uf
+    tree, tables = synth.batch_tables(n_tables=3, n_min=2000, n_max=3000, seed=104)
+    ut = uf.Tree(tree.parent, tree.length)
+    uts = [uf.Table(ut, t.indptr, t.tips, t.counts) for t in tables]
+    b = uf.Batch(ut, uts)
+    print("C4-scale tables", [t.n_samples for t in tables], "config", b.config(), flush=True)
+    ref = _copy(b.run(use_graph=True))
+    torch.cuda.synchronize()
+    for ts in (64, 256):
+        b.set_config(16, 1, ts)
+        got = b.run(use_graph=True)
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, c) for a, c in zip(ref, got)), ts
+    rng = np.random.default_rng(7)
+    for r, (t, tu) in enumerate(zip(tables, uts)):
+        n = t.n_samples
+        emb = uf.Embedding(ut, tu)
+        single, _, _ = uf.dm(emb, "weighted_normalized", "fp32", out_dtype=torch.float32)
+        torch.cuda.synchronize()
+        assert torch.equal(ref[r], single[: n * (n - 1) // 2]), r
+        ii = rng.choice(n, size=16, replace=False)
+        pairs = [(int(min(a, c)), int(max(a, c))) for a, c in zip(ii[:8], ii[8:])]
+        want = oracle.dm_pairs(tree, t, pairs, "weighted_normalized")
+        idx = torch.tensor([uf.condensed_index(n, a, c) for a, c in pairs], device="cuda")
+        got = ref[r][idx].double().cpu().numpy()
+        err = np.abs(got - want)
+        print(f"[C4-scale table {r} n={n}] sampled max|err| {err.max():.3e}", flush=True)
+        assert err.max() <= 1e-4
