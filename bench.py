@@ -71,9 +71,10 @@ def measured_traffic(kernel: str, workload: str):
         parts = line.split()
         if len(parts) >= 6 and parts[0] == "traffic" and parts[1] == kernel and \
                 parts[2] == f"workload={workload}" and parts[3] == f"sha={want}":
-            return {"fetch_bytes_per_launch": float(parts[4].split("=")[1]),
-                    "write_bytes_per_launch": float(parts[5].split("=")[1]),
-                    "source": "profiles/hbm_traffic.md"}
+            fetch = float(parts[4].split("=")[1])
+            write = float(parts[5].split("=")[1])
+            return {"bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
+                    "write_bytes_per_launch": write, "source": "profiles/hbm_traffic.md"}
     return None
 
 
