@@ -362,6 +362,21 @@ uf_status uf_mlp_backward(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const in
 uf_status uf_mlp_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const int32_t* pair_a,
                            const int32_t* pair_b, const float* target, int64_t n_pairs,
                            float rel_floor, float* loss, void* hip_stream);
+/* Ranking loss over n_triples triples (anchor a, near p, far n; device index
+ * arrays into x) with exact distances d_near = d(a, p), d_far = d(a, n)
+ * (device FP32).  With e_p = ||z_a - z_p||, e_n = ||z_a - z_n||:
+ *   loss = mean_t [ (e_p - d_p)^2 + (e_n - d_n)^2
+ *                   + rank_weight * tau * softplus((e_p - e_n) / tau) ]
+ * -- both pairs' distance regression plus a smooth hinge (tau -> 0 gives
+ * rank_weight * max(e_p - e_n, 0)) that asks the encoder to keep the order of
+ * exact distances, which is what a nearest-neighbour search of the encoded
+ * reference set needs.  3 * n_triples <= max_rows.  The gradients are left in
+ * the MLP as for uf_mlp_loss_grad; loss (device, 1 float) receives the mean.
+ * Errors: UF_ERR_ARG (NULL, sizes, rank_weight < 0, tau <= 0), UF_ERR_DEVICE. */
+uf_status uf_mlp_triplet_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx,
+                                   const int32_t* anchor, const int32_t* near, const int32_t* far,
+                                   const float* d_near, const float* d_far, int64_t n_triples,
+                                   float rank_weight, float tau, float* loss, void* hip_stream);
 /* One Adam step (bias-corrected, step >= 1) on every parameter, with
  * decoupled weight decay on the weight matrices (weight_decay = 0: plain
  * Adam). */

@@ -95,6 +95,70 @@ def loss_and_grads(x, params, pair_a, pair_b, target, bf16_storage=False, rel_fl
     return loss, grads
 
 
+def _backward(dz, hs, params, bf16_storage=False, skip=None):
+    """Parameter gradients [(dW_l, db_l)] (+ (dS, None) if skip) for the output
+    gradient dz of rows whose activations are hs (FP64)."""
+    rnd = bf16 if bf16_storage else (lambda t: t)
+    grads: List[Tuple[np.ndarray, np.ndarray]] = [None] * len(params)
+    if skip is not None:
+        grads.append((dz.T @ hs[0], None))
+    g = dz
+    for l in range(len(params) - 1, -1, -1):
+        w = np.asarray(params[l][0], np.float64)
+        grads[l] = (g.T @ hs[l], g.sum(axis=0))
+        if l > 0:
+            g = rnd((g @ w) * (hs[l] > 0))
+    return grads
+
+
+def softplus(x):
+    """log(1 + e^x), without overflow."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def sigmoid(x):
+    x = np.asarray(x, dtype=np.float64)
+    e = np.exp(-np.abs(x))
+    return np.where(x >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
+
+
+def triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
+                           bf16_storage=False, skip=None):
+    """Mean over triples (a, p, n) of the distance-regression terms of both pairs
+    plus a ranking term that asks the encoder to place p closer to a than n:
+
+        e_p = ||z_a - z_p||,  e_n = ||z_a - z_n||
+        L = mean_t [ (e_p - d_p)^2 + (e_n - d_n)^2 + lam * tau * softplus((e_p - e_n) / tau) ]
+
+    (lam = rank_weight, tau = temperature).  Returns (loss, grads) as
+    loss_and_grads does; rows are anchors, then near ends, then far ends."""
+    rnd = bf16 if bf16_storage else (lambda t: t)
+    rows = np.concatenate([anchor, near, far])
+    hs, z = forward(np.asarray(x)[rows], params, bf16_storage, skip)
+    T = len(anchor)
+    za, zp, zn = z[:T], z[T:2 * T], z[2 * T:]
+    dap, dan = za - zp, za - zn
+    ep = np.sqrt((dap * dap).sum(axis=1))
+    en = np.sqrt((dan * dan).sum(axis=1))
+    tp, tn = np.asarray(d_near, np.float64), np.asarray(d_far, np.float64)
+    s = (ep - en) / tau
+    loss = float(np.mean((ep - tp) ** 2 + (en - tn) ** 2 + rank_weight * tau * softplus(s)))
+    # dL/de_p and dL/de_n of each triple (divided by T for the mean)
+    gp = (2.0 * (ep - tp) + rank_weight * sigmoid(s)) / T
+    gn = (2.0 * (en - tn) - rank_weight * sigmoid(s)) / T
+    cp = np.where(ep > 0, gp / np.where(ep > 0, ep, 1.0), 0.0)[:, None] * dap
+    cn = np.where(en > 0, gn / np.where(en > 0, en, 1.0), 0.0)[:, None] * dan
+    dz = rnd(np.concatenate([cp + cn, -cp, -cn]))
+    return loss, _backward(dz, hs, params, bf16_storage, skip)
+
+
+def triplet_loss_only(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
+                      skip=None) -> float:
+    return triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
+                                  skip=skip)[0]
+
+
 def loss_only(x, params, pair_a, pair_b, target, rel_floor=0.0) -> float:
     return loss_and_grads(x, params, pair_a, pair_b, target, rel_floor=rel_floor)[0]
 

@@ -111,6 +111,8 @@ _SIGS = {
     "uf_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "uf_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, ctypes.c_float, _vp,
                                         _vp]),
+    "uf_mlp_triplet_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64,
+                                                ctypes.c_float, ctypes.c_float, _vp, _vp]),
     "uf_mlp_adam": (ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_float, _i64, _vp]),
     "uf_free_mlp": (None, [_vp]),
@@ -595,6 +597,20 @@ class MLP(_Handle):
         _check(lib().uf_mlp_loss_grad(self._h, _tptr(x), x.stride(0), _tptr(pair_a), _tptr(pair_b),
                                       _tptr(target), int(pair_a.numel()), float(rel_floor),
                                       _tptr(loss), _stream_ptr(stream)))
+        return loss
+
+    def triplet_loss_grad(self, x, anchor, near, far, d_near, d_far, rank_weight: float = 1.0,
+                          tau: float = 0.01, loss=None, stream=None):
+        """Ranking loss over (anchor, near, far) triples (device int32 index tensors
+        into x, device FP32 exact distances d(a, near), d(a, far)); gradients stay in
+        the MLP."""
+        import torch
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().uf_mlp_triplet_loss_grad(self._h, _tptr(x), x.stride(0), _tptr(anchor),
+                                              _tptr(near), _tptr(far), _tptr(d_near), _tptr(d_far),
+                                              int(anchor.numel()), float(rank_weight), float(tau),
+                                              _tptr(loss), _stream_ptr(stream)))
         return loss
 
     def backward(self, x, dz, rows=None, stream=None):

@@ -411,6 +411,54 @@ __global__ __launch_bounds__(256) void k_pairloss(const float* __restrict__ Z, i
     if (lane == 0) loss[p] = r * r;
 }
 
+// Ranking loss, one wave per triple; Z rows [0, T) are the anchors, [T, 2T) the
+// near ends, [2T, 3T) the far ends.  Per triple, with e_p = ||z_a - z_p|| and
+// e_n = ||z_a - z_n||:
+//   L = (e_p - d_p)^2 + (e_n - d_n)^2 + lam * tau * softplus((e_p - e_n) / tau)
+// and dZ receives dL/dz / T for the mean over triples.
+__global__ __launch_bounds__(256) void k_tripletloss(const float* __restrict__ Z, int64_t T, int D,
+                                                     const float* __restrict__ d_near,
+                                                     const float* __restrict__ d_far, float lam,
+                                                     float tau, uint16_t* __restrict__ dZ,
+                                                     float* __restrict__ loss) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (t >= T) return;
+    const float* za = Z + t * D;
+    const float* zp = Z + (T + t) * D;
+    const float* zn = Z + (2 * T + t) * D;
+    float sp = 0.0f, sn = 0.0f;
+    for (int d = lane; d < D; d += 64) {
+        const float a = za[d];
+        const float dp = a - zp[d], dn = a - zn[d];
+        sp = fmaf(dp, dp, sp);
+        sn = fmaf(dn, dn, sn);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sp += __shfl_xor(sp, off, 64);
+        sn += __shfl_xor(sn, off, 64);
+    }
+    const float ep = sqrtf(sp), en = sqrtf(sn);
+    const float s = (ep - en) / tau;
+    const float e = expf(-fabsf(s));                           // in (0, 1]
+    const float sig = s >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+    const float rp = ep - d_near[t], rn = en - d_far[t];
+    const float inv_t = 1.0f / float(T);
+    const float gp = (2.0f * rp + lam * sig) * inv_t;
+    const float gn = (2.0f * rn - lam * sig) * inv_t;
+    const float cp = ep > 0.0f ? gp / ep : 0.0f;
+    const float cn = en > 0.0f ? gn / en : 0.0f;
+    for (int d = lane; d < D; d += 64) {
+        const float a = za[d];
+        const float vp = cp * (a - zp[d]), vn = cn * (a - zn[d]);
+        dZ[t * D + d] = f2bf(vp + vn);
+        dZ[(T + t) * D + d] = f2bf(-vp);
+        dZ[(2 * T + t) * D + d] = f2bf(-vn);
+    }
+    if (lane == 0) loss[t] = rp * rp + rn * rn + lam * tau * (fmaxf(s, 0.0f) + log1pf(e));
+}
+
 __global__ __launch_bounds__(256) void k_mean(const float* __restrict__ x, int64_t n,
                                               float* __restrict__ out) {
     __shared__ double red[256];
@@ -818,6 +866,18 @@ hipError_t pairloss(const float* Z, int64_t P, int D, const float* target, float
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, loss_per_pair, P, loss_mean);
+    return hipGetLastError();
+}
+
+hipError_t tripletloss(const float* Z, int64_t T, int D, const float* d_near, const float* d_far,
+                       float lam, float tau, uint16_t* dZ, float* loss_per_triple,
+                       float* loss_mean, hipStream_t st) {
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tripletloss, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st, Z, T, D, d_near,
+                       d_far, lam, tau, dZ, loss_per_triple);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, loss_per_triple, T, loss_mean);
     return hipGetLastError();
 }
 

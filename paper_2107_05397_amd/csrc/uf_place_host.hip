@@ -396,6 +396,37 @@ uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int
     });
 }
 
+uf_status uf_mlp_triplet_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx,
+                                   const int32_t* anchor, const int32_t* near, const int32_t* far,
+                                   const float* d_near, const float* d_far, int64_t n_triples,
+                                   float rank_weight, float tau, float* loss, void* stream) {
+    return guarded([&]() -> uf_status {
+        if (!m || !x_bf16 || !anchor || !near || !far || !d_near || !d_far || !loss ||
+            n_triples < 1)
+            return fail(UF_ERR_ARG, "NULL argument or no triples");
+        if (3 * n_triples > m->max_rows) return fail(UF_ERR_ARG, "3 * n_triples exceeds max_rows");
+        if (ldx < m->dims[0] || ldx % 8 != 0) return fail(UF_ERR_ARG, "ldx must be >= d0 and a multiple of 8");
+        if (!(rank_weight >= 0.0f) || !(tau > 0.0f)) return fail(UF_ERR_ARG, "need rank_weight >= 0 and tau > 0");
+        int dev = 0;
+        uf_status st = check_device(&dev);
+        if (st != UF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const uint16_t* x = static_cast<const uint16_t*>(x_bf16);
+        const int64_t T = n_triples, R = 3 * T, L = m->L;
+        UF_HIP(hipMemcpyAsync(m->rows, anchor, size_t(T) * 4, hipMemcpyDeviceToDevice, s));
+        UF_HIP(hipMemcpyAsync(m->rows + T, near, size_t(T) * 4, hipMemcpyDeviceToDevice, s));
+        UF_HIP(hipMemcpyAsync(m->rows + 2 * T, far, size_t(T) * 4, hipMemcpyDeviceToDevice, s));
+        st = mlp_forward(m, x, ldx, m->rows, R, m->Z, s);
+        if (st != UF_OK) return st;
+        {
+            ufh::ProfGuard pl("encoder_loss", s);
+            UF_HIP(ufp::tripletloss(m->Z, T, int(m->dims[L]), d_near, d_far, rank_weight, tau, m->dZ,
+                                    m->loss_pp, loss, s));
+        }
+        return mlp_backward(m, x, ldx, m->rows, R, m->dZ, s);
+    });
+}
+
 uf_status uf_mlp_adam(uf_mlp* m, float lr, float beta1, float beta2, float eps,
                       float weight_decay, int64_t step, void* stream) {
     return guarded([&]() -> uf_status {

@@ -193,6 +193,53 @@ def test_mlp_loss_and_gradients_vs_oracle(with_skip, rel_floor):
         assert corr > 0.99
 
 
+@pytest.mark.parametrize("rank_weight,tau", [(0.0, 0.05), (2.0, 0.05), (5.0, 0.01)])
+@pytest.mark.parametrize("with_skip", [False, True])
+def test_triplet_loss_and_gradients_vs_oracle(with_skip, rank_weight, tau):
+    """The ranking loss: loss and every gradient vs the FP64 oracle at the
+    kernels' BF16 storage points (tolerances as for the pair loss).  With tau =
+    0.05 the ranking term's slope sigmoid((e_p - e_n) / tau) takes values across
+    (0, 1); with rank_weight 0 only the two regression terms remain."""
+    import torch
+    import paper_2107_05397_amd as uf
+    dims = (64, 32, 32, 32)
+    x, params, _, _, _ = _mlp_problem(seed=21, dims=dims)
+    rng = np.random.default_rng(22)
+    n, T = x.shape[0], 40
+    a = rng.integers(0, n, size=T).astype(np.int32)
+    p = ((a + rng.integers(1, n, size=T)) % n).astype(np.int32)
+    q = ((a + rng.integers(1, n, size=T)) % n).astype(np.int32)
+    dp = (rng.random(T) * 2.0).astype(np.float32)
+    dq = (rng.random(T) * 2.0).astype(np.float32)
+    skip = synth.bf16_grid(rng.normal(size=(dims[-1], dims[0])) * 0.05) if with_skip else None
+    mlp = uf.MLP(dims, max_rows=3 * T, params=params, skip=skip)
+    loss = mlp.triplet_loss_grad(_t(x, torch.bfloat16), _t(a, torch.int32), _t(p, torch.int32),
+                                 _t(q, torch.int32), _t(dp, torch.float32), _t(dq, torch.float32),
+                                 rank_weight=rank_weight, tau=tau)
+    torch.cuda.synchronize()
+    w_loss, w_grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, rank_weight, tau,
+                                                bf16_storage=True, skip=skip)
+    f_loss, f_grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, rank_weight, tau,
+                                                skip=skip)
+    assert float(loss.cpu()[0]) == pytest.approx(w_loss, rel=1e-3)
+    assert float(loss.cpu()[0]) == pytest.approx(f_loss, rel=2e-2)
+    layers = list(range(3)) + ([3] if with_skip else [])
+    for l in layers:
+        gw, gb = mlp.get(l, "grads")
+        pairs = [(gw, w_grads[l][0])] + ([(gb, w_grads[l][1])] if gb is not None else [])
+        for got, want in pairs:
+            scale = np.abs(want).max()
+            err = np.abs(got - want).max()
+            print(f"[triplet layer {l} skip={with_skip} lam={rank_weight}] grad max|err|={err:.3e} "
+                  f"scale={scale:.3e}")
+            assert err <= 2e-2 * scale + 1e-7
+        assert np.corrcoef(gw.ravel(), f_grads[l][0].ravel())[0, 1] > 0.99
+    with pytest.raises(uf.UFError):   # 3 * 41 rows do not fit max_rows = 120
+        mlp.triplet_loss_grad(_t(x, torch.bfloat16), *(_t(np.resize(v, 41), torch.int32)
+                                                       for v in (a, p, q)),
+                              *(_t(np.resize(v, 41), torch.float32) for v in (dp, dq)))
+
+
 @pytest.mark.parametrize("weight_decay", [0.0, 0.01])
 def test_adam_three_steps_vs_oracle(weight_decay):
     """Three Adam steps on every parameter (weights, biases, linear path): after each

@@ -276,3 +276,116 @@ def test_bf16_storage_matches_an_independent_cast_chain():
                 g = rb((g @ torch.tensor(params[l][0])) * (hs[l] > 0))
         if sk is not None:
             assert np.allclose((dz.T @ h0).numpy(), grads[-1][0], rtol=1e-10, atol=1e-13)
+
+
+def _triplets(seed=5, n=10, t=6):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, n, size=t)
+    p = (a + rng.integers(1, n, size=t)) % n
+    q = (a + rng.integers(1, n, size=t)) % n
+    return a, p, q, rng.random(t), rng.random(t)
+
+
+def test_softplus_and_sigmoid_match_scipy():
+    from scipy.special import expit
+    x = np.array([-800.0, -40.0, -1.5, -1e-9, 0.0, 1e-9, 2.0, 40.0, 800.0])
+    assert np.allclose(op.sigmoid(x), expit(x), rtol=1e-15, atol=0)
+    assert np.allclose(op.softplus(x), np.logaddexp(0.0, x), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("with_skip", [False, True])
+def test_triplet_gradients_match_finite_differences(with_skip):
+    x, params, _, _, _ = _problem(seed=11)
+    a, p, q, dp, dq = _triplets()
+    skip = np.random.default_rng(2).normal(size=(4, 16)) * 0.1 if with_skip else None
+    lam, tau = 2.0, 0.05
+    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip)
+    h = 1e-6
+    rng = np.random.default_rng(4)
+
+    def f(ps, sk):
+        return op.triplet_loss_only(x, ps, a, p, q, dp, dq, lam, tau, skip=sk)
+
+    for l, (w, b) in enumerate(params):
+        for _ in range(5):
+            i, j = rng.integers(w.shape[0]), rng.integers(w.shape[1])
+            wp = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wm = [(ww.copy(), bb.copy()) for ww, bb in params]
+            wp[l][0][i, j] += h
+            wm[l][0][i, j] -= h
+            fd = (f(wp, skip) - f(wm, skip)) / (2 * h)
+            assert grads[l][0][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+        i = rng.integers(b.shape[0])
+        bp = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bm = [(ww.copy(), bb.copy()) for ww, bb in params]
+        bp[l][1][i] += h
+        bm[l][1][i] -= h
+        fd = (f(bp, skip) - f(bm, skip)) / (2 * h)
+        assert grads[l][1][i] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+    if with_skip:
+        for _ in range(5):
+            i, j = rng.integers(skip.shape[0]), rng.integers(skip.shape[1])
+            sp, sm = skip.copy(), skip.copy()
+            sp[i, j] += h
+            sm[i, j] -= h
+            fd = (f(params, sp) - f(params, sm)) / (2 * h)
+            assert grads[-1][0][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+def test_triplet_loss_matches_torch_autograd():
+    x, params, _, _, _ = _problem(seed=13)
+    a, p, q, dp, dq = _triplets(seed=6)
+    skip = np.random.default_rng(8).normal(size=(4, 16)) * 0.1
+    lam, tau = 3.0, 0.02
+    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip)
+    tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for w, b in params]
+    ts = torch.tensor(skip, requires_grad=True)
+
+    def enc(rows):
+        h0 = torch.tensor(x[rows])
+        h = h0
+        for l, (w, b) in enumerate(tp):
+            h = h @ w.T + b
+            if l < len(tp) - 1:
+                h = torch.relu(h)
+        return h + h0 @ ts.T
+
+    za, zp, zq = enc(a), enc(p), enc(q)
+    ep = torch.linalg.vector_norm(za - zp, dim=1)
+    eq = torch.linalg.vector_norm(za - zq, dim=1)
+    tl = ((ep - torch.tensor(dp)) ** 2 + (eq - torch.tensor(dq)) ** 2 +
+          lam * tau * torch.nn.functional.softplus((ep - eq) / tau)).mean()
+    tl.backward()
+    assert float(tl) == pytest.approx(loss, rel=1e-12)
+    for l, (w, b) in enumerate(tp):
+        assert np.allclose(grads[l][0], w.grad.numpy(), rtol=1e-9, atol=1e-12)
+        assert np.allclose(grads[l][1], b.grad.numpy(), rtol=1e-9, atol=1e-12)
+    assert np.allclose(grads[-1][0], ts.grad.numpy(), rtol=1e-9, atol=1e-12)
+
+
+def test_triplet_without_ranking_is_twice_the_pair_loss():
+    """lam = 0 leaves the two regression terms: the pair loss over the 2T pairs
+    (a, p) and (a, n), times 2 (a mean over T triples of two terms each)."""
+    x, params, _, _, _ = _problem(seed=17)
+    a, p, q, dp, dq = _triplets(seed=9)
+    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, 0.0, 0.1)
+    l2, g2 = op.loss_and_grads(x, params, np.concatenate([a, a]), np.concatenate([p, q]),
+                               np.concatenate([dp, dq]))
+    assert loss == pytest.approx(2 * l2, rel=1e-12)
+    for (w, b), (w2, b2) in zip(grads, g2):
+        assert np.allclose(w, 2 * w2, rtol=1e-10, atol=1e-14)
+        assert np.allclose(b, 2 * b2, rtol=1e-10, atol=1e-14)
+
+
+def test_triplet_ranking_term_tends_to_the_hinge():
+    """tau softplus(s / tau) -> max(s, 0) as tau -> 0: the ranking term becomes
+    lam * max(e_p - e_n, 0)."""
+    x, params, _, _, _ = _problem(seed=19)
+    a, p, q, dp, dq = _triplets(seed=10)
+    base = op.triplet_loss_only(x, params, a, p, q, dp, dq, 0.0, 1.0)
+    _, z = op.forward(x, params)
+    ep = np.linalg.norm(z[a] - z[p], axis=1)
+    eq = np.linalg.norm(z[a] - z[q], axis=1)
+    hinge = np.mean(np.maximum(ep - eq, 0.0))
+    got = op.triplet_loss_only(x, params, a, p, q, dp, dq, 1.0, 1e-6) - base
+    assert got == pytest.approx(hinge, abs=1e-6)
