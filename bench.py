@@ -282,7 +282,9 @@ def bench_placement(args) -> int:
     import torch
     from paper_2107_05397_amd import placement
     torch.cuda.set_device(0)
-    res = placement.experiment(tree, ref, query, epochs=args.epochs, log=log)
+    res = placement.experiment(tree, ref, query, epochs=args.epochs, objective=args.objective,
+                               dist_weight=args.dist_weight, rank_weight=args.rank_weight,
+                               tau=args.tau, lr=args.lr, skip_init=args.skip_init, log=log)
     rec = {
         "metric": "placement queries/s (1 GPU) with recall@10 against exact UniFrac",
         "value": c["n_query"] / res["placement_s"], "unit": "queries/s", "n_gpus": 1,
@@ -292,6 +294,14 @@ def bench_placement(args) -> int:
         "config": {"workload": f"C5: {res['n_ref']} reference + {res['n_query']} query samples "
                                f"on the {tree.n_nodes}-node tree; encoder {res['dims']}",
                    "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_bf16 (encoder training GEMMs)",
+                     "achieved": res["train_gemm_tflops"], "peak": PEAK_BF16_MFMA / 1e12,
+                     "unit": "TFLOP/s",
+                     "frac": (res["train_gemm_tflops"] * 1e12 / PEAK_BF16_MFMA
+                              if res["train_gemm_tflops"] else None),
+                     "traffic": None,
+                     "note": "multiply-add flops of every training step's forward, data-gradient "
+                             "and weight-gradient GEMMs over the GEMMs' own event-timed duration"},
         "extra": res,
     }
     print(json.dumps(rec), flush=True)
@@ -304,7 +314,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3", "C4", "C5"])
-    ap.add_argument("--epochs", type=int, default=5, help="C5: training epochs")
+    ap.add_argument("--epochs", type=int, default=8, help="C5: training epochs")
+    ap.add_argument("--objective", default="triplets", choices=["triplets", "pairs"],
+                    help="C5: ranking loss over triples, or distance regression over pairs")
+    ap.add_argument("--dist-weight", type=float, default=1.0, help="C5: regression weight")
+    ap.add_argument("--rank-weight", type=float, default=30.0, help="C5: ranking weight")
+    ap.add_argument("--tau", type=float, default=0.01, help="C5: ranking temperature")
+    ap.add_argument("--lr", type=float, default=1e-4, help="C5: Adam learning rate")
+    ap.add_argument("--skip-init", default="pca", choices=["pca", "gaussian"],
+                    help="C5: start of the encoder's linear path")
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
     ap.add_argument("--tune-cache", default=None, help="C4: autotuner cache path")
     ap.add_argument("--samples", type=int, default=None, help="override the sample count")

@@ -365,18 +365,19 @@ uf_status uf_mlp_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx, const i
 /* Ranking loss over n_triples triples (anchor a, near p, far n; device index
  * arrays into x) with exact distances d_near = d(a, p), d_far = d(a, n)
  * (device FP32).  With e_p = ||z_a - z_p||, e_n = ||z_a - z_n||:
- *   loss = mean_t [ (e_p - d_p)^2 + (e_n - d_n)^2
+ *   loss = mean_t [ dist_weight * ((e_p - d_p)^2 + (e_n - d_n)^2)
  *                   + rank_weight * tau * softplus((e_p - e_n) / tau) ]
  * -- both pairs' distance regression plus a smooth hinge (tau -> 0 gives
  * rank_weight * max(e_p - e_n, 0)) that asks the encoder to keep the order of
  * exact distances, which is what a nearest-neighbour search of the encoded
  * reference set needs.  3 * n_triples <= max_rows.  The gradients are left in
  * the MLP as for uf_mlp_loss_grad; loss (device, 1 float) receives the mean.
- * Errors: UF_ERR_ARG (NULL, sizes, rank_weight < 0, tau <= 0), UF_ERR_DEVICE. */
+ * Errors: UF_ERR_ARG (NULL, sizes, a negative weight, tau <= 0), UF_ERR_DEVICE. */
 uf_status uf_mlp_triplet_loss_grad(uf_mlp* mlp, const void* x_bf16, int64_t ldx,
                                    const int32_t* anchor, const int32_t* near, const int32_t* far,
                                    const float* d_near, const float* d_far, int64_t n_triples,
-                                   float rank_weight, float tau, float* loss, void* hip_stream);
+                                   float dist_weight, float rank_weight, float tau, float* loss,
+                                   void* hip_stream);
 /* One Adam step (bias-corrected, step >= 1) on every parameter, with
  * decoupled weight decay on the weight matrices (weight_decay = 0: plain
  * Adam). */
@@ -464,6 +465,31 @@ uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const do
                   int64_t dims, int64_t n_cols, int power_iters, const double* omega,
                   double* coords, double* eigvals, double* trace, void* ws, size_t ws_bytes,
                   void* stream);
+
+/* Principal directions of a data matrix, used to start the placement encoder's
+ * linear path at the best linear map of its output width (the covariance's top
+ * eigenvectors give the rank-k projection that keeps the most of the rows'
+ * pairwise Euclidean distances).  The same randomized subspace iteration as
+ * uf_pcoa, on C = Xc^T Xc / n with Xc = X minus its column means; C is never
+ * formed (C Q = Xc^T (Xc Q), two passes over X in FP64 arithmetic).
+ *
+ * x_bf16:     device BF16 [n][ldx], the first d columns used (e.g. the
+ *             projected reference set of uf_project).
+ * k, n_cols:  directions wanted and columns of the test matrix
+ *             (1 <= k <= n_cols <= min(160, d)).
+ * power_iters: 0..64 passes of Q = orth(C Q).
+ * omega:      device FP64 [d][n_cols] row major: the caller's i.i.d. standard
+ *             normal test matrix.
+ * basis:      device FP32 [k][d], written: orthonormal rows, by decreasing
+ *             eigenvalue (signs arbitrary; zero rows past the rank of Xc).
+ * eigvals:    host FP64 [k] or NULL: the Ritz values (variances along the rows).
+ * ws:         device workspace of uf_pca_workspace_size(n, d, n_cols) bytes.
+ * The call returns after the stream has drained.
+ * Errors: UF_ERR_ARG (NULL pointers, sizes), UF_ERR_WORKSPACE, UF_ERR_DEVICE. */
+uf_status uf_pca_workspace_size(int64_t n, int64_t d, int64_t n_cols, size_t* bytes);
+uf_status uf_pca_basis(const void* x_bf16, int64_t n, int64_t d, int64_t ldx, int64_t k,
+                       int64_t n_cols, int power_iters, const double* omega, float* basis,
+                       double* eigvals, void* ws, size_t ws_bytes, void* hip_stream);
 
 /* ---- Mantel test -------------------------------------------------------------- */
 

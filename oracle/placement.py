@@ -124,15 +124,17 @@ def sigmoid(x):
 
 
 def triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
-                           bf16_storage=False, skip=None):
+                           bf16_storage=False, skip=None, dist_weight=1.0):
     """Mean over triples (a, p, n) of the distance-regression terms of both pairs
     plus a ranking term that asks the encoder to place p closer to a than n:
 
         e_p = ||z_a - z_p||,  e_n = ||z_a - z_n||
-        L = mean_t [ (e_p - d_p)^2 + (e_n - d_n)^2 + lam * tau * softplus((e_p - e_n) / tau) ]
+        L = mean_t [ alpha ((e_p - d_p)^2 + (e_n - d_n)^2)
+                     + lam * tau * softplus((e_p - e_n) / tau) ]
 
-    (lam = rank_weight, tau = temperature).  Returns (loss, grads) as
-    loss_and_grads does; rows are anchors, then near ends, then far ends."""
+    (alpha = dist_weight, lam = rank_weight, tau = temperature).  Returns
+    (loss, grads) as loss_and_grads does; rows are anchors, then near ends, then
+    far ends."""
     rnd = bf16 if bf16_storage else (lambda t: t)
     rows = np.concatenate([anchor, near, far])
     hs, z = forward(np.asarray(x)[rows], params, bf16_storage, skip)
@@ -143,10 +145,11 @@ def triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_wei
     en = np.sqrt((dan * dan).sum(axis=1))
     tp, tn = np.asarray(d_near, np.float64), np.asarray(d_far, np.float64)
     s = (ep - en) / tau
-    loss = float(np.mean((ep - tp) ** 2 + (en - tn) ** 2 + rank_weight * tau * softplus(s)))
+    loss = float(np.mean(dist_weight * ((ep - tp) ** 2 + (en - tn) ** 2) +
+                         rank_weight * tau * softplus(s)))
     # dL/de_p and dL/de_n of each triple (divided by T for the mean)
-    gp = (2.0 * (ep - tp) + rank_weight * sigmoid(s)) / T
-    gn = (2.0 * (en - tn) - rank_weight * sigmoid(s)) / T
+    gp = (2.0 * dist_weight * (ep - tp) + rank_weight * sigmoid(s)) / T
+    gn = (2.0 * dist_weight * (en - tn) - rank_weight * sigmoid(s)) / T
     cp = np.where(ep > 0, gp / np.where(ep > 0, ep, 1.0), 0.0)[:, None] * dap
     cn = np.where(en > 0, gn / np.where(en > 0, en, 1.0), 0.0)[:, None] * dan
     dz = rnd(np.concatenate([cp + cn, -cp, -cn]))
@@ -154,9 +157,9 @@ def triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_wei
 
 
 def triplet_loss_only(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
-                      skip=None) -> float:
+                      skip=None, dist_weight=1.0) -> float:
     return triplet_loss_and_grads(x, params, anchor, near, far, d_near, d_far, rank_weight, tau,
-                                  skip=skip)[0]
+                                  skip=skip, dist_weight=dist_weight)[0]
 
 
 def loss_only(x, params, pair_a, pair_b, target, rel_floor=0.0) -> float:
@@ -170,6 +173,18 @@ def adam(param, grad, m, v, lr, b1, b2, eps, step, weight_decay=0.0):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return param - lr * (mh / (np.sqrt(vh) + eps) + weight_decay * param), m, v
+
+
+def pca_basis(x, k: int):
+    """Top-k principal directions of the rows of x: eigenvectors of the covariance
+    (1/n) (x - mean)^T (x - mean) with the k largest eigenvalues, returned as
+    (basis [k][d], eigenvalues [k]) in descending order (FP64)."""
+    x = np.asarray(x, dtype=np.float64)
+    xc = x - x.mean(axis=0, keepdims=True)
+    cov = xc.T @ xc / x.shape[0]
+    w, v = np.linalg.eigh(cov)
+    order = np.argsort(-w, kind="stable")[:k]
+    return v[:, order].T, w[order]
 
 
 def knn(zq: np.ndarray, zr: np.ndarray, k: int):

@@ -112,7 +112,8 @@ _SIGS = {
     "uf_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i64, ctypes.c_float, _vp,
                                         _vp]),
     "uf_mlp_triplet_loss_grad": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64,
-                                                ctypes.c_float, ctypes.c_float, _vp, _vp]),
+                                                ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                                _vp, _vp]),
     "uf_mlp_adam": (ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_float, _i64, _vp]),
     "uf_free_mlp": (None, [_vp]),
@@ -131,6 +132,9 @@ _SIGS = {
     "uf_pcoa_workspace_size": (ctypes.c_int, [_i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
     "uf_pcoa": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _i64, ctypes.c_int, _vp, _vp, _vp, _vp,
                                _vp, ctypes.c_size_t, _vp]),
+    "uf_pca_workspace_size": (ctypes.c_int, [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "uf_pca_basis": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _i64, ctypes.c_int, _vp, _vp,
+                                    _f64p, _vp, ctypes.c_size_t, _vp]),
     "uf_mantel_workspace_size": (ctypes.c_int, [_i64, ctypes.c_int, _i64,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "uf_mantel": (ctypes.c_int, [_vp, _vp, _i64, ctypes.c_int, _vp, _i64, ctypes.c_int, _vp, _vp,
@@ -600,7 +604,7 @@ class MLP(_Handle):
         return loss
 
     def triplet_loss_grad(self, x, anchor, near, far, d_near, d_far, rank_weight: float = 1.0,
-                          tau: float = 0.01, loss=None, stream=None):
+                          tau: float = 0.01, dist_weight: float = 1.0, loss=None, stream=None):
         """Ranking loss over (anchor, near, far) triples (device int32 index tensors
         into x, device FP32 exact distances d(a, near), d(a, far)); gradients stay in
         the MLP."""
@@ -609,8 +613,9 @@ class MLP(_Handle):
             loss = torch.empty(1, dtype=torch.float32, device="cuda")
         _check(lib().uf_mlp_triplet_loss_grad(self._h, _tptr(x), x.stride(0), _tptr(anchor),
                                               _tptr(near), _tptr(far), _tptr(d_near), _tptr(d_far),
-                                              int(anchor.numel()), float(rank_weight), float(tau),
-                                              _tptr(loss), _stream_ptr(stream)))
+                                              int(anchor.numel()), float(dist_weight),
+                                              float(rank_weight), float(tau), _tptr(loss),
+                                              _stream_ptr(stream)))
         return loss
 
     def backward(self, x, dz, rows=None, stream=None):
@@ -748,6 +753,28 @@ def pcoa(dm, n: int, dims: int, omega, power_iters: int = 3, row_means=None, gra
 
 MANTEL_METHOD = {"pearson": 0, "spearman": 1}
 ALTERNATIVE = {"two-sided": 0, "greater": 1, "less": 2}
+
+
+def pca_basis(x, k: int, omega, power_iters: int = 3, d: Optional[int] = None, workspace=None,
+              stream=None):
+    """Top-k principal directions of the rows of x (device BF16 [n][ldx], first d
+    columns): (basis device FP32 [k][d], eigenvalues numpy [k]).  omega: device
+    FP64 [d][n_cols] standard normal test matrix."""
+    import torch
+    n, ldx = int(x.shape[0]), int(x.stride(0))
+    d = int(d if d is not None else x.shape[1])
+    c = int(omega.shape[1])
+    if omega.dtype != torch.float64 or not omega.is_contiguous() or int(omega.shape[0]) != d:
+        raise UFError(1, "omega must be a contiguous float64 [d][n_cols] tensor")
+    nb = ctypes.c_size_t(0)
+    _check(lib().uf_pca_workspace_size(n, d, c, ctypes.byref(nb)))
+    ws = _workspace(int(nb.value), workspace)
+    basis = torch.empty((k, d), dtype=torch.float32, device="cuda")
+    vals = np.zeros(k, dtype=np.float64)
+    _check(lib().uf_pca_basis(_tptr(x), n, d, ldx, int(k), c, int(power_iters), _tptr(omega),
+                              _tptr(basis), vals.ctypes.data_as(_f64p), _tptr(ws),
+                              ws.numel() * ws.element_size(), _stream_ptr(stream)))
+    return basis, vals
 
 
 def mantel(x, y, n: int, method: str = "pearson", perms=None, alternative: str = "two-sided",

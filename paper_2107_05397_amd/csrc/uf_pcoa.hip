@@ -334,6 +334,152 @@ Plan make_plan(int64_t n, int cols) {
     return p;
 }
 
+// ------------------------------------------------------------------ PCA basis
+// Principal directions of a BF16 data matrix X [n][d] (row stride ldx): the
+// same randomized subspace iteration, on the covariance C = Xc^T Xc / n with
+// Xc = X - column means.  C is never formed: C Q = Xc^T (Xc Q).
+constexpr int kPcaMaxCols = 160;   // columns of the test matrix
+constexpr int kPcaT = 64;          // rows and columns of an X tile
+constexpr int kPcaSplits = 8;      // row ranges of the X^T Y kernel
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// mu[j] = (1/n) sum_i X[i][j] (FP64, fixed order)
+__global__ __launch_bounds__(256) void k_pca_mean(const uint16_t* __restrict__ X, int64_t ldx,
+                                                  int64_t n, int64_t d, double* __restrict__ mu) {
+    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= d) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += double(bf16_to_f32(X[i * ldx + j]));
+    mu[j] = s / double(n);
+}
+
+// Y[i][c] = sum_j (X[i][j] - mu[j]) Q[j][c] for a block of 64 rows.  Thread t
+// owns row t/4 and columns t%4 + 4m; tiles of 64 columns of X (centred, FP32)
+// and the matching 64 rows of Q (FP64) pass through LDS.
+__global__ __launch_bounds__(256) void k_pca_xq(const uint16_t* __restrict__ X, int64_t ldx,
+                                                int64_t n, int64_t d, const double* __restrict__ mu,
+                                                const double* __restrict__ Q, int c,
+                                                double* __restrict__ Y) {
+    __shared__ float xs[kPcaT][kPcaT + 1];
+    __shared__ double qs[kPcaT][kPcaMaxCols];
+    const int t = threadIdx.x, r = t >> 2, g = t & 3;
+    const int64_t i0 = int64_t(blockIdx.x) * kPcaT;
+    constexpr int kM = kPcaMaxCols / 4;
+    double acc[kM];
+#pragma unroll
+    for (int m = 0; m < kM; ++m) acc[m] = 0.0;
+    for (int64_t j0 = 0; j0 < d; j0 += kPcaT) {
+        for (int e = t; e < kPcaT * kPcaT; e += 256) {
+            const int rr = e / kPcaT, jj = e % kPcaT;
+            const int64_t i = i0 + rr, j = j0 + jj;
+            xs[rr][jj] = (i < n && j < d) ? float(double(bf16_to_f32(X[i * ldx + j])) - mu[j]) : 0.0f;
+        }
+        for (int e = t; e < kPcaT * c; e += 256) {
+            const int jj = e / c, cc = e % c;
+            const int64_t j = j0 + jj;
+            qs[jj][cc] = j < d ? Q[j * c + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < kPcaT; ++jj) {
+            const double xv = xs[r][jj];
+#pragma unroll
+            for (int m = 0; m < kM; ++m)
+                if (g + 4 * m < c) acc[m] = fma(xv, qs[jj][g + 4 * m], acc[m]);
+        }
+        __syncthreads();
+    }
+    const int64_t i = i0 + r;
+    if (i >= n) return;
+#pragma unroll
+    for (int m = 0; m < kM; ++m)
+        if (g + 4 * m < c) Y[i * c + g + 4 * m] = acc[m];
+}
+
+// Zp[s][j][c] = sum over rows i of range s of (X[i][j] - mu[j]) Y[i][c], for a
+// block of 64 columns j; thread t owns column t/4 and outputs t%4 + 4m.
+__global__ __launch_bounds__(256) void k_pca_xty(const uint16_t* __restrict__ X, int64_t ldx,
+                                                 int64_t n, int64_t d, const double* __restrict__ mu,
+                                                 const double* __restrict__ Y, int c,
+                                                 double* __restrict__ Zp) {
+    __shared__ float xs[kPcaT][kPcaT + 1];     // [row i][column j]
+    __shared__ double ys[kPcaT][kPcaMaxCols];
+    const int t = threadIdx.x, jl = t >> 2, g = t & 3;
+    const int64_t j0 = int64_t(blockIdx.x) * kPcaT;
+    const int64_t per = (n + kPcaSplits - 1) / kPcaSplits;
+    const int64_t ib = int64_t(blockIdx.y) * per, ie = min(n, ib + per);
+    constexpr int kM = kPcaMaxCols / 4;
+    double acc[kM];
+#pragma unroll
+    for (int m = 0; m < kM; ++m) acc[m] = 0.0;
+    for (int64_t r0 = ib; r0 < ie; r0 += kPcaT) {
+        for (int e = t; e < kPcaT * kPcaT; e += 256) {
+            const int rr = e / kPcaT, jj = e % kPcaT;
+            const int64_t i = r0 + rr, j = j0 + jj;
+            xs[rr][jj] = (i < ie && j < d) ? float(double(bf16_to_f32(X[i * ldx + j])) - mu[j]) : 0.0f;
+        }
+        for (int e = t; e < kPcaT * c; e += 256) {
+            const int rr = e / c, cc = e % c;
+            const int64_t i = r0 + rr;
+            ys[rr][cc] = i < ie ? Y[i * c + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < kPcaT; ++rr) {
+            const double xv = xs[rr][jl];
+#pragma unroll
+            for (int m = 0; m < kM; ++m)
+                if (g + 4 * m < c) acc[m] = fma(xv, ys[rr][g + 4 * m], acc[m]);
+        }
+        __syncthreads();
+    }
+    const int64_t j = j0 + jl;
+    if (j >= d) return;
+    double* out = Zp + int64_t(blockIdx.y) * d * c;
+#pragma unroll
+    for (int m = 0; m < kM; ++m)
+        if (g + 4 * m < c) out[j * c + g + 4 * m] = acc[m];
+}
+
+// Z = sum over the row ranges of Zp, in range order
+__global__ __launch_bounds__(256) void k_pca_sum(const double* __restrict__ Zp, int64_t count,
+                                                 double* __restrict__ Z) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= count) return;
+    double v = 0.0;
+    for (int s = 0; s < kPcaSplits; ++s) v += Zp[s * count + e];
+    Z[e] = v;
+}
+
+// out[r][j] = B[j][r] as FP32 (B: d x k FP64)
+__global__ __launch_bounds__(256) void k_pca_out(const double* __restrict__ B, int64_t d, int k,
+                                                 float* __restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= d * k) return;
+    const int64_t r = e / d, j = e % d;
+    out[e] = float(B[j * k + r]);
+}
+
+struct PcaPlan {
+    size_t off_mu = 0, off_y = 0, off_zp = 0, off_z = 0, off_q = 0, off_gp = 0, off_m = 0,
+           off_b = 0, total = 0;
+};
+
+PcaPlan make_pca_plan(int64_t n, int64_t d, int c) {
+    PcaPlan p;
+    size_t off = 0;
+    const int64_t rows = std::max(n, d);
+    p.off_mu = take(off, size_t(d) * 8);
+    p.off_y = take(off, size_t(n) * c * 8);
+    p.off_zp = take(off, size_t(kPcaSplits) * d * c * 8);
+    p.off_z = take(off, size_t(d) * c * 8);
+    p.off_q = take(off, size_t(d) * c * 8);
+    p.off_gp = take(off, size_t((rows + kGramRows - 1) / kGramRows) * c * c * 8);
+    p.off_m = take(off, size_t(c) * c * 8);
+    p.off_b = take(off, size_t(d) * c * 8);
+    p.total = off + 256;
+    return p;
+}
+
 }  // namespace
 }  // namespace ufq
 
@@ -544,6 +690,174 @@ uf_status uf_pcoa(const double* dm, int64_t n, const double* row_means, const do
         *trace = -double(n) * hg;
     }
     UFQ_HIP(hipStreamSynchronize(s));
+    return UF_OK;
+}
+
+
+uf_status uf_pca_workspace_size(int64_t n, int64_t d, int64_t n_cols, size_t* bytes) {
+    if (!bytes) return fail(UF_ERR_ARG, "bytes is NULL");
+    if (n < 2 || d < 1 || n_cols < 1 || n_cols > ufq::kPcaMaxCols || n_cols > d)
+        return fail(UF_ERR_ARG, "need n >= 2, d >= 1 and 1 <= n_cols <= min(160, d)");
+    *bytes = ufq::make_pca_plan(n, d, int(n_cols)).total;
+    return UF_OK;
+}
+
+uf_status uf_pca_basis(const void* x_bf16, int64_t n, int64_t d, int64_t ldx, int64_t k,
+                       int64_t n_cols, int power_iters, const double* omega, float* basis,
+                       double* eigvals, void* ws, size_t ws_bytes, void* stream) {
+    using namespace ufq;
+    if (!x_bf16 || !omega || !basis) return fail(UF_ERR_ARG, "NULL argument");
+    if (n < 2 || d < 1 || ldx < d) return fail(UF_ERR_ARG, "need n >= 2, d >= 1 and ldx >= d");
+    if (k < 1 || n_cols < k || n_cols > kPcaMaxCols || n_cols > d)
+        return fail(UF_ERR_ARG, "need 1 <= k <= n_cols <= min(160, d)");
+    if (power_iters < 0 || power_iters > 64) return fail(UF_ERR_ARG, "power_iters in [0, 64]");
+    if (n > (int64_t(1) << 31) || d > (int64_t(1) << 24)) return fail(UF_ERR_ARG, "matrix too large");
+    int dev = 0;
+    uf_status st = ufh::check_device(&dev);
+    if (st != UF_OK) return st;
+    const int c = int(n_cols);
+    const PcaPlan p = make_pca_plan(n, d, c);
+    if (!ws || ws_bytes < p.total) return fail(UF_ERR_WORKSPACE, "workspace missing or too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    const uint16_t* X = static_cast<const uint16_t*>(x_bf16);
+    double* mu = reinterpret_cast<double*>(base + p.off_mu);
+    double* Y = reinterpret_cast<double*>(base + p.off_y);
+    double* Zp = reinterpret_cast<double*>(base + p.off_zp);
+    double* Z = reinterpret_cast<double*>(base + p.off_z);
+    double* Q = reinterpret_cast<double*>(base + p.off_q);
+    double* Gp = reinterpret_cast<double*>(base + p.off_gp);
+    double* Md = reinterpret_cast<double*>(base + p.off_m);
+    double* B = reinterpret_cast<double*>(base + p.off_b);
+
+    hipLaunchKernelGGL(k_pca_mean, dim3(unsigned((d + 255) / 256)), dim3(256), 0, s, X, ldx, n, d, mu);
+    UFQ_HIP(hipGetLastError());
+    // Y = Xc Qin (n x cq)
+    auto xq = [&](const double* Qin, int cq) -> uf_status {
+        hipLaunchKernelGGL(k_pca_xq, dim3(unsigned((n + kPcaT - 1) / kPcaT)), dim3(256), 0, s, X, ldx,
+                           n, d, mu, Qin, cq, Y);
+        UFQ_HIP(hipGetLastError());
+        return UF_OK;
+    };
+    // Z = Xc^T Y (d x cq)
+    auto xty = [&](int cq) -> uf_status {
+        hipLaunchKernelGGL(k_pca_xty, dim3(unsigned((d + kPcaT - 1) / kPcaT), unsigned(kPcaSplits)),
+                           dim3(256), 0, s, X, ldx, n, d, mu, Y, cq, Zp);
+        UFQ_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_pca_sum, dim3(unsigned((d * cq + 255) / 256)), dim3(256), 0, s, Zp,
+                           d * cq, Z);
+        UFQ_HIP(hipGetLastError());
+        return UF_OK;
+    };
+    // host copy of the fixed-order sum of A^T A over `rows` rows (ca x ca)
+    auto gram = [&](const double* A, int ca, int64_t rows, std::vector<double>& G) -> uf_status {
+        const int64_t nbg = (rows + kGramRows - 1) / kGramRows;
+        hipLaunchKernelGGL(k_gram, dim3(unsigned(nbg)), dim3(256), 0, s, A, ca, A, ca, rows, Gp);
+        UFQ_HIP(hipGetLastError());
+        std::vector<double> part(size_t(nbg) * ca * ca);
+        UFQ_HIP(hipMemcpyAsync(part.data(), Gp, part.size() * 8, hipMemcpyDeviceToHost, s));
+        UFQ_HIP(hipStreamSynchronize(s));
+        G.assign(size_t(ca) * ca, 0.0);
+        for (int64_t b = 0; b < nbg; ++b)
+            for (size_t e = 0; e < G.size(); ++e) G[e] += part[size_t(b) * G.size() + e];
+        return UF_OK;
+    };
+    // SVQB of the d x cin matrix Ain into out (columns above the relative floor)
+    auto svqb = [&](const double* Ain, int cin, double* out, int* kept) -> uf_status {
+        std::vector<double> G, w, v;
+        uf_status e = gram(Ain, cin, d, G);
+        if (e != UF_OK) return e;
+        jacobi_eig(G, cin, w, v);
+        std::vector<int> order(static_cast<size_t>(cin));
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+        const double top = cin > 0 ? w[size_t(order[0])] : 0.0;
+        int kk = 0;
+        while (kk < cin && top > 0.0 && w[size_t(order[size_t(kk)])] > 1e-14 * top) ++kk;
+        *kept = kk;
+        if (kk == 0) return UF_OK;
+        std::vector<double> M(size_t(cin) * kk, 0.0);
+        for (int j = 0; j < kk; ++j) {
+            const int o = order[size_t(j)];
+            const double sc = 1.0 / std::sqrt(w[size_t(o)]);
+            for (int r = 0; r < cin; ++r) M[size_t(r) * kk + j] = v[size_t(r) * cin + o] * sc;
+        }
+        UFQ_HIP(hipMemcpyAsync(Md, M.data(), M.size() * 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_rightmul, dim3(unsigned((d * kk + 255) / 256)), dim3(256), 0, s, Ain, cin,
+                           d, Md, kk, out);
+        UFQ_HIP(hipGetLastError());
+        UFQ_HIP(hipStreamSynchronize(s));   // M is reused by the next call
+        return UF_OK;
+    };
+    // Q <- orthonormal basis of Z's columns (SVQB twice, through B as scratch)
+    auto orth = [&](int cin, int* kept) -> uf_status {
+        int k1 = 0;
+        uf_status e = svqb(Z, cin, B, &k1);
+        if (e != UF_OK || k1 == 0) {
+            *kept = k1;
+            return e;
+        }
+        return svqb(B, k1, Q, kept);
+    };
+
+    int kq = 0;
+    st = xq(omega, c);
+    if (st != UF_OK) return st;
+    st = xty(c);
+    if (st != UF_OK) return st;
+    st = orth(c, &kq);
+    if (st != UF_OK) return st;
+    for (int it = 0; it < power_iters && kq > 0; ++it) {
+        st = xq(Q, kq);
+        if (st != UF_OK) return st;
+        st = xty(kq);
+        if (st != UF_OK) return st;
+        st = orth(kq, &kq);
+        if (st != UF_OK) return st;
+    }
+    // Rayleigh-Ritz: H = (Xc Q)^T (Xc Q) = Q^T C Q n; its top eigenvectors W give
+    // the directions Q W and the eigenvalues of C
+    const int kk = int(std::min<int64_t>(k, kq));
+    std::vector<double> lam(size_t(k), 0.0);
+    std::vector<double> W(size_t(std::max(kq, 1)) * k, 0.0);
+    if (kq > 0) {
+        st = xq(Q, kq);
+        if (st != UF_OK) return st;
+        std::vector<double> H, w, v;
+        const int64_t nbg = (n + kGramRows - 1) / kGramRows;
+        hipLaunchKernelGGL(k_gram, dim3(unsigned(nbg)), dim3(256), 0, s, Y, kq, Y, kq, n, Gp);
+        UFQ_HIP(hipGetLastError());
+        {
+            std::vector<double> part(size_t(nbg) * kq * kq);
+            UFQ_HIP(hipMemcpyAsync(part.data(), Gp, part.size() * 8, hipMemcpyDeviceToHost, s));
+            UFQ_HIP(hipStreamSynchronize(s));
+            H.assign(size_t(kq) * kq, 0.0);
+            for (int64_t b = 0; b < nbg; ++b)
+                for (size_t e = 0; e < H.size(); ++e) H[e] += part[size_t(b) * H.size() + e];
+        }
+        jacobi_eig(H, kq, w, v);
+        std::vector<int> order(static_cast<size_t>(kq));
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+        for (int j = 0; j < kk; ++j) {
+            const int o = order[size_t(j)];
+            lam[size_t(j)] = w[size_t(o)] / double(n);
+            for (int r = 0; r < kq; ++r) W[size_t(r) * k + j] = v[size_t(r) * kq + o];
+        }
+    }
+    UFQ_HIP(hipMemcpyAsync(Md, W.data(), size_t(std::max(kq, 1)) * k * 8, hipMemcpyHostToDevice, s));
+    if (kq > 0) {
+        hipLaunchKernelGGL(k_rightmul, dim3(unsigned((d * k + 255) / 256)), dim3(256), 0, s, Q, kq, d,
+                           Md, int(k), B);
+        UFQ_HIP(hipGetLastError());
+    } else {
+        UFQ_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(B), 2 * d * k, s));
+    }
+    hipLaunchKernelGGL(k_pca_out, dim3(unsigned((d * k + 255) / 256)), dim3(256), 0, s, B, d, int(k),
+                       basis);
+    UFQ_HIP(hipGetLastError());
+    UFQ_HIP(hipStreamSynchronize(s));   // W goes out of scope
+    if (eigvals) std::memcpy(eigvals, lam.data(), size_t(k) * 8);
     return UF_OK;
 }
 

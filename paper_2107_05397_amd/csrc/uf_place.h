@@ -53,7 +53,7 @@ hipError_t pairloss(const float* Z, int64_t P, int D, const float* target, float
                     uint16_t* dZ, float* loss_per_pair, float* loss_mean, hipStream_t st);
 // Ranking loss over T triples (rows: anchors, near ends, far ends of Z [3T][D]).
 hipError_t tripletloss(const float* Z, int64_t T, int D, const float* d_near, const float* d_far,
-                       float lam, float tau, uint16_t* dZ, float* loss_per_triple,
+                       float alpha, float lam, float tau, uint16_t* dZ, float* loss_per_triple,
                        float* loss_mean, hipStream_t st);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                 float b2, float eps, float bc1, float bc2, float wd, uint16_t* pbf, hipStream_t st);

@@ -414,12 +414,13 @@ __global__ __launch_bounds__(256) void k_pairloss(const float* __restrict__ Z, i
 // Ranking loss, one wave per triple; Z rows [0, T) are the anchors, [T, 2T) the
 // near ends, [2T, 3T) the far ends.  Per triple, with e_p = ||z_a - z_p|| and
 // e_n = ||z_a - z_n||:
-//   L = (e_p - d_p)^2 + (e_n - d_n)^2 + lam * tau * softplus((e_p - e_n) / tau)
+//   L = alpha ((e_p - d_p)^2 + (e_n - d_n)^2) + lam * tau * softplus((e_p - e_n) / tau)
 // and dZ receives dL/dz / T for the mean over triples.
 __global__ __launch_bounds__(256) void k_tripletloss(const float* __restrict__ Z, int64_t T, int D,
                                                      const float* __restrict__ d_near,
-                                                     const float* __restrict__ d_far, float lam,
-                                                     float tau, uint16_t* __restrict__ dZ,
+                                                     const float* __restrict__ d_far, float alpha,
+                                                     float lam, float tau,
+                                                     uint16_t* __restrict__ dZ,
                                                      float* __restrict__ loss) {
     const int lane = threadIdx.x & 63;
     const int64_t t = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -445,8 +446,8 @@ __global__ __launch_bounds__(256) void k_tripletloss(const float* __restrict__ Z
     const float sig = s >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
     const float rp = ep - d_near[t], rn = en - d_far[t];
     const float inv_t = 1.0f / float(T);
-    const float gp = (2.0f * rp + lam * sig) * inv_t;
-    const float gn = (2.0f * rn - lam * sig) * inv_t;
+    const float gp = (2.0f * alpha * rp + lam * sig) * inv_t;
+    const float gn = (2.0f * alpha * rn - lam * sig) * inv_t;
     const float cp = ep > 0.0f ? gp / ep : 0.0f;
     const float cn = en > 0.0f ? gn / en : 0.0f;
     for (int d = lane; d < D; d += 64) {
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void k_tripletloss(const float* __restrict__ Z
         dZ[(T + t) * D + d] = f2bf(-vp);
         dZ[(2 * T + t) * D + d] = f2bf(-vn);
     }
-    if (lane == 0) loss[t] = rp * rp + rn * rn + lam * tau * (fmaxf(s, 0.0f) + log1pf(e));
+    if (lane == 0) loss[t] = alpha * (rp * rp + rn * rn) + lam * tau * (fmaxf(s, 0.0f) + log1pf(e));
 }
 
 __global__ __launch_bounds__(256) void k_mean(const float* __restrict__ x, int64_t n,
@@ -870,11 +871,11 @@ hipError_t pairloss(const float* Z, int64_t P, int D, const float* target, float
 }
 
 hipError_t tripletloss(const float* Z, int64_t T, int D, const float* d_near, const float* d_far,
-                       float lam, float tau, uint16_t* dZ, float* loss_per_triple,
+                       float alpha, float lam, float tau, uint16_t* dZ, float* loss_per_triple,
                        float* loss_mean, hipStream_t st) {
     if (T <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tripletloss, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st, Z, T, D, d_near,
-                       d_far, lam, tau, dZ, loss_per_triple);
+                       d_far, alpha, lam, tau, dZ, loss_per_triple);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, loss_per_triple, T, loss_mean);

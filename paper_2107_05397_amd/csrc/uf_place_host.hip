@@ -399,14 +399,16 @@ uf_status uf_mlp_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx, const int
 uf_status uf_mlp_triplet_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx,
                                    const int32_t* anchor, const int32_t* near, const int32_t* far,
                                    const float* d_near, const float* d_far, int64_t n_triples,
-                                   float rank_weight, float tau, float* loss, void* stream) {
+                                   float dist_weight, float rank_weight, float tau, float* loss,
+                                   void* stream) {
     return guarded([&]() -> uf_status {
         if (!m || !x_bf16 || !anchor || !near || !far || !d_near || !d_far || !loss ||
             n_triples < 1)
             return fail(UF_ERR_ARG, "NULL argument or no triples");
         if (3 * n_triples > m->max_rows) return fail(UF_ERR_ARG, "3 * n_triples exceeds max_rows");
         if (ldx < m->dims[0] || ldx % 8 != 0) return fail(UF_ERR_ARG, "ldx must be >= d0 and a multiple of 8");
-        if (!(rank_weight >= 0.0f) || !(tau > 0.0f)) return fail(UF_ERR_ARG, "need rank_weight >= 0 and tau > 0");
+        if (!(dist_weight >= 0.0f) || !(rank_weight >= 0.0f) || !(tau > 0.0f))
+            return fail(UF_ERR_ARG, "need dist_weight >= 0, rank_weight >= 0 and tau > 0");
         int dev = 0;
         uf_status st = check_device(&dev);
         if (st != UF_OK) return st;
@@ -420,8 +422,8 @@ uf_status uf_mlp_triplet_loss_grad(uf_mlp* m, const void* x_bf16, int64_t ldx,
         if (st != UF_OK) return st;
         {
             ufh::ProfGuard pl("encoder_loss", s);
-            UF_HIP(ufp::tripletloss(m->Z, T, int(m->dims[L]), d_near, d_far, rank_weight, tau, m->dZ,
-                                    m->loss_pp, loss, s));
+            UF_HIP(ufp::tripletloss(m->Z, T, int(m->dims[L]), d_near, d_far, dist_weight, rank_weight,
+                                    tau, m->dZ, m->loss_pp, loss, s));
         }
         return mlp_backward(m, x, ldx, m->rows, R, m->dZ, s);
     });

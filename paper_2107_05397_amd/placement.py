@@ -25,8 +25,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from . import (MLP, Sparse, gather_pairs, profile_enable, profile_read, profile_reset, rerank,
-               sqdist, topk_rows)
+from . import (MLP, Sparse, gather_pairs, pca_basis, profile_enable, profile_read, profile_reset,
+               rerank, sqdist, topk_rows)
 
 
 def train(x, pair_a: np.ndarray, pair_b: np.ndarray, target, dims: Sequence[int],
@@ -57,6 +57,43 @@ def train(x, pair_a: np.ndarray, pair_b: np.ndarray, target, dims: Sequence[int]
             pb = pb_all[sel].contiguous()
             tg = target[sel].contiguous()
             mlp.loss_grad(x, pa, pb, tg, loss=loss, rel_floor=rel_floor)
+            step += 1
+            mlp.adam(lr, step, weight_decay=weight_decay)
+            acc += loss
+            nb += 1
+        losses.append(float(acc.item()) / max(nb, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mean loss {losses[-1]:.3e}")
+    return mlp, losses
+
+
+def train_triplets(x, anchor: np.ndarray, near: np.ndarray, far: np.ndarray, d_near, d_far,
+                   dims: Sequence[int], init_params, epochs: int = 5, batch_triples: int = 4096,
+                   lr: float = 1e-3, rank_weight: float = 1.0, tau: float = 0.01,
+                   dist_weight: float = 0.0, seed: int = 0, skip=None, weight_decay: float = 0.0,
+                   log=None) -> Tuple[MLP, List[float]]:
+    """Train the encoder on (anchor, near, far) triples with the ranking loss
+    (uf_mlp_triplet_loss_grad) and Adam.  d_near, d_far: device FP32 exact
+    distances d(anchor, near), d(anchor, far).  Returns the MLP and the mean loss
+    of every epoch."""
+    import torch
+    mlp = MLP(dims, max_rows=3 * batch_triples, params=init_params, skip=skip)
+    T = len(anchor)
+    dev = [torch.as_tensor(np.asarray(v, np.int32), device="cuda") for v in (anchor, near, far)]
+    rng = np.random.default_rng(seed)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    losses: List[float] = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(T).astype(np.int64), device="cuda")
+        acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+        nb = 0
+        for b0 in range(0, T - batch_triples + 1 if T >= batch_triples else 1, batch_triples):
+            sel = perm[b0:b0 + batch_triples]
+            a, p, q = (v[sel].contiguous() for v in dev)
+            mlp.triplet_loss_grad(x, a, p, q, d_near[sel].contiguous(), d_far[sel].contiguous(),
+                                  rank_weight=rank_weight, tau=tau, dist_weight=dist_weight,
+                                  loss=loss)
             step += 1
             mlp.adam(lr, step, weight_decay=weight_decay)
             acc += loss
@@ -124,13 +161,24 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
                batch_pairs: int = 4096, lr: float = 1e-3, k: int = 10,
                k_candidates=(10, 100), proj_seed: int = 7, init_seed: int = 11,
                pair_seed: int = 13, rel_floor: float = 0.02, input_scale: float = 1.0,
-               skip: bool = True, weight_decay: float = 0.0, log=None) -> Dict:
+               skip: bool = True, weight_decay: float = 0.0, objective: str = "pairs",
+               n_triplets: int = 1_000_000, rank_weight: float = 1.0, tau: float = 0.01,
+               dist_weight: float = 0.0, far_k: int = 100, skip_init: str = "pca",
+               log=None) -> Dict:
     """Train the encoder on a reference table and place a query table.
 
     Exact distances (training targets and ground truth) come from the
     weighted-normalized matrix of the union of both tables (reference rows
-    first), computed by the FP32 stripe kernels.  Returns metrics and timings.
+    first), computed by the FP32 stripe kernels.  objective "pairs": the
+    distance regression over n_uniform uniform + n_near neighbour pairs;
+    "triplets": the ranking loss over n_triplets (anchor, near, far) triples
+    (near among the anchor's near_k nearest, far among its ranks near_k..far_k-1
+    or uniform).  Returns metrics and timings.
     """
+    if objective not in ("pairs", "triplets"):
+        raise ValueError("objective is 'pairs' or 'triplets'")
+    if skip_init not in ("pca", "gaussian"):
+        raise ValueError("skip_init is 'pca' or 'gaussian'")
     import torch
     import synth
     from . import Embedding, Table, Tree, condensed_block, dm, project
@@ -157,17 +205,26 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
     log(f"exact union matrix: {out['exact_union_dm_s']:.2f}s")
     cross = condensed_block(d_union, n_all, nr, nq, 0, nr)              # [nq][nr] exact
     # training data: uniform pairs + pairs from each reference's exact neighbours
-    neigh = np.empty((nr, near_k), dtype=np.int32)
+    kn = near_k if objective == "pairs" else max(far_k, near_k + 1)
+    neigh = np.empty((nr, kn), dtype=np.int32)
     step_rows = 4096
     for r0 in range(0, nr, step_rows):
         rr = min(step_rows, nr - r0)
         blk = condensed_block(d_union, n_all, r0, rr, 0, nr)
-        idx, _ = topk_rows(blk, near_k)
+        idx, _ = topk_rows(blk, kn)
         neigh[r0:r0 + rr] = idx.cpu().numpy()
         del blk
-    pa, pb = synth.placement_pairs(nr, n_uniform, neigh, n_near, seed=pair_seed)
+    # the pairs also give the skip path's scale and the projection-only fit below
+    pa, pb = synth.placement_pairs(nr, n_uniform, neigh[:, :near_k], n_near, seed=pair_seed)
     tg = gather_pairs(d_union, n_all, torch.as_tensor(pa, device="cuda"),
                       torch.as_tensor(pb, device="cuda"))
+    if objective == "triplets":
+        ta, tn, tf = synth.placement_triplets(nr, neigh, n_triplets, near_k=near_k,
+                                              far_lo=near_k, seed=pair_seed + 1)
+        d_near = gather_pairs(d_union, n_all, torch.as_tensor(ta, device="cuda"),
+                              torch.as_tensor(tn, device="cuda"))
+        d_far = gather_pairs(d_union, n_all, torch.as_tensor(ta, device="cuda"),
+                             torch.as_tensor(tf, device="cuda"))
     del d_union
     # inputs
     pdims, psigns = synth.sparse_projection(tree.n_nodes, out_dim=dims[0], per_node=4, seed=proj_seed)
@@ -180,29 +237,58 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
     init = synth.mlp_init(dims, seed=init_seed)
     s_init = None
     if skip:
-        # start from a projection metric: z = S x with S a scaled Gaussian map and
-        # the network's last layer at zero; the scale matches the median target
+        # start from a linear metric: z = S x with the network's last layer at zero.
+        # skip_init "pca": S = the top dims[-1] principal directions of the
+        # projected reference set (uf_pca_basis), the linear map of that width that
+        # keeps the most of the pairwise distances; "gaussian": a random map.  The
+        # scale matches the median target.
         sel = torch.arange(min(4096, len(pa)), device="cuda")
         pa_t = torch.as_tensor(pa, device="cuda")[sel].long()
         pb_t = torch.as_tensor(pb, device="cuda")[sel].long()
-        dx = (x_ref[pa_t].float() - x_ref[pb_t].float()).norm(dim=1)
-        ratio = float(tg[sel].median()) / max(float(dx.median()), 1e-30)
-        s_init = synth.gaussian_matrix(dims[-1], dims[0], seed=init_seed + 1) * np.float32(
-            ratio / np.sqrt(dims[-1]))
+        diff = x_ref[pa_t].float() - x_ref[pb_t].float()
+        if skip_init == "pca":
+            cols = min(dims[-1] + 32, 160, dims[0])
+            omega = torch.tensor(synth.gaussian_matrix(dims[0], cols, seed=init_seed + 1),
+                                 dtype=torch.float64, device="cuda")
+            basis, pca_vals = pca_basis(x_ref, dims[-1], omega, power_iters=3)
+            out["pca_init_s"] = time.perf_counter() - t2
+            out["pca_top_eigenvalues"] = [float(v) for v in pca_vals[:5]]
+            dx = (diff @ basis.T).norm(dim=1)
+            ratio = float(tg[sel].median()) / max(float(dx.median()), 1e-30)
+            s_init = basis.cpu().numpy() * np.float32(ratio)
+        else:
+            dx = diff.norm(dim=1)
+            ratio = float(tg[sel].median()) / max(float(dx.median()), 1e-30)
+            s_init = synth.gaussian_matrix(dims[-1], dims[0], seed=init_seed + 1) * np.float32(
+                ratio / np.sqrt(dims[-1]))
         init[-1] = (np.zeros_like(init[-1][0]), np.zeros_like(init[-1][1]))
     profile_reset()
     profile_enable(True)
-    mlp, losses = train(x_ref, pa, pb, tg, dims, init, epochs=epochs, batch_pairs=batch_pairs,
-                        lr=lr, rel_floor=rel_floor, skip=s_init, weight_decay=weight_decay,
-                        log=log)
+    if objective == "pairs":
+        mlp, losses = train(x_ref, pa, pb, tg, dims, init, epochs=epochs, batch_pairs=batch_pairs,
+                            lr=lr, rel_floor=rel_floor, skip=s_init, weight_decay=weight_decay,
+                            log=log)
+        rows_per_step, n_items = 2 * batch_pairs, len(pa)
+        out["train_pairs"] = int(len(pa))
+    else:
+        # a batch of batch_pairs // 2 triples has 1.5x the rows of a pair batch
+        bt = batch_pairs // 2
+        mlp, losses = train_triplets(x_ref, ta, tn, tf, d_near, d_far, dims, init, epochs=epochs,
+                                     batch_triples=bt, lr=lr, rank_weight=rank_weight, tau=tau,
+                                     dist_weight=dist_weight, skip=s_init,
+                                     weight_decay=weight_decay, log=log)
+        rows_per_step, n_items, batch_pairs_eff = 3 * bt, len(ta), bt
+        out["train_triplets"] = int(len(ta))
+        out["rank_weight"], out["tau"], out["dist_weight"] = rank_weight, tau, dist_weight
+    out["objective"] = objective
     sync()
     profile_enable(False)
     out["train_s"] = time.perf_counter() - t2
     out["train_losses"] = losses
-    out["train_pairs"] = int(len(pa))
     # the training GEMMs, timed with HIP events on the training stream
-    steps = epochs * (len(pa) // batch_pairs if len(pa) >= batch_pairs else 1)
-    flops = steps * train_step_flops(dims, 2 * batch_pairs, skip)
+    per_batch = batch_pairs if objective == "pairs" else batch_pairs_eff
+    steps = epochs * (n_items // per_batch if n_items >= per_batch else 1)
+    flops = steps * train_step_flops(dims, rows_per_step, skip)
     out["train_steps"] = steps
     out["train_gemm_flops"] = flops
     for name in ("encoder_gemm", "encoder_colsum", "encoder_loss", "encoder_adam"):
@@ -215,7 +301,7 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
 
     def encode(x):
         z = torch.empty((x.shape[0], dims[-1]), dtype=torch.float32, device="cuda")
-        rows = 2 * batch_pairs
+        rows = mlp.max_rows
         for r0 in range(0, x.shape[0], rows):
             mlp.forward(x[r0:r0 + rows], out=z[r0:r0 + rows])
         return z
@@ -240,6 +326,13 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
     for kc in k_candidates:
         idx, ex, cand = place(xr, xq, s_q, s_ref, kc, k)
         out[f"projection_only_recall@{k}_kprime{kc}"] = recall_at_k(idx, cross, k)
+    # the encoder's starting point at its own width: the linear PCA map alone
+    if skip and skip_init == "pca":
+        zr_l, zq_l = (xr @ basis.T).contiguous(), (xq @ basis.T).contiguous()
+        for kc in k_candidates:
+            idx, ex, cand = place(zr_l, zq_l, s_q, s_ref, kc, k)
+            out[f"pca_only_recall@{k}_kprime{kc}"] = recall_at_k(idx, cross, k)
+        del zr_l, zq_l
     # encoder distances against exact ones on random pairs
     rng = np.random.default_rng(3)
     qi = torch.as_tensor(rng.integers(0, nq, 20000), device="cuda")

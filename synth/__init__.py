@@ -343,6 +343,22 @@ def placement_pairs(n: int, n_uniform: int, neighbours: np.ndarray, n_near: int,
     return pa[perm], pb[perm]
 
 
+def placement_triplets(n: int, neighbours: np.ndarray, n_triplets: int, near_k: int = 10,
+                       far_lo: int = 10, seed: int = 14):
+    """Training triples (anchor, near, far) for the ranking loss: anchors uniform;
+    near drawn from the anchor's ``near_k`` nearest neighbours; far, for half of
+    the triples, from its neighbours ranked ``far_lo`` .. k-1 (``neighbours`` is
+    [n, k], nearest first), for the other half uniform among the other samples."""
+    rng = _rng(seed, 9)
+    k = neighbours.shape[1]
+    a = rng.integers(0, n, size=n_triplets)
+    near = neighbours[a, rng.integers(0, near_k, size=n_triplets)]
+    far = neighbours[a, rng.integers(far_lo, k, size=n_triplets)]
+    half = n_triplets // 2
+    far[half:] = (a[half:] + rng.integers(1, n, size=n_triplets - half)) % n
+    return a.astype(np.int32), near.astype(np.int32), far.astype(np.int32)
+
+
 def gaussian_matrix(rows: int, cols: int, seed: int = 17) -> np.ndarray:
     """Standard normal entries on the bfloat16 grid (a Johnson-Lindenstrauss map
     when scaled), float32 [rows, cols]."""

@@ -193,13 +193,16 @@ def test_mlp_loss_and_gradients_vs_oracle(with_skip, rel_floor):
         assert corr > 0.99
 
 
-@pytest.mark.parametrize("rank_weight,tau", [(0.0, 0.05), (2.0, 0.05), (5.0, 0.01)])
+@pytest.mark.parametrize("dist_weight,rank_weight,tau", [(1.0, 0.0, 0.05), (1.0, 2.0, 0.05),
+                                                         (1.0, 5.0, 0.01), (0.0, 1.0, 0.05),
+                                                         (0.1, 1.0, 0.01)])
 @pytest.mark.parametrize("with_skip", [False, True])
-def test_triplet_loss_and_gradients_vs_oracle(with_skip, rank_weight, tau):
+def test_triplet_loss_and_gradients_vs_oracle(with_skip, dist_weight, rank_weight, tau):
     """The ranking loss: loss and every gradient vs the FP64 oracle at the
     kernels' BF16 storage points (tolerances as for the pair loss).  With tau =
     0.05 the ranking term's slope sigmoid((e_p - e_n) / tau) takes values across
-    (0, 1); with rank_weight 0 only the two regression terms remain."""
+    (0, 1); with rank_weight 0 only the two regression terms remain, with
+    dist_weight 0 only the ranking term."""
     import torch
     import paper_2107_05397_amd as uf
     dims = (64, 32, 32, 32)
@@ -215,12 +218,13 @@ def test_triplet_loss_and_gradients_vs_oracle(with_skip, rank_weight, tau):
     mlp = uf.MLP(dims, max_rows=3 * T, params=params, skip=skip)
     loss = mlp.triplet_loss_grad(_t(x, torch.bfloat16), _t(a, torch.int32), _t(p, torch.int32),
                                  _t(q, torch.int32), _t(dp, torch.float32), _t(dq, torch.float32),
-                                 rank_weight=rank_weight, tau=tau)
+                                 rank_weight=rank_weight, tau=tau, dist_weight=dist_weight)
     torch.cuda.synchronize()
     w_loss, w_grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, rank_weight, tau,
-                                                bf16_storage=True, skip=skip)
+                                                bf16_storage=True, skip=skip,
+                                                dist_weight=dist_weight)
     f_loss, f_grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, rank_weight, tau,
-                                                skip=skip)
+                                                skip=skip, dist_weight=dist_weight)
     assert float(loss.cpu()[0]) == pytest.approx(w_loss, rel=1e-3)
     assert float(loss.cpu()[0]) == pytest.approx(f_loss, rel=2e-2)
     layers = list(range(3)) + ([3] if with_skip else [])
@@ -408,3 +412,50 @@ def test_dm_pairs_across_tables_vs_oracle():
     want = oracle.dm_pairs(tree, both, [(int(r), nr + int(q)) for q, r in zip(qa, rb)],
                            "weighted_normalized")
     assert np.max(np.abs(got - want)) <= 1e-12
+
+
+def test_pca_basis_vs_oracle():
+    """Principal directions of a BF16 data matrix with 12 planted directions
+    (standard deviations 3 down to 1.5) over small noise, plus a mean: the
+    library's subspace equals the oracle's (eigenvectors of the FP64 covariance
+    of the same BF16 values): each returned row lies in the oracle's span up to a
+    residual of 1e-5 (the rows are FP32: 6e-8 per entry over 256 entries), its
+    rows are orthonormal to 1e-6 and its eigenvalues agree to 1e-6 relative."""
+    import torch
+    import paper_2107_05397_amd as uf
+    rng = np.random.default_rng(41)
+    n, d, k, c = 3000, 256, 12, 24
+    u = rng.normal(size=(n, k)) * np.linspace(3.0, 1.5, k)
+    v = np.linalg.qr(rng.normal(size=(d, k)))[0].T
+    x = synth.bf16_grid(u @ v + 0.05 * rng.normal(size=(n, d)) + 1.0)
+    omega = torch.tensor(synth.gaussian_matrix(d, c, seed=5), dtype=torch.float64, device="cuda")
+    basis, vals = uf.pca_basis(_t(x, torch.bfloat16), k, omega, power_iters=3)
+    torch.cuda.synchronize()
+    got = basis.double().cpu().numpy()
+    want, wv = op.pca_basis(x, k)
+    resid = np.linalg.norm(got - (got @ want.T) @ want, axis=1)
+    print("max residual", resid.max(), "eig rel err", np.abs(vals / wv - 1).max())
+    assert resid.max() <= 1e-5
+    assert np.allclose(got @ got.T, np.eye(k), atol=1e-6)
+    assert np.allclose(vals, wv, rtol=1e-6)
+
+
+def test_pca_basis_rank_deficient():
+    """Fewer samples than directions: Xc has rank n - 1, so rows past it are zero
+    and their eigenvalues 0; the others still match the oracle."""
+    import torch
+    import paper_2107_05397_amd as uf
+    rng = np.random.default_rng(43)
+    n, d, k, c = 6, 32, 8, 10
+    x = synth.bf16_grid(rng.normal(size=(n, d)))
+    omega = torch.tensor(synth.gaussian_matrix(d, c, seed=6), dtype=torch.float64, device="cuda")
+    basis, vals = uf.pca_basis(_t(x, torch.bfloat16), k, omega, power_iters=2)
+    torch.cuda.synchronize()
+    got = basis.double().cpu().numpy()
+    want, wv = op.pca_basis(x, n - 1)
+    assert np.all(vals[n - 1:] == 0.0) and np.all(got[n - 1:] == 0.0)
+    assert np.allclose(vals[:n - 1], wv, rtol=1e-6)
+    resid = np.linalg.norm(got[:n - 1] - (got[:n - 1] @ want.T) @ want, axis=1)
+    assert resid.max() <= 1e-5
+    with pytest.raises(uf.UFError):   # more directions than test-matrix columns
+        uf.pca_basis(_t(x, torch.bfloat16), 12, omega)

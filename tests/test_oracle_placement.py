@@ -293,18 +293,19 @@ def test_softplus_and_sigmoid_match_scipy():
     assert np.allclose(op.softplus(x), np.logaddexp(0.0, x), rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("with_skip", [False, True])
-def test_triplet_gradients_match_finite_differences(with_skip):
+@pytest.mark.parametrize("with_skip,alpha", [(False, 1.0), (True, 1.0), (True, 0.0), (False, 0.3)])
+def test_triplet_gradients_match_finite_differences(with_skip, alpha):
     x, params, _, _, _ = _problem(seed=11)
     a, p, q, dp, dq = _triplets()
     skip = np.random.default_rng(2).normal(size=(4, 16)) * 0.1 if with_skip else None
     lam, tau = 2.0, 0.05
-    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip)
+    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip,
+                                            dist_weight=alpha)
     h = 1e-6
     rng = np.random.default_rng(4)
 
     def f(ps, sk):
-        return op.triplet_loss_only(x, ps, a, p, q, dp, dq, lam, tau, skip=sk)
+        return op.triplet_loss_only(x, ps, a, p, q, dp, dq, lam, tau, skip=sk, dist_weight=alpha)
 
     for l, (w, b) in enumerate(params):
         for _ in range(5):
@@ -332,12 +333,14 @@ def test_triplet_gradients_match_finite_differences(with_skip):
             assert grads[-1][0][i, j] == pytest.approx(fd, rel=1e-5, abs=1e-8)
 
 
-def test_triplet_loss_matches_torch_autograd():
+@pytest.mark.parametrize("alpha", [1.0, 0.25])
+def test_triplet_loss_matches_torch_autograd(alpha):
     x, params, _, _, _ = _problem(seed=13)
     a, p, q, dp, dq = _triplets(seed=6)
     skip = np.random.default_rng(8).normal(size=(4, 16)) * 0.1
     lam, tau = 3.0, 0.02
-    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip)
+    loss, grads = op.triplet_loss_and_grads(x, params, a, p, q, dp, dq, lam, tau, skip=skip,
+                                            dist_weight=alpha)
     tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True)) for w, b in params]
     ts = torch.tensor(skip, requires_grad=True)
 
@@ -353,7 +356,7 @@ def test_triplet_loss_matches_torch_autograd():
     za, zp, zq = enc(a), enc(p), enc(q)
     ep = torch.linalg.vector_norm(za - zp, dim=1)
     eq = torch.linalg.vector_norm(za - zq, dim=1)
-    tl = ((ep - torch.tensor(dp)) ** 2 + (eq - torch.tensor(dq)) ** 2 +
+    tl = (alpha * ((ep - torch.tensor(dp)) ** 2 + (eq - torch.tensor(dq)) ** 2) +
           lam * tau * torch.nn.functional.softplus((ep - eq) / tau)).mean()
     tl.backward()
     assert float(tl) == pytest.approx(loss, rel=1e-12)
@@ -389,3 +392,30 @@ def test_triplet_ranking_term_tends_to_the_hinge():
     hinge = np.mean(np.maximum(ep - eq, 0.0))
     got = op.triplet_loss_only(x, params, a, p, q, dp, dq, 1.0, 1e-6) - base
     assert got == pytest.approx(hinge, abs=1e-6)
+
+
+def test_pca_basis_of_orthogonal_columns():
+    """Columns that are centred and mutually orthogonal make the covariance
+    diagonal: the principal directions are the coordinate axes, ordered by the
+    columns' mean squares, and the eigenvalues are those mean squares."""
+    rng = np.random.default_rng(31)
+    n, d = 64, 6
+    q, _ = np.linalg.qr(rng.normal(size=(n, d)) - 0.0)
+    q -= q.mean(axis=0, keepdims=True)              # centre, then re-orthogonalise
+    q, _ = np.linalg.qr(q)
+    q -= q.mean(axis=0, keepdims=True)
+    # exact orthogonality after centring: Gram-Schmidt on centred columns
+    cols = []
+    for j in range(d):
+        c = q[:, j].copy()
+        for b in cols:
+            c -= (c @ b) / (b @ b) * b
+        cols.append(c)
+    scales = np.array([3.0, 0.5, 2.0, 1.0, 4.0, 0.25])
+    x = np.stack([c / np.linalg.norm(c) * s * np.sqrt(n) for c, s in zip(cols, scales)], axis=1)
+    x += np.array([5.0, -1.0, 0.0, 2.0, 0.0, 7.0])  # a mean, which the covariance removes
+    basis, w = op.pca_basis(x, 3)
+    assert np.allclose(w, [16.0, 9.0, 4.0], rtol=1e-12)
+    want = np.zeros((3, d))
+    want[0, 4] = want[1, 0] = want[2, 2] = 1.0
+    assert np.allclose(np.abs(basis), want, atol=1e-12)
