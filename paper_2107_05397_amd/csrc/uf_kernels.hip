@@ -269,6 +269,26 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n_tiles) {
     return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
 }
 
+// Tile l of the band grid (n_iblk sample blocks x n_sblk stripe blocks) in
+// patches of 8 x 8 tiles: patches along the sample blocks first, then the next
+// row of patches; inside a patch the sample block runs fastest.  With the XCD
+// remap above, the blocks an XCD holds at once form about one patch, whose
+// sample windows and partner windows overlap (the partner window of (b, t)
+// starts at sample block b + t * (stripes per tile) / 128), so they share L2
+// lines instead of each streaming its own.
+constexpr int64_t kPatch = 8;
+__device__ __forceinline__ void band_patch_tile(int64_t l, int64_t n_iblk, int64_t n_sblk,
+                                                int64_t* ib, int64_t* sblk) {
+    const int64_t ps = l / (kPatch * n_iblk);
+    const int64_t rem = l - ps * kPatch * n_iblk;
+    const int64_t hs = min(kPatch, n_sblk - ps * kPatch);
+    const int64_t pi = rem / (kPatch * hs);
+    const int64_t rem2 = rem - pi * kPatch * hs;
+    const int64_t wi = min(kPatch, n_iblk - pi * kPatch);
+    *ib = pi * kPatch + rem2 % wi;
+    *sblk = ps * kPatch + rem2 / wi;
+}
+
 // LDS of one band tile of 16*MS stripes: two staging buffers of KS branches.
 template <typename T, int KS, int MS = 8>
 struct BandLds {
@@ -394,10 +414,12 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
                                               int first, T* __restrict__ acc) {
     constexpr int KS = BandCfg<T>::KS, MS = BandCfg<T>::MS, TS = 16 * MS;
     __shared__ __attribute__((aligned(16))) BandLds<T, KS, MS> L;
-    const int64_t n_tiles = n_iblk * ((se - sb + TS - 1) / TS);
-    const int64_t tile = xcd_tile(blockIdx.x, n_tiles);
-    const int64_t i0 = (tile % n_iblk) * kBandI;
-    const int64_t s0 = sb + (tile / n_iblk) * TS;
+    const int64_t n_sblk = (se - sb + TS - 1) / TS;
+    const int64_t n_tiles = n_iblk * n_sblk;
+    int64_t ib = 0, sblk = 0;
+    band_patch_tile(xcd_tile(blockIdx.x, n_tiles), n_iblk, n_sblk, &ib, &sblk);
+    const int64_t i0 = ib * kBandI;
+    const int64_t s0 = sb + sblk * TS;
     band_tile<T, W, KS, MS>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
 }
 
