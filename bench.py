@@ -284,7 +284,8 @@ def bench_placement(args) -> int:
     torch.cuda.set_device(0)
     res = placement.experiment(tree, ref, query, epochs=args.epochs, objective=args.objective,
                                dist_weight=args.dist_weight, rank_weight=args.rank_weight,
-                               tau=args.tau, lr=args.lr, skip_init=args.skip_init, log=log)
+                               tau=args.tau, lr=args.lr, skip_init=args.skip_init,
+                               batch_pairs=args.batch_pairs, log=log)
     rec = {
         "metric": "placement queries/s (1 GPU) with recall@10 against exact UniFrac",
         "value": c["n_query"] / res["placement_s"], "unit": "queries/s", "n_gpus": 1,
@@ -317,10 +318,12 @@ def main() -> int:
     ap.add_argument("--epochs", type=int, default=8, help="C5: training epochs")
     ap.add_argument("--objective", default="triplets", choices=["triplets", "pairs"],
                     help="C5: ranking loss over triples, or distance regression over pairs")
-    ap.add_argument("--dist-weight", type=float, default=1.0, help="C5: regression weight")
-    ap.add_argument("--rank-weight", type=float, default=30.0, help="C5: ranking weight")
+    ap.add_argument("--dist-weight", type=float, default=0.0, help="C5: regression weight")
+    ap.add_argument("--rank-weight", type=float, default=1.0, help="C5: ranking weight")
     ap.add_argument("--tau", type=float, default=0.01, help="C5: ranking temperature")
     ap.add_argument("--lr", type=float, default=1e-4, help="C5: Adam learning rate")
+    ap.add_argument("--batch-pairs", type=int, default=4096,
+                    help="C5: pairs per training step (triples: half as many)")
     ap.add_argument("--skip-init", default="pca", choices=["pca", "gaussian"],
                     help="C5: start of the encoder's linear path")
     ap.add_argument("--tables", type=int, default=64, help="C4: number of tables")
