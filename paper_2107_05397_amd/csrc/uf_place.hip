@@ -105,8 +105,9 @@ __global__ __launch_bounds__(256) void k_project(Emb e, const int32_t* __restric
 // Layout 1 (col): element (r, k) at P[src(k) * ld + r]   (r contiguous)
 // src() applies the optional row-index array (a gather of storage rows).
 //
-// A block computes a BM x 128 tile (BM = 128 or 256) with 4 waves in 2 x 2; a
-// wave owns (BM/2) x 64 as (BM/64) x 2 blocks of v_mfma_f32_32x32x16_bf16.  The
+// A block computes a BM x BN tile: 128 x 128 or 256 x 128 with 4 waves in 2 x 2
+// (a wave owns (BM/2) x 64), or 256 x 256 with 8 waves in 2 x 4 (a wave owns
+// 128 x 64), as 32 x 32 blocks of v_mfma_f32_32x32x16_bf16.  The
 // K loop steps by 64 through two LDS stages that hold the tile's rows as
 // [row][k] with a 144-byte pitch (an odd multiple of 16 bytes, so the 16-byte
 // fragment reads of consecutive rows fall on distinct banks).  Row-layout
@@ -121,7 +122,6 @@ __global__ __launch_bounds__(256) void k_project(Emb e, const int32_t* __restric
 // part[z][M][N] and k_gemm_reduce adds the ranges in order and applies the
 // epilogue, so the result never depends on the order blocks run in.
 // ----------------------------------------------------------------------------
-constexpr int kGemmBN = 128;             // tile columns
 constexpr int kGemmKS = 64;              // K per step
 constexpr int kGemmLD = kGemmKS + 8;     // LDS row pitch in bf16 (144 bytes)
 
@@ -148,10 +148,12 @@ __device__ __forceinline__ void gemm_store(float v, int64_t i, int64_t j,
 // One operand's share of a K step in a thread's registers: TR rows of the tile,
 // TR/32 uint4 per thread in either layout (row: TR*8 pieces of 16 bytes; col:
 // TR*2 pieces of 4 x 16 bytes).
-template <int LAY, int TR>
+template <int LAY, int TR, int NT = 256>
 struct GemmOperand {
-    static constexpr int NV = TR / 32;
-    static constexpr int NP = LAY == 0 ? NV : TR / 128;   // pieces per thread
+    // pieces per thread: row layout TR*8 of 16 bytes, column layout TR*2 of 4 x 16
+    static constexpr int NV = TR * 8 / NT;
+    static constexpr int NP = LAY == 0 ? NV : TR * 2 / NT;
+    static_assert(NP >= 1 && (LAY == 0 ? TR * 8 : TR * 2) % NT == 0, "operand split");
     const uint16_t* P;
     int64_t ld;
     const int32_t* rows;
@@ -167,10 +169,11 @@ struct GemmOperand {
         R = R_;
         K = K_;
         if constexpr (LAY == 0) {
+            // rows past the end read the last row (always a valid address)
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const int64_t gr = r0 + ((tid + 256 * i) >> 3);
-                rowp[i] = gr < R ? P + (rows ? int64_t(rows[gr]) : gr) * ld : nullptr;
+                const int64_t gr = min(r0 + ((tid + NT * i) >> 3), R - 1);
+                rowp[i] = P + (rows ? int64_t(rows[gr]) : gr) * ld;
             }
         }
     }
@@ -181,31 +184,32 @@ struct GemmOperand {
         uint4 v[NV];
     };
 
+    // Every load is issued unconditionally from a clamped, valid address (16-byte
+    // vector loads, no branches).  Pieces of rows past R hold copies of the last
+    // row: they only reach output rows or columns that are never stored.  Pieces
+    // past K are zeroed when they are written to LDS (stash), so no wait on the
+    // loads is placed before the MFMAs that overlap them.
     __device__ __forceinline__ Regs fetch(int64_t k0, int tid) const {
         Regs out;
         uint4* v = out.v;
-        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
         if constexpr (LAY == 0) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const int64_t k = k0 + 8 * ((tid + 256 * i) & 7);
-                v[i] = (rowp[i] && k < K) ? *reinterpret_cast<const uint4*>(rowp[i] + k) : z;
+                const int p = tid + NT * i;
+                const int64_t k = k0 + 8 * (p & 7);
+                v[i] = *reinterpret_cast<const uint4*>(rowp[i] + min(k, K - 8));
             }
         } else {
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                const int p = tid + 256 * i;
-                const int64_t rr = r0 + 8 * (p / 16);
+                const int p = tid + NT * i;
+                const int64_t rc = min(r0 + 8 * (p / 16), R - 8);
                 const int64_t kb = k0 + 4 * (p % 16);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int64_t k = kb + e;
-                    if (k < K && rr < R) {
-                        const int64_t src = rows ? int64_t(rows[k]) : k;
-                        v[4 * i + e] = *reinterpret_cast<const uint4*>(P + src * ld + rr);
-                    } else {
-                        v[4 * i + e] = z;
-                    }
+                    const int64_t kcl = min(kb + e, K - 1);
+                    const int64_t src = rows ? int64_t(rows[kcl]) : kcl;
+                    v[4 * i + e] = *reinterpret_cast<const uint4*>(P + src * ld + rc);
                 }
             }
         }
@@ -217,24 +221,37 @@ struct GemmOperand {
         return (j & 1) ? (w >> 16) : (w & 0xFFFFu);
     }
 
-    static __device__ __forceinline__ void stash(const Regs in, uint16_t* __restrict__ S, int tid) {
+    // a piece, or zeros (component by component: a select between two uint4
+    // objects would be compiled as a select between their addresses, in memory)
+    static __device__ __forceinline__ uint4 keep(const uint4& w, bool ok) {
+        return make_uint4(ok ? w.x : 0u, ok ? w.y : 0u, ok ? w.z : 0u, ok ? w.w : 0u);
+    }
+
+    // the K step at k0 into LDS, its pieces at k >= K as zeros
+    __device__ __forceinline__ void stash(const Regs in, uint16_t* __restrict__ S, int tid,
+                                          int64_t k0) const {
         const uint4* v = in.v;
         if constexpr (LAY == 0) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const int p = tid + 256 * i;
-                *reinterpret_cast<uint4*>(S + (p >> 3) * kGemmLD + 8 * (p & 7)) = v[i];
+                const int p = tid + NT * i;
+                const bool ok = k0 + 8 * (p & 7) < K;
+                *reinterpret_cast<uint4*>(S + (p >> 3) * kGemmLD + 8 * (p & 7)) = keep(v[i], ok);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < NP; ++i) {
-                const int p = tid + 256 * i;
+                const int p = tid + NT * i;
                 const int rb = p / 16, kq = p % 16;
+                const int64_t kb = k0 + 4 * kq;
+                uint4 u[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) u[e] = keep(v[4 * i + e], kb + e < K);
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     uint2 w;
-                    w.x = half_of(v[4 * i + 0], j) | (half_of(v[4 * i + 1], j) << 16);
-                    w.y = half_of(v[4 * i + 2], j) | (half_of(v[4 * i + 3], j) << 16);
+                    w.x = half_of(u[0], j) | (half_of(u[1], j) << 16);
+                    w.y = half_of(u[2], j) | (half_of(u[3], j) << 16);
                     *reinterpret_cast<uint2*>(S + (8 * rb + j) * kGemmLD + 4 * kq) = w;
                 }
             }
@@ -242,16 +259,35 @@ struct GemmOperand {
     }
 };
 
-template <int LA, int LB, int EPI, int BM>
-__global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void k_gemm_bf16(
+// Block b runs on XCD b mod 8.  Tile t = that XCD's share of the row-major tile
+// order: XCD x takes the x-th eighth (whole runs of row blocks across all column
+// blocks), so the row panels of A it streams are its own and the column panels of
+// B are shared by all its blocks, in its L2.
+__device__ __forceinline__ int64_t gemm_xcd_tile(int64_t b, int64_t n_tiles) {
+    const int64_t x = b & 7, local = b >> 3;
+    const int64_t per = n_tiles >> 3, rem = n_tiles & 7;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+template <int LA, int LB, int EPI, int BM, int BN, int NT>
+__global__ __launch_bounds__(NT, BM * BN >= 65536 ? 1 : 2) void k_gemm_bf16(
     const uint16_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ arow,
     const uint16_t* __restrict__ B, int64_t ldb, const int32_t* __restrict__ brow, int64_t M,
     int64_t N, int64_t K, const float* __restrict__ bias, const uint16_t* __restrict__ mask,
     int64_t ldm, void* __restrict__ C, int64_t ldc, float* __restrict__ part) {
-    constexpr int XB = BM / 64;   // 32-row blocks per wave
+    // NT/64 waves in 2 x WJ; a wave owns (BM/2) x (BN/WJ) as XB x YB MFMA blocks
+    constexpr int WJ = NT / 128;
+    constexpr int XB = BM / 64;          // 32-row blocks per wave
+    constexpr int YB = BN / (32 * WJ);   // 32-column blocks per wave
+    // operand pieces: 128-row halves with 256 threads, whole tiles with 512
+    constexpr int TRA = NT == 512 ? BM : 128, TRB = NT == 512 ? BN : 128;
+    constexpr int HA = BM / TRA, HB = BN / TRB;
+    static_assert(YB >= 1 && HA >= 1 && HA <= 2 && HB >= 1 && HB <= 2, "GEMM tile shape");
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * kGemmLD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN * kGemmLD];
-    const int64_t m0 = int64_t(blockIdx.y) * BM, n0 = int64_t(blockIdx.x) * kGemmBN;
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * kGemmLD];
+    const int64_t tn = (N + BN - 1) / BN;
+    const int64_t tile = gemm_xcd_tile(blockIdx.x, int64_t(gridDim.x));
+    const int64_t m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave & 1, wj = wave >> 1;
 
@@ -261,19 +297,20 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void k_gemm_bf16(
     const int64_t t0 = int64_t(blockIdx.z) * per;
     const int64_t t1 = min(nk, t0 + per);
 
-    // A in 128-row halves, so that no staged array exceeds 16 registers (larger
-    // ones would be kept in memory)
-    GemmOperand<LA, 128> oa0, oa1;
-    GemmOperand<LB, kGemmBN> ob;
+    // operands in pieces of at most 16 staged registers per thread (larger
+    // arrays would be kept in memory)
+    GemmOperand<LA, TRA, NT> oa0, oa1;
+    GemmOperand<LB, TRB, NT> ob0, ob1;
     oa0.init(A, lda, arow, m0, M, K, tid);
-    if constexpr (BM == 256) oa1.init(A, lda, arow, m0 + 128, M, K, tid);
-    ob.init(B, ldb, brow, n0, N, K, tid);
+    if constexpr (HA == 2) oa1.init(A, lda, arow, m0 + TRA, M, K, tid);
+    ob0.init(B, ldb, brow, n0, N, K, tid);
+    if constexpr (HB == 2) ob1.init(B, ldb, brow, n0 + TRB, N, K, tid);
 
-    floatx16 c[XB][2];
+    floatx16 c[XB][YB];
 #pragma unroll
     for (int x = 0; x < XB; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < YB; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) c[x][y][r] = 0.0f;
 
@@ -281,46 +318,49 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void k_gemm_bf16(
 #pragma unroll
         for (int s = 0; s < kGemmKS / 16; ++s) {
             const int kq = 16 * s + 8 * (lane >> 5);
-            bf16x8 fa[XB], fb[2];
+            bf16x8 fa[XB], fb[YB];
 #pragma unroll
             for (int x = 0; x < XB; ++x)
                 fa[x] = *reinterpret_cast<const bf16x8*>(
                     As[buf] + (wi * (BM / 2) + x * 32 + (lane & 31)) * kGemmLD + kq);
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < YB; ++y)
                 fb[y] = *reinterpret_cast<const bf16x8*>(
-                    Bs[buf] + (wj * 64 + y * 32 + (lane & 31)) * kGemmLD + kq);
+                    Bs[buf] + (wj * (BN / WJ) + y * 32 + (lane & 31)) * kGemmLD + kq);
 #pragma unroll
             for (int x = 0; x < XB; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < YB; ++y)
                     c[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[y], c[x][y], 0, 0, 0);
         }
     };
 
     if (t0 < t1) {
-        using OA = GemmOperand<LA, 128>;
-        using OB = GemmOperand<LB, kGemmBN>;
+        using OA = GemmOperand<LA, TRA, NT>;
+        using OB = GemmOperand<LB, TRB, NT>;
         typename OA::Regs ra0 = oa0.fetch(t0 * kGemmKS, tid), ra1{};
-        if constexpr (BM == 256) ra1 = oa1.fetch(t0 * kGemmKS, tid);
-        typename OB::Regs rb = ob.fetch(t0 * kGemmKS, tid);
-        auto stash_all = [&](int buf) {
-            OA::stash(ra0, As[buf], tid);
-            if constexpr (BM == 256) OA::stash(ra1, As[buf] + 128 * kGemmLD, tid);
-            OB::stash(rb, Bs[buf], tid);
+        if constexpr (HA == 2) ra1 = oa1.fetch(t0 * kGemmKS, tid);
+        typename OB::Regs rb0 = ob0.fetch(t0 * kGemmKS, tid), rb1{};
+        if constexpr (HB == 2) rb1 = ob1.fetch(t0 * kGemmKS, tid);
+        auto stash_all = [&](int buf, int64_t k0) {
+            oa0.stash(ra0, As[buf], tid, k0);
+            if constexpr (HA == 2) oa1.stash(ra1, As[buf] + TRA * kGemmLD, tid, k0);
+            ob0.stash(rb0, Bs[buf], tid, k0);
+            if constexpr (HB == 2) ob1.stash(rb1, Bs[buf] + TRB * kGemmLD, tid, k0);
         };
         auto fetch_all = [&](int64_t k0) {
             ra0 = oa0.fetch(k0, tid);
-            if constexpr (BM == 256) ra1 = oa1.fetch(k0, tid);
-            rb = ob.fetch(k0, tid);
+            if constexpr (HA == 2) ra1 = oa1.fetch(k0, tid);
+            rb0 = ob0.fetch(k0, tid);
+            if constexpr (HB == 2) rb1 = ob1.fetch(k0, tid);
         };
         for (int64_t t = t0; t < t1; t += 2) {
-            stash_all(0);
+            stash_all(0, t * kGemmKS);
             fetch_all(min(t + 1, t1 - 1) * kGemmKS);   // past the end: re-read, unused
             __syncthreads();
             compute(0);
             if (t + 1 < t1) {   // block-uniform
-                stash_all(1);
+                stash_all(1, (t + 1) * kGemmKS);
                 fetch_all(min(t + 2, t1 - 1) * kGemmKS);
                 __syncthreads();
                 compute(1);
@@ -334,11 +374,11 @@ __global__ __launch_bounds__(256, BM == 128 ? 2 : 1) void k_gemm_bf16(
 #pragma unroll
     for (int x = 0; x < XB; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < YB; ++y)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t i = m0 + wi * (BM / 2) + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t j = n0 + wj * 64 + y * 32 + (lane & 31);
+                const int64_t j = n0 + wj * (BN / WJ) + y * 32 + (lane & 31);
                 if (i >= M || j >= N) continue;
                 if (split) pz[i * N + j] = c[x][y][r];
                 else gemm_store<EPI>(c[x][y][r], i, j, bias, mask, ldm, C, ldc);
@@ -768,10 +808,12 @@ hipError_t project(const Emb& e, const int32_t* dims, const int8_t* signs, int p
     return hipGetLastError();
 }
 
-// Launch plan of one GEMM: 256-row tiles while they still give every CU a
-// block, else 128-row tiles (two blocks per CU); K is split in powers of two
-// while the blocks do not fill those slots, every range keeps at least four K
-// steps and the partial sums fit in part_elems floats.
+// Launch plan of one GEMM: 256 x 256 tiles when both sides have at least 256
+// rows (each wave then runs 64 MFMAs per K step between barriers); else
+// 256 x 128 while those still give every CU a block; else 128 x 128 (two blocks
+// per CU).  K is split in powers of two while the blocks do not fill the CUs'
+// slots, every range keeps at least four K steps and the partial sums fit in
+// part_elems floats.
 hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, const int32_t* arow,
                      const uint16_t* B, int64_t ldb, const int32_t* brow, int64_t M, int64_t N,
                      int64_t K, const float* bias, const uint16_t* mask, int64_t ldm, void* C,
@@ -783,26 +825,31 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
     if (!aligned(A) || !aligned(B) || lda % 8 || ldb % 8) return hipErrorInvalidValue;
     if ((la == 0 ? K : M) % 8 || (lb == 0 ? K : N) % 8) return hipErrorInvalidValue;
-    const int64_t tn = (N + kGemmBN - 1) / kGemmBN;
-    const int bm = (M + 255) / 256 * tn >= 256 ? 256 : 128;
+    int bm = 128, bn = 128;
+    if (M >= 256 && N >= 256) bm = bn = 256;
+    else if ((M + 255) / 256 * ((N + 127) / 128) >= 256) bm = 256;
+    const int64_t tn = (N + bn - 1) / bn;
     const int64_t tm = (M + bm - 1) / bm;
-    const int64_t slots = bm == 128 ? 512 : 256;
+    const int64_t slots = bm * bn >= 65536 ? 256 : 512;
     const int64_t nk = (K + kGemmKS - 1) / kGemmKS;
     int64_t splits = 1;
     while (part && tm * tn * splits < slots && nk / (2 * splits) >= 4 &&
            2 * splits * M * N <= part_elems)
         splits *= 2;
-    if (tm > 65535 || tn > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid{unsigned(tn), unsigned(tm), unsigned(splits)};
+    if (tm * tn > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid{unsigned(tm * tn), 1u, unsigned(splits)};
     bool launched = false;
+#define UF_GEMM_T(LA_, LB_, EPI_, BM_, BN_, NT_)                                                \
+    hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, BM_, BN_, NT_>), grid, dim3(NT_), 0, st, A,  \
+                       lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part)
 #define UF_GEMM(LA_, LB_, EPI_)                                                                  \
     if (!launched && la == LA_ && lb == LB_ && epi == EPI_) {                                    \
-        if (bm == 256)                                                                           \
-            hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, 256>), grid, dim3(256), 0, st, A,    \
-                               lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part); \
+        if (bn == 256)                                                                           \
+            UF_GEMM_T(LA_, LB_, EPI_, 256, 256, 512);                                            \
+        else if (bm == 256)                                                                      \
+            UF_GEMM_T(LA_, LB_, EPI_, 256, 128, 256);                                            \
         else                                                                                     \
-            hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, 128>), grid, dim3(256), 0, st, A,    \
-                               lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part); \
+            UF_GEMM_T(LA_, LB_, EPI_, 128, 128, 256);                                            \
         launched = true;                                                                         \
     }
     UF_GEMM(0, 0, EPI_BIAS_RELU_BF16)
@@ -813,6 +860,7 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     UF_GEMM(0, 1, EPI_F32)
     UF_GEMM(1, 1, EPI_F32)
 #undef UF_GEMM
+#undef UF_GEMM_T
     if (!launched) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;

@@ -176,7 +176,7 @@ uf_status uf_mlp_create(int64_t n_layers, const int64_t* dims, int64_t max_rows,
         take(size_t(max_rows * dims[n_layers]) * 2);   // dZ
         take(size_t(max_rows) * 4);                    // loss per pair
         take(size_t(max_rows) * 4);                    // rows
-        const int64_t part_elems = int64_t(8) << 20;   // 32 MiB of GEMM / column-sum scratch
+        const int64_t part_elems = int64_t(32) << 20;  // 128 MiB of GEMM / column-sum scratch
         take(size_t(part_elems) * 4);                  // part
         m->skip = skip != 0;
         const size_t ns = m->skip ? size_t(dims[n_layers] * dims[0]) : 0;

@@ -55,27 +55,31 @@ def test_gemm_forward_layout_against_numpy(M, N, K):
     assert np.all(np.abs(z - want) <= 1e-5 * bound + 1e-30)
 
 
-def test_all_gemm_layouts_exact_on_integers():
+@pytest.mark.parametrize("d0,d1,d2,n_src,n", [(288, 160, 64, 250, 300),
+                                             (608, 544, 288, 500, 777)])
+def test_all_gemm_layouts_exact_on_integers(d0, d1, d2, n_src, n):
     """Forward (row x row, gathered rows, bias + ReLU, linear path), backward-data
     ((dz W) masked by the ReLU) and weight-gradient (column x column, gathered
     rows) layouts, each checked bit for bit: small integer operands keep every
     product, every FP32 sum and every BF16-stored activation exact, so the result
-    must equal an int64 numpy computation.  Sizes span several 128-wide tiles in
-    every dimension with ragged edges."""
+    must equal an int64 numpy computation.  Sizes span several tiles in every
+    dimension with ragged edges; the second case puts every layout on 256 x 256
+    tiles (both sides >= 256) with a K tail of 9 rows in the weight gradients."""
     import torch
     import paper_2107_05397_amd as uf
     rng = np.random.default_rng(77)
-    d0, d1, d2, n_src, n = 288, 160, 64, 250, 300
     x = rng.integers(-1, 2, size=(n_src, d0))
     w1 = np.zeros((d1, d0), dtype=np.int64)            # 100 entries of +-1 per row: |h1| <= 103
     for r in range(d1):
         w1[r, rng.choice(d0, size=100, replace=False)] = rng.choice([-1, 1], size=100)
     b1 = rng.integers(-3, 4, size=d1)
-    w2 = rng.integers(-1, 2, size=(d2, d1))
+    w2 = np.zeros((d2, d1), dtype=np.int64)            # at most 60 entries of +-1 per column
+    for c in range(d1):
+        w2[rng.choice(d2, size=min(60, d2), replace=False), c] = rng.choice([-1, 1], size=min(60, d2))
     b2 = rng.integers(-3, 4, size=d2)
     sk = rng.integers(-1, 2, size=(d2, d0))
     rows = rng.integers(0, n_src, size=n).astype(np.int32)   # a gather with repeats
-    dz = rng.integers(-2, 3, size=(n, d2))
+    dz = rng.integers(-2, 3, size=(n, d2))             # |dz w2| <= 120: exact in bf16
     mlp = uf.MLP([d0, d1, d2], max_rows=n, params=[(w1, b1), (w2, b2)], skip=sk)
     xt = _t(x, torch.bfloat16)
     rt = _t(rows, torch.int32)
