@@ -57,6 +57,27 @@ hipError_t tripletloss(const float* Z, int64_t T, int D, const float* d_near, co
                        float* loss_mean, hipStream_t st);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                 float b2, float eps, float bc1, float bc2, float wd, uint16_t* pbf, hipStream_t st);
+// Adam / AdamW over up to kAdamMaxTensors tensors in one launch (per tensor: FP32
+// parameters p, gradient g, moments m and v, n elements, decoupled weight decay wd,
+// optional BF16 copy pbf).
+constexpr int kAdamMaxTensors = 20;
+struct AdamTensor {
+    float* p;
+    const float* g;
+    float* m;
+    float* v;
+    uint16_t* pbf;
+    int64_t n;
+    float wd;
+    bool vec;   // set by adam_multi: 16-byte accesses allowed
+};
+struct AdamBatch {
+    AdamTensor t[kAdamMaxTensors];
+    int64_t start[kAdamMaxTensors + 1];   // first 4-element group of each tensor
+    int count;
+};
+hipError_t adam_multi(const AdamTensor* ts, int count, float lr, float b1, float b2, float eps,
+                      float bc1, float bc2, hipStream_t st);
 hipError_t f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st);
 hipError_t sqdist(const float* A, int64_t na, const float* B, int64_t nb, int64_t D, float* out,
                   hipStream_t st);

@@ -6,13 +6,18 @@
 //                      with fused bias / ReLU / ReLU-mask epilogues
 //   k_colsum_*         bias gradients (fixed-order FP64 column sums)
 //   k_pairloss         (||z_a - z_b|| - d)^2 and its gradient
-//   k_adam             Adam on FP32 master weights + BF16 copy
+//   k_tripletloss      ranking loss over (anchor, near, far) triples
+//   k_adam, k_adam_multi   Adam on FP32 master weights + BF16 copy (one tensor,
+//                      or all of an MLP's tensors in one launch)
 //   k_sqdist           FP32 pairwise squared distances (kNN)
 //   k_topk_rows        exact k smallest per row (radix select, ties by index)
 //   k_sparse_*         per-sample lists of (branch, l*u) for nonzero branches
 //   k_rerank           exact weighted-normalized distance across two tables
 //   k_condensed_block, k_gather_pairs   reads of a condensed matrix
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
 
 #include "uf_internal.h"
 #include "uf_place.h"
@@ -145,6 +150,49 @@ __device__ __forceinline__ void gemm_store(float v, int64_t i, int64_t j,
     }
 }
 
+// The epilogue on four consecutive columns j..j+3 of row i (j a multiple of 4,
+// all four inside the matrix): 16-byte FP32 or 8-byte BF16 accesses, each
+// element computed exactly as gemm_store computes it.
+template <int EPI>
+__device__ __forceinline__ void gemm_store4(float4 v, int64_t i, int64_t j,
+                                            const float* __restrict__ bias,
+                                            const uint16_t* __restrict__ mask, int64_t ldm,
+                                            void* __restrict__ C, int64_t ldc) {
+    if (EPI == EPI_F32) {
+        *reinterpret_cast<float4*>(static_cast<float*>(C) + i * ldc + j) = v;
+    } else if (EPI == EPI_ACC_F32) {
+        float4* c = reinterpret_cast<float4*>(static_cast<float*>(C) + i * ldc + j);
+        const float4 o = *c;
+        *c = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+    } else if (EPI == EPI_BIAS_F32) {
+        const float4 b = *reinterpret_cast<const float4*>(bias + j);
+        *reinterpret_cast<float4*>(static_cast<float*>(C) + i * ldc + j) =
+            make_float4(v.x + b.x, v.y + b.y, v.z + b.z, v.w + b.w);
+    } else {
+        uint32_t h0, h1, h2, h3;
+        if (EPI == EPI_BIAS_RELU_BF16) {
+            const float4 b = *reinterpret_cast<const float4*>(bias + j);
+            h0 = f2bf(fmaxf(v.x + b.x, 0.0f));
+            h1 = f2bf(fmaxf(v.y + b.y, 0.0f));
+            h2 = f2bf(fmaxf(v.z + b.z, 0.0f));
+            h3 = f2bf(fmaxf(v.w + b.w, 0.0f));
+        } else if (EPI == EPI_MASK_BF16) {
+            const uint2 mk = *reinterpret_cast<const uint2*>(mask + i * ldm + j);
+            h0 = (mk.x & 0xFFFFu) != 0 ? f2bf(v.x) : 0u;
+            h1 = (mk.x >> 16) != 0 ? f2bf(v.y) : 0u;
+            h2 = (mk.y & 0xFFFFu) != 0 ? f2bf(v.z) : 0u;
+            h3 = (mk.y >> 16) != 0 ? f2bf(v.w) : 0u;
+        } else {
+            h0 = f2bf(v.x);
+            h1 = f2bf(v.y);
+            h2 = f2bf(v.z);
+            h3 = f2bf(v.w);
+        }
+        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(C) + i * ldc + j) =
+            make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+    }
+}
+
 // One operand's share of a K step in a thread's registers: TR rows of the tile,
 // TR/32 uint4 per thread in either layout (row: TR*8 pieces of 16 bytes; col:
 // TR*2 pieces of 4 x 16 bytes).
@@ -159,15 +207,33 @@ struct GemmOperand {
     const int32_t* rows;
     int64_t r0, R, K;
     const uint16_t* rowp[LAY == 0 ? NV : 1];              // row layout: source row of each piece
+    // column layout with a row gather: the storage rows of the next fetch's k,
+    // loaded one fetch ahead so that no fetch waits on its own index loads
+    int32_t ix[LAY == 1 ? NP : 1][4];
 
+    __device__ __forceinline__ void load_ix(int64_t k0, int tid) {
+        if (K <= 0) return;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int64_t kb = k0 + 4 * ((tid + NT * i) % 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ix[i][e] = rows[min(kb + e, K - 1)];
+        }
+    }
+
+    // k_first: the K offset of the first fetch
     __device__ __forceinline__ void init(const uint16_t* P_, int64_t ld_, const int32_t* rows_,
-                                         int64_t r0_, int64_t R_, int64_t K_, int tid) {
+                                         int64_t r0_, int64_t R_, int64_t K_, int tid,
+                                         int64_t k_first) {
         P = P_;
         ld = ld_;
         rows = rows_;
         r0 = r0_;
         R = R_;
         K = K_;
+        if constexpr (LAY == 1) {
+            if (rows) load_ix(k_first, tid);
+        }
         if constexpr (LAY == 0) {
             // rows past the end read the last row (always a valid address)
 #pragma unroll
@@ -189,7 +255,9 @@ struct GemmOperand {
     // row: they only reach output rows or columns that are never stored.  Pieces
     // past K are zeroed when they are written to LDS (stash), so no wait on the
     // loads is placed before the MFMAs that overlap them.
-    __device__ __forceinline__ Regs fetch(int64_t k0, int tid) const {
+    // (k0 advances by one K step per call, except repeats of the last step,
+    // whose data is never used)
+    __device__ __forceinline__ Regs fetch(int64_t k0, int tid) {
         Regs out;
         uint4* v = out.v;
         if constexpr (LAY == 0) {
@@ -208,10 +276,11 @@ struct GemmOperand {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int64_t kcl = min(kb + e, K - 1);
-                    const int64_t src = rows ? int64_t(rows[kcl]) : kcl;
+                    const int64_t src = rows ? int64_t(ix[i][e]) : kcl;
                     v[4 * i + e] = *reinterpret_cast<const uint4*>(P + src * ld + rc);
                 }
             }
+            if (rows) load_ix(k0 + kGemmKS, tid);
         }
         return out;
     }
@@ -259,22 +328,31 @@ struct GemmOperand {
     }
 };
 
-// Block b runs on XCD b mod 8.  Tile t = that XCD's share of the row-major tile
-// order: XCD x takes the x-th eighth (whole runs of row blocks across all column
-// blocks), so the row panels of A it streams are its own and the column panels of
-// B are shared by all its blocks, in its L2.
-__device__ __forceinline__ int64_t gemm_xcd_tile(int64_t b, int64_t n_tiles) {
+// Block b runs on XCD b mod 8 and takes the (b / 8)-th tile of that XCD's
+// eighth of the tiles in grouped order: bands of gh tile rows, column by column
+// inside a band.  An XCD's consecutive tiles then form about a gh x (P / gh)
+// rectangle (P tiles per XCD), whose blocks share gh row panels of A and P / gh
+// column panels of B in the XCD's L2.
+__device__ __forceinline__ void gemm_xcd_tile(int64_t b, int64_t tm, int64_t tn, int64_t gh,
+                                              int64_t& mt, int64_t& nt) {
+    const int64_t n_tiles = tm * tn;
     const int64_t x = b & 7, local = b >> 3;
     const int64_t per = n_tiles >> 3, rem = n_tiles & 7;
-    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int64_t t = x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+    const int64_t band = t / (gh * tn);
+    const int64_t r0 = band * gh;
+    const int64_t h = min(gh, tm - r0);   // the last band may be shorter
+    const int64_t w = t - band * gh * tn;
+    nt = w / h;
+    mt = r0 + w % h;
 }
 
 template <int LA, int LB, int EPI, int BM, int BN, int NT>
-__global__ __launch_bounds__(NT, BM * BN >= 65536 ? 1 : 2) void k_gemm_bf16(
+__global__ __launch_bounds__(NT, BM * BN >= 32768 ? 1 : 2) void k_gemm_bf16(
     const uint16_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ arow,
     const uint16_t* __restrict__ B, int64_t ldb, const int32_t* __restrict__ brow, int64_t M,
     int64_t N, int64_t K, const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-    int64_t ldm, void* __restrict__ C, int64_t ldc, float* __restrict__ part) {
+    int64_t ldm, void* __restrict__ C, int64_t ldc, float* __restrict__ part, int64_t gh) {
     // NT/64 waves in 2 x WJ; a wave owns (BM/2) x (BN/WJ) as XB x YB MFMA blocks
     constexpr int WJ = NT / 128;
     constexpr int XB = BM / 64;          // 32-row blocks per wave
@@ -285,9 +363,9 @@ __global__ __launch_bounds__(NT, BM * BN >= 65536 ? 1 : 2) void k_gemm_bf16(
     static_assert(YB >= 1 && HA >= 1 && HA <= 2 && HB >= 1 && HB <= 2, "GEMM tile shape");
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * kGemmLD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * kGemmLD];
-    const int64_t tn = (N + BN - 1) / BN;
-    const int64_t tile = gemm_xcd_tile(blockIdx.x, int64_t(gridDim.x));
-    const int64_t m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+    int64_t mt, nt;
+    gemm_xcd_tile(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, gh, mt, nt);
+    const int64_t m0 = mt * BM, n0 = nt * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave & 1, wj = wave >> 1;
 
@@ -301,10 +379,10 @@ __global__ __launch_bounds__(NT, BM * BN >= 65536 ? 1 : 2) void k_gemm_bf16(
     // arrays would be kept in memory)
     GemmOperand<LA, TRA, NT> oa0, oa1;
     GemmOperand<LB, TRB, NT> ob0, ob1;
-    oa0.init(A, lda, arow, m0, M, K, tid);
-    if constexpr (HA == 2) oa1.init(A, lda, arow, m0 + TRA, M, K, tid);
-    ob0.init(B, ldb, brow, n0, N, K, tid);
-    if constexpr (HB == 2) ob1.init(B, ldb, brow, n0 + TRB, N, K, tid);
+    oa0.init(A, lda, arow, m0, M, K, tid, t0 * kGemmKS);
+    if constexpr (HA == 2) oa1.init(A, lda, arow, m0 + TRA, M, K, tid, t0 * kGemmKS);
+    ob0.init(B, ldb, brow, n0, N, K, tid, t0 * kGemmKS);
+    if constexpr (HB == 2) ob1.init(B, ldb, brow, n0 + TRB, N, K, tid, t0 * kGemmKS);
 
     floatx16 c[XB][YB];
 #pragma unroll
@@ -368,57 +446,130 @@ __global__ __launch_bounds__(NT, BM * BN >= 65536 ? 1 : 2) void k_gemm_bf16(
         }
     }
 
-    // D of a 32x32 block: lane holds column lane%32, rows 8*(r/4) + 4*(lane/32) + r%4
+    // Epilogue through LDS.  D of a 32x32 block: lane holds column lane%32, rows
+    // 8*(r/4) + 4*(lane/32) + r%4 -- column-wise, so direct stores would be 2 or
+    // 4 bytes per lane.  Once every wave has left the K loop the A stages are
+    // free: each wave stages one 32-row strip of its sub-tile at a time (32 x
+    // 32*YB floats) in an area of its own and reads it back as rows of 4
+    // consecutive columns per lane, for 16-byte FP32 (partial sums) or 8-byte
+    // BF16 stores.  The area is private to the wave, so wave-scope ordering
+    // between its LDS writes and reads suffices.
+    __syncthreads();
+    constexpr int EW = 32 * YB;          // strip width in columns
+    constexpr int EP = EW + 8;           // strip pitch in floats (rows 4 apart on other banks)
+    constexpr int CPR = EW / 4;          // 4-column pieces per strip row
+    static_assert((NT / 64) * 32 * EP * 4 <= int(sizeof(As)), "epilogue staging");
+    float* strip = reinterpret_cast<float*>(&As[0][0]) + wave * (32 * EP);
     const bool split = gridDim.z > 1;
     float* pz = split ? part + int64_t(blockIdx.z) * M * N : nullptr;
+    const int64_t ci0 = m0 + wi * (BM / 2), cj0 = n0 + wj * (BN / WJ);
 #pragma unroll
-    for (int x = 0; x < XB; ++x)
+    for (int x = 0; x < XB; ++x) {
 #pragma unroll
         for (int y = 0; y < YB; ++y)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = m0 + wi * (BM / 2) + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int64_t j = n0 + wj * (BN / WJ) + y * 32 + (lane & 31);
-                if (i >= M || j >= N) continue;
-                if (split) pz[i * N + j] = c[x][y][r];
-                else gemm_store<EPI>(c[x][y][r], i, j, bias, mask, ldm, C, ldc);
-            }
+            for (int r = 0; r < 16; ++r)
+                strip[(8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * EP + 32 * y + (lane & 31)] =
+                    c[x][y][r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 32 * CPR / 64; ++q) {
+            const int pc = lane + 64 * q;
+            const int rr = pc / CPR, cc = pc % CPR;
+            const float4 v = *reinterpret_cast<const float4*>(strip + rr * EP + 4 * cc);
+            const int64_t i = ci0 + 32 * x + rr, j = cj0 + 4 * cc;
+            if (i >= M || j >= N) continue;
+            if (split) *reinterpret_cast<float4*>(pz + i * N + j) = v;
+            else gemm_store4<EPI>(v, i, j, bias, mask, ldm, C, ldc);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
-// Split-K: the ranges' sums added in range order, then the epilogue.
+// Split-K: the ranges' sums added in range order, then the epilogue; four
+// consecutive elements of a row per thread (N is a multiple of 4).
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_reduce(const float* __restrict__ part, int splits,
                                                      int64_t M, int64_t N,
                                                      const float* __restrict__ bias,
                                                      const uint16_t* __restrict__ mask, int64_t ldm,
                                                      void* __restrict__ C, int64_t ldc) {
-    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (idx >= M * N) return;
-    float v = part[idx];
-    for (int z = 1; z < splits; ++z) v += part[int64_t(z) * M * N + idx];
-    gemm_store<EPI>(v, idx / N, idx % N, bias, mask, ldm, C, ldc);
+    const int64_t e = 4 * (int64_t(blockIdx.x) * 256 + threadIdx.x);
+    const int64_t MN = M * N;
+    if (e >= MN) return;
+    float4 v = *reinterpret_cast<const float4*>(part + e);
+    for (int z = 1; z < splits; ++z) {
+        const float4 w = *reinterpret_cast<const float4*>(part + int64_t(z) * MN + e);
+        v = make_float4(v.x + w.x, v.y + w.y, v.z + w.z, v.w + w.w);
+    }
+    const int64_t i = e / N;
+    gemm_store4<EPI>(v, i, e - i * N, bias, mask, ldm, C, ldc);
 }
 
-// Column sums of a BF16 matrix in FP64 in a fixed order: block (x, y) sums rows
-// [y*chunk, (y+1)*chunk) of 256 columns into part[y][cols]; k_colsum_final adds
-// the chunks in order.
+// Column sums of a BF16 [rows][cols] matrix (cols a multiple of 8) in FP64, in a
+// fixed order.  Block (x, y) takes the G = min(cols/8, 256) groups of 8 columns
+// from 8*G*x and rows [y*chunk, (y+1)*chunk): each thread holds one column group
+// and strides over the chunk's rows with 256/G others (16-byte loads), then the
+// row lanes are added in lane order into part[y][cols].  k_colsum_final adds the
+// chunks: 8 lanes per column take every 8th chunk, then are added in lane order.
+constexpr int kColsumChunks = 128;
 __global__ __launch_bounds__(256) void k_colsum_part(const uint16_t* __restrict__ X, int64_t rows,
                                                      int64_t cols, int64_t chunk,
                                                      double* __restrict__ part) {
-    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= cols) return;
+    __shared__ double red[256][9];
+    const int64_t groups = cols / 8;
+    const int G = groups < 256 ? int(groups) : 256;
+    const int R = 256 / G;
+    const int t = threadIdx.x, cg = t % G, rl = t / G;
+    const int64_t grp = int64_t(blockIdx.x) * G + cg;
     const int64_t r0 = int64_t(blockIdx.y) * chunk, r1 = min(rows, r0 + chunk);
-    double s = 0.0;
-    for (int64_t i = r0; i < r1; ++i) s += bf2f(X[i * cols + j]);
-    part[int64_t(blockIdx.y) * cols + j] = s;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (rl < R && grp < groups) {
+        const uint16_t* col = X + 8 * grp;
+        for (int64_t r = r0 + rl; r < r1; r += R) {
+            const uint4 w = *reinterpret_cast<const uint4*>(col + r * cols);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                s[2 * e] += double(__uint_as_float(ws[e] << 16));
+                s[2 * e + 1] += double(__uint_as_float(ws[e] & 0xFFFF0000u));
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[t][e] = s[e];
+    __syncthreads();
+    // column 8*cg' + e' of the block (t' = 8*cg' + e' < 8*G), summed over the R
+    // row lanes
+    for (int t2 = t; t2 < 8 * G; t2 += 256) {
+        const int cg2 = t2 / 8, e2 = t2 % 8;
+        const int64_t g2 = int64_t(blockIdx.x) * G + cg2;
+        if (g2 < groups) {
+            double a = 0.0;
+            for (int k = 0; k < R; ++k) a += red[k * G + cg2][e2];
+            part[int64_t(blockIdx.y) * cols + 8 * g2 + e2] = a;
+        }
+    }
 }
 __global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ part, int chunks,
                                                       int64_t cols, float* __restrict__ out) {
-    const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= cols) return;
+    __shared__ double red[8][32];
+    const int c = threadIdx.x % 32, ln = threadIdx.x / 32;
+    const int64_t j = int64_t(blockIdx.x) * 32 + c;
     double s = 0.0;
-    for (int y = 0; y < chunks; ++y) s += part[int64_t(y) * cols + j];
-    out[j] = float(s);
+    if (j < cols)
+        for (int y = ln; y < chunks; y += 8) s += part[int64_t(y) * cols + j];
+    red[ln][c] = s;
+    __syncthreads();
+    if (ln == 0 && j < cols) {
+        double a = 0.0;
+        for (int k = 0; k < 8; ++k) a += red[k][c];
+        out[j] = float(a);
+    }
 }
 
 // one wave per pair; Z rows [0, P) are the a-ends, [P, 2P) the b-ends
@@ -530,6 +681,57 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
     const float pi = p[i] - lr * ((mi / bc1) / (sqrtf(vi / bc2) + eps) + wd * p[i]);
     p[i] = pi;
     if (pbf) pbf[i] = f2bf(pi);
+}
+
+// Adam over several tensors in one launch: thread t of the launch takes four
+// consecutive elements of the tensor whose range of 4-element groups holds t
+// (16-byte accesses where the tensor allows them); each element is updated
+// exactly as k_adam updates it.
+__device__ __forceinline__ float adam_elem(float& p, float g, float& m, float& v, float lr,
+                                           float b1, float b2, float eps, float bc1, float bc2,
+                                           float wd) {
+    const float mi = b1 * m + (1.0f - b1) * g;
+    const float vi = b2 * v + (1.0f - b2) * g * g;
+    m = mi;
+    v = vi;
+    p = p - lr * ((mi / bc1) / (sqrtf(vi / bc2) + eps) + wd * p);
+    return p;
+}
+__global__ __launch_bounds__(256) void k_adam_multi(AdamBatch ab, float lr, float b1, float b2,
+                                                    float eps, float bc1, float bc2) {
+    const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (q >= ab.start[ab.count]) return;
+    int k = 0;
+    while (q >= ab.start[k + 1]) ++k;
+    const AdamTensor& t = ab.t[k];
+    const int64_t i0 = 4 * (q - ab.start[k]);
+    if (t.vec) {   // n % 4 == 0, 16-byte aligned FP32 arrays, 8-byte aligned BF16 copy
+        float4 p = *reinterpret_cast<const float4*>(t.p + i0);
+        const float4 g = *reinterpret_cast<const float4*>(t.g + i0);
+        float4 m = *reinterpret_cast<const float4*>(t.m + i0);
+        float4 v = *reinterpret_cast<const float4*>(t.v + i0);
+        adam_elem(p.x, g.x, m.x, v.x, lr, b1, b2, eps, bc1, bc2, t.wd);
+        adam_elem(p.y, g.y, m.y, v.y, lr, b1, b2, eps, bc1, bc2, t.wd);
+        adam_elem(p.z, g.z, m.z, v.z, lr, b1, b2, eps, bc1, bc2, t.wd);
+        adam_elem(p.w, g.w, m.w, v.w, lr, b1, b2, eps, bc1, bc2, t.wd);
+        *reinterpret_cast<float4*>(t.p + i0) = p;
+        *reinterpret_cast<float4*>(t.m + i0) = m;
+        *reinterpret_cast<float4*>(t.v + i0) = v;
+        if (t.pbf)
+            *reinterpret_cast<uint2*>(t.pbf + i0) =
+                make_uint2(f2bf(p.x) | (uint32_t(f2bf(p.y)) << 16), f2bf(p.z) | (uint32_t(f2bf(p.w)) << 16));
+        return;
+    }
+    const int64_t cnt = min(int64_t(4), t.n - i0);
+    for (int64_t e = 0; e < cnt; ++e) {
+        const int64_t i = i0 + e;
+        float p = t.p[i], m = t.m[i], v = t.v[i];
+        adam_elem(p, t.g[i], m, v, lr, b1, b2, eps, bc1, bc2, t.wd);
+        t.m[i] = m;
+        t.v[i] = v;
+        t.p[i] = p;
+        if (t.pbf) t.pbf[i] = f2bf(p);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ x, int64_t n,
@@ -809,11 +1011,12 @@ hipError_t project(const Emb& e, const int32_t* dims, const int8_t* signs, int p
 }
 
 // Launch plan of one GEMM: 256 x 256 tiles when both sides have at least 256
-// rows (each wave then runs 64 MFMAs per K step between barriers); else
-// 256 x 128 while those still give every CU a block; else 128 x 128 (two blocks
-// per CU).  K is split in powers of two while the blocks do not fill the CUs'
-// slots, every range keeps at least four K steps and the partial sums fit in
-// part_elems floats.
+// rows (each wave then runs 64 MFMAs per K step between barriers) and K has
+// more than four steps or the tiles fill the CUs; else 256 x 128 while those
+// still give every CU a block; else 128 x 128 (two blocks per CU).  K is split into s ranges (s a power of two, every range at least
+// four K steps, the partial sums within part_elems floats) for the s of least
+// estimated time: rounds of blocks over the CUs' slots times the K steps per
+// range, plus, for s > 1, writing and re-reading the s partial matrices.
 hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, const int32_t* arow,
                      const uint16_t* B, int64_t ldb, const int32_t* brow, int64_t M, int64_t N,
                      int64_t K, const float* bias, const uint16_t* mask, int64_t ldm, void* C,
@@ -822,26 +1025,55 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     if (K < 0) return hipErrorInvalidValue;
     // the 16-byte loads: row layout reads 8 consecutive k, column layout 8
     // consecutive rows, from 16-byte aligned storage rows
-    auto aligned = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
-    if (!aligned(A) || !aligned(B) || lda % 8 || ldb % 8) return hipErrorInvalidValue;
+    auto aligned = [](const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+    if (!aligned(A, 16) || !aligned(B, 16) || lda % 8 || ldb % 8) return hipErrorInvalidValue;
     if ((la == 0 ? K : M) % 8 || (lb == 0 ? K : N) % 8) return hipErrorInvalidValue;
+    // the epilogue writes 4 consecutive columns: 16-byte FP32 or 8-byte BF16
+    // stores, 16-byte bias and 8-byte mask reads
+    const bool f32_out = epi == EPI_F32 || epi == EPI_ACC_F32 || epi == EPI_BIAS_F32;
+    if (N % 4 || ldc % 4 || !aligned(C, f32_out ? 16 : 8)) return hipErrorInvalidValue;
+    if ((epi == EPI_BIAS_RELU_BF16 || epi == EPI_BIAS_F32) && !aligned(bias, 16))
+        return hipErrorInvalidValue;
+    if (epi == EPI_MASK_BF16 && (ldm % 4 || !aligned(mask, 8))) return hipErrorInvalidValue;
+    if (part && !aligned(part, 16)) return hipErrorInvalidValue;
+    const int64_t nk = (K + kGemmKS - 1) / kGemmKS;
     int bm = 128, bn = 128;
-    if (M >= 256 && N >= 256) bm = bn = 256;
-    else if ((M + 255) / 256 * ((N + 127) / 128) >= 256) bm = 256;
+    // (with at most four K steps, 256 x 256 tiles would leave CUs idle through
+    // the epilogue when they do not fill every CU)
+    if (M >= 256 && N >= 256 && (nk > 4 || (M / 256) * (N / 256) >= 256)) bm = bn = 256;
+    else if (M >= 256 && (M + 255) / 256 * ((N + 127) / 128) >= 256) bm = 256;
     const int64_t tn = (N + bn - 1) / bn;
     const int64_t tm = (M + bm - 1) / bm;
-    const int64_t slots = bm * bn >= 65536 ? 256 : 512;
-    const int64_t nk = (K + kGemmKS - 1) / kGemmKS;
+    const int64_t slots = bm * bn >= 32768 ? 256 : 512;   // blocks resident at once (LDS)
+    // K step of a block ~3 us at 256 x 256 (2 us smaller); partial sums move at
+    // ~5 TB/s (written once, read once by the reduction)
+    const double t_step = bm * bn >= 65536 ? 3.0e-6 : 2.0e-6;
+    auto cost = [&](int64_t s) {
+        const int64_t rounds = (tm * tn * s + slots - 1) / slots;
+        const double t = double(rounds) * double((nk + s - 1) / s) * t_step;
+        return s > 1 ? t + double(2 * s + 1) * double(M * N) * 4.0 / 5.0e12 : t;
+    };
     int64_t splits = 1;
-    while (part && tm * tn * splits < slots && nk / (2 * splits) >= 4 &&
-           2 * splits * M * N <= part_elems)
-        splits *= 2;
+    double best = cost(1);
+    for (int64_t s = 2; part && nk / s >= 4 && s * M * N <= part_elems; s *= 2)
+        if (cost(s) < best) {
+            best = cost(s);
+            splits = s;
+        }
     if (tm * tn > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid{unsigned(tm * tn), 1u, unsigned(splits)};
+    // band height of the tile order: the divisor of an XCD's share P nearest
+    // sqrt(P), at most tm
+    const int64_t per_xcd = (tm * tn + 7) / 8;
+    int64_t gh = 1;
+    for (int64_t h = 1; h <= std::min(tm, per_xcd); ++h)
+        if (per_xcd % h == 0 && std::abs(double(h) - std::sqrt(double(per_xcd))) <
+                                    std::abs(double(gh) - std::sqrt(double(per_xcd))))
+            gh = h;
     bool launched = false;
 #define UF_GEMM_T(LA_, LB_, EPI_, BM_, BN_, NT_)                                                \
     hipLaunchKernelGGL((k_gemm_bf16<LA_, LB_, EPI_, BM_, BN_, NT_>), grid, dim3(NT_), 0, st, A,  \
-                       lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part)
+                       lda, arow, B, ldb, brow, M, N, K, bias, mask, ldm, C, ldc, part, gh)
 #define UF_GEMM(LA_, LB_, EPI_)                                                                  \
     if (!launched && la == LA_ && lb == LB_ && epi == EPI_) {                                    \
         if (bn == 256)                                                                           \
@@ -864,7 +1096,7 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     if (!launched) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || splits == 1) return e;
-    const dim3 rg{unsigned((M * N + 255) / 256)};
+    const dim3 rg{unsigned((M * N / 4 + 255) / 256)};
     switch (epi) {
         case EPI_BIAS_RELU_BF16:
             hipLaunchKernelGGL(k_gemm_reduce<EPI_BIAS_RELU_BF16>, rg, dim3(256), 0, st, part,
@@ -892,18 +1124,24 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
 hipError_t colsum_bf16(const uint16_t* X, int64_t rows, int64_t cols, double* part,
                        int64_t part_elems, float* out, hipStream_t st) {
     if (cols <= 0) return hipSuccess;
-    if (rows < 0 || !part || part_elems < cols) return hipErrorInvalidValue;
-    int64_t chunks = rows / 128 < 64 ? rows / 128 : 64;
-    if (chunks < 1) chunks = 1;
+    if (rows < 0 || !part || part_elems < cols || cols % 8 ||
+        (reinterpret_cast<uintptr_t>(X) & 15u))
+        return hipErrorInvalidValue;
+    const int64_t groups = cols / 8;
+    const int64_t G = groups < 256 ? groups : 256;
+    const int64_t gx = (groups + G - 1) / G;
+    // about kColsumChunks chunks of at least 16 rows, as far as part holds them
+    int64_t chunks = std::min<int64_t>(kColsumChunks, std::max<int64_t>(rows / 16, 1));
     while (chunks > 1 && chunks * cols > part_elems) chunks /= 2;
-    const int64_t chunk = (rows + chunks - 1) / chunks;
-    if (chunk > 0) chunks = (rows + chunk - 1) / chunk;
-    const unsigned gx = unsigned((cols + 255) / 256);
-    hipLaunchKernelGGL(k_colsum_part, dim3(gx, unsigned(chunks)), dim3(256), 0, st, X, rows, cols,
-                       chunk, part);
+    const int64_t chunk = std::max<int64_t>((rows + chunks - 1) / chunks, 1);
+    chunks = std::max<int64_t>((rows + chunk - 1) / chunk, 1);
+    if (gx > 0x7fffffff || chunks > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colsum_part, dim3(unsigned(gx), unsigned(chunks)), dim3(256), 0, st, X,
+                       rows, cols, chunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_final, dim3(gx), dim3(256), 0, st, part, int(chunks), cols, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3(unsigned((cols + 31) / 32)), dim3(256), 0, st, part,
+                       int(chunks), cols, out);
     return hipGetLastError();
 }
 
@@ -935,6 +1173,27 @@ hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float l
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr,
                        b1, b2, eps, bc1, bc2, wd, pbf);
+    return hipGetLastError();
+}
+
+hipError_t adam_multi(const AdamTensor* ts, int count, float lr, float b1, float b2, float eps,
+                      float bc1, float bc2, hipStream_t st) {
+    if (count < 0 || count > kAdamMaxTensors) return hipErrorInvalidValue;
+    AdamBatch ab{};
+    ab.count = count;
+    ab.start[0] = 0;
+    auto al = [](const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; };
+    for (int k = 0; k < count; ++k) {
+        if (ts[k].n < 0) return hipErrorInvalidValue;
+        ab.t[k] = ts[k];
+        ab.t[k].vec = ts[k].n % 4 == 0 && al(ts[k].p, 16) && al(ts[k].g, 16) && al(ts[k].m, 16) &&
+                      al(ts[k].v, 16) && al(ts[k].pbf, 8);
+        ab.start[k + 1] = ab.start[k] + (ts[k].n + 3) / 4;
+    }
+    const int64_t groups = ab.start[count];
+    if (groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam_multi, dim3(unsigned((groups + 255) / 256)), dim3(256), 0, st, ab, lr,
+                       b1, b2, eps, bc1, bc2);
     return hipGetLastError();
 }
 

@@ -437,16 +437,16 @@ uf_status uf_mlp_adam(uf_mlp* m, float lr, float beta1, float beta2, float eps,
         const float bc1 = float(1.0 - std::pow(double(beta1), double(step)));
         const float bc2 = float(1.0 - std::pow(double(beta2), double(step)));
         ufh::ProfGuard pa("encoder_adam", s);
+        // every weight, bias and the linear path in one launch
+        std::vector<ufp::AdamTensor> ts;
         for (int64_t l = 0; l < m->L; ++l) {
-            const int64_t nw = m->dims[l + 1] * m->dims[l], nb = m->dims[l + 1];
-            UF_HIP(ufp::adam(m->W[l], m->gW[l], m->mW[l], m->vW[l], nw, lr, beta1, beta2, eps, bc1, bc2,
-                             weight_decay, m->Wbf[l], s));
-            UF_HIP(ufp::adam(m->b[l], m->gb[l], m->mb[l], m->vb[l], nb, lr, beta1, beta2, eps, bc1, bc2,
-                             0.0f, nullptr, s));
+            ts.push_back({m->W[l], m->gW[l], m->mW[l], m->vW[l], m->Wbf[l],
+                          m->dims[l + 1] * m->dims[l], weight_decay});
+            ts.push_back({m->b[l], m->gb[l], m->mb[l], m->vb[l], nullptr, m->dims[l + 1], 0.0f});
         }
         if (m->skip)
-            UF_HIP(ufp::adam(m->S, m->gS, m->mS, m->vS, m->dims[m->L] * m->dims[0], lr, beta1, beta2, eps,
-                             bc1, bc2, weight_decay, m->Sbf, s));
+            ts.push_back({m->S, m->gS, m->mS, m->vS, m->Sbf, m->dims[m->L] * m->dims[0], weight_decay});
+        UF_HIP(ufp::adam_multi(ts.data(), int(ts.size()), lr, beta1, beta2, eps, bc1, bc2, s));
         return UF_OK;
     });
 }

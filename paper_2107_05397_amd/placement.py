@@ -49,14 +49,13 @@ def train(x, pair_a: np.ndarray, pair_b: np.ndarray, target, dims: Sequence[int]
     step = 0
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(P).astype(np.int64), device="cuda")
+        # the epoch's order applied once; every batch is then a contiguous slice
+        pa_e, pb_e, tg_e = pa_all[perm], pb_all[perm], target[perm]
         acc = torch.zeros(1, dtype=torch.float64, device="cuda")
         nb = 0
         for b0 in range(0, P - batch_pairs + 1 if P >= batch_pairs else 1, batch_pairs):
-            sel = perm[b0:b0 + batch_pairs]
-            pa = pa_all[sel].contiguous()
-            pb = pb_all[sel].contiguous()
-            tg = target[sel].contiguous()
-            mlp.loss_grad(x, pa, pb, tg, loss=loss, rel_floor=rel_floor)
+            s_ = slice(b0, b0 + batch_pairs)
+            mlp.loss_grad(x, pa_e[s_], pb_e[s_], tg_e[s_], loss=loss, rel_floor=rel_floor)
             step += 1
             mlp.adam(lr, step, weight_decay=weight_decay)
             acc += loss
@@ -86,12 +85,14 @@ def train_triplets(x, anchor: np.ndarray, near: np.ndarray, far: np.ndarray, d_n
     step = 0
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(T).astype(np.int64), device="cuda")
+        # the epoch's order applied once; every batch is then a contiguous slice
+        a_e, p_e, q_e = (v[perm] for v in dev)
+        dn_e, df_e = d_near[perm], d_far[perm]
         acc = torch.zeros(1, dtype=torch.float64, device="cuda")
         nb = 0
         for b0 in range(0, T - batch_triples + 1 if T >= batch_triples else 1, batch_triples):
-            sel = perm[b0:b0 + batch_triples]
-            a, p, q = (v[sel].contiguous() for v in dev)
-            mlp.triplet_loss_grad(x, a, p, q, d_near[sel].contiguous(), d_far[sel].contiguous(),
+            s_ = slice(b0, b0 + batch_triples)
+            mlp.triplet_loss_grad(x, a_e[s_], p_e[s_], q_e[s_], dn_e[s_], df_e[s_],
                                   rank_weight=rank_weight, tau=tau, dist_weight=dist_weight,
                                   loss=loss)
             step += 1
