@@ -1045,13 +1045,17 @@ hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, co
     const int64_t tn = (N + bn - 1) / bn;
     const int64_t tm = (M + bm - 1) / bm;
     const int64_t slots = bm * bn >= 32768 ? 256 : 512;   // blocks resident at once (LDS)
-    // K step of a block ~3 us at 256 x 256 (2 us smaller); partial sums move at
-    // ~5 TB/s (written once, read once by the reduction)
-    const double t_step = bm * bn >= 65536 ? 3.0e-6 : 2.0e-6;
+    // Measured on MI355X: a K step of a block takes ~2.3 us at 256 x 256 (~2 us
+    // smaller); a block's epilogue stores its tile at ~40 GB/s (4-byte partial
+    // sums, or the output's width); the reduction reads the s partial matrices
+    // and writes the output at ~6 TB/s.
+    const double t_step = bm * bn >= 65536 ? 2.3e-6 : 2.0e-6;
+    const double out_b = f32_out ? 4.0 : 2.0;
     auto cost = [&](int64_t s) {
         const int64_t rounds = (tm * tn * s + slots - 1) / slots;
-        const double t = double(rounds) * double((nk + s - 1) / s) * t_step;
-        return s > 1 ? t + double(2 * s + 1) * double(M * N) * 4.0 / 5.0e12 : t;
+        const double epi = double(bm * bn) * (s > 1 ? 4.0 : out_b) / 40.0e9;
+        const double t = double(rounds) * (double((nk + s - 1) / s) * t_step + epi);
+        return s > 1 ? t + double(M * N) * (4.0 * double(s) + out_b) / 6.0e12 : t;
     };
     int64_t splits = 1;
     double best = cost(1);
