@@ -209,22 +209,30 @@ char* split_scratch(uf_embedding* e, size_t bytes, uf_status* st) {
     return static_cast<char*>(e->split_tmp.buf);
 }
 
-// Samples touching each branch (device, then host).  Both variants' splits
-// classify branches by these counts.
+// Samples touching each branch.  Both variants' splits classify branches by
+// these counts.  The device puts +1 / -1 points on positions (ufs::branch_points);
+// positions are in postorder, so the subtree of position v is the range
+// [sub_first[v], v], and the count of branch v is the sum of the points there:
+// a difference of two prefix sums (host, exact integers).
 uf_status branch_counts(uf_embedding* e, hipStream_t s, std::vector<int32_t>* out) {
     const int64_t nb = e->nb;
     uf_status st = UF_OK;
     char* tmp = split_scratch(e, size_t(std::max<int64_t>(nb, 1)) * 4 + 256, &st);
     if (!tmp) return st;
-    int32_t* dcnt = reinterpret_cast<int32_t*>(tmp);
-    out->assign(size_t(std::max<int64_t>(nb, 1)), 0);
+    int32_t* dpt = reinterpret_cast<int32_t*>(tmp);
+    std::vector<int32_t> pt(size_t(std::max<int64_t>(nb, 1)), 0);
     {
         ProfScope ps("branch_count", s);
-        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dcnt), std::max<int64_t>(nb, 1), s));
-        UF_HIP(ufs::branch_count(emb_view(*e), dcnt, s));
+        UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dpt), std::max<int64_t>(nb, 1), s));
+        UF_HIP(ufs::branch_points(emb_view(*e), dpt, s));
     }
     UF_HIP(hipStreamSynchronize(s));
-    if (nb) UF_HIP(hipMemcpy(out->data(), dcnt, size_t(nb) * 4, hipMemcpyDeviceToHost));
+    if (nb) UF_HIP(hipMemcpy(pt.data(), dpt, size_t(nb) * 4, hipMemcpyDeviceToHost));
+    std::vector<int64_t> pre(size_t(nb) + 1, 0);   // pre[k] = sum of pt[0, k)
+    for (int64_t v = 0; v < nb; ++v) pre[size_t(v) + 1] = pre[size_t(v)] + pt[size_t(v)];
+    out->assign(size_t(std::max<int64_t>(nb, 1)), 0);
+    for (int64_t v = 0; v < nb; ++v)
+        (*out)[size_t(v)] = int32_t(pre[size_t(v) + 1] - pre[size_t(e->sub_first[size_t(v)])]);
     return UF_OK;
 }
 
@@ -1032,6 +1040,9 @@ uf_status embed_impl(const uf_tree* t, const uf_table* tb, void* stream, uf_embe
         int32_t* tpos = reinterpret_cast<int32_t*>(b + o_tpos);
         e->parent_pos = ppos;
         e->tip_pos = tpos;
+        // first position of each position's subtree: its leftmost tip's
+        e->sub_first.resize(size_t(nb));
+        for (int64_t k = 0; k < nb; ++k) e->sub_first[size_t(k)] = t->tip_pos[size_t(t->lo[size_t(k)])];
         double* dd64 = reinterpret_cast<double*>(b + o_d64);
         double* dd32 = reinterpret_cast<double*>(b + o_d32);
         double* ddbf = reinterpret_cast<double*>(b + o_dbf);

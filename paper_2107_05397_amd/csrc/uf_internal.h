@@ -124,6 +124,7 @@ struct uf_embedding {
     std::mutex split_mu;
     int32_t* parent_pos = nullptr;  // [nb+1], -1 for the root
     int32_t* tip_pos = nullptr;     // [n_tips] position of the tip with rank r
+    std::vector<int32_t> sub_first; // host, [nb]: first position of each position's subtree
     // root distances by position for the three length roundings (per-sample scalars)
     double* d64 = nullptr;
     double* d32 = nullptr;

@@ -41,7 +41,10 @@ struct SlotEntry {
     unsigned long long v;
 };
 
-hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st);
+// Per position, +1 for every sample with that tip and -1 for every sample whose
+// consecutive tips meet there: the sum over a subtree is the number of samples
+// touching the branch above it.
+hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st);
 // Unsorted list members (sample, fixed-point l*u), sigma, per-sample list counts
 // (scnt) and per-sample counts of dense branches of nonzero length (dnnz).
 hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,

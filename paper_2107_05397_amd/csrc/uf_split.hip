@@ -35,11 +35,25 @@ namespace {
 
 constexpr double kFix = 1099511627776.0;   // 2^40
 
-__global__ __launch_bounds__(256) void k_branch_count(ufp::Emb e, int32_t* __restrict__ cnt) {
+// Points whose subtree sums count the samples touching each branch: per sample,
+// +1 at each of its tips and -1 at the lowest common ancestor of each tip and
+// the sample's previous tip (in rank order).  The tips of a sample below a node
+// are consecutive in rank order, so a subtree holding k >= 1 of them holds the
+// k - 1 ancestors of their consecutive pairs and sums to 1.  The walk up from a
+// tip stops at exactly that ancestor (the first node whose leaf interval also
+// covers the previous tip); the root is never counted.
+__global__ __launch_bounds__(256) void k_branch_points(ufp::Emb e, int32_t* __restrict__ pt) {
     const int64_t s = blockIdx.x;
     const int64_t a = e.row_ptr[s], b = e.row_ptr[s + 1];
-    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256)
-        ufd::for_each_branch(e, ent, a, [&](int32_t v) { atomicAdd(&cnt[v], 1); });
+    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        const int32_t r = e.rank[ent];
+        const int32_t prev = ent > a ? e.rank[ent - 1] : -1;
+        const int32_t tip = e.tip_pos[r];
+        int32_t v = tip;
+        while (v < e.root_pos && e.lo[v] > prev) v = e.parent_pos[v];
+        if (tip < e.root_pos) atomicAdd(&pt[tip], 1);
+        if (v < e.root_pos) atomicAdd(&pt[v], -1);
+    }
 }
 
 // Unsorted list fill: members of each shared non-dense branch's list (sample,
@@ -589,9 +603,9 @@ __global__ __launch_bounds__(kSlotThreads) void k_rare_slots(
 
 }  // namespace
 
-hipError_t branch_count(const ufp::Emb& e, int32_t* cnt, hipStream_t st) {
+hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st) {
     if (e.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_branch_count, dim3(unsigned(e.n)), dim3(256), 0, st, e, cnt);
+    hipLaunchKernelGGL(k_branch_points, dim3(unsigned(e.n)), dim3(256), 0, st, e, pt);
     return hipGetLastError();
 }
 
