@@ -401,8 +401,8 @@ uf_status build_split(uf_embedding* e, int weighted, double thr, const std::vect
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(scur), int64_t(nn), s));
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dnnz), int64_t(nn), s));
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(sc->sigma), int64_t(nn) * 2, s));
-        UF_HIP(ufs::split_fill(ev, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma, scnt, dnnz,
-                               1.0 / sc->unit, s));
+        UF_HIP(ufs::split_fill(ev, weighted != 0, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma,
+                               scnt, dnnz, 1.0 / sc->unit, s));
     }
     std::vector<int32_t> hcnt(nn, 0), hdnnz(nn, 0);
     std::vector<double> hsw(nn, 0.0);

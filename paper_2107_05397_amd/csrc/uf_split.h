@@ -45,11 +45,12 @@ struct SlotEntry {
 // consecutive tips meet there: the sum over a subtree is the number of samples
 // touching the branch above it.
 hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st);
-// Unsorted list members (sample, fixed-point l*u), sigma, per-sample list counts
-// (scnt) and per-sample counts of dense branches of nonzero length (dnnz).
-hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
-                      int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
-                      int32_t* dnnz, double fix, hipStream_t st);
+// Unsorted list members and per-sample list counts (scnt); weighted, also each
+// member's fixed-point l*u (rq), sigma and per-sample counts of dense branches of
+// nonzero length (dnnz), which the unweighted split leaves untouched.
+hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, const int64_t* roff,
+                      int32_t* rfill, int32_t* rs, int64_t* rq, unsigned long long* sigma,
+                      int32_t* scnt, int32_t* dnnz, double fix, hipStream_t st);
 // Lists of at most kSortSmall members are ranked by one wave each; longer ones by
 // one workgroup each.
 constexpr int kSortSmall = 64;

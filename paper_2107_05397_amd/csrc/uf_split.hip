@@ -56,9 +56,11 @@ __global__ __launch_bounds__(256) void k_branch_points(ufp::Emb e, int32_t* __re
     }
 }
 
-// Unsorted list fill: members of each shared non-dense branch's list (sample,
-// fixed-point l*u), sigma per sample, the number of lists of each sample, and the
-// number of dense branches of nonzero length it touches.
+// Unsorted list fill: members of each shared non-dense branch's list and the
+// number of lists of each sample; weighted (W) also each member's fixed-point
+// l*u, sigma per sample and the number of dense branches of nonzero length it
+// touches (the unweighted lists need the samples alone).
+template <bool W>
 __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* __restrict__ cls,
                                                     const int64_t* __restrict__ roff,
                                                     int32_t* __restrict__ rfill,
@@ -72,26 +74,37 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
     const double inv_t = 1.0 / e.total[s];
     unsigned long long part = 0;
     int32_t lists = 0, dense = 0;
-    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256)
+    for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        // the sample's entries under a branch v of this walk are [ent, p2): none
+        // before ent lies under v (v does not cover the previous tip), and p2, the
+        // first entry at rank >= hi_v, only moves forward as the walk climbs
+        int64_t p2 = ent + 1;
         ufd::for_each_branch(e, ent, a, [&](int32_t v) {
             const int32_t c = cls[v];
             if (c == kClassDense) {
-                dense += e.len[v] > 0.0;
+                if constexpr (W) dense += e.len[v] > 0.0;
                 return;
             }
-            const int64_t cn = ufd::count_in(e, s, e.lo[v], e.hi[v]);
-            const long long q = llrint(e.len[v] * (double(cn) * inv_t) * fix);
-            part += (unsigned long long)q;
+            long long q = 0;
+            if constexpr (W) {
+                p2 = ufd::lower_bound_rank(e.rank, p2, b, e.hi[v]);
+                const int64_t cn = e.cum[p2 + s] - e.cum[ent + s];
+                q = llrint(e.len[v] * (double(cn) * inv_t) * fix);
+                part += (unsigned long long)q;
+            }
             if (c >= 0) {
                 const int32_t slot = atomicAdd(&rfill[c], 1);
                 rs[roff[c] + slot] = int32_t(s);
-                rq[roff[c] + slot] = q;
+                if constexpr (W) rq[roff[c] + slot] = q;
                 ++lists;
             }
         });
-    atomicAdd(&sigma[s], part);
+    }
+    if constexpr (W) {
+        atomicAdd(&sigma[s], part);
+        if (dense) atomicAdd(&dnnz[s], dense);
+    }
     if (lists) atomicAdd(&scnt[s], lists);
-    if (dense) atomicAdd(&dnnz[s], dense);
 }
 
 // Sort each list by sample: a member's new position is the number of members
@@ -107,7 +120,7 @@ __device__ __forceinline__ void place_member(int64_t L, int64_t base, int64_t k,
                                              const int64_t* __restrict__ soff,
                                              int32_t* __restrict__ scur, int32_t m,
                                              SlotEntry* __restrict__ se) {
-    const unsigned long long q = (unsigned long long)rq_in[base + k];
+    const unsigned long long q = rw_out ? (unsigned long long)rq_in[base + k] : 0ull;
     if (rw_out)
         rw_out[base + r] = (q << kSampleBits) | unsigned(smp);
     else
@@ -609,12 +622,16 @@ hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t split_fill(const ufp::Emb& e, const int32_t* cls, const int64_t* roff, int32_t* rfill,
-                      int32_t* rs, int64_t* rq, unsigned long long* sigma, int32_t* scnt,
-                      int32_t* dnnz, double fix, hipStream_t st) {
+hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, const int64_t* roff,
+                      int32_t* rfill, int32_t* rs, int64_t* rq, unsigned long long* sigma,
+                      int32_t* scnt, int32_t* dnnz, double fix, hipStream_t st) {
     if (e.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_split_fill, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff, rfill, rs,
-                       rq, sigma, scnt, dnnz, fix);
+    if (weighted)
+        hipLaunchKernelGGL(k_split_fill<true>, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff,
+                           rfill, rs, rq, sigma, scnt, dnnz, fix);
+    else
+        hipLaunchKernelGGL(k_split_fill<false>, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff,
+                           rfill, rs, rq, sigma, scnt, dnnz, fix);
     return hipGetLastError();
 }
 
