@@ -365,6 +365,7 @@ uf_status build_split(uf_embedding* e, int weighted, double thr, const std::vect
     const size_t t_dnnz = t.take(nn * 4);
     const size_t t_small = t.take(std::max<size_t>(small_ids.size(), 1) * 4);
     const size_t t_large = t.take(std::max<size_t>(large_ids.size(), 1) * 4);
+    const size_t t_nodes = t.take(size_t(std::max<int64_t>(nb, 1)) * 16);
     uf_status sst = UF_OK;
     char* tb = split_scratch(e, t.off + 256, &sst);
     if (!tb) return sst;
@@ -376,6 +377,7 @@ uf_status build_split(uf_embedding* e, int weighted, double thr, const std::vect
     int32_t* dnnz = reinterpret_cast<int32_t*>(tb + t_dnnz);
     int32_t* d_small = reinterpret_cast<int32_t*>(tb + t_small);
     int32_t* d_large = reinterpret_cast<int32_t*>(tb + t_large);
+    int4* nodes = reinterpret_cast<int4*>(tb + t_nodes);
     if (sc->n_dense) UF_HIP(hipMemcpy(sc->dense, dense.data(), size_t(sc->n_dense) * 4, hipMemcpyHostToDevice));
     if (weighted && sc->n_dense) {
         // the dense list in ascending lo, for the merge embedding of the dense chunks
@@ -401,8 +403,8 @@ uf_status build_split(uf_embedding* e, int weighted, double thr, const std::vect
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(scur), int64_t(nn), s));
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(dnnz), int64_t(nn), s));
         UF_HIP(ufk::zero_u32(reinterpret_cast<unsigned*>(sc->sigma), int64_t(nn) * 2, s));
-        UF_HIP(ufs::split_fill(ev, weighted != 0, sc->cls, sc->roff, fill, rs_tmp, rq_tmp, sc->sigma,
-                               scnt, dnnz, 1.0 / sc->unit, s));
+        UF_HIP(ufs::split_fill(ev, weighted != 0, sc->cls, nodes, sc->roff, fill, rs_tmp, rq_tmp,
+                               sc->sigma, scnt, dnnz, 1.0 / sc->unit, s));
     }
     std::vector<int32_t> hcnt(nn, 0), hdnnz(nn, 0);
     std::vector<double> hsw(nn, 0.0);

@@ -47,10 +47,12 @@ struct SlotEntry {
 hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st);
 // Unsorted list members and per-sample list counts (scnt); weighted, also each
 // member's fixed-point l*u (rq), sigma and per-sample counts of dense branches of
-// nonzero length (dnnz), which the unweighted split leaves untouched.
-hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, const int64_t* roff,
-                      int32_t* rfill, int32_t* rs, int64_t* rq, unsigned long long* sigma,
-                      int32_t* scnt, int32_t* dnnz, double fix, hipStream_t st);
+// nonzero length (dnnz), which the unweighted split leaves untouched.  nodes:
+// device scratch of max(nb, 1) records (filled here: the walk's node fields).
+hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, int4* nodes,
+                      const int64_t* roff, int32_t* rfill, int32_t* rs, int64_t* rq,
+                      unsigned long long* sigma, int32_t* scnt, int32_t* dnnz, double fix,
+                      hipStream_t st);
 // Lists of at most kSortSmall members are ranked by one wave each; longer ones by
 // one workgroup each.
 constexpr int kSortSmall = 64;

@@ -56,12 +56,22 @@ __global__ __launch_bounds__(256) void k_branch_points(ufp::Emb e, int32_t* __re
     }
 }
 
+// The fields the list fill reads at every node of its walks, packed in one
+// 16-byte record per position (leaf interval, parent, class) so that a step of a
+// walk touches one cache line.
+__global__ __launch_bounds__(256) void k_pack_nodes(ufp::Emb e, const int32_t* __restrict__ cls,
+                                                    int64_t nb, int4* __restrict__ nodes) {
+    const int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (v < nb) nodes[v] = make_int4(e.lo[v], e.hi[v], e.parent_pos[v], cls[v]);
+}
+
 // Unsorted list fill: members of each shared non-dense branch's list and the
 // number of lists of each sample; weighted (W) also each member's fixed-point
 // l*u, sigma per sample and the number of dense branches of nonzero length it
-// touches (the unweighted lists need the samples alone).
+// touches (the unweighted lists need the samples alone).  The walk is the one of
+// ufd::for_each_branch over the packed node records.
 template <bool W>
-__global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* __restrict__ cls,
+__global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int4* __restrict__ nodes,
                                                     const int64_t* __restrict__ roff,
                                                     int32_t* __restrict__ rfill,
                                                     int32_t* __restrict__ rs,
@@ -75,30 +85,35 @@ __global__ __launch_bounds__(256) void k_split_fill(ufp::Emb e, const int32_t* _
     unsigned long long part = 0;
     int32_t lists = 0, dense = 0;
     for (int64_t ent = a + threadIdx.x; ent < b; ent += 256) {
+        const int32_t prev = ent > a ? e.rank[ent - 1] : -1;
         // the sample's entries under a branch v of this walk are [ent, p2): none
         // before ent lies under v (v does not cover the previous tip), and p2, the
         // first entry at rank >= hi_v, only moves forward as the walk climbs
         int64_t p2 = ent + 1;
-        ufd::for_each_branch(e, ent, a, [&](int32_t v) {
-            const int32_t c = cls[v];
+        int32_t v = e.tip_pos[e.rank[ent]];
+        while (v < e.root_pos) {
+            const int4 nd = nodes[v];   // lo, hi, parent, class
+            if (nd.x <= prev) break;
+            const int32_t c = nd.w;
             if (c == kClassDense) {
                 if constexpr (W) dense += e.len[v] > 0.0;
-                return;
+            } else {
+                long long q = 0;
+                if constexpr (W) {
+                    p2 = ufd::lower_bound_rank(e.rank, p2, b, nd.y);
+                    const int64_t cn = e.cum[p2 + s] - e.cum[ent + s];
+                    q = llrint(e.len[v] * (double(cn) * inv_t) * fix);
+                    part += (unsigned long long)q;
+                }
+                if (c >= 0) {
+                    const int32_t slot = atomicAdd(&rfill[c], 1);
+                    rs[roff[c] + slot] = int32_t(s);
+                    if constexpr (W) rq[roff[c] + slot] = q;
+                    ++lists;
+                }
             }
-            long long q = 0;
-            if constexpr (W) {
-                p2 = ufd::lower_bound_rank(e.rank, p2, b, e.hi[v]);
-                const int64_t cn = e.cum[p2 + s] - e.cum[ent + s];
-                q = llrint(e.len[v] * (double(cn) * inv_t) * fix);
-                part += (unsigned long long)q;
-            }
-            if (c >= 0) {
-                const int32_t slot = atomicAdd(&rfill[c], 1);
-                rs[roff[c] + slot] = int32_t(s);
-                if constexpr (W) rq[roff[c] + slot] = q;
-                ++lists;
-            }
-        });
+            v = nd.z;
+        }
     }
     if constexpr (W) {
         atomicAdd(&sigma[s], part);
@@ -622,15 +637,23 @@ hipError_t branch_points(const ufp::Emb& e, int32_t* pt, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, const int64_t* roff,
-                      int32_t* rfill, int32_t* rs, int64_t* rq, unsigned long long* sigma,
-                      int32_t* scnt, int32_t* dnnz, double fix, hipStream_t st) {
+hipError_t split_fill(const ufp::Emb& e, bool weighted, const int32_t* cls, int4* nodes,
+                      const int64_t* roff, int32_t* rfill, int32_t* rs, int64_t* rq,
+                      unsigned long long* sigma, int32_t* scnt, int32_t* dnnz, double fix,
+                      hipStream_t st) {
     if (e.n <= 0) return hipSuccess;
+    const int64_t nb = e.root_pos;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_pack_nodes, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, e, cls,
+                           nb, nodes);
+        hipError_t er = hipGetLastError();
+        if (er != hipSuccess) return er;
+    }
     if (weighted)
-        hipLaunchKernelGGL(k_split_fill<true>, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff,
+        hipLaunchKernelGGL(k_split_fill<true>, dim3(unsigned(e.n)), dim3(256), 0, st, e, nodes, roff,
                            rfill, rs, rq, sigma, scnt, dnnz, fix);
     else
-        hipLaunchKernelGGL(k_split_fill<false>, dim3(unsigned(e.n)), dim3(256), 0, st, e, cls, roff,
+        hipLaunchKernelGGL(k_split_fill<false>, dim3(unsigned(e.n)), dim3(256), 0, st, e, nodes, roff,
                            rfill, rs, rq, sigma, scnt, dnnz, fix);
     return hipGetLastError();
 }
