@@ -38,15 +38,19 @@ hipError_t project(const Emb& e, const int32_t* dims, const int8_t* signs, int p
                    int out_dim, double scale, uint16_t* out, hipStream_t st);
 // la/lb: 0 = row layout (k contiguous), 1 = column layout (row index contiguous).
 // part: device FP32 scratch of part_elems floats for split-K partial sums
-// (nullable: no split).  Requires 16-byte aligned A and B, lda and ldb
-// multiples of 8, and the contiguous extent of each operand (K for the row
-// layout, M or N for the column layout) a multiple of 8.
+// (nullable: no split; 16-byte aligned).  Requires 16-byte aligned A and B, lda
+// and ldb multiples of 8, the contiguous extent of each operand (K for the row
+// layout, M or N for the column layout) a multiple of 8, and for the epilogue's
+// 4-column stores N and ldc multiples of 4, C 16-byte (FP32 outputs) or 8-byte
+// (BF16) aligned, bias 16-byte aligned, mask 8-byte aligned with ldm a multiple
+// of 4.  Other arguments give hipErrorInvalidValue.
 hipError_t gemm_bf16(int la, int lb, int epi, const uint16_t* A, int64_t lda, const int32_t* arow,
                      const uint16_t* B, int64_t ldb, const int32_t* brow, int64_t M, int64_t N,
                      int64_t K, const float* bias, const uint16_t* mask, int64_t ldm, void* C,
                      int64_t ldc, float* part, int64_t part_elems, hipStream_t st);
 // Column sums of a BF16 [rows][cols] matrix in FP64, fixed order; part: device
-// FP64 scratch of part_elems (>= cols) doubles.
+// FP64 scratch of part_elems (>= cols) doubles.  cols a multiple of 8 and X
+// 16-byte aligned (16-byte loads), else hipErrorInvalidValue.
 hipError_t colsum_bf16(const uint16_t* X, int64_t rows, int64_t cols, double* part,
                        int64_t part_elems, float* out, hipStream_t st);
 hipError_t pairloss(const float* Z, int64_t P, int D, const float* target, float rel_floor,
