@@ -740,45 +740,53 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float* __restrict__ x
     if (i < n) y[i] = f2bf(x[i]);
 }
 
-// out[i][j] = sum_d (a_i[d] - b_j[d])^2 ; 64x64 tiles, 4x4 per thread
+// out[i][j] = sum_d (a_i[d] - b_j[d])^2, d in increasing order (one fused
+// multiply-add per d).  128 x 128 tiles, 8 x 8 per thread; the tile's rows go
+// through LDS 16 dimensions at a time as [d][row], so a thread reads its eight
+// rows of A and of B as two 16-byte loads each.
+constexpr int kSqT = 128, kSqD = 16, kSqP = kSqT + 4;
 __global__ __launch_bounds__(256) void k_sqdist(const float* __restrict__ A, int64_t na,
                                                 const float* __restrict__ B, int64_t nb, int64_t D,
                                                 float* __restrict__ out) {
-    __shared__ float as[32][65];
-    __shared__ float bs[32][65];
+    __shared__ __attribute__((aligned(16))) float as[kSqD][kSqP];
+    __shared__ __attribute__((aligned(16))) float bs[kSqD][kSqP];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int64_t i0 = int64_t(blockIdx.y) * 64, j0 = int64_t(blockIdx.x) * 64;
-    float acc[4][4] = {};
-    for (int64_t d0 = 0; d0 < D; d0 += 32) {
+    const int64_t i0 = int64_t(blockIdx.y) * kSqT, j0 = int64_t(blockIdx.x) * kSqT;
+    float acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int w = 0; w < 8; ++w) acc[u][w] = 0.0f;
+    for (int64_t d0 = 0; d0 < D; d0 += kSqD) {
         __syncthreads();
-        for (int t = threadIdx.x; t < 64 * 32; t += 256) {
-            const int r = t / 32, dd = t % 32;
+        for (int t = threadIdx.x; t < kSqT * kSqD; t += 256) {
+            const int r = t / kSqD, dd = t % kSqD;
             as[dd][r] = (i0 + r < na && d0 + dd < D) ? A[(i0 + r) * D + d0 + dd] : 0.0f;
             bs[dd][r] = (j0 + r < nb && d0 + dd < D) ? B[(j0 + r) * D + d0 + dd] : 0.0f;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int dd = 0; dd < 32; ++dd) {
-            float a[4], b[4];
+        const int dn = int(min<int64_t>(kSqD, D - d0));
+        for (int dd = 0; dd < dn; ++dd) {
+            const float4 a0 = *reinterpret_cast<const float4*>(&as[dd][ty * 8]);
+            const float4 a1 = *reinterpret_cast<const float4*>(&as[dd][ty * 8 + 4]);
+            const float4 b0 = *reinterpret_cast<const float4*>(&bs[dd][tx * 8]);
+            const float4 b1 = *reinterpret_cast<const float4*>(&bs[dd][tx * 8 + 4]);
+            const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const float b[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = as[dd][ty * 4 + u];
-                b[u] = bs[dd][tx * 4 + u];
-            }
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) {
+                for (int w = 0; w < 8; ++w) {
                     const float df = a[u] - b[w];
                     acc[u][w] = fmaf(df, df, acc[u][w]);
                 }
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int64_t i = i0 + ty * 4 + u, j = j0 + tx * 4 + w;
+        for (int w = 0; w < 8; ++w) {
+            const int64_t i = i0 + ty * 8 + u, j = j0 + tx * 8 + w;
             if (i < na && j < nb) out[i * nb + j] = acc[u][w];
         }
 }
@@ -923,11 +931,6 @@ __global__ __launch_bounds__(256) void k_sparse_fill(Emb e, const int64_t* __res
     }
 }
 
-// Exact weighted-normalized distance of query q against each candidate r:
-// sum_v |x_q - x_r| = s_q + s_r - 2 sum_v min(x_q, x_r), where the min is
-// nonzero only on branches both samples touch.  The query is scattered into
-// a dense FP64 row (one per resident block, left zeroed afterwards); each
-// candidate's list gathers from it.  Persistent grid over queries.
 __global__ __launch_bounds__(256) void k_rerank(SparseView q, SparseView rf,
                                                 const int32_t* __restrict__ qids,
                                                 const int32_t* __restrict__ cand, int64_t nq,
@@ -1210,9 +1213,10 @@ hipError_t f32_to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
 hipError_t sqdist(const float* A, int64_t na, const float* B, int64_t nb, int64_t D, float* out,
                   hipStream_t st) {
     if (na <= 0 || nb <= 0) return hipSuccess;
-    if ((na + 63) / 64 > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sqdist, dim3(unsigned((nb + 63) / 64), unsigned((na + 63) / 64)), dim3(256),
-                       0, st, A, na, B, nb, D, out);
+    if ((na + kSqT - 1) / kSqT > 65535 || (nb + kSqT - 1) / kSqT > 0x7fffffff)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sqdist, dim3(unsigned((nb + kSqT - 1) / kSqT), unsigned((na + kSqT - 1) / kSqT)),
+                       dim3(256), 0, st, A, na, B, nb, D, out);
     return hipGetLastError();
 }
 

@@ -118,13 +118,16 @@ def train_step_flops(dims: Sequence[int], rows: int, skip: bool) -> int:
     return 2 * rows * total
 
 
-def place(z_ref, z_q, q_sparse: Sparse, r_sparse: Sparse, k_candidates: int, k: int = 10):
+def place(z_ref, z_q, q_sparse: Sparse, r_sparse: Sparse, k_candidates: int, k: int = 10,
+          d=None):
     """k nearest references of every query: candidates in z-space, exact re-rank.
+    d: the squared z-space distances [nq][n_ref] if already computed (sqdist).
 
     Returns (idx int32 [nq][k], exact FP64 distances [nq][k], candidate idx).
     """
     import torch
-    d = sqdist(z_q, z_ref)
+    if d is None:
+        d = sqdist(z_q, z_ref)
     cand, _ = topk_rows(d, k_candidates)
     del d
     nq = z_q.shape[0]
@@ -314,10 +317,12 @@ def experiment(tree, ref_table, q_table, dims=(4096, 1024, 1024, 128), epochs: i
     x_q = project(t_tree, e_q, pdims, psigns, out_dim=dims[0], scale=input_scale)
     z_q = encode(x_q)
     res = {}
+    d_q = sqdist(z_q, z_ref)   # one z-space distance matrix serves every K'
     for kc in k_candidates:
-        idx, ex, cand = place(z_ref, z_q, s_q, s_ref, kc, k)
+        idx, ex, cand = place(z_ref, z_q, s_q, s_ref, kc, k, d=d_q)
         sync()
         res[kc] = (idx, ex, cand)
+    del d_q
     out["placement_s"] = time.perf_counter() - t3          # project + encode + all kNN/re-rank
     for kc, (idx, ex, cand) in res.items():
         out[f"recall@{k}_kprime{kc}"] = recall_at_k(idx, cross, k)
