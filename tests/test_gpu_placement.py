@@ -152,6 +152,27 @@ def test_gemm_paths_exact_at_encoder_shapes():
     assert np.array_equal(gs.astype(np.float64), dz.T @ xr)
 
 
+@pytest.mark.parametrize("d1,n", [(32, 1), (96, 33), (2080, 17), (1024, 3000), (128, 6144)])
+def test_bias_gradients_and_weight_gradients_exact(d1, n):
+    """One layer: its bias gradient is the column sum of dZ (16-byte column
+    groups, up to 128 row chunks, a second column block above 2,048 columns)
+    and its weight gradient dZ^T x; with small integer operands both are exact
+    and must equal int64 numpy.  Covers a single row, ragged row counts and the
+    column-group layouts of every branch of the column-sum kernel."""
+    import torch
+    import paper_2107_05397_amd as uf
+    rng = np.random.default_rng(d1 + n)
+    d0 = 64
+    x = rng.integers(-2, 3, size=(n, d0))
+    dz = rng.integers(-3, 4, size=(n, d1))
+    w = rng.integers(-1, 2, size=(d1, d0)).astype(np.float64)
+    mlp = uf.MLP([d0, d1], max_rows=max(n, 2), params=[(w, np.zeros(d1))])
+    mlp.backward(_t(x, torch.bfloat16), _t(dz, torch.bfloat16))
+    gw, gb = mlp.get(0, "grads")
+    assert np.array_equal(gb.astype(np.int64), dz.sum(0))
+    assert np.array_equal(gw.astype(np.int64), dz.T @ x)
+
+
 def _mlp_problem(seed=0, dims=(64, 32, 32, 32), n=50, p=40):
     rng = np.random.default_rng(seed)
     x = _bf(rng, (n, dims[0]))
