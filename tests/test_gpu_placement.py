@@ -399,6 +399,30 @@ def test_sparse_rerank_vs_oracle():
     assert np.max(np.abs(got.cpu().numpy() - want)) <= 1e-12
 
 
+def test_rerank_long_lists_vs_oracle():
+    """Samples of 6,000 tips on a 300,000-node tree (about 40,000 branches
+    each): the re-rank against the FP64 oracle on long lists."""
+    import torch
+    import paper_2107_05397_amd as uf
+    tree = synth.gen_tree(150000, 0.05, seed=61)
+    ref = synth.gen_table_zipf(5, np.arange(150000), 6000, seed=62)
+    qry = synth.gen_table_zipf(3, np.arange(150000), 6000, seed=63)
+    t = uf.Tree(tree.parent, tree.length)
+    er = uf.Embedding(t, uf.Table(t, ref.indptr, ref.tips, ref.counts))
+    eq = uf.Embedding(t, uf.Table(t, qry.indptr, qry.tips, qry.counts))
+    sr, sq = uf.Sparse(er), uf.Sparse(eq)
+    assert sq.nnz > 100000
+    nq, nr = qry.n_samples, ref.n_samples
+    cand = np.tile(np.arange(nr, dtype=np.int32), (nq, 1))
+    got = uf.rerank(sq, sr, _t(np.arange(nq, dtype=np.int32), torch.int32), _t(cand, torch.int32))
+    both = synth.Table(indptr=np.concatenate([ref.indptr, ref.indptr[-1] + qry.indptr[1:]]),
+                       tips=np.concatenate([ref.tips, qry.tips]),
+                       counts=np.concatenate([ref.counts, qry.counts]))
+    want = oracle.dm_pairs(tree, both, [(nr + q, r) for q in range(nq) for r in range(nr)],
+                           "weighted_normalized").reshape(nq, nr)
+    assert np.max(np.abs(got.cpu().numpy() - want)) <= 1e-12
+
+
 def test_condensed_reads():
     import torch
     import paper_2107_05397_amd as uf
