@@ -168,6 +168,30 @@ def test_two_segment_slots_exact_and_mergeable(variant, threshold):
     assert err <= 1e-10
 
 
+def test_weighted_split_stripe_range_at_70000_samples(threshold):
+    """N = 70,000 with no dense branch: a stripe-range call (the first 64
+    stripes) through the weighted split; sampled pairs match the oracle within
+    the 2^-40 quantisation of the list values (1e-10)."""
+    import torch
+    import paper_2107_05397_amd as uf
+    n = 70000
+    threshold(1.0, "weighted_normalized")
+    tree = synth.gen_tree(3000, 0.1, seed=71)
+    table = synth.gen_table_zipf(n, np.arange(3000), 12, seed=72)
+    emb = _emb(tree, table)
+    out, _ = uf.dm_stripes(emb, "weighted_normalized", "fp32_split", 0, 64)
+    torch.cuda.synchronize()
+    st = out.cpu().numpy().reshape(64, n)
+    rng = np.random.default_rng(73)
+    ss = rng.integers(0, 64, size=400)
+    ii = rng.integers(0, n, size=400)
+    pairs = [(int(i), int((i + s + 1) % n)) for s, i in zip(ss, ii)]
+    want = oracle.dm_pairs(tree, table, pairs, "weighted_normalized")
+    err = np.abs(st[ss, ii] - want).max()
+    print(f"[weighted split, N={n}, stripes 0-63] max|err|={err:.3e}")
+    assert err <= 1e-10
+
+
 def test_mfma_split_exact_with_integer_lengths(threshold):
     """Integer lengths < 256 are exact in bf16 and their FP32 Gram sums stay below
     2^24, so the dense MFMA part is exact too: the split equals the oracle."""
