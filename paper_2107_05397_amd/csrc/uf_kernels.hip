@@ -290,6 +290,27 @@ __device__ __forceinline__ void band_patch_tile(int64_t l, int64_t n_iblk, int64
 }
 
 // LDS of one band tile of 16*MS stripes: two staging buffers of KS branches.
+// With SWZ, rows are stored in 16-byte quads, quad q of a row at position band_swz(q):
+// the two low bits are flipped by bits 3 and 4, inside each group of four
+// quads.  The fragment reads of a wave start at even quads 2*DW*t (t = 0..15
+// for the sample window), which fall on the same banks for t and t+4 (t and
+// t+8 with 64 banks) when stored in place; with the flip, the first 8 and all
+// 16 of those quads use distinct banks.  The flip never leaves a 64-dword
+// segment, so each direct-to-LDS load still fills one segment, its lanes
+// taking the permuted source columns.  (Without SWZ, quads stay in place: the
+// batch kernel's 256-stripe tiles would need more than 256 VGPRs for the
+// permuted reads' offsets, halving their occupancy, and so would the FP64 tiles.)
+template <bool SWZ>
+__device__ __forceinline__ int band_swz(int q) {
+    return SWZ ? q ^ ((((q >> 3) ^ (q >> 4)) & 1) | ((q >> 2) & 2)) : q;
+}
+template <typename T>
+__device__ __forceinline__ T band_from_dw(const uint32_t* d) {
+    if constexpr (sizeof(T) == 8) return __hiloint2double(int(d[1]), int(d[0]));
+    else if constexpr (std::is_same<T, float>::value) return __uint_as_float(d[0]);
+    else return d[0];
+}
+
 template <typename T, int KS, int MS = 8>
 struct BandLds {
     T wi[2][KS][kBandI];
@@ -302,7 +323,7 @@ struct BandLds {
 // (ti, ts) = (tid % 16, tid / 16) owns the 8 x MS register block of samples
 // i0 + 8ti + [0, 8) and stripes s0 + MS*ts + [0, MS); its partners are the
 // 8 + MS - 1 consecutive samples from i0 + s0 + 1 + 8ti + MS*ts.
-template <typename T, bool W, int KS, int MS = 8>
+template <typename T, bool W, int KS, int MS = 8, bool SWZ = true>
 __device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __restrict__ E,
                                           const T* __restrict__ lenk, int64_t kc, int64_t n,
                                           int64_t sb, int64_t se, int64_t i0, int64_t s0,
@@ -314,13 +335,27 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __rest
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ti = tid & 15, ts = tid >> 4;
 
-    // lane -> (element of its segment, dword of that element)
-    const int part = lane % DW;
+    // lane -> the dword of segment p it fills (its quad at band_swz), as
+    // (element of the segment, dword of that element)
+    auto seg_dword = [&](int p) { return 4 * (band_swz<SWZ>(16 * p + (lane >> 2)) - 16 * p) + (lane & 3); };
     int64_t coli[SEG_I], colj[SEG_J];
 #pragma unroll
-    for (int p = 0; p < SEG_I; ++p) coli[p] = ((i0 + p * EPS + lane / DW) % n) * DW + part;
+    for (int p = 0; p < SEG_I; ++p) {
+        const int dl = seg_dword(p);
+        coli[p] = ((i0 + p * EPS + dl / DW) % n) * DW + dl % DW;
+    }
 #pragma unroll
-    for (int p = 0; p < SEG_J; ++p) colj[p] = ((i0 + s0 + 1 + p * EPS + lane / DW) % n) * DW + part;
+    for (int p = 0; p < SEG_J; ++p) {
+        const int dl = seg_dword(p);
+        colj[p] = ((i0 + s0 + 1 + p * EPS + dl / DW) % n) * DW + dl % DW;
+    }
+    // this thread's fragment quads: 2*DW from its 8 samples, NQJ from its 7+MS partners
+    constexpr int NQI = 2 * DW, NQJ = ((7 + MS) * DW + 3) / 4;
+    int oi[NQI], oj[NQJ];
+#pragma unroll
+    for (int q = 0; q < NQI; ++q) oi[q] = 4 * band_swz<SWZ>(2 * DW * ti + q);
+#pragma unroll
+    for (int q = 0; q < NQJ; ++q) oj[q] = 4 * band_swz<SWZ>((ti * 8 + ts * MS) * DW / 4 + q);
 
     auto stage = [&](int buf, int64_t k0) {
 #pragma unroll
@@ -366,11 +401,18 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __rest
         if (blk + 1 < nblk) stage(cur ^ 1, (blk + 1) * KS);
 #pragma unroll 2
         for (int kk = 0; kk < KS; ++kk) {
+            const uint32_t* rwi = reinterpret_cast<const uint32_t*>(&L.wi[cur][kk][0]);
+            const uint32_t* rwj = reinterpret_cast<const uint32_t*>(&L.wj[cur][kk][0]);
+            uint32_t bi[4 * NQI], bj[4 * NQJ];
+#pragma unroll
+            for (int q = 0; q < NQI; ++q) *reinterpret_cast<uint4*>(bi + 4 * q) = *reinterpret_cast<const uint4*>(rwi + oi[q]);
+#pragma unroll
+            for (int q = 0; q < NQJ; ++q) *reinterpret_cast<uint4*>(bj + 4 * q) = *reinterpret_cast<const uint4*>(rwj + oj[q]);
             T xi[8], xj[8 + MS];
 #pragma unroll
-            for (int a = 0; a < 8; ++a) xi[a] = L.wi[cur][kk][ti * 8 + a];
+            for (int a = 0; a < 8; ++a) xi[a] = band_from_dw<T>(bi + a * DW);
 #pragma unroll
-            for (int c = 0; c < 7 + MS; ++c) xj[c] = L.wj[cur][kk][ti * 8 + ts * MS + c];
+            for (int c = 0; c < 7 + MS; ++c) xj[c] = band_from_dw<T>(bj + c * DW);
             if constexpr (std::is_same<T, uint32_t>::value) {
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
@@ -420,7 +462,7 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
     band_patch_tile(xcd_tile(blockIdx.x, n_tiles), n_iblk, n_sblk, &ib, &sblk);
     const int64_t i0 = ib * kBandI;
     const int64_t s0 = sb + sblk * TS;
-    band_tile<T, W, KS, MS>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
+    band_tile<T, W, KS, MS, sizeof(T) == 4>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
 }
 
 // ----------------------------------------------------------------------------
@@ -977,7 +1019,7 @@ __global__ __launch_bounds__(256) void k_band_persistent_f32(
             const BatchTable t = tabs[it.x];
             const int64_t i0 = (int64_t(it.y) % t.n_iblk) * kBandI;
             const int64_t s0 = (int64_t(it.y) / t.n_iblk) * (16 * MS);
-            band_tile<float, true, KS, MS>(L, E + t.e_off, nullptr, kc, t.n, 0, t.n / 2, i0, s0,
+            band_tile<float, true, KS, MS, false>(L, E + t.e_off, nullptr, kc, t.n, 0, t.n / 2, i0, s0,
                                            first, acc + t.acc_off);
         }
     }
