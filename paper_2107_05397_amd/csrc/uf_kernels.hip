@@ -299,7 +299,7 @@ __device__ __forceinline__ void band_patch_tile(int64_t l, int64_t n_iblk, int64
 // segment, so each direct-to-LDS load still fills one segment, its lanes
 // taking the permuted source columns.  (Without SWZ, quads stay in place: the
 // batch kernel's 256-stripe tiles would need more than 256 VGPRs for the
-// permuted reads' offsets, halving their occupancy, and so would the FP64 tiles.)
+// permuted reads' offsets, halving their occupancy.)
 template <bool SWZ>
 __device__ __forceinline__ int band_swz(int q) {
     return SWZ ? q ^ ((((q >> 3) ^ (q >> 4)) & 1) | ((q >> 2) & 2)) : q;
@@ -392,6 +392,9 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __rest
         }
     }
 
+    // FP64 tiles: one branch at a time (two in flight would take them past 256
+    // VGPRs and halve their occupancy)
+    constexpr int UNR = sizeof(T) == 8 ? 1 : 2;
     const int64_t nblk = (kc + KS - 1) / KS;
     stage(0, 0);
     __builtin_amdgcn_s_waitcnt(0);
@@ -399,7 +402,7 @@ __device__ __forceinline__ void band_tile(BandLds<T, KS, MS>& L, const T* __rest
     for (int64_t blk = 0; blk < nblk; ++blk) {
         const int cur = int(blk & 1);
         if (blk + 1 < nblk) stage(cur ^ 1, (blk + 1) * KS);
-#pragma unroll 2
+#pragma unroll UNR
         for (int kk = 0; kk < KS; ++kk) {
             const uint32_t* rwi = reinterpret_cast<const uint32_t*>(&L.wi[cur][kk][0]);
             const uint32_t* rwj = reinterpret_cast<const uint32_t*>(&L.wj[cur][kk][0]);
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(256) void k_band(const T* __restrict__ E,
     band_patch_tile(xcd_tile(blockIdx.x, n_tiles), n_iblk, n_sblk, &ib, &sblk);
     const int64_t i0 = ib * kBandI;
     const int64_t s0 = sb + sblk * TS;
-    band_tile<T, W, KS, MS, sizeof(T) == 4>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
+    band_tile<T, W, KS, MS, true>(L, E, lenk, kc, n, sb, se, i0, s0, first, acc);
 }
 
 // ----------------------------------------------------------------------------
