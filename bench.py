@@ -320,7 +320,7 @@ def main() -> int:
                     help="C5: ranking loss over triples, or distance regression over pairs")
     ap.add_argument("--dist-weight", type=float, default=0.0, help="C5: regression weight")
     ap.add_argument("--rank-weight", type=float, default=1.0, help="C5: ranking weight")
-    ap.add_argument("--tau", type=float, default=0.01, help="C5: ranking temperature")
+    ap.add_argument("--tau", type=float, default=0.03, help="C5: ranking temperature")
     ap.add_argument("--lr", type=float, default=1e-4, help="C5: Adam learning rate")
     ap.add_argument("--batch-pairs", type=int, default=4096,
                     help="C5: pairs per training step (triples: half as many)")
