@@ -112,19 +112,21 @@ __global__ __launch_bounds__(256) void k_square(const double* __restrict__ v, in
 // part[b][w] for permutations b0 + [0, nb) (perm == nullptr: identity, nb = 1):
 // sum over the rows w and n-2-w of sum_{j>i} y'_ij S[pi(i)][pi(j)].
 // One block of kRowThreads threads per (row pair, batch).  The block keeps its
-// partners' y'_ij (up to kJPT per thread) and pi(j) in registers, stages the
-// permuted row S[pi(i)] in LDS part by part (coalesced reads of the row), and
-// gathers S[pi(i)][pi(j)] from LDS: each permutation reads S once, in order.
+// partners' y'_ij (up to kJPT per thread) and pi(j) in registers and streams the
+// permuted row S[pi(i)] through LDS in parts of part_len: each part goes in with
+// direct-to-LDS loads, all of it in flight at once, then the block gathers
+// S[pi(i)][pi(j)] from it.  Each permutation reads S once, in order.
 __global__ __launch_bounds__(kRowThreads) void k_perm_rows(const double* __restrict__ S,
                                                            const double* __restrict__ yv, int64_t n,
                                                            const int32_t* __restrict__ perm,
                                                            int64_t b0, int nb, int64_t n_pairs,
                                                            int64_t part_len,
                                                            double* __restrict__ part) {
-    extern __shared__ double row[];           // [part_len], then kRowThreads for the reduction
-    double* red = row + part_len;
+    extern __shared__ double lds[];           // [part_len], then kRowThreads for the reduction
+    double* red = lds + part_len;
     const int64_t w = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nparts = (n + part_len - 1) / part_len;
     for (int q = 0; q < nb; ++q) {            // one permutation at a time; y' rows stay in L2
         const int32_t* pb = perm ? perm + (b0 + q) * n : nullptr;
         double a = 0.0;
@@ -134,6 +136,16 @@ __global__ __launch_bounds__(kRowThreads) void k_perm_rows(const double* __restr
             if (i < 0 || i >= n - 1) continue;
             const int64_t base = cidx(n, i, i + 1);   // y'_{i, i+1 ..}
             const int64_t pi = pb ? int64_t(pb[i]) : i;
+            const uint32_t* srow = reinterpret_cast<const uint32_t*>(S + pi * n);
+            // part k of the row into LDS, 64 dwords per wave instruction
+            auto issue = [&](int64_t k) {
+                const int64_t lo = k * part_len;
+                const int len2 = int(2 * min(part_len, n - lo));
+                const uint32_t* src = srow + 2 * lo;
+                uint32_t* dst = reinterpret_cast<uint32_t*>(lds);
+                for (int c = 64 * wave; c < len2; c += kRowThreads)
+                    if (c + lane < len2) __builtin_amdgcn_global_load_lds(src + c + lane, dst + c, 4, 0, 0);
+            };
             for (int64_t jc = i + 1; jc < n; jc += int64_t(kRowThreads) * kJPT) {
                 double yr[kJPT];
                 int32_t pr[kJPT];
@@ -143,25 +155,14 @@ __global__ __launch_bounds__(kRowThreads) void k_perm_rows(const double* __restr
                     yr[t] = j < n ? yv[base + (j - i - 1)] : 0.0;
                     pr[t] = j < n ? (pb ? pb[j] : int32_t(j)) : -1;
                 }
-                for (int64_t lo = 0; lo < n; lo += part_len) {
-                    const int len = int(min(part_len, n - lo));
-                    __syncthreads();
-                    // eight loads in flight per thread before their LDS stores
-                    for (int k0 = tid; k0 < len; k0 += kRowThreads * 8) {
-                        double v[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int k = k0 + u * kRowThreads;
-                            v[u] = k < len ? S[pi * n + lo + k] : 0.0;
-                        }
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int k = k0 + u * kRowThreads;
-                            if (k < len) row[k] = v[u];
-                        }
-                    }
-                    __syncthreads();
-                    const int lo32 = int(lo);
+                for (int64_t k = 0; k < nparts; ++k) {
+                    __syncthreads();   // every wave done with the previous part
+                    issue(k);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();   // part k in LDS for every wave
+                    const double* row = lds;
+                    const int lo32 = int(k * part_len);
+                    const int len = int(min(part_len, n - k * part_len));
 #pragma unroll
                     for (int t = 0; t < kJPT; ++t) {
                         const int c = pr[t] - lo32;
