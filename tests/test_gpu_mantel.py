@@ -8,7 +8,9 @@
 * the identity among the permutations reproduces the statistic exactly;
 * constant matrix, out-of-range permutation entries;
 * full C2 matrices: the statistic and two permuted statistics against torch's
-  own correlation of the (permuted) condensed vectors.
+  own correlation of the (permuted) condensed vectors;
+* N = 40,000 random matrices, rows with more partners than one register pass
+  holds, three LDS parts per row: the same checks.
 """
 import numpy as np
 import pytest
@@ -118,3 +120,37 @@ def test_mantel_full_size():
     assert np.allclose(ps[:2], checks, atol=1e-9)
     assert ps[len(ps) // 2] == st
     assert 1 / 10 <= p <= 1
+
+
+def test_mantel_rows_longer_than_one_register_pass():
+    """N = 40,000: a block holds 32,768 partners in registers, so the first 7,231
+    rows take a second pass over S's row, and each row streams in three LDS parts.
+    Statistic and two permuted statistics against torch's correlation of the
+    (permuted) condensed vectors."""
+    import torch
+    import paper_2107_05397_amd as uf
+    n = 40_000
+    m = n * (n - 1) // 2
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    x = torch.rand(m, dtype=torch.float64, device="cuda", generator=g)
+    y = x + 0.5 * torch.rand(m, dtype=torch.float64, device="cuda", generator=g)
+    perms = _perms(n, 5, seed=12)
+    st, p, ps = uf.mantel(x, y, n, "pearson", torch.tensor(perms, device="cuda"))
+    torch.cuda.synchronize()
+    want = torch.corrcoef(torch.stack([x, y]))[0, 1].item()
+    iu = torch.triu_indices(n, n, 1, device="cuda")
+    full = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    full[iu[0], iu[1]] = x
+    full = full + full.T
+    checks = []
+    for b in (0, 1):
+        pm = torch.tensor(perms[b], dtype=torch.int64, device="cuda")
+        xp = full[pm[iu[0]], pm[iu[1]]]
+        checks.append(torch.corrcoef(torch.stack([xp, y]))[0, 1].item())
+        del xp
+    print(f"[mantel n=40000] r={st:.12f} torch {want:.12f}; perm {ps[:2]} torch {checks}")
+    assert st == pytest.approx(want, abs=1e-9)
+    assert np.allclose(ps[:2], checks, atol=1e-9)
+    assert ps[len(ps) // 2] == st
+    assert p == pytest.approx(2 / 6)   # the identity and r itself are as extreme as r
